@@ -1,0 +1,314 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than itself: a
+closed form, an invariant, a special case that reduces to a textbook result or
+library routine, a value printed in the paper, or brute force.  Small sizes
+only (the whole file runs in well under a minute).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.special import gamma as Gamma
+
+from paper_2607_27440_amd import workloads as W
+from oracle import eig as E
+from oracle import grid as G
+from oracle import jd as J
+from oracle import operator as O
+from oracle import velocity as Vq
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- P1 grid --
+@pytest.mark.parametrize("N", [4, 9, 23])
+def test_cheb_diff_exact_on_polynomials(N):
+    """D_y differentiates polynomials of degree <= N exactly at the nodes."""
+    y = G.cheb_nodes(N)
+    D = G.cheb_diff(N)
+    for k in range(N + 1):
+        err = np.max(np.abs(D @ y ** k - k * y ** max(k - 1, 0) * (k > 0)))
+        assert err <= 1e-11 * max(1, k) * N ** 2, (k, err)
+
+
+def test_mapped_derivative():
+    """D_x (y(x)^k) = k y^{k-1} dy/dx, and dy/dx matches a centred difference of
+    the inverse map y(x) = x sqrt(1+s) / sqrt(L^2 + x^2)."""
+    Ny, L, sinf = 17, 2.0, 10.0
+    x, dydx, Dx = G.mapped_grid(Ny, L, sinf)
+    s = (L / sinf) ** 2
+    y = G.cheb_nodes(Ny - 1)
+    assert np.allclose(x[[0, -1]], [sinf, -sinf], rtol=1e-14)
+    yofx = lambda xx: xx * math.sqrt(1 + s) / np.sqrt(L ** 2 + xx ** 2)
+    assert np.allclose(yofx(x), y, atol=1e-14)
+    h = 1e-6
+    fd = (yofx(x + h) - yofx(x - h)) / (2 * h)
+    assert np.allclose(dydx, fd, rtol=1e-8)
+    for k in range(1, 6):
+        assert np.allclose(Dx @ y ** k, k * y ** (k - 1) * dydx, atol=1e-10)
+
+
+# ------------------------------------------------------------ P2 quadrature --
+def test_gauss_hermite_exactness():
+    """Sec. 3.2: n-point Gauss-Hermite is exact for degree <= 2n - 1:
+    sum W x^{2m} = Gamma(m + 1/2), odd moments vanish."""
+    for n in (4, 10, 20):
+        x, w = Vq.gauss_hermite(n)
+        for m in range(n):
+            assert abs(w @ x ** (2 * m) - Gamma(m + 0.5)) <= 1e-12 * Gamma(m + 0.5)
+            assert abs(w @ x ** (2 * m + 1)) <= 1e-12 * max(1.0, Gamma(m + 1.0))
+
+
+def _fine(base, Ny=5, nu_inf=W.NU_INF_HS, beta=0.7, mach=2.0, Qx=48, Qy=40, a=9.0, s_visc=0.5):
+    return W.make_workload("fine", mach=mach, Ny=Ny, Qx=Qx, Qy=Qy, beta=beta, sigma=0.0, nev=4,
+                           base=base, delta=2.5, vmax=a, nu_inf=nu_inf, s_visc=s_visc)
+
+
+def test_maxwellian_moments_closed_form():
+    """Discrete moments of the reduced Maxwellians reproduce rho, u, E = u^2/2 + 3T/4
+    (Sec. 2.2 units) on a fine grid; the Dv = 1 reduction gives the same E."""
+    for Dv in (2, 1):
+        wl = W.make_workload("m", mach=3.0, Ny=6, Qx=64, Qy=1 if Dv == 1 else 48, beta=0.5,
+                             sigma=0, nev=2, base="maxwellian", delta=2.0, vmax=10.0, Dv=Dv)
+        ge, he = O.equilibrium(wl.rho, wl.u, wl.T, wl.xi_x, wl.xi_y, Dv)
+        rho, u, v, E_, T = O.moments(ge, he, wl.xi_x, wl.xi_y, wl.w)
+        assert np.allclose(rho, wl.rho, rtol=1e-11)
+        assert np.allclose(u, wl.u, rtol=1e-11)
+        assert np.allclose(E_, 0.5 * wl.u ** 2 + 0.75 * wl.T, rtol=1e-11)
+        assert np.allclose(v, 0, atol=1e-12)
+
+
+# ------------------------------------------------- P3 linearisation pin ----
+@pytest.mark.parametrize("base", ["bimodal", "maxwellian"])
+@pytest.mark.parametrize("s_visc", [0.5, 1.0])
+def test_collision_is_complex_step_derivative(base, s_visc):
+    """The coupling and relaxation rows of A equal the exact directional
+    derivative of the nonlinear discrete BGK relaxation nu(m)(f^e(m) - f)
+    (complex step, step 1e-30), i.e. the linearisation of eq. CompBGKtilde.
+    NONEQ base: macros from discrete moments (exact derivative).  EQ base: macros
+    given, so the match holds to quadrature accuracy on this fine grid."""
+    wl = _fine(base, s_visc=s_visc)
+    P = O.Pencil(wl)
+    st = P.state
+    rng = np.random.default_rng(5)
+    dg = rng.standard_normal((P.Ny, P.Nxi))
+    dh = rng.standard_normal((P.Ny, P.Nxi))
+    eps = 1e-30
+    Qg, Qh = O.collision_nonlinear(st["gc"] + 1j * eps * dg, st["hc"] + 1j * eps * dh, wl)
+    dQg, dQh = Qg.imag / eps, Qh.imag / eps
+    X = np.stack([dg, dh], axis=1)                                   # [j, f, k]
+    m = np.einsum("jafk,jfk->ja", P.M, X)
+    lin = -st["nu"][:, None, None] * X + np.einsum("jfak,ja->jfk", P.U, m)
+    scale = np.abs(lin).max()
+    tol = 1e-13 if base == "bimodal" else 1e-9
+    assert np.abs(lin[:, 0] - dQg).max() <= tol * scale
+    assert np.abs(lin[:, 1] - dQh).max() <= tol * scale
+
+
+# ----------------------------------------------------- P4 conservation ----
+def test_collision_conserves_mass_momentum_energy():
+    """phi^T W L = 0 for phi in {1, xi_x, xi_y, (|xi|^2 on g, 1 on h)}: the
+    linearised relaxation conserves the collision invariants (quadrature level)."""
+    wl = _fine("bimodal")
+    P = O.Pencil(wl)
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((P.Ny, 2, P.Nxi))
+    m = np.einsum("jafk,jfk->ja", P.M, X)
+    L = -P.state["nu"][:, None, None] * X + np.einsum("jfak,ja->jfk", P.U, m)
+    w, xx, yy = wl.w, wl.xi_x, wl.xi_y
+    scale = np.abs(L).max() * np.sum(w * (1 + xx ** 2 + yy ** 2))
+    for phi_g, phi_h in [(np.ones_like(w), 0 * w), (xx, 0 * w), (yy, 0 * w), (xx ** 2 + yy ** 2, np.ones_like(w))]:
+        inv = L[:, 0, :] @ (w * phi_g) + L[:, 1, :] @ (w * phi_h)
+        assert np.abs(inv).max() <= 1e-10 * scale
+
+
+# ------------------------------------------------------ P5 null space ----
+def test_collision_block_spectrum_about_maxwellian():
+    """About a Maxwellian the collision block nu I - U M at each node has the
+    eigenvalue 0 with multiplicity r (null vectors dg^e/da, dh^e/da) and nu_j for
+    the remaining 2 Nxi - r directions."""
+    wl = _fine("maxwellian", Qx=40, Qy=36)
+    P = O.Pencil(wl)
+    for j in (0, 2, 4):
+        Uj = P.U[j].transpose(0, 2, 1).reshape(2 * P.Nxi, P.r)
+        Mj = P.M[j].reshape(P.r, 2 * P.Nxi)
+        nu = P.state["nu"][j]
+        C = nu * np.eye(2 * P.Nxi) - Uj @ Mj
+        ev = np.linalg.eigvals(C)
+        near0 = np.sort(np.abs(ev))[:P.r]
+        assert np.all(near0 <= 1e-9 * nu)
+        rest = ev[np.argsort(np.abs(ev))[P.r:]]
+        assert np.allclose(rest, nu, rtol=1e-9)
+        # null vectors: the coupling columns themselves (G_a = nu dg^e/da for EQ)
+        assert np.abs(C @ Uj).max() <= 1e-9 * nu * np.abs(Uj).max()
+
+
+# ------------------------------------------- P6/P7 special-case spectra ----
+def test_collisionless_spectrum_is_union_of_line_spectra():
+    """nu_inf = 0: the coupling vanishes and the finite spectrum of the pencil is
+    the union over velocity lines of eig(xi_x D_x + i beta xi_y) with the inflow
+    row removed (Chebyshev advection with inflow Dirichlet condition)."""
+    wl = W.make_workload("free", mach=1.5, Ny=9, Qx=4, Qy=2, beta=0.8, sigma=0, nev=3,
+                         base="bimodal", delta=2.0, vmax=5.0, nu_inf=0.0)
+    P = O.Pencil(wl)
+    lam, _, _, ninf = E.qz_all(P)
+    ref = []
+    for k in range(P.Nxi):
+        Lk = wl.xi_x[k] * P.Dx + 1j * wl.beta * wl.xi_y[k] * np.eye(P.Ny)
+        keep = ~P.bc[:, 0, k]
+        ref.extend(list(np.linalg.eigvals(Lk[np.ix_(keep, keep)])) * 2)   # g and h lines
+    ref = np.array(ref)
+    assert len(ref) == len(lam) and ninf == int(P.bc.sum())
+    for l in lam:
+        assert np.min(np.abs(ref - l)) <= 1e-8 * max(1, abs(l))
+
+
+def test_free_transverse_transport_closed_form():
+    """No streaming (single node xi_x = 0) and no collisions: the normal mode
+    exp(i(beta y - omega t)) of free transport has omega = beta xi_y, so every
+    eigenvalue is lambda = i omega = i beta xi_y,k, with multiplicity 2 Ny."""
+    wl = W.make_workload("tr", mach=1.5, Ny=6, Qx=1, Qy=5, beta=1.3, sigma=0, nev=3,
+                         base="bimodal", delta=2.0, vmax=4.0, nu_inf=0.0)
+    P = O.Pencil(wl)
+    lam, _, _, ninf = E.qz_all(P)
+    assert ninf == 0
+    expect = np.sort_complex(np.repeat(1j * wl.beta * wl.xi_y, 2 * wl.Ny))
+    assert np.allclose(np.sort_complex(lam), expect, atol=1e-12)
+
+
+# ---------------------------------------------------- P8 pencil structure --
+def test_pencil_infinite_eigenvalues_and_reduction():
+    """#infinite eigenvalues = number of inflow rows; the finite spectrum equals
+    eig(A) restricted to non-inflow rows and columns."""
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam, _, _, ninf = E.qz_all(P)
+    assert ninf == int(P.bc.sum()) == 32
+    keep = ~P.bc.ravel()
+    Ared = P.A.toarray()[np.ix_(keep, keep)]
+    ev = np.linalg.eigvals(Ared)
+    for l in lam:
+        assert np.min(np.abs(ev - l)) <= 1e-9 * max(1.0, abs(l))
+
+
+# ------------------------------------------------ P9 conjugate symmetry ----
+def test_spectrum_closed_under_conjugation():
+    """A symmetric xi_y grid with v = 0: reflecting xi_y maps A to conj(A) up to
+    a permutation, so the spectrum is closed under conjugation."""
+    wl = W.make_workload("cj", mach=2.0, Ny=10, Qx=4, Qy=4, beta=0.9, sigma=0, nev=3,
+                         base="bimodal", delta=2.0, vmax=6.0)
+    P = O.Pencil(wl)
+    lam, _, _, _ = E.qz_all(P)
+    for l in lam:
+        assert np.min(np.abs(lam - np.conj(l))) <= 1e-9 * max(1, abs(l))
+
+
+# -------------------------------------------------------- P10 nnz table ----
+def test_nnz_formula_reproduces_paper_table():
+    """nnz(A) = n (N_y - 1 + 2 Nxi) - n_bc (N_y - 2 + 2 Nxi) reproduces every row
+    of the paper's benchmark table (Gauss-Hermite nodes: even Q, no zero node,
+    so each boundary has Q^2/2 inflow nodes per field, n_bc = 2 Q^2)."""
+    rows = np.loadtxt(os.path.join(HERE, "golden", "nnz_benchmark_cases.txt"), dtype=np.int64)
+    for Q, n, nnz in rows:
+        Ny, Nxi = 81, Q * Q
+        x, _ = Vq.gauss_hermite(Q)
+        xx, _, _ = Vq.tensor_table(x, np.ones(Q), x, np.ones(Q))
+        n_bc = 2 * (int(np.sum(xx > 0)) + int(np.sum(xx < 0)))
+        assert 2 * Ny * Nxi == n
+        assert O.nnz_formula(Ny, Nxi, n_bc) == nnz
+
+
+def test_structural_pattern_matches_formula_and_matrix():
+    for wl in (W.config1(), _fine("bimodal", Ny=7, Qx=5, Qy=4)):
+        P = O.Pencil(wl)
+        S = O.structural_pattern(P.Ny, wl.xi_x)
+        assert S.nnz == O.nnz_formula(P.Ny, P.Nxi, int(P.bc.sum()))
+        A = P.A
+        # every stored entry of A lies in the structural pattern
+        Ab = (A != 0).astype(bool)
+        assert (Ab.multiply(S) != Ab).nnz == 0
+
+
+# ------------------------------------------------------- P11 Woodbury ----
+@pytest.mark.parametrize("sigma", [0.0, 0.05j, 0.4 - 0.2j])
+def test_structured_inverse_solves(sigma):
+    wl = W.config1()
+    P = O.Pencil(wl)
+    S = E.ShiftInvert(P, sigma)
+    b = W.random_vector(P.n, 4)
+    y = S.solve(b)
+    r = P.apply(y, sigma) - b
+    assert np.linalg.norm(r) <= 1e-12 * np.linalg.norm(b) * np.abs(P.A).sum(1).max()
+    Sa = E.ShiftInvert(P, sigma, adjoint=True)
+    ya = Sa.solve(b)
+    Ah = (P.A - sigma * P.B).conj().T
+    assert np.linalg.norm(Ah @ ya - b) <= 1e-12 * np.linalg.norm(b) * np.abs(P.A).sum(1).max()
+
+
+# ------------------------------------------- preconditioner definitions ----
+def test_line_block_ilu0_properties():
+    """ILU(0) is characterised by (L U)_ij = C_ij on the pattern (eq. ilu with no
+    fill); with one line per block the pattern is dense and ILU(0) is the exact
+    LU, so K^{-1} C = I on each block."""
+    wl = W.config1()
+    P = O.Pencil(wl)
+    sigma = 0.1 + 0.02j
+    for lines in (1, 3):
+        K = J.LineBlockILU0(P, sigma, lines)
+        C = (P.A - sigma * P.B).tocsr()[K.perm][:, K.perm].toarray()
+        S = O.structural_pattern(P.Ny, wl.xi_x)[K.perm][:, K.perm].toarray()
+        for a, b, F in K.blocks:
+            Lf = np.tril(F, -1) + np.eye(b - a)
+            Uf = np.triu(F)
+            D = (Lf @ Uf - C[a:b, a:b]) * S[a:b, a:b]
+            assert np.abs(D).max() <= 1e-11 * np.abs(C[a:b, a:b]).max()
+            if lines == 1:
+                assert np.allclose(Lf @ Uf, C[a:b, a:b], atol=1e-11 * np.abs(C[a:b, a:b]).max())
+                x = np.random.default_rng(a).standard_normal(b - a) + 0j
+                full = np.zeros(P.n, complex)
+                full[K.perm[a:b]] = x
+                got = K.solve(full)[K.perm[a:b]]
+                assert np.allclose(got, sla.solve(C[a:b, a:b], x), rtol=1e-10, atol=1e-12)
+
+
+def test_gmres_exact_in_n_steps():
+    rng = np.random.default_rng(8)
+    n = 12
+    Am = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)) + 4 * np.eye(n)
+    b = rng.standard_normal(n) + 0j
+    x, steps = J.gmres(lambda v: Am @ v, b, n, 1e-14)
+    assert np.allclose(x, np.linalg.solve(Am, b), atol=1e-10)
+
+
+def test_sorted_schur():
+    rng = np.random.default_rng(9)
+    Gm = rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9))
+    U, T, mu = J._sorted_schur(Gm)
+    assert np.allclose(Gm @ U, U @ T, atol=1e-12)
+    assert np.allclose(np.tril(T, -1), 0, atol=1e-12)
+    assert np.all(np.diff(np.abs(np.diag(T))) <= 1e-12)
+
+
+def test_start_vector_splitmix_reference_values():
+    """SplitMix64 reference outputs for seed 0 (published test vector of the
+    generator: first outputs of splitmix64 with state 0)."""
+    z = J.splitmix64(np.arange(3, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15))
+    assert [int(v) for v in z] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+# ------------------------------------------------ P12 cross-method agreement --
+def test_qz_shift_invert_jd_agree_c1():
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lq, _, kap, _ = E.qz_nearest(P, wl.sigma, wl.nev + 4)
+    ls, Xs = E.si_nearest(P, wl.sigma, wl.nev + 4)
+    for l in ls:
+        assert np.min(np.abs(lq - l)) <= 1e-12 * abs(l)
+    out = J.jd(P, wl.sigma, 6, precond=J.LineBlockILU0(P, wl.sigma, 4))
+    assert out["nconv"] == 6
+    assert np.all(out["resid"] <= 1e-10)
+    for l in out["lam"]:
+        assert np.min(np.abs(lq - l)) <= 1e-9 * abs(l)
