@@ -1,0 +1,192 @@
+/*
+ * klst.h -- C ABI of the MI355X kinetic linear stability (kLST) eigen-solver.
+ *
+ * The library solves the generalized eigenproblem A q = lambda B q of the
+ * BGK-linearised reduced Boltzmann equation for a 1-D normal shock with a
+ * transverse normal mode exp(i(beta y - omega t)), lambda = i omega
+ * (paper Sec. 2.2, eqs. Comp1DHarm, comp_ghat1Dshock, comp_hhat1Dshock,
+ * MatrixSystem; Sec. 4 eq. MatrixProblem), discretised with mapped
+ * Chebyshev-Gauss-Lobatto collocation in x (Sec. 3.1) times a micro-velocity
+ * node table (Sec. 3.2).  It returns the eigenvalues nearest a target sigma
+ * with their right eigenvectors, computed by Jacobi-Davidson with a
+ * block-Jacobi ILU(0) preconditioned GMRES correction equation (Sec. 4.2).
+ *
+ * Conventions shared by every entry point
+ *  - Complex numbers cross the ABI as interleaved (re, im) double pairs.
+ *  - Unknown ordering: q[(2 j + f) * Nxi + k], j = spatial node (j = 0 at
+ *    x = +s_inf, downstream), f = 0 for g_hat and 1 for h_hat, k = velocity
+ *    node.  n = 2 Ny Nxi.
+ *  - Inflow rows (j = Ny-1 with xi_x > 0, j = 0 with xi_x < 0) are identity
+ *    rows of A and zero rows of B (zero-perturbation Dirichlet conditions of
+ *    Sec. 2.2), so finite eigenvectors vanish there.
+ *  - Every entry point returns a klst_status; nothing throws or exits.  On
+ *    error, klst_last_error() describes the cause.  Input arrays are copied;
+ *    the caller keeps ownership of everything it passes.  Output buffers are
+ *    caller-allocated.  A context is not thread-safe: use one per host thread.
+ *  - "device" pointers are HIP device addresses on the context's device (for
+ *    example torch tensor data_ptr()); work is ordered on the context's stream.
+ */
+#ifndef KLST_H
+#define KLST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct klst_ctx klst_ctx;
+
+typedef enum {
+  KLST_OK = 0,
+  KLST_EINVAL = 1,      /* bad argument or inconsistent input                   */
+  KLST_ENOMEM = 2,      /* device or host allocation failed                     */
+  KLST_EDEVICE = 3,     /* HIP runtime error, or no usable device               */
+  KLST_ENOCONV = 4,     /* max_it reached; the first nconv results are valid    */
+  KLST_EBUSY = 5,       /* (served mode) not admitted: slots or memory are full */
+  KLST_ECANCELLED = 6,  /* (served mode) request was cancelled                  */
+  KLST_ESTATE = 7       /* call out of order (e.g. solve before assemble)       */
+} klst_status;
+
+/* Solver options (defaults from klst_default_options).  Paper defaults for the
+ * JD solve are listed in its Appendix C; the values here follow the same
+ * scheme: tol on ||A u - theta B u|| / (|theta| ||u||), restart from m_max to
+ * m_min, GMRES correction-equation solves of at most gmres_m steps. */
+typedef struct {
+  int device;           /* HIP device ordinal                                        */
+  void* stream;         /* hipStream_t to order work on; NULL = library-owned stream */
+  int precision;        /* 0 = FP64 everywhere; 1 = FP32 inner GMRES + preconditioner
+                           inside an FP64 iterative refinement of the correction eq. */
+  int op_mode;          /* 0 = matrix-free operator; 1 = explicit CSR (built on device) */
+  int lines_per_block;  /* block-Jacobi block = this many whole velocity lines       */
+  int m_max, m_min;     /* search-space size before / after a restart               */
+  int gmres_m;          /* GMRES steps per correction-equation solve                 */
+  int max_it;           /* outer-iteration budget                                    */
+  double tol;           /* eigenpair acceptance: relative residual                   */
+  double inner_rtol;    /* GMRES relative tolerance                                  */
+  double fix;           /* correction shift = sigma until rel. residual < fix        */
+  uint64_t seed;        /* start vector: counter-based SplitMix64 stream             */
+} klst_options;
+
+/* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]
+ * by x = L y / sqrt(1 + s - y^2), s = (L/s_inf)^2 (Sec. 3.1, eq. Chebmapping). */
+typedef struct {
+  int Ny;
+  double L;
+  double s_inf;
+} klst_grid;
+
+/* Micro-velocity node table (Sec. 3.2), Nxi nodes with weights w > 0.  Dv = 2
+ * resolves (xi_x, xi_y) and couples rho, u, v, E (rank 4); Dv = 1 requires
+ * xi_y == 0 and couples rho, u, E (rank 3). */
+typedef struct {
+  int Nxi;
+  const double* xi_x;   /* [Nxi] host */
+  const double* xi_y;   /* [Nxi] host */
+  const double* w;      /* [Nxi] host */
+  int Dv;
+} klst_vel;
+
+/* Base flow on the Ny nodes.  mode 0 (EQ): macros rho, u, T given and the base
+ * VDFs are the local Maxwellians.  mode 1 (NONEQ): reduced VDFs g_c, h_c
+ * [Ny * Nxi] given; macros are their discrete moments.  Collision rate
+ * nu = nu_inf * rho * T^(1 - s_visc) (BGK rate P/mu with mu ~ T^s, Sec. 2.1). */
+typedef struct {
+  int mode;
+  const double *rho, *u, *T;   /* [Ny] host, mode 0 */
+  const double *g_c, *h_c;     /* [Ny*Nxi] host, mode 1, row-major (j, k) */
+  double s_visc;
+  double nu_inf;
+} klst_base;
+
+/* Per-solve statistics of the last klst_solve. */
+typedef struct {
+  int outer_iterations;
+  int inner_iterations;      /* total GMRES steps                               */
+  int restarts;
+  int nconv;
+  int pivots_floored;        /* ILU(0) pivots raised to the floor (reading R9)  */
+  double seconds_total;      /* wall time of klst_solve                         */
+  double seconds_setup;      /* preconditioner set-up inside klst_solve         */
+  double seconds_op;         /* device time in operator applications (events)   */
+  double seconds_pc;         /* device time in preconditioner applications      */
+  int64_t op_applies;
+  int64_t pc_applies;
+} klst_stats;
+
+void        klst_default_options(klst_options* opt);
+const char* klst_strerror(klst_status s);
+const char* klst_last_error(const klst_ctx* ctx);
+
+/* Create a context bound to opt->device.  Allocates no problem memory yet.
+ * Errors: EINVAL (bad options), EDEVICE (no such device / HIP failure). */
+klst_status klst_create(klst_ctx** out, const klst_options* opt);
+void        klst_destroy(klst_ctx* ctx);
+
+/* Build the discrete operator of Sec. 2.2 for this grid, velocity table, base
+ * flow and transverse wavenumber beta; uploads coefficient tables (and, in
+ * op_mode 1, generates the CSR matrix on the device).  Replaces any previous
+ * problem in ctx.  Errors: EINVAL (Ny < 3, Nxi < 1, w <= 0, non-finite input,
+ * rho <= 0 or T <= 0 after moments, Dv = 1 with xi_y != 0), ENOMEM, EDEVICE. */
+klst_status klst_assemble(klst_ctx* ctx, const klst_grid* grid, const klst_vel* vel,
+                          const klst_base* base, double beta);
+
+/* Problem sizes: n unknowns, structural nnz of A (n (Ny-1+2Nxi) - n_bc (Ny-2+2Nxi)),
+ * number of inflow rows.  Any pointer may be NULL. */
+klst_status klst_dims(const klst_ctx* ctx, int64_t* n, int64_t* nnz, int* n_bc);
+
+/* y = (A - tau B) x for device vectors x, y of n complex doubles (the operator
+ * rows of eqs. comp_ghat1Dshock / comp_hhat1Dshock).  x and y must not
+ * overlap.  Uses op_mode's operator.  Errors: ESTATE (no problem), EINVAL. */
+klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* y);
+
+/* Same product, batched over nvec vectors stored contiguously (vector i at
+ * x + i n).  Matrix-free only. */
+klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);
+
+/* y = (A - tau B) x with the explicit CSR matrix regardless of op_mode
+ * (generated on first use).  Errors: ENOMEM if the matrix does not fit. */
+klst_status klst_apply_csr(klst_ctx* ctx, const double tau[2], const void* x, void* y);
+
+/* Set up the block-Jacobi ILU(0) preconditioner of (A - sigma B) (Sec. 4.2,
+ * eqs. ilu and bjilu): contiguous row blocks of `lines_per_block` whole
+ * velocity lines in the velocity-major ordering (field, velocity node, spatial
+ * node).  klst_solve calls this itself; exposed for testing. */
+klst_status klst_precond_setup(klst_ctx* ctx, const double sigma[2]);
+
+/* y = K^{-1} x with the current preconditioner, device vectors. */
+klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
+
+/* Jacobi-Davidson solve for the nev eigenvalues nearest sigma (Sec. 4.2).
+ * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at
+ * X + 2 n i doubles), on the host or the device (X_on_device), or NULL.
+ * Eigenvectors are scaled to unit 2-norm with the largest entry real positive.
+ * resid: [nev] host relative residuals ||A x - lambda B x|| / (|lambda| ||x||),
+ * or NULL.  nconv: converged count.  Returns ENOCONV (with nconv < nev valid
+ * results) when max_it is reached.  Errors: ESTATE, EINVAL (nev < 1 or
+ * nev > n - n_bc or nev + m_min > m_max), ENOMEM, EDEVICE. */
+klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* lambda,
+                       void* X, int X_on_device, double* resid, int* nconv);
+
+/* Statistics of the last solve. */
+klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);
+
+/* Host-only (no device needed): the tables klst_assemble builds, for testing
+ * against an independent implementation.  Dx [Ny*Ny] row-major, nu [Ny],
+ * U [Ny][2][r][Nxi] (coupling columns: G_a on g rows, H_a on h rows), M
+ * [Ny][r][2][Nxi] (moment functionals m_a), bc [Ny*2*Nxi] (1 = inflow row),
+ * where r = 4 (Dv = 2) or 3.  Any output may be NULL. */
+klst_status klst_host_tables(const klst_grid* grid, const klst_vel* vel, const klst_base* base,
+                             double beta, double* Dx, double* nu, double* U, double* M,
+                             uint8_t* bc);
+
+/* Host-only: sorted complex Schur form of a small m x m complex matrix G
+ * (row-major interleaved), G U = U T with |T_00| >= |T_11| >= ...; used by the
+ * solver for its projected problems; exposed for testing.  U, T row-major. */
+klst_status klst_host_sorted_schur(int m, const double* G, double* U, double* T);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KLST_H */

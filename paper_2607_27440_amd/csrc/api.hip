@@ -1,0 +1,854 @@
+// C ABI of the kLST library (include/klst.h): context, assembly, operator and
+// preconditioner entry points, and the Jacobi-Davidson driver.
+//
+// The driver keeps every n-vector in HBM.  The host sees only small projected
+// matrices (R, M_B, the partial Schur form), scalars and flags: one host
+// synchronisation per expansion and one per residual check.  The GMRES solve of
+// the correction equation runs entirely on the device (Hessenberg, Givens
+// rotations and early-exit flag in device memory).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "host.hpp"
+#include "kernels.hpp"
+#include "klst.h"
+
+using klst::cd;
+
+struct klst_ctx {
+  klst_options opt{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  bool assembled = false;
+  klst::Problem prob;
+  // device tables
+  double *d_Dx = nullptr, *d_xix = nullptr, *d_xiy = nullptr, *d_nu = nullptr, *d_U = nullptr,
+         *d_M = nullptr;
+  double2* d_mom = nullptr;
+  int mom_cap = 0;   // vectors
+  // explicit CSR
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_col = nullptr;
+  double2* d_val = nullptr;
+  // preconditioner
+  klst::ILU0 ilu;
+  double2 *d_F = nullptr, *d_C = nullptr;
+  bool pc_ready = false;
+  cd pc_sigma = 0.0;
+  int pc_lines = 0;
+  // reductions
+  double2* d_partial = nullptr;
+  unsigned* d_counter = nullptr;
+  klst_stats stats{};
+};
+
+namespace {
+
+#define HIPCHK(expr)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);             \
+      return KLST_EDEVICE;                                                      \
+    }                                                                           \
+  } while (0)
+
+klst_status fail(klst_ctx* ctx, klst_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) hipFree(p);
+  p = nullptr;
+}
+
+klst_status dalloc(klst_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    ctx->err = "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return KLST_ENOMEM;
+  }
+  return KLST_OK;
+}
+
+#define ALLOC(ptr, bytes)                                                        \
+  do {                                                                           \
+    klst_status s_ = dalloc(ctx, (void**)&(ptr), (bytes));                       \
+    if (s_ != KLST_OK) return s_;                                                \
+  } while (0)
+
+void free_problem(klst_ctx* ctx) {
+  dfree(ctx->d_Dx); dfree(ctx->d_xix); dfree(ctx->d_xiy); dfree(ctx->d_nu); dfree(ctx->d_U);
+  dfree(ctx->d_M); dfree(ctx->d_mom); dfree(ctx->d_rowptr); dfree(ctx->d_col); dfree(ctx->d_val);
+  dfree(ctx->d_F); dfree(ctx->d_C);
+  ctx->mom_cap = 0;
+  ctx->pc_ready = false;
+  ctx->assembled = false;
+}
+
+klst_status ensure_mom(klst_ctx* ctx, int nvec) {
+  if (ctx->mom_cap >= nvec) return KLST_OK;
+  dfree(ctx->d_mom);
+  ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec);
+  ctx->mom_cap = nvec;
+  return KLST_OK;
+}
+
+klst_status ensure_csr(klst_ctx* ctx) {
+  if (ctx->d_val) return KLST_OK;
+  const klst::Problem& p = ctx->prob;
+  const int64_t n = p.n(), nnz = p.nnz();
+  if (nnz >= (int64_t)1 << 62) return fail(ctx, KLST_EINVAL, "matrix too large");
+  ALLOC(ctx->d_rowptr, sizeof(int64_t) * (n + 1));
+  ALLOC(ctx->d_col, sizeof(int32_t) * nnz);
+  const klst_status s = dalloc(ctx, (void**)&ctx->d_val, sizeof(double2) * nnz);
+  if (s != KLST_OK) {
+    dfree(ctx->d_rowptr); dfree(ctx->d_col);
+    return s;
+  }
+  int npos = 0, nneg = 0;
+  for (int k = 0; k < p.Nxi; ++k) { npos += p.xi_x[k] > 0; nneg += p.xi_x[k] < 0; }
+  klst::dev::launch_csr_build(ctx->stream, ctx->d_rowptr, ctx->d_col, ctx->d_val, p.Ny, p.Nxi, p.r,
+                              p.beta, ctx->d_Dx, ctx->d_xix, ctx->d_xiy, ctx->d_nu, ctx->d_U,
+                              ctx->d_M, npos, nneg);
+  HIPCHK(hipGetLastError());
+  return KLST_OK;
+}
+
+// y = (A - tau B) x on the device (nvec vectors).
+klst_status op_apply(klst_ctx* ctx, cd tau, const double2* x, double2* y, int nvec, int mode,
+                     const int* skip) {
+  const klst::Problem& p = ctx->prob;
+  if (mode == 1) {
+    klst_status s = ensure_csr(ctx);
+    if (s != KLST_OK) return s;
+    for (int v = 0; v < nvec; ++v)
+      klst::dev::launch_csr_spmv(ctx->stream, ctx->d_rowptr, ctx->d_col, ctx->d_val, x + v * p.n(),
+                                 y + v * p.n(), p.n(), p.Ny, p.Nxi, ctx->d_xix, tau.real(),
+                                 tau.imag(), skip);
+  } else {
+    klst_status s = ensure_mom(ctx, nvec);
+    if (s != KLST_OK) return s;
+    klst::dev::launch_moments(ctx->stream, x, p.n(), nvec, p.Ny, p.Nxi, p.r, ctx->d_M, ctx->d_mom,
+                              skip);
+    klst::dev::launch_apply(ctx->stream, x, y, p.n(), nvec, p.Ny, p.Nxi, p.r, tau.real(), tau.imag(),
+                            p.beta, ctx->d_Dx, ctx->d_xix, ctx->d_xiy, ctx->d_nu, ctx->d_U,
+                            ctx->d_mom, skip);
+  }
+  HIPCHK(hipGetLastError());
+  ctx->stats.op_applies += nvec;
+  return KLST_OK;
+}
+
+klst_status pc_setup(klst_ctx* ctx, cd sigma) {
+  const klst::Problem& p = ctx->prob;
+  const int lines = std::max(1, ctx->opt.lines_per_block);
+  if (ctx->pc_ready && ctx->pc_sigma == sigma && ctx->pc_lines == lines) return KLST_OK;
+  ctx->pc_ready = false;
+  const unsigned hw = std::thread::hardware_concurrency();
+  klst::build_ilu0(p, sigma, lines, ctx->ilu, (int)std::max(1u, std::min(hw, 16u)));
+  // F column-major per line for the device sweeps
+  const int Ny = p.Ny;
+  std::vector<cd> Fc(ctx->ilu.F.size());
+  for (int l = 0; l < ctx->ilu.nlines; ++l) {
+    const cd* Fr = &ctx->ilu.F[(size_t)l * Ny * Ny];
+    cd* Fo = &Fc[(size_t)l * Ny * Ny];
+    for (int j = 0; j < Ny; ++j)
+      for (int m = 0; m < Ny; ++m) Fo[(size_t)m * Ny + j] = Fr[(size_t)j * Ny + m];
+  }
+  dfree(ctx->d_F);
+  dfree(ctx->d_C);
+  ALLOC(ctx->d_F, sizeof(double2) * Fc.size());
+  ALLOC(ctx->d_C, sizeof(double2) * std::max<size_t>(1, ctx->ilu.C.size()));
+  HIPCHK(hipMemcpyAsync(ctx->d_F, Fc.data(), sizeof(double2) * Fc.size(), hipMemcpyHostToDevice,
+                        ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_C, ctx->ilu.C.data(), sizeof(double2) * ctx->ilu.C.size(),
+                        hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->pc_ready = true;
+  ctx->pc_sigma = sigma;
+  ctx->pc_lines = lines;
+  ctx->stats.pivots_floored = ctx->ilu.floored;
+  return KLST_OK;
+}
+
+klst_status pc_apply(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_ilu_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks, ctx->d_F,
+                              ctx->d_C, skip);
+  HIPCHK(hipGetLastError());
+  ctx->stats.pc_applies += 1;
+  return KLST_OK;
+}
+
+// ---- SplitMix64 start vector (Steele, Lea & Flood 2014) ----
+uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+void start_vector(const klst::Problem& p, uint64_t seed, uint64_t stream, std::vector<cd>& out) {
+  const int64_t n = p.n();
+  out.resize(n);
+  const uint64_t key = seed * 0x100000001B3ULL + stream;
+  const double scale = 1.0 / 9007199254740992.0;   // 2^-53
+  for (int64_t i = 0; i < n; ++i) {
+    const double a = 2.0 * (double)(splitmix64(key + 2 * (uint64_t)i) >> 11) * scale - 1.0;
+    const double b = 2.0 * (double)(splitmix64(key + 2 * (uint64_t)i + 1) >> 11) * scale - 1.0;
+    const int64_t nc = 2LL * p.Nxi;
+    const int j = (int)(i / nc);
+    const int k = (int)(i % nc) % p.Nxi;
+    out[i] = p.is_bc(j, k) ? cd(0.0) : cd(a, b);
+  }
+}
+
+}  // namespace
+
+// =================================================================== ABI ===
+
+extern "C" {
+
+void klst_default_options(klst_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->device = 0;
+  o->stream = nullptr;
+  o->precision = 0;
+  o->op_mode = 0;
+  o->lines_per_block = 1;
+  o->m_max = 30;
+  o->m_min = 6;
+  o->gmres_m = 20;
+  o->max_it = 10000;
+  o->tol = 1e-10;
+  o->inner_rtol = 1e-6;
+  o->fix = 0.01;
+  o->seed = 0;
+}
+
+const char* klst_strerror(klst_status s) {
+  switch (s) {
+    case KLST_OK: return "ok";
+    case KLST_EINVAL: return "invalid argument";
+    case KLST_ENOMEM: return "out of memory";
+    case KLST_EDEVICE: return "device error";
+    case KLST_ENOCONV: return "not converged";
+    case KLST_EBUSY: return "busy";
+    case KLST_ECANCELLED: return "cancelled";
+    case KLST_ESTATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char* klst_last_error(const klst_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+klst_status klst_create(klst_ctx** out, const klst_options* opt) {
+  if (!out) return KLST_EINVAL;
+  *out = nullptr;
+  klst_options o;
+  if (opt) o = *opt; else klst_default_options(&o);
+  if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
+      !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
+      (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120)
+    return KLST_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
+    (void)hipGetLastError();
+    return KLST_EDEVICE;
+  }
+  klst_ctx* ctx = new klst_ctx();
+  ctx->opt = o;
+  if (hipSetDevice(o.device) != hipSuccess) { delete ctx; return KLST_EDEVICE; }
+  if (o.stream) {
+    ctx->stream = (hipStream_t)o.stream;
+  } else {
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete ctx;
+      return KLST_EDEVICE;
+    }
+    ctx->own_stream = true;
+  }
+  if (dalloc(ctx, (void**)&ctx->d_partial, sizeof(double2) * 512 * 256) != KLST_OK ||
+      dalloc(ctx, (void**)&ctx->d_counter, sizeof(unsigned) * 4) != KLST_OK) {
+    klst_destroy(ctx);
+    return KLST_ENOMEM;
+  }
+  if (hipMemsetAsync(ctx->d_counter, 0, sizeof(unsigned) * 4, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    klst_destroy(ctx);
+    return KLST_EDEVICE;
+  }
+  *out = ctx;
+  return KLST_OK;
+}
+
+void klst_destroy(klst_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->opt.device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  free_problem(ctx);
+  dfree(ctx->d_partial);
+  dfree(ctx->d_counter);
+  if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+klst_status klst_host_tables(const klst_grid* grid, const klst_vel* vel, const klst_base* base,
+                             double beta, double* Dx, double* nu, double* U, double* M, uint8_t* bc) {
+  klst::Problem p;
+  const std::string e = klst::build_problem(grid, vel, base, beta, p);
+  if (!e.empty()) return KLST_EINVAL;
+  if (Dx) std::memcpy(Dx, p.Dx.data(), sizeof(double) * p.Dx.size());
+  if (nu) std::memcpy(nu, p.nu.data(), sizeof(double) * p.nu.size());
+  if (U) std::memcpy(U, p.U.data(), sizeof(double) * p.U.size());
+  if (M) std::memcpy(M, p.M.data(), sizeof(double) * p.M.size());
+  if (bc) std::memcpy(bc, p.bc.data(), p.bc.size());
+  return KLST_OK;
+}
+
+klst_status klst_host_sorted_schur(int m, const double* G, double* U, double* T) {
+  if (m < 1 || !G || !U || !T) return KLST_EINVAL;
+  std::vector<cd> g(m * m), u(m * m), t(m * m);
+  for (int i = 0; i < m * m; ++i) g[i] = cd(G[2 * i], G[2 * i + 1]);
+  if (!klst::sorted_schur(m, g.data(), u.data(), t.data())) return KLST_ENOCONV;
+  for (int i = 0; i < m * m; ++i) {
+    U[2 * i] = u[i].real(); U[2 * i + 1] = u[i].imag();
+    T[2 * i] = t[i].real(); T[2 * i + 1] = t[i].imag();
+  }
+  return KLST_OK;
+}
+
+klst_status klst_assemble(klst_ctx* ctx, const klst_grid* grid, const klst_vel* vel,
+                          const klst_base* base, double beta) {
+  if (!ctx) return KLST_EINVAL;
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  klst::Problem p;
+  const std::string e = klst::build_problem(grid, vel, base, beta, p);
+  if (!e.empty()) return fail(ctx, KLST_EINVAL, e);
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  free_problem(ctx);
+  ctx->prob = std::move(p);
+  const klst::Problem& q = ctx->prob;
+  ALLOC(ctx->d_Dx, sizeof(double) * q.Dx.size());
+  ALLOC(ctx->d_xix, sizeof(double) * q.Nxi);
+  ALLOC(ctx->d_xiy, sizeof(double) * q.Nxi);
+  ALLOC(ctx->d_nu, sizeof(double) * q.Ny);
+  ALLOC(ctx->d_U, sizeof(double) * q.U.size());
+  ALLOC(ctx->d_M, sizeof(double) * q.M.size());
+  HIPCHK(hipMemcpyAsync(ctx->d_Dx, q.Dx.data(), sizeof(double) * q.Dx.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_xix, q.xi_x.data(), sizeof(double) * q.Nxi, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_xiy, q.xi_y.data(), sizeof(double) * q.Nxi, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_nu, q.nu.data(), sizeof(double) * q.Ny, hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_U, q.U.data(), sizeof(double) * q.U.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->d_M, q.M.data(), sizeof(double) * q.M.size(), hipMemcpyHostToDevice, ctx->stream));
+  klst_status s = ensure_mom(ctx, 1);
+  if (s != KLST_OK) return s;
+  if (ctx->opt.op_mode == 1) {
+    s = ensure_csr(ctx);
+    if (s != KLST_OK) return s;
+  }
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  ctx->assembled = true;
+  return KLST_OK;
+}
+
+klst_status klst_dims(const klst_ctx* ctx, int64_t* n, int64_t* nnz, int* n_bc) {
+  if (!ctx) return KLST_EINVAL;
+  if (!ctx->assembled) return KLST_ESTATE;
+  if (n) *n = ctx->prob.n();
+  if (nnz) *nnz = ctx->prob.nnz();
+  if (n_bc) *n_bc = ctx->prob.n_bc;
+  return KLST_OK;
+}
+
+klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* y) {
+  if (!ctx || !tau || !x || !y) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return op_apply(ctx, cd(tau[0], tau[1]), (const double2*)x, (double2*)y, 1, ctx->opt.op_mode, nullptr);
+}
+
+klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y) {
+  if (!ctx || !tau || !x || !y || nvec < 1 || nvec > 65535) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return op_apply(ctx, cd(tau[0], tau[1]), (const double2*)x, (double2*)y, nvec, 0, nullptr);
+}
+
+klst_status klst_apply_csr(klst_ctx* ctx, const double tau[2], const void* x, void* y) {
+  if (!ctx || !tau || !x || !y) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_csr before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return op_apply(ctx, cd(tau[0], tau[1]), (const double2*)x, (double2*)y, 1, 1, nullptr);
+}
+
+klst_status klst_precond_setup(klst_ctx* ctx, const double sigma[2]) {
+  if (!ctx || !sigma) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_precond_setup before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return pc_setup(ctx, cd(sigma[0], sigma[1]));
+}
+
+klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y) {
+  if (!ctx || !x || !y) return KLST_EINVAL;
+  if (!ctx->pc_ready) return fail(ctx, KLST_ESTATE, "klst_precond_apply before klst_precond_setup");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return pc_apply(ctx, (const double2*)x, (double2*)y, nullptr);
+}
+
+klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out) {
+  if (!ctx || !out) return KLST_EINVAL;
+  *out = ctx->stats;
+  return KLST_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ solver ===
+
+namespace {
+
+struct Workspace {
+  klst_ctx* ctx;
+  int64_t n;
+  std::vector<void*> ptrs;
+  ~Workspace() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  double2* vec(int count) {
+    void* p = nullptr;
+    if (dalloc(ctx, &p, sizeof(double2) * (size_t)count * n) != KLST_OK) return nullptr;
+    ptrs.push_back(p);
+    return (double2*)p;
+  }
+  template <class T>
+  T* small(size_t count) {
+    void* p = nullptr;
+    if (dalloc(ctx, &p, sizeof(T) * count) != KLST_OK) return nullptr;
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+};
+
+// Upper-triangular solve R X = B (m x m, row-major), in place on B (m x ncols).
+void trsm_upper(int m, const std::vector<cd>& R, std::vector<cd>& B, int ncols) {
+  for (int c = 0; c < ncols; ++c)
+    for (int i = m - 1; i >= 0; --i) {
+      cd s = B[(size_t)i * ncols + c];
+      for (int q = i + 1; q < m; ++q) s -= R[(size_t)i * m + q] * B[(size_t)q * ncols + c];
+      B[(size_t)i * ncols + c] = s / R[(size_t)i * m + i];
+    }
+}
+
+}  // namespace
+
+extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int nev, double* lambda,
+                                  void* X, int X_on_device, double* resid, int* nconv_out) {
+  using namespace klst::dev;
+  if (!ctx || !sigma_in || !lambda) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_solve before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const auto t_start = std::chrono::steady_clock::now();
+  const klst::Problem& p = ctx->prob;
+  const klst_options& o = ctx->opt;
+  const int64_t n = p.n();
+  if (nev < 1 || nev > n - p.n_bc || nev > 100 || nev + std::max(o.m_max, o.m_min + 2) > 250)
+    return fail(ctx, KLST_EINVAL, "nev out of range (1 <= nev <= min(100, n - n_bc, 250 - m_max))");
+  const int m_max = std::max(o.m_max, o.m_min + 2);
+  const int m_min = o.m_min;
+  const int gm = o.gmres_m;
+  const cd sigma(sigma_in[0], sigma_in[1]);
+  hipStream_t st = ctx->stream;
+  ctx->stats = klst_stats{};
+
+  klst_status s = pc_setup(ctx, sigma);
+  if (s != KLST_OK) return s;
+  ctx->stats.pivots_floored = ctx->ilu.floored;
+  const double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+
+  Workspace ws{ctx, n, {}};
+  double2* V = ws.vec(m_max + 1);
+  double2* W = ws.vec(m_max + 1);
+  double2* Qb = ws.vec(nev + 1);
+  double2* Zb = ws.vec(nev + 1);
+  double2* Yb = ws.vec(nev + 1);
+  double2* Gb = ws.vec(gm + 1);
+  double2* Tmp = ws.vec(m_max);
+  double2* tv = ws.vec(1);
+  double2* uv = ws.vec(1);
+  double2* zv = ws.vec(1);
+  double2* rv = ws.vec(1);
+  double2* av = ws.vec(1);
+  double2* bv = ws.vec(1);
+  const int SM = 4 * 128 + 64;
+  double2* d_c = ws.small<double2>(SM);        // coefficients of Gram-Schmidt passes
+  double2* d_c2 = ws.small<double2>(SM);
+  double2* d_cw = ws.small<double2>(SM);
+  double2* d_small = ws.small<double2>(SM);    // host-bound results
+  double2* d_coef = ws.small<double2>(128 * 128);
+  double2* d_Hinv = ws.small<double2>(128 * 128);
+  double2* d_H = ws.small<double2>((size_t)(gm + 1) * gm);
+  double* d_cs = ws.small<double>(gm);
+  double2* d_sn = ws.small<double2>(gm);
+  double2* d_g = ws.small<double2>(gm + 1);
+  double2* d_yk = ws.small<double2>(gm + 1);
+  int* d_done = ws.small<int>(4);
+  int* d_steps = ws.small<int>(4);
+  double* d_beta = ws.small<double>(2);
+  if (!V || !W || !Qb || !Zb || !Yb || !Gb || !Tmp || !tv || !uv || !zv || !rv || !av || !bv || !d_c || !d_cw ||
+      !d_c2 || !d_small || !d_coef || !d_Hinv || !d_H || !d_cs || !d_sn || !d_g || !d_yk || !d_done ||
+      !d_steps || !d_beta)
+    return KLST_ENOMEM;
+  double2* partial = ctx->d_partial;
+  unsigned* counter = ctx->d_counter;
+  std::vector<double2> hsmall(SM);
+
+  auto dot = [&](const double2* s0, int m0, const double2* s1, int m1, const double2* x, double2* out,
+                 int mode, const double2* Hinv = nullptr, double2* out2 = nullptr,
+                 const int* skip = nullptr) {
+    launch_dotm(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
+  };
+  auto sub = [&](const double2* s0, int m0, const double2* s1, int m1, const double2* c, double2* x,
+                 const int* skip = nullptr) { launch_subm(st, s0, m0, s1, m1, c, x, nullptr, n, 1.0, skip); };
+  auto fetch = [&](int count) -> klst_status {
+    HIPCHK(hipMemcpyAsync(hsmall.data(), d_small, sizeof(double2) * count, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return KLST_OK;
+  };
+  auto upload = [&](double2* dst, const std::vector<cd>& src) -> klst_status {
+    HIPCHK(hipMemcpyAsync(dst, src.data(), sizeof(double2) * src.size(), hipMemcpyHostToDevice, st));
+    return KLST_OK;
+  };
+  // CGS2 of x against (s0: m0, s1: m1); coefficients summed into c (device), norm^2 into nrm.
+  auto cgs2 = [&](const double2* s0, int m0, const double2* s1, int m1, double2* x, double2* c,
+                  double2* nrm) {
+    if (m0 + m1 > 0) {
+      dot(s0, m0, s1, m1, x, c, 0);
+      sub(s0, m0, s1, m1, c, x);
+      dot(s0, m0, s1, m1, x, d_c2, 0, nullptr, c);
+      sub(s0, m0, s1, m1, d_c2, x);
+    }
+    dot(nullptr, 0, nullptr, 0, x, nrm, 3);
+  };
+
+  // host mirrors of projected quantities
+  std::vector<cd> R, MB, SA, SB, HQY;   // R, MB: m x m; SA, SB, HQY: k x k (row-major)
+  int m = 0, k = 0;
+  std::vector<cd> h_t;
+  start_vector(p, o.seed, 0, h_t);
+  if ((s = upload(tv, h_t)) != KLST_OK) return s;
+  launch_set_int(st, d_steps, 0);
+
+  int outer = 0, inner = 0, restarts = 0;
+  const int lines_ok = 1;
+  (void)lines_ok;
+  std::vector<cd> U, T, UL, SR, G, coef;
+  cd theta = 0.0;
+  bool need_fresh = false;
+
+  auto resize_sq = [](std::vector<cd>& A, int oldm, int newm) {
+    std::vector<cd> B((size_t)newm * newm, cd(0.0));
+    for (int i = 0; i < std::min(oldm, newm); ++i)
+      for (int j = 0; j < std::min(oldm, newm); ++j) B[(size_t)i * newm + j] = A[(size_t)i * oldm + j];
+    A.swap(B);
+  };
+  // sorted Schur of G = R^{-1} MB and QR of R U
+  auto extract = [&]() -> bool {
+    G = MB;
+    trsm_upper(m, R, G, m);
+    U.assign((size_t)m * m, 0.0);
+    T.assign((size_t)m * m, 0.0);
+    if (!klst::sorted_schur(m, G.data(), U.data(), T.data())) return false;
+    std::vector<cd> RU((size_t)m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int q = i; q < m; ++q) {
+        const cd rv_ = R[(size_t)i * m + q];
+        for (int j = 0; j < m; ++j) RU[(size_t)i * m + j] += rv_ * U[(size_t)q * m + j];
+      }
+    UL.assign((size_t)m * m, 0.0);
+    SR.assign((size_t)m * m, 0.0);
+    klst::qr_square(m, RU.data(), UL.data(), SR.data());
+    return true;
+  };
+  // rotate basis B (m vectors) by columns [c0, c0+cnt) of Mx (m x m) in place
+  auto rotate = [&](double2* Bv, const std::vector<cd>& Mx, int c0, int cnt) -> klst_status {
+    coef.assign((size_t)m * cnt, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < cnt; ++j) coef[(size_t)i * cnt + j] = Mx[(size_t)i * m + c0 + j];
+    klst_status s2 = upload(d_coef, coef);
+    if (s2 != KLST_OK) return s2;
+    launch_combine(st, Bv, m, n, d_coef, cnt, cnt, Tmp, nullptr);
+    HIPCHK(hipMemcpyAsync(Bv, Tmp, sizeof(double2) * n * cnt, hipMemcpyDeviceToDevice, st));
+    return KLST_OK;
+  };
+  // new projected matrices after keeping Schur columns [c0, c0+cnt)
+  auto project = [&](int c0, int cnt) {
+    // MB' = UL^H MB U, R' = SR
+    std::vector<cd> MU((size_t)m * m, 0.0), MBn((size_t)cnt * cnt, 0.0), Rn((size_t)cnt * cnt, 0.0);
+    for (int i = 0; i < m; ++i)
+      for (int q = 0; q < m; ++q) {
+        const cd a = MB[(size_t)i * m + q];
+        for (int j = c0; j < c0 + cnt; ++j) MU[(size_t)i * m + j] += a * U[(size_t)q * m + j];
+      }
+    for (int i = c0; i < c0 + cnt; ++i)
+      for (int j = c0; j < c0 + cnt; ++j) {
+        cd acc = 0.0;
+        for (int q = 0; q < m; ++q) acc += std::conj(UL[(size_t)q * m + i]) * MU[(size_t)q * m + j];
+        MBn[(size_t)(i - c0) * cnt + (j - c0)] = acc;
+        Rn[(size_t)(i - c0) * cnt + (j - c0)] = SR[(size_t)i * m + j];
+      }
+    MB.swap(MBn);
+    R.swap(Rn);
+  };
+
+  klst_status status = KLST_OK;
+  while (k < nev) {
+    if (outer >= o.max_it) { status = KLST_ENOCONV; break; }
+    ++outer;
+    // ---- restart
+    if (m >= m_max) {
+      if (!extract()) return fail(ctx, KLST_ENOCONV, "projected Schur form did not converge");
+      if ((s = rotate(V, U, 0, m_min)) != KLST_OK) return s;
+      if ((s = rotate(W, UL, 0, m_min)) != KLST_OK) return s;
+      project(0, m_min);
+      m = m_min;
+      ++restarts;
+    }
+    // ---- expansion: v = orth(t | Q, V); w = orth((A - sigma B) v | Z, W)
+    double2* vnew = V + (size_t)m * n;
+    double2* wnew = W + (size_t)m * n;
+    cgs2(Qb, k, V, m, tv, d_c, d_small + 0);
+    launch_scale_rsqrt(st, tv, vnew, n, d_small + 0, nullptr);
+    if ((s = op_apply(ctx, sigma, vnew, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+    cgs2(Zb, k, W, m, av, d_cw, d_small + 1);
+    launch_scale_rsqrt(st, av, wnew, n, d_small + 1, nullptr);
+    // small results gathered for one transfer: [0] |v|^2, [1] |w|^2, [3] GMRES steps,
+    // [4..] M_B column W^H v_new (m + 1), [132..] V^H w_new (m), [260..] Z,W coefficients
+    dot(W, m + 1, nullptr, 0, vnew, d_small + 4, 0);
+    if (m > 0) dot(V, m, nullptr, 0, wnew, d_small + 132, 0);
+    HIPCHK(hipMemcpyAsync(d_small + 3, d_steps, sizeof(int), hipMemcpyDeviceToDevice, st));
+    if (k + m > 0)
+      HIPCHK(hipMemcpyAsync(d_small + 260, d_cw, sizeof(double2) * (k + m), hipMemcpyDeviceToDevice, st));
+    if ((s = fetch(260 + k + m)) != KLST_OK) return s;
+    {
+      const double v2 = hsmall[0].x, w2 = hsmall[1].x;
+      if (!(v2 > 0) || !std::isfinite(v2) || !(w2 > 0) || !std::isfinite(w2))
+        return fail(ctx, KLST_ENOCONV, "search space breakdown (zero or non-finite expansion vector)");
+      int st_prev;
+      std::memcpy(&st_prev, &hsmall[3], sizeof(int));
+      if (outer > 1 && !need_fresh) inner += st_prev;
+      need_fresh = false;
+      resize_sq(R, m, m + 1);
+      resize_sq(MB, m, m + 1);
+      // R column: Gram-Schmidt coefficients against W (after the k Z-coefficients)
+      for (int i = 0; i < m; ++i) R[(size_t)i * (m + 1) + m] = cd(hsmall[260 + k + i].x, hsmall[260 + k + i].y);
+      R[(size_t)m * (m + 1) + m] = std::sqrt(w2);
+      for (int i = 0; i <= m; ++i) MB[(size_t)i * (m + 1) + m] = cd(hsmall[4 + i].x, hsmall[4 + i].y);
+      for (int i = 0; i < m; ++i)
+        MB[(size_t)m * (m + 1) + i] = std::conj(cd(hsmall[132 + i].x, hsmall[132 + i].y));
+      ++m;
+    }
+    // ---- extraction, locking while pairs converge
+    double rel = 0.0;
+    bool have_pair = false;
+    while (true) {
+      if (!extract()) return fail(ctx, KLST_ENOCONV, "projected Schur form did not converge");
+      theta = sigma + 1.0 / T[0];
+      // u = V U[:,0], z = W UL[:,0]
+      coef.assign(2 * (size_t)m, 0.0);
+      for (int i = 0; i < m; ++i) { coef[i] = U[(size_t)i * m]; coef[m + i] = UL[(size_t)i * m]; }
+      if ((s = upload(d_coef, coef)) != KLST_OK) return s;
+      launch_combine(st, V, m, n, d_coef, 1, 1, uv, nullptr);
+      launch_combine(st, W, m, n, d_coef + m, 1, 1, zv, nullptr);
+      if ((s = op_apply(ctx, theta, uv, rv, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+      if (k > 0) {
+        dot(Zb, k, nullptr, 0, rv, d_c, 0);
+        sub(Zb, k, nullptr, 0, d_c, rv);
+      }
+      dot(nullptr, 0, nullptr, 0, rv, d_small, 3);
+      if ((s = fetch(1)) != KLST_OK) return s;
+      const double rn = std::sqrt(hsmall[0].x);
+      const double scale = std::abs(theta) >= 1e-6 ? std::abs(theta) : 1.0;
+      rel = rn / scale;
+      if (!std::isfinite(rel)) return fail(ctx, KLST_ENOCONV, "non-finite residual");
+      if (rel > o.tol) { have_pair = true; break; }
+      // ---- lock (u, z): Q, Z, Y = K^{-1} z, partial Schur columns, Q^H Y
+      HIPCHK(hipMemcpyAsync(Qb + (size_t)k * n, uv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(Zb + (size_t)k * n, zv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+      if ((s = pc_apply(ctx, zv, Yb + (size_t)k * n, nullptr)) != KLST_OK) return s;
+      if ((s = op_apply(ctx, 0.0, uv, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+      launch_mask_bc(st, uv, bv, n, p.Ny, p.Nxi, ctx->d_xix);
+      dot(Zb, k + 1, nullptr, 0, av, d_small + 0, 0);            // S_A column
+      dot(Zb, k + 1, nullptr, 0, bv, d_small + 128, 0);          // S_B column
+      dot(Qb, k + 1, nullptr, 0, Yb + (size_t)k * n, d_small + 256, 0);   // Q^H y_new
+      dot(Yb, k, nullptr, 0, Qb + (size_t)k * n, d_small + 384, 0);       // Y^H q_new
+      if ((s = fetch(384 + k)) != KLST_OK) return s;
+      resize_sq(SA, k, k + 1);
+      resize_sq(SB, k, k + 1);
+      resize_sq(HQY, k, k + 1);
+      for (int i = 0; i <= k; ++i) {
+        SA[(size_t)i * (k + 1) + k] = cd(hsmall[i].x, hsmall[i].y);
+        SB[(size_t)i * (k + 1) + k] = cd(hsmall[128 + i].x, hsmall[128 + i].y);
+        HQY[(size_t)i * (k + 1) + k] = cd(hsmall[256 + i].x, hsmall[256 + i].y);
+      }
+      for (int i = 0; i < k; ++i) HQY[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[384 + i].x, hsmall[384 + i].y));
+      ++k;
+      // deflate the search and test spaces
+      if (m > 1) {
+        if ((s = rotate(V, U, 1, m - 1)) != KLST_OK) return s;
+        if ((s = rotate(W, UL, 1, m - 1)) != KLST_OK) return s;
+      }
+      project(1, m - 1);
+      --m;
+      if (k >= nev) break;
+      if (m == 0) break;
+    }
+    if (k >= nev) break;
+    if (!have_pair) {
+      // search space emptied by deflation: start again from a fresh vector
+      start_vector(p, o.seed, (uint64_t)outer, h_t);
+      if ((s = upload(tv, h_t)) != KLST_OK) return s;
+      need_fresh = true;
+      launch_set_int(st, d_steps, 0);
+      continue;
+    }
+    // ---- correction equation
+    // Qt = [Q, u], Zt = [Z, z], Yt = [Y, K^{-1} z], Ht = Qt^H Yt
+    double2* ynew = Yb + (size_t)k * n;
+    if ((s = pc_apply(ctx, zv, ynew, nullptr)) != KLST_OK) return s;
+    dot(Qb, k, uv, 1, ynew, d_small + 0, 0);                  // Qt^H y_new  (k + 1)
+    if (k > 0) dot(Yb, k, nullptr, 0, uv, d_small + 128, 0);  // Y^H u (k)
+    if ((s = fetch(128 + k)) != KLST_OK) return s;
+    {
+      const int kt = k + 1;
+      std::vector<cd> Ht((size_t)kt * kt), Hi((size_t)kt * kt);
+      for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) Ht[(size_t)i * kt + j] = HQY[(size_t)i * k + j];
+      for (int i = 0; i < kt; ++i) Ht[(size_t)i * kt + k] = cd(hsmall[i].x, hsmall[i].y);
+      for (int j = 0; j < k; ++j) Ht[(size_t)k * kt + j] = std::conj(cd(hsmall[128 + j].x, hsmall[128 + j].y));
+      if (!klst::invert(kt, Ht.data(), Hi.data()))
+        return fail(ctx, KLST_ENOCONV, "singular projected preconditioner (Q^H K^-1 Z)");
+      if ((s = upload(d_Hinv, Hi)) != KLST_OK) return s;
+    }
+    const cd shift = (rel <= o.fix) ? theta : sigma;
+    // rhs = -(I - Yt Ht^{-1} Qt^H) K^{-1} r
+    if ((s = pc_apply(ctx, rv, av, nullptr)) != KLST_OK) return s;
+    dot(Qb, k, uv, 1, av, d_c, 2, d_Hinv);
+    sub(Yb, k + 1, nullptr, 0, d_c, av);
+    launch_axpby(st, av, av, n, -1.0, 0.0, 0);
+    dot(nullptr, 0, nullptr, 0, av, d_small, 3);
+    launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta);
+    launch_scale_rsqrt(st, av, Gb, n, d_small, d_done);
+    for (int j = 0; j < gm; ++j) {
+      double2* gj = Gb + (size_t)j * n;
+      double2* gj1 = Gb + (size_t)(j + 1) * n;
+      if ((s = op_apply(ctx, shift, gj, bv, 1, o.op_mode, d_done)) != KLST_OK) return s;
+      if ((s = pc_apply(ctx, bv, gj1, d_done)) != KLST_OK) return s;
+      dot(Qb, k, uv, 1, gj1, d_c, 2, d_Hinv, nullptr, d_done);
+      launch_subm(st, Yb, k + 1, nullptr, 0, d_c, gj1, nullptr, n, 1.0, d_done);
+      double2* hcol = d_H + (size_t)j * (gm + 1);
+      dot(Gb, j + 1, nullptr, 0, gj1, hcol, 0, nullptr, nullptr, d_done);
+      launch_subm(st, Gb, j + 1, nullptr, 0, hcol, gj1, nullptr, n, 1.0, d_done);
+      dot(Gb, j + 1, nullptr, 0, gj1, d_c2, 0, nullptr, hcol, d_done);
+      launch_subm(st, Gb, j + 1, nullptr, 0, d_c2, gj1, nullptr, n, 1.0, d_done);
+      dot(nullptr, 0, nullptr, 0, gj1, d_small + 2, 3, nullptr, nullptr, d_done);
+      launch_gmres_givens(st, d_H, gm + 1, j, d_small + 2, d_cs, d_sn, d_g, d_done, d_steps, d_beta,
+                          o.inner_rtol);
+      launch_scale_rsqrt(st, gj1, nullptr, n, d_small + 2, d_done);
+    }
+    launch_gmres_solve(st, d_H, gm + 1, d_g, d_steps, d_yk);
+    launch_combine(st, Gb, gm, n, d_yk, 1, 1, tv, d_steps);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  {
+    int st_prev = 0;
+    HIPCHK(hipMemcpy(&st_prev, d_steps, sizeof(int), hipMemcpyDeviceToHost));
+    if (status == KLST_ENOCONV && !need_fresh) inner += st_prev;
+  }
+
+  // ---- eigenpairs of the triangular pencil (S_A, S_B), x_i = Q s_i
+  const int nconv = k;
+  std::vector<cd> lam(nconv), Sv((size_t)nconv * nconv, 0.0);
+  for (int i = 0; i < nconv; ++i) {
+    lam[i] = SA[(size_t)i * k + i] / SB[(size_t)i * k + i];
+    Sv[(size_t)i * nconv + i] = 1.0;
+    for (int q = i - 1; q >= 0; --q) {
+      cd acc = 0.0;
+      for (int t = q + 1; t <= i; ++t)
+        acc += (SA[(size_t)q * k + t] - lam[i] * SB[(size_t)q * k + t]) * Sv[(size_t)t * nconv + i];
+      const cd d = SA[(size_t)q * k + q] - lam[i] * SB[(size_t)q * k + q];
+      Sv[(size_t)q * nconv + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
+    }
+  }
+  std::vector<double> res(nconv, 0.0);
+  if (nconv > 0) {
+    double2* Xd = ws.vec(nconv);
+    if (!Xd) return KLST_ENOMEM;
+    if ((s = upload(d_coef, Sv)) != KLST_OK) return s;
+    launch_combine(st, Qb, nconv, n, d_coef, nconv, nconv, Xd, nullptr);
+    std::vector<cd> hx((size_t)nconv * n);
+    HIPCHK(hipMemcpyAsync(hx.data(), Xd, sizeof(double2) * hx.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < nconv; ++i) {
+      cd* xi = &hx[(size_t)i * n];
+      double nrm = 0.0, big = -1.0;
+      int64_t ib = 0;
+      for (int64_t t = 0; t < n; ++t) {
+        const double a = std::norm(xi[t]);
+        nrm += a;
+        if (a > big * (1.0 + 1e-12)) { big = a; ib = t; }
+      }
+      const cd ph = std::conj(xi[ib]) / std::abs(xi[ib]) / std::sqrt(nrm);
+      for (int64_t t = 0; t < n; ++t) xi[t] *= ph;
+    }
+    HIPCHK(hipMemcpyAsync(Xd, hx.data(), sizeof(double2) * hx.size(), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < nconv; ++i) {
+      if ((s = op_apply(ctx, lam[i], Xd + (size_t)i * n, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+      dot(nullptr, 0, nullptr, 0, av, d_small + i, 3);
+    }
+    if ((s = fetch(nconv)) != KLST_OK) return s;
+    for (int i = 0; i < nconv; ++i) {
+      const double sc = std::abs(lam[i]) >= 1e-6 ? std::abs(lam[i]) : 1.0;
+      res[i] = std::sqrt(hsmall[i].x) / sc;
+    }
+    if (X) {
+      if (X_on_device) {
+        HIPCHK(hipMemcpyAsync(X, Xd, sizeof(double2) * (size_t)nconv * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+      } else {
+        std::memcpy(X, hx.data(), sizeof(double2) * hx.size());
+      }
+    }
+  }
+  for (int i = 0; i < nconv; ++i) {
+    lambda[2 * i] = lam[i].real();
+    lambda[2 * i + 1] = lam[i].imag();
+    if (resid) resid[i] = res[i];
+  }
+  if (nconv_out) *nconv_out = nconv;
+  ctx->stats.outer_iterations = outer;
+  ctx->stats.inner_iterations = inner;
+  ctx->stats.restarts = restarts;
+  ctx->stats.nconv = nconv;
+  ctx->stats.seconds_setup = t_setup;
+  ctx->stats.seconds_total =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  return status;
+}

@@ -1,0 +1,534 @@
+// Host-side problem tables, block-Jacobi ILU(0) set-up and small dense
+// complex linear algebra.  See host.hpp.
+#include "host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+namespace klst {
+
+namespace {
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// Grid: Chebyshev-Gauss-Lobatto nodes y_i = cos(i pi / N) (eq. ChebPoints), the
+// derivative matrix of eqs. ChebOffDiag / ChebDiag / ChebBC, and the algebraic map
+// x = L y / sqrt(1 + s - y^2), dy/dx = sqrt(1+s) L^2 / (L^2 + x^2)^{3/2}
+// (eq. Chebmapping), giving D_x = diag(dy/dx) D_y.
+//
+// Operator coefficients: linearisation of the discrete BGK relaxation
+// nu(m) (f^e(m) - f) about the base state (eq. CompBGKtilde), in units where
+// 2RT -> T and P = rho T / 2, with macros a = (rho, u, v, E) and
+// T = (4/3)(E - (u^2 + v^2)/2):
+//   g^e = rho / (pi T)^{Dv/2} exp(-|xi - u e_x|^2 / T),  h^e = ((3 - Dv)/2) T g^e,
+//   G_a = nu (dg^e/da + (g^e - g_c) dln(nu)/da),  H_a likewise with h,
+// and the perturbation moments of the discrete rows (eq. comp_ghat1Dshock):
+//   m_rho = sum W g, m_u = sum W (xi_x - u) g / rho, m_v = sum W xi_y g / rho,
+//   m_E = sum W ((|xi|^2 - 2E) g + h) / (2 rho).
+std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
+                          double beta, Problem& p) {
+  if (!g || !v || !b) return "null grid, velocity table or base flow";
+  if (g->Ny < 3) return "Ny must be >= 3";
+  if (v->Nxi < 1) return "Nxi must be >= 1";
+  if (v->Dv != 1 && v->Dv != 2) return "Dv must be 1 or 2";
+  if (!v->xi_x || !v->xi_y || !v->w) return "velocity table pointers must be non-null";
+  if (!(g->L > 0) || !(g->s_inf > 0) || !std::isfinite(g->L) || !std::isfinite(g->s_inf))
+    return "L and s_inf must be finite and > 0";
+  if (!std::isfinite(beta) || !std::isfinite(b->s_visc) || !std::isfinite(b->nu_inf) ||
+      b->nu_inf < 0)
+    return "beta, s_visc, nu_inf must be finite (nu_inf >= 0)";
+  const int Ny = g->Ny, Nxi = v->Nxi, Dv = v->Dv;
+  const int r = (Dv == 2) ? 4 : 3;
+  if (!finite_all(v->xi_x, Nxi) || !finite_all(v->xi_y, Nxi) || !finite_all(v->w, Nxi))
+    return "non-finite velocity table";
+  for (int k = 0; k < Nxi; ++k) {
+    if (!(v->w[k] > 0)) return "velocity weights must be > 0";
+    if (Dv == 1 && v->xi_y[k] != 0.0) return "Dv = 1 requires xi_y == 0";
+  }
+  p = Problem();
+  p.Ny = Ny; p.Nxi = Nxi; p.r = r; p.Dv = Dv;
+  p.beta = beta; p.L = g->L; p.s_inf = g->s_inf; p.s_visc = b->s_visc; p.nu_inf = b->nu_inf;
+  p.xi_x.assign(v->xi_x, v->xi_x + Nxi);
+  p.xi_y.assign(v->xi_y, v->xi_y + Nxi);
+  p.w.assign(v->w, v->w + Nxi);
+
+  // --- grid and mapped derivative
+  const int N = Ny - 1;
+  const double pi = 3.14159265358979323846;
+  std::vector<double> y(Ny), x(Ny), dydx(Ny);
+  const double s = (g->L / g->s_inf) * (g->L / g->s_inf);
+  for (int i = 0; i < Ny; ++i) {
+    y[i] = std::cos(pi * i / N);
+    x[i] = g->L * y[i] / std::sqrt(1.0 + s - y[i] * y[i]);
+    const double q = g->L * g->L + x[i] * x[i];
+    dydx[i] = std::sqrt(1.0 + s) * g->L * g->L / (q * std::sqrt(q));
+  }
+  p.Dx.assign((size_t)Ny * Ny, 0.0);
+  for (int j = 0; j < Ny; ++j) {
+    const double cj = (j == 0 || j == N) ? 2.0 : 1.0;
+    for (int m = 0; m < Ny; ++m) {
+      double d;
+      if (j != m) {
+        const double cm = (m == 0 || m == N) ? 2.0 : 1.0;
+        const double sgn = ((j + m) % 2 == 0) ? 1.0 : -1.0;
+        d = cj / cm * sgn / (y[j] - y[m]);
+      } else if (j == 0) {
+        d = (2.0 * N * N + 1.0) / 6.0;
+      } else if (j == N) {
+        d = -(2.0 * N * N + 1.0) / 6.0;
+      } else {
+        d = -y[j] / (2.0 * (1.0 - y[j] * y[j]));
+      }
+      p.Dx[(size_t)j * Ny + m] = dydx[j] * d;
+    }
+  }
+
+  // --- base macros and VDFs
+  p.rho.resize(Ny); p.u.resize(Ny); p.E.resize(Ny); p.T.resize(Ny); p.nu.resize(Ny);
+  std::vector<double> ge((size_t)Ny * Nxi), he((size_t)Ny * Nxi), gc((size_t)Ny * Nxi),
+      hc((size_t)Ny * Nxi);
+  const double hfac = 0.5 * (3 - Dv);
+  auto maxwell = [&](int j) {
+    const double T = p.T[j], rho = p.rho[j], u = p.u[j];
+    const double pre = rho / std::pow(pi * T, 0.5 * Dv);
+    for (int k = 0; k < Nxi; ++k) {
+      const double cx = p.xi_x[k] - u, cy = p.xi_y[k];
+      const double gv = pre * std::exp(-(cx * cx + cy * cy) / T);
+      ge[(size_t)j * Nxi + k] = gv;
+      he[(size_t)j * Nxi + k] = hfac * T * gv;
+    }
+  };
+  if (b->mode == 0) {
+    if (!b->rho || !b->u || !b->T) return "EQ base flow needs rho, u, T";
+    if (!finite_all(b->rho, Ny) || !finite_all(b->u, Ny) || !finite_all(b->T, Ny))
+      return "non-finite base macros";
+    for (int j = 0; j < Ny; ++j) {
+      p.rho[j] = b->rho[j]; p.u[j] = b->u[j]; p.T[j] = b->T[j];
+      if (!(p.rho[j] > 0) || !(p.T[j] > 0)) return "base rho and T must be > 0";
+      p.E[j] = 0.5 * p.u[j] * p.u[j] + 0.75 * p.T[j];
+      maxwell(j);
+    }
+    gc = ge; hc = he;
+  } else if (b->mode == 1) {
+    if (!b->g_c || !b->h_c) return "NONEQ base flow needs g_c, h_c";
+    if (!finite_all(b->g_c, (size_t)Ny * Nxi) || !finite_all(b->h_c, (size_t)Ny * Nxi))
+      return "non-finite base VDF";
+    gc.assign(b->g_c, b->g_c + (size_t)Ny * Nxi);
+    hc.assign(b->h_c, b->h_c + (size_t)Ny * Nxi);
+    for (int j = 0; j < Ny; ++j) {
+      double m0 = 0, m1 = 0, m2 = 0;
+      for (int k = 0; k < Nxi; ++k) {
+        const double gv = gc[(size_t)j * Nxi + k], hv = hc[(size_t)j * Nxi + k];
+        const double xx = p.xi_x[k], yy = p.xi_y[k];
+        m0 += p.w[k] * gv;
+        m1 += p.w[k] * xx * gv;
+        m2 += p.w[k] * ((xx * xx + yy * yy) * gv + hv);
+      }
+      if (!(m0 > 0)) return "base density must be > 0";
+      p.rho[j] = m0;
+      p.u[j] = m1 / m0;
+      p.E[j] = 0.5 * m2 / m0;
+      p.T[j] = (4.0 / 3.0) * (p.E[j] - 0.5 * p.u[j] * p.u[j]);
+      if (!(p.T[j] > 0)) return "base temperature must be > 0";
+      maxwell(j);
+    }
+  } else {
+    return "base mode must be 0 (EQ) or 1 (NONEQ)";
+  }
+  for (int j = 0; j < Ny; ++j) p.nu[j] = b->nu_inf * p.rho[j] * std::pow(p.T[j], 1.0 - b->s_visc);
+
+  // --- coefficients U[j][f][a][k] and functionals M[j][a][f][k]
+  p.U.assign((size_t)Ny * 2 * r * Nxi, 0.0);
+  p.M.assign((size_t)Ny * r * 2 * Nxi, 0.0);
+  const double sv = b->s_visc;
+  for (int j = 0; j < Ny; ++j) {
+    const double rho = p.rho[j], u = p.u[j], T = p.T[j], E = p.E[j], nu = p.nu[j];
+    // d T / d a for a = rho, u, v, E at v = 0
+    const double dT[4] = {0.0, -4.0 * u / 3.0, 0.0, 4.0 / 3.0};
+    // d ln(nu) / d a = d ln P / d a - d ln mu / d a, nu = P / mu, P = rho T / 2, mu ~ T^s
+    const double dlnu[4] = {1.0 / rho, (1.0 - sv) * dT[1] / T, 0.0, (1.0 - sv) * dT[3] / T};
+    const int amap3[3] = {0, 1, 3};   // Dv = 1: (rho, u, E)
+    for (int k = 0; k < Nxi; ++k) {
+      const size_t jk = (size_t)j * Nxi + k;
+      const double gev = ge[jk], hev = he[jk];
+      const double cx = p.xi_x[k] - u, cy = p.xi_y[k];
+      const double c2 = cx * cx + cy * cy;
+      const double dlng_dT = c2 / (T * T) - 0.5 * Dv / T;
+      double dg[4];
+      dg[0] = gev / rho;
+      dg[1] = gev * (2.0 * cx / T + dlng_dT * dT[1]);
+      dg[2] = gev * (2.0 * cy / T);
+      dg[3] = gev * dlng_dT * dT[3];
+      for (int ia = 0; ia < r; ++ia) {
+        const int a = (r == 4) ? ia : amap3[ia];
+        const double dh = hfac * (T * dg[a] + gev * dT[a]);
+        p.U[(((size_t)j * 2 + 0) * r + ia) * Nxi + k] = nu * (dg[a] + (gev - gc[jk]) * dlnu[a]);
+        p.U[(((size_t)j * 2 + 1) * r + ia) * Nxi + k] = nu * (dh + (hev - hc[jk]) * dlnu[a]);
+        double mg = 0, mh = 0;
+        switch (a) {
+          case 0: mg = p.w[k]; break;
+          case 1: mg = p.w[k] * cx / rho; break;
+          case 2: mg = p.w[k] * p.xi_y[k] / rho; break;
+          default:
+            mg = p.w[k] * (p.xi_x[k] * p.xi_x[k] + p.xi_y[k] * p.xi_y[k] - 2.0 * E) / (2.0 * rho);
+            mh = p.w[k] / (2.0 * rho);
+        }
+        p.M[(((size_t)j * r + ia) * 2 + 0) * Nxi + k] = mg;
+        p.M[(((size_t)j * r + ia) * 2 + 1) * Nxi + k] = mh;
+      }
+    }
+  }
+  // --- inflow rows: x = -s_inf (j = N) with xi_x > 0, x = +s_inf (j = 0) with xi_x < 0
+  p.bc.assign((size_t)Ny * 2 * Nxi, 0);
+  p.n_bc = 0;
+  for (int f = 0; f < 2; ++f)
+    for (int k = 0; k < Nxi; ++k) {
+      if (p.xi_x[k] > 0) { p.bc[((size_t)N * 2 + f) * Nxi + k] = 1; ++p.n_bc; }
+      if (p.xi_x[k] < 0) { p.bc[((size_t)0 * 2 + f) * Nxi + k] = 1; ++p.n_bc; }
+    }
+  return std::string();
+}
+
+// ILU(0) of one block of whole velocity lines, rows ordered (line, node).  The
+// pattern of a non-inflow row (l, j) is {(l, m): all m} (streaming along the
+// line, D_x is dense) and {(l2, j): all block lines l2} (moment coupling at node
+// j); an inflow row holds its diagonal only.  Eliminating in column order, the
+// coupling columns (l2 < l, j) come first and only update the coupling entries
+// and the diagonal of row (l, j); the line columns (l, m < j) then update the
+// line part, and the fill they would create in (l2, m) is dropped.
+static void ilu0_block(const Problem& p, cd sigma, int b, int nl_blk, int nl, ILU0& f,
+                       std::vector<double>& rownorm, int& floored) {
+  const int Ny = p.Ny, Nxi = p.Nxi, r = p.r;
+  const int l0 = b * nl;
+  auto line_fk = [&](int lg, int& fo, int& ko) { fo = lg / Nxi; ko = lg % Nxi; };
+  auto coupling = [&](int j, int fa, int ka, int fb, int kb) {
+    double s = 0;
+    for (int a = 0; a < r; ++a)
+      s += p.U[(((size_t)j * 2 + fa) * r + a) * Nxi + ka] * p.M[(((size_t)j * r + a) * 2 + fb) * Nxi + kb];
+    return s;
+  };
+  for (int l = 0; l < nl_blk; ++l) {
+    int fl, kl;
+    line_fk(l0 + l, fl, kl);
+    cd* F = &f.F[(size_t)(l0 + l) * Ny * Ny];
+    cd* Cl = &f.C[(((size_t)b * nl + l) * nl) * Ny];   // Cl[l2 * Ny + j]
+    // initial values
+    for (int j = 0; j < Ny; ++j) {
+      const bool bcr = p.is_bc(j, kl);
+      for (int m = 0; m < Ny; ++m) F[(size_t)j * Ny + m] = 0.0;
+      for (int l2 = 0; l2 < nl; ++l2) Cl[(size_t)l2 * Ny + j] = 0.0;
+      if (bcr) { F[(size_t)j * Ny + j] = 1.0; rownorm[j] = 1.0; continue; }
+      const double xi = p.xi_x[kl];
+      double nrm = 0;
+      for (int m = 0; m < Ny; ++m) F[(size_t)j * Ny + m] = xi * p.Dx[(size_t)j * Ny + m];
+      F[(size_t)j * Ny + j] += cd(p.nu[j], p.beta * p.xi_y[kl]) - sigma - coupling(j, fl, kl, fl, kl);
+      for (int m = 0; m < Ny; ++m) nrm += std::abs(F[(size_t)j * Ny + m]);
+      for (int l2 = 0; l2 < nl_blk; ++l2) {
+        if (l2 == l) continue;
+        int f2, k2;
+        line_fk(l0 + l2, f2, k2);
+        Cl[(size_t)l2 * Ny + j] = -coupling(j, fl, kl, f2, k2);
+        nrm += std::abs(Cl[(size_t)l2 * Ny + j]);
+      }
+      // the row also couples to block-external lines; count them in the norm
+      for (int lg = 0; lg < 2 * Nxi; ++lg) {
+        if (lg >= l0 && lg < l0 + nl_blk) continue;
+        int f2, k2;
+        line_fk(lg, f2, k2);
+        nrm += std::abs(coupling(j, fl, kl, f2, k2));
+      }
+      rownorm[j] = nrm;
+    }
+    for (int j = 0; j < Ny; ++j) {
+      if (p.is_bc(j, kl)) continue;
+      cd* Fj = F + (size_t)j * Ny;
+      // coupling columns (l2, j), l2 < l
+      for (int l2 = 0; l2 < l; ++l2) {
+        int f2, k2;
+        line_fk(l0 + l2, f2, k2);
+        const bool bc2 = p.is_bc(j, k2);
+        const cd piv = bc2 ? cd(1.0) : f.F[((size_t)(l0 + l2) * Ny + j) * Ny + j];
+        const cd lc = Cl[(size_t)l2 * Ny + j] / piv;
+        Cl[(size_t)l2 * Ny + j] = lc;
+        if (bc2) continue;   // an inflow row has no entries right of its diagonal
+        const cd* C2 = &f.C[(((size_t)b * nl + l2) * nl) * Ny];
+        for (int l3 = l2 + 1; l3 < nl_blk; ++l3) {
+          if (l3 == l) Fj[j] -= lc * C2[(size_t)l3 * Ny + j];
+          else Cl[(size_t)l3 * Ny + j] -= lc * C2[(size_t)l3 * Ny + j];
+        }
+      }
+      // line columns (l, m), m < j
+      for (int m = 0; m < j; ++m) {
+        if (p.is_bc(m, kl)) continue;   // row m is e_m: L entry stays, no update
+        const cd lm = Fj[m] / F[(size_t)m * Ny + m];
+        Fj[m] = lm;
+        const cd* Fm = F + (size_t)m * Ny;
+        for (int q = m + 1; q < Ny; ++q) Fj[q] -= lm * Fm[q];
+      }
+      // pivot floor (reading R9)
+      const double fl_abs = 1e-12 * rownorm[j];
+      const double a = std::abs(Fj[j]);
+      if (a < fl_abs) {
+        Fj[j] = (a > 0) ? Fj[j] * (fl_abs / a) : cd(fl_abs);
+        ++floored;
+      }
+    }
+  }
+}
+
+void build_ilu0(const Problem& p, cd sigma, int lines_per_block, ILU0& f, int nthreads) {
+  const int nlines = 2 * p.Nxi;
+  const int nl = std::max(1, std::min(lines_per_block, nlines));
+  f.nl = nl;
+  f.Ny = p.Ny;
+  f.nlines = nlines;
+  f.nblocks = (nlines + nl - 1) / nl;
+  f.F.assign((size_t)nlines * p.Ny * p.Ny, cd(0.0));
+  f.C.assign((size_t)f.nblocks * nl * nl * p.Ny, cd(0.0));
+  nthreads = std::max(1, std::min(nthreads, f.nblocks));
+  std::vector<int> floored(nthreads, 0);
+  auto work = [&](int t) {
+    std::vector<double> rownorm(p.Ny);
+    for (int b = t; b < f.nblocks; b += nthreads) {
+      const int nb = std::min(nl, nlines - b * nl);
+      ilu0_block(p, sigma, b, nb, nl, f, rownorm, floored[t]);
+    }
+  };
+  if (nthreads == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  f.floored = 0;
+  for (int v : floored) f.floored += v;
+}
+
+// ---------------------------------------------------------------- dense ----
+
+namespace {
+
+// Givens rotation (c real, s complex) with [c s; -conj(s) c] [f; g] = [r; 0].
+void givens(cd f, cd g, double& c, cd& s) {
+  const double af = std::abs(f), ag = std::abs(g);
+  if (ag == 0.0) { c = 1.0; s = 0.0; return; }
+  if (af == 0.0) { c = 0.0; s = std::conj(g) / ag; return; }
+  const double nrm = std::hypot(af, ag);
+  c = af / nrm;
+  s = (f / af) * std::conj(g) / nrm;
+}
+
+}  // namespace
+
+void qr_square(int m, const cd* A, cd* Qm, cd* Rm) {
+  std::vector<cd> R(A, A + (size_t)m * m), Q((size_t)m * m, cd(0.0));
+  for (int i = 0; i < m; ++i) Q[(size_t)i * m + i] = 1.0;
+  std::vector<cd> v(m);
+  for (int k = 0; k < m - 1; ++k) {
+    double nrm = 0;
+    for (int i = k; i < m; ++i) nrm += std::norm(R[(size_t)i * m + k]);
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const cd x0 = R[(size_t)k * m + k];
+    const cd ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cd(1.0);
+    const cd alpha = -ph * nrm;
+    for (int i = k; i < m; ++i) v[i] = R[(size_t)i * m + k];
+    v[k] -= alpha;
+    double vn = 0;
+    for (int i = k; i < m; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    // R <- (I - 2 v v^H / v^H v) R ; Q <- Q (I - 2 v v^H / v^H v)
+    for (int jc = 0; jc < m; ++jc) {
+      cd s = 0;
+      for (int i = k; i < m; ++i) s += std::conj(v[i]) * R[(size_t)i * m + jc];
+      s *= 2.0 / vn;
+      for (int i = k; i < m; ++i) R[(size_t)i * m + jc] -= s * v[i];
+    }
+    for (int ir = 0; ir < m; ++ir) {
+      cd s = 0;
+      for (int i = k; i < m; ++i) s += Q[(size_t)ir * m + i] * v[i];
+      s *= 2.0 / vn;
+      for (int i = k; i < m; ++i) Q[(size_t)ir * m + i] -= s * std::conj(v[i]);
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) R[(size_t)i * m + j] = 0.0;
+  std::copy(Q.begin(), Q.end(), Qm);
+  std::copy(R.begin(), R.end(), Rm);
+}
+
+// Complex Schur form by Householder reduction to Hessenberg form followed by
+// single-shift QR iterations with Wilkinson shifts and Givens rotations
+// (Golub & Van Loan, Matrix Computations, Sec. 7.4-7.5), then a selection sort
+// of the diagonal by adjacent swaps of 1x1 blocks (the exchange of Bai & Demmel
+// used by LAPACK's ZTREXC).
+bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
+  std::vector<cd> H(G, G + (size_t)m * m), U((size_t)m * m, cd(0.0));
+  for (int i = 0; i < m; ++i) U[(size_t)i * m + i] = 1.0;
+  auto h = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
+  auto u = [&](int i, int j) -> cd& { return U[(size_t)i * m + j]; };
+  // Hessenberg reduction
+  std::vector<cd> v(m);
+  for (int k = 0; k < m - 2; ++k) {
+    double nrm = 0;
+    for (int i = k + 1; i < m; ++i) nrm += std::norm(h(i, k));
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const cd x0 = h(k + 1, k);
+    const cd ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cd(1.0);
+    const cd alpha = -ph * nrm;
+    for (int i = k + 1; i < m; ++i) v[i] = h(i, k);
+    v[k + 1] -= alpha;
+    double vn = 0;
+    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    for (int jc = 0; jc < m; ++jc) {          // H <- P H
+      cd s = 0;
+      for (int i = k + 1; i < m; ++i) s += std::conj(v[i]) * h(i, jc);
+      s *= 2.0 / vn;
+      for (int i = k + 1; i < m; ++i) h(i, jc) -= s * v[i];
+    }
+    for (int ir = 0; ir < m; ++ir) {          // H <- H P, U <- U P
+      cd s = 0, t = 0;
+      for (int i = k + 1; i < m; ++i) { s += h(ir, i) * v[i]; t += u(ir, i) * v[i]; }
+      s *= 2.0 / vn; t *= 2.0 / vn;
+      for (int i = k + 1; i < m; ++i) { h(ir, i) -= s * std::conj(v[i]); u(ir, i) -= t * std::conj(v[i]); }
+    }
+    for (int i = k + 2; i < m; ++i) h(i, k) = 0.0;
+  }
+  // QR iterations on the active window [lo, hi]
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1;
+  int iter = 0, since = 0;
+  while (hi > 0) {
+    if (++iter > 100 * m + 1000) return false;
+    int lo = hi;
+    while (lo > 0) {
+      const double sub = std::abs(h(lo, lo - 1));
+      double scale = std::abs(h(lo, lo)) + std::abs(h(lo - 1, lo - 1));
+      if (scale == 0.0) scale = 1.0;
+      if (sub <= eps * scale) { h(lo, lo - 1) = 0.0; break; }
+      --lo;
+    }
+    if (lo == hi) { --hi; since = 0; continue; }
+    ++since;
+    // Wilkinson shift from the trailing 2x2 block; exceptional shift now and then
+    cd mu;
+    const cd a = h(hi - 1, hi - 1), bb = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+    if (since % 11 == 10) {
+      mu = d + cd(0.75 * std::abs(c), 0.0);
+    } else {
+      const cd tr = 0.5 * (a - d);
+      const cd disc = std::sqrt(tr * tr + bb * c);
+      const cd e1 = d - (bb * c) / (tr + disc), e2 = d - (bb * c) / (tr - disc);
+      const bool ok1 = std::abs(tr + disc) > 0, ok2 = std::abs(tr - disc) > 0;
+      if (ok1 && ok2) mu = (std::abs(e1 - d) < std::abs(e2 - d)) ? e1 : e2;
+      else if (ok1) mu = e1;
+      else if (ok2) mu = e2;
+      else mu = d;
+    }
+    // implicit single-shift step via the explicit first rotation and chasing
+    for (int k = lo; k < hi; ++k) {
+      cd f0, g0;
+      if (k == lo) { f0 = h(lo, lo) - mu; g0 = h(lo + 1, lo); }
+      else { f0 = h(k, k - 1); g0 = h(k + 1, k - 1); }
+      double cs; cd sn;
+      givens(f0, g0, cs, sn);
+      // rows k, k+1 from column (k == lo ? lo : k-1)
+      for (int jc = (k == lo ? lo : k - 1); jc < m; ++jc) {
+        const cd x = h(k, jc), y = h(k + 1, jc);
+        h(k, jc) = cs * x + sn * y;
+        h(k + 1, jc) = -std::conj(sn) * x + cs * y;
+      }
+      if (k > lo) h(k + 1, k - 1) = 0.0;
+      // columns k, k+1 of H rows 0..min(k+2, hi), and of U
+      const int rmax = std::min(k + 2, hi);
+      for (int ir = 0; ir <= rmax; ++ir) {
+        const cd x = h(ir, k), y = h(ir, k + 1);
+        h(ir, k) = cs * x + std::conj(sn) * y;
+        h(ir, k + 1) = -sn * x + cs * y;
+      }
+      for (int ir = 0; ir < m; ++ir) {
+        const cd x = u(ir, k), y = u(ir, k + 1);
+        u(ir, k) = cs * x + std::conj(sn) * y;
+        u(ir, k + 1) = -sn * x + cs * y;
+      }
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) h(i, j) = 0.0;
+  // swap the 1x1 blocks at positions k, k+1 of the triangular T
+  auto swap_adj = [&](int k) {
+    const cd t11 = h(k, k), t22 = h(k + 1, k + 1);
+    double cs; cd sn;
+    givens(h(k, k + 1), t22 - t11, cs, sn);
+    for (int jc = k + 2; jc < m; ++jc) {       // rows k, k+1
+      const cd x = h(k, jc), y = h(k + 1, jc);
+      h(k, jc) = cs * x + sn * y;
+      h(k + 1, jc) = -std::conj(sn) * x + cs * y;
+    }
+    for (int ir = 0; ir < k; ++ir) {           // columns k, k+1
+      const cd x = h(ir, k), y = h(ir, k + 1);
+      h(ir, k) = cs * x + std::conj(sn) * y;
+      h(ir, k + 1) = -sn * x + cs * y;
+    }
+    h(k, k) = t22;
+    h(k + 1, k + 1) = t11;
+    for (int ir = 0; ir < m; ++ir) {
+      const cd x = u(ir, k), y = u(ir, k + 1);
+      u(ir, k) = cs * x + std::conj(sn) * y;
+      u(ir, k + 1) = -sn * x + cs * y;
+    }
+  };
+  for (int pos = 0; pos < m; ++pos) {
+    int best = pos;
+    for (int i = pos + 1; i < m; ++i)
+      if (std::abs(h(i, i)) > std::abs(h(best, best))) best = i;
+    for (int k = best - 1; k >= pos; --k) swap_adj(k);
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < i; ++j) h(i, j) = 0.0;
+  std::copy(H.begin(), H.end(), To);
+  std::copy(U.begin(), U.end(), Uo);
+  return true;
+}
+
+bool invert(int m, const cd* A, cd* Ainv) {
+  std::vector<cd> a(A, A + (size_t)m * m), inv((size_t)m * m, cd(0.0));
+  for (int i = 0; i < m; ++i) inv[(size_t)i * m + i] = 1.0;
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::abs(a[(size_t)i * m + k]) > std::abs(a[(size_t)p * m + k])) p = i;
+    if (std::abs(a[(size_t)p * m + k]) == 0.0) return false;
+    if (p != k)
+      for (int j = 0; j < m; ++j) {
+        std::swap(a[(size_t)p * m + j], a[(size_t)k * m + j]);
+        std::swap(inv[(size_t)p * m + j], inv[(size_t)k * m + j]);
+      }
+    const cd piv = a[(size_t)k * m + k];
+    for (int j = 0; j < m; ++j) { a[(size_t)k * m + j] /= piv; inv[(size_t)k * m + j] /= piv; }
+    for (int i = 0; i < m; ++i) {
+      if (i == k) continue;
+      const cd f = a[(size_t)i * m + k];
+      if (f == 0.0) continue;
+      for (int j = 0; j < m; ++j) {
+        a[(size_t)i * m + j] -= f * a[(size_t)k * m + j];
+        inv[(size_t)i * m + j] -= f * inv[(size_t)k * m + j];
+      }
+    }
+  }
+  std::copy(inv.begin(), inv.end(), Ainv);
+  return true;
+}
+
+}  // namespace klst

@@ -1,0 +1,61 @@
+// Host-side pieces of the kLST library: problem tables, block-Jacobi ILU(0)
+// factorisation, and small dense complex linear algebra for projected problems.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "klst.h"
+
+namespace klst {
+
+using cd = std::complex<double>;
+
+// Discrete operator tables (Sec. 2.2 with the grid of Sec. 3.1).
+struct Problem {
+  int Ny = 0, Nxi = 0, r = 0, Dv = 2;
+  double beta = 0, L = 0, s_inf = 0, s_visc = 0, nu_inf = 0;
+  std::vector<double> xi_x, xi_y, w;   // [Nxi]
+  std::vector<double> Dx;              // [Ny*Ny] row-major, mapped derivative
+  std::vector<double> rho, u, E, T, nu;
+  std::vector<double> U;               // [Ny][2][r][Nxi] coupling columns G_a / H_a
+  std::vector<double> M;               // [Ny][r][2][Nxi] moment functionals
+  std::vector<uint8_t> bc;             // [Ny][2][Nxi] inflow rows
+  int n_bc = 0;
+  int64_t n() const { return 2LL * Ny * Nxi; }
+  int64_t nnz() const {
+    return n() * (Ny - 1 + 2LL * Nxi) - (int64_t)n_bc * (Ny - 2 + 2LL * Nxi);
+  }
+  bool is_bc(int j, int k) const { return bc[((size_t)j * 2) * Nxi + k] != 0; }
+};
+
+// Fills `p`; returns an empty string on success, else a description of the error.
+std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
+                          double beta, Problem& p);
+
+// Block-Jacobi ILU(0) of (A - sigma B) over blocks of whole velocity lines in
+// the velocity-major ordering.  Line l = f * Nxi + k; block = lines
+// [b*nl, min((b+1)*nl, 2 Nxi)).  For every line, F holds the combined unit-lower
+// L and upper U factors of its dense Ny x Ny diagonal block; C holds, per block,
+// the factor entries that couple two lines of the block at the same node j:
+// C[((b*nl + l)*nl + l2)*Ny + j], l2 < l in L, l2 > l in U (l, l2 block-local).
+struct ILU0 {
+  int nl = 1, nblocks = 0, Ny = 0, nlines = 0;
+  std::vector<cd> F;    // [nlines][Ny][Ny]
+  std::vector<cd> C;    // [nblocks][nl][nl][Ny]
+  int floored = 0;
+};
+void build_ilu0(const Problem& p, cd sigma, int lines_per_block, ILU0& f, int nthreads);
+
+// ---- small dense complex matrices, row-major m x m ----
+// Sorted Schur form: G U = U T, T upper triangular, |T_00| >= |T_11| >= ...
+// Returns false if the QR iteration failed to converge.
+bool sorted_schur(int m, const cd* G, cd* U, cd* T);
+// Householder QR of an m x m matrix A = Qm Rm.
+void qr_square(int m, const cd* A, cd* Qm, cd* Rm);
+// Inverse of an m x m matrix by LU with partial pivoting; false if singular.
+bool invert(int m, const cd* A, cd* Ainv);
+
+}  // namespace klst

@@ -1,0 +1,717 @@
+// HIP kernels for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// Vectors are complex FP64 stored as double2 (re, im), unknown (j, f, k) at
+// (2 j + f) * Nxi + k.  All reductions are deterministic: fixed partitions and
+// a fixed-order final sum done by the last workgroup to finish ("last block"
+// pattern with one global counter that the last block resets).
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace klst {
+namespace dev {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {   // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum of a double2 over a 256-thread block, result valid in thread 0.
+__device__ __forceinline__ double2 block_sum256(double2 v, double2* sh /*[4]*/) {
+  v.x = wave_sum(v.x);
+  v.y = wave_sum(v.y);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) r = cadd(r, sh[i]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------ operator ----
+
+// Perturbation moments m_a(j) = sum_{f,p} M[j][a][f][p] x[j][f][p] (rank r <= 4)
+// for each node j and vector v.  grid (Ny, nvec), block 256.
+__global__ void __launch_bounds__(256) k_moments(const double2* __restrict__ x, int64_t n, int Ny,
+                                                 int Nxi, int r, const double* __restrict__ M,
+                                                 double2* __restrict__ mom, const int* __restrict__ skip) {
+  __shared__ double2 sh[4];
+  if (skip && *skip) return;
+  const int j = blockIdx.x, v = blockIdx.y;
+  const int nc = 2 * Nxi;
+  const double2* xj = x + (int64_t)v * n + (int64_t)j * nc;
+  double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int c = threadIdx.x; c < nc; c += 256) {
+    const double2 xv = xj[c];
+    for (int a = 0; a < 4; ++a) {
+      if (a < r) {
+        const double mw = M[((int64_t)j * r + a) * nc + c];
+        acc[a].x += mw * xv.x;
+        acc[a].y += mw * xv.y;
+      }
+    }
+  }
+  for (int a = 0; a < 4; ++a) {
+    if (a < r) {
+      const double2 s = block_sum256(acc[a], sh);
+      if (threadIdx.x == 0) mom[((int64_t)v * Ny + j) * r + a] = s;
+    }
+  }
+}
+
+// y = (A - tau B) x, matrix-free.  The streaming term is a real GEMM
+// Y[j, c] = sum_m D_x[j, m] X[m, c] over the 2 Nxi complex columns c = (f, k);
+// a workgroup stages an Ny x TC column tile of X in LDS once and computes the
+// rows [row0, row1) of the tile.  Epilogue per entry: xi_x scaling, diagonal
+// (nu_j + i beta xi_y - tau), rank-r moment update, identity inflow rows.
+// grid (col tiles, row groups, nvec), block 256, dynamic LDS Ny * TC * 16 B.
+template <int TC>
+__global__ void __launch_bounds__(256) k_apply(const double2* __restrict__ x, double2* __restrict__ y,
+                                               int64_t n, int Ny, int Nxi, int r, double tau_re,
+                                               double tau_im, double beta,
+                                               const double* __restrict__ Dx,
+                                               const double* __restrict__ xi_x,
+                                               const double* __restrict__ xi_y,
+                                               const double* __restrict__ nu,
+                                               const double* __restrict__ U,
+                                               const double2* __restrict__ mom, int rows_per_group,
+                                               const int* __restrict__ skip) {
+  extern __shared__ double2 xs[];   // [Ny][TC]
+  if (skip && *skip) return;
+  const int nc = 2 * Nxi;
+  const int c0 = blockIdx.x * TC;
+  const int v = blockIdx.z;
+  const double2* xv = x + (int64_t)v * n;
+  double2* yv = y + (int64_t)v * n;
+  for (int idx = threadIdx.x; idx < Ny * TC; idx += 256) {
+    const int m = idx / TC, cc = idx % TC;
+    const int c = c0 + cc;
+    xs[idx] = (c < nc) ? xv[(int64_t)m * nc + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int cc = threadIdx.x % TC;
+  const int c = c0 + cc;
+  if (c >= nc) return;
+  const int f = c / Nxi, k = c - f * Nxi;
+  const double xik = xi_x[k], bxy = beta * xi_y[k];
+  const int row0 = blockIdx.y * rows_per_group;
+  const int row1 = min(Ny, row0 + rows_per_group);
+  const double2* momv = mom + (int64_t)v * Ny * r;
+  for (int j = row0 + threadIdx.x / TC; j < row1; j += 256 / TC) {
+    const double2 xjc = xs[j * TC + cc];
+    const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
+    double2 out;
+    if (bc) {
+      out = xjc;
+    } else {
+      const double* drow = Dx + (int64_t)j * Ny;
+      double sr = 0.0, si = 0.0;
+      for (int m = 0; m < Ny; ++m) {
+        const double d = drow[m];
+        const double2 xm = xs[m * TC + cc];
+        sr = fma(d, xm.x, sr);
+        si = fma(d, xm.y, si);
+      }
+      const double dre = nu[j] - tau_re, dim = bxy - tau_im;
+      out.x = xik * sr + dre * xjc.x - dim * xjc.y;
+      out.y = xik * si + dre * xjc.y + dim * xjc.x;
+      const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+      for (int a = 0; a < r; ++a) {
+        const double ua = Uj[(int64_t)a * Nxi];
+        const double2 ma = momv[j * r + a];
+        out.x -= ua * ma.x;
+        out.y -= ua * ma.y;
+      }
+    }
+    yv[(int64_t)j * nc + c] = out;
+  }
+}
+
+// ----------------------------------------------------------------- CSR -----
+
+// Row pointer of the explicit matrix: uniform length Ny - 1 + 2 Nxi for
+// non-inflow rows, 1 for inflow rows.  One thread per row writes rowptr[i+1];
+// the prefix is closed-form because row lengths are known: rows before i in
+// node order j' < j contribute per-node counts.
+__global__ void k_csr_rowptr(int64_t* __restrict__ rowptr, int Ny, int Nxi,
+                             const double* __restrict__ xi_x, int npos_x, int nneg_x) {
+  const int64_t n = 2LL * Ny * Nxi;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t L = Ny - 1 + 2LL * Nxi;
+  const int nc = 2 * Nxi;
+  const int j = (int)(i / nc);
+  const int c = (int)(i - (int64_t)j * nc);
+  const int k = c % Nxi, f = c / Nxi;
+  // inflow rows strictly before row i
+  int64_t nbc_before = 0;
+  if (j > 0) nbc_before += 2LL * nneg_x;                 // node 0, both fields
+  if (j == Ny - 1 && j > 0) {
+    // node Ny-1: inflow rows are xi_x > 0; count those before column c
+    int cnt = 0;
+    for (int cc = 0; cc < c; ++cc) cnt += (xi_x[cc % Nxi] > 0.0) ? 1 : 0;
+    nbc_before += cnt;
+  } else if (j == 0) {
+    int cnt = 0;
+    for (int cc = 0; cc < c; ++cc) cnt += (xi_x[cc % Nxi] < 0.0) ? 1 : 0;
+    nbc_before = cnt;
+  }
+  (void)f;
+  const bool bc = (j == Ny - 1 && xi_x[k] > 0.0) || (j == 0 && xi_x[k] < 0.0);
+  const int64_t before = i - nbc_before;   // non-inflow rows before i
+  const int64_t start = before * L + nbc_before;
+  rowptr[i + 1] = start + (bc ? 1 : L);
+  if (i == 0) rowptr[0] = 0;
+  (void)npos_x;
+}
+
+// Values and columns of the explicit matrix, one wavefront per row; columns in
+// ascending order: (m, f, k) for m < j, the 2 Nxi entries of node j, (m, f, k)
+// for m > j.
+__global__ void __launch_bounds__(256) k_csr_fill(const int64_t* __restrict__ rowptr,
+                                                  int32_t* __restrict__ col, double2* __restrict__ val,
+                                                  int Ny, int Nxi, int r, double beta,
+                                                  const double* __restrict__ Dx,
+                                                  const double* __restrict__ xi_x,
+                                                  const double* __restrict__ xi_y,
+                                                  const double* __restrict__ nu,
+                                                  const double* __restrict__ U,
+                                                  const double* __restrict__ M) {
+  const int64_t n = 2LL * Ny * Nxi;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int nc = 2 * Nxi;
+  const int j = (int)(i / nc);
+  const int c = (int)(i - (int64_t)j * nc);
+  const int f = c / Nxi, k = c - f * Nxi;
+  const int64_t s = rowptr[i];
+  const bool bc = (j == Ny - 1 && xi_x[k] > 0.0) || (j == 0 && xi_x[k] < 0.0);
+  if (bc) {
+    if (lane == 0) { col[s] = (int32_t)i; val[s] = make_double2(1.0, 0.0); }
+    return;
+  }
+  const int L = Ny - 1 + nc;
+  const double xik = xi_x[k];
+  for (int e = lane; e < L; e += 64) {
+    int32_t cidx;
+    double2 v;
+    if (e < j) {                                 // streaming, m = e < j
+      cidx = (int32_t)((2LL * e + f) * Nxi + k);
+      v = make_double2(xik * Dx[(int64_t)j * Ny + e], 0.0);
+    } else if (e < j + nc) {                     // node block
+      const int cb = e - j;
+      const int fb = cb / Nxi, kb = cb - fb * Nxi;
+      cidx = (int32_t)((int64_t)j * nc + cb);
+      double cp = 0.0;
+      for (int a = 0; a < r; ++a)
+        cp += U[(((int64_t)j * 2 + f) * r + a) * Nxi + k] * M[(((int64_t)j * r + a) * 2 + fb) * Nxi + kb];
+      v = make_double2(-cp, 0.0);
+      if (cb == c) { v.x += xik * Dx[(int64_t)j * Ny + j] + nu[j]; v.y += beta * xi_y[k]; }
+    } else {                                     // streaming, m > j
+      const int m = e - nc + 1;
+      cidx = (int32_t)((2LL * m + f) * Nxi + k);
+      v = make_double2(xik * Dx[(int64_t)j * Ny + m], 0.0);
+    }
+    col[s + e] = cidx;
+    val[s + e] = v;
+  }
+}
+
+// y = A x - tau B x with the CSR matrix, one wavefront per row.
+__global__ void __launch_bounds__(256) k_csr_spmv(const int64_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const double2* __restrict__ val,
+                                                  const double2* __restrict__ x, double2* __restrict__ y,
+                                                  int64_t n, int Ny, int Nxi,
+                                                  const double* __restrict__ xi_x, double tau_re,
+                                                  double tau_im, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const int64_t s = rowptr[i], e = rowptr[i + 1];
+  double sr = 0.0, si = 0.0;
+  for (int64_t p = s + lane; p < e; p += 64) {
+    const double2 a = val[p];
+    const double2 b = x[col[p]];
+    sr = fma(a.x, b.x, sr); sr = fma(-a.y, b.y, sr);
+    si = fma(a.x, b.y, si); si = fma(a.y, b.x, si);
+  }
+  sr = wave_sum(sr);
+  si = wave_sum(si);
+  if (lane == 0) {
+    const int nc = 2 * Nxi;
+    const int j = (int)(i / nc);
+    const int k = (int)(i - (int64_t)j * nc) % Nxi;
+    const bool bc = (j == Ny - 1 && xi_x[k] > 0.0) || (j == 0 && xi_x[k] < 0.0);
+    if (!bc) {
+      const double2 xi = x[i];
+      sr -= tau_re * xi.x - tau_im * xi.y;
+      si -= tau_re * xi.y + tau_im * xi.x;
+    }
+    y[i] = make_double2(sr, si);
+  }
+}
+
+// ------------------------------------------------- block-Jacobi ILU(0) -----
+
+// y = (L U)^{-1} x for every block of `nl` whole velocity lines.  One workgroup
+// per block, one wavefront per line; lane q holds the rows j = q + 64 s of its
+// line in registers.  Forward sweep: at step t, wavefront l finalises row
+// j = t - l (the level set l + j = t of the lower factor), taking the coupling
+// entries of earlier lines of the block at the same node from LDS, then updates
+// its later rows with column j of L (right-looking).  Backward sweep mirrors it.
+// F is stored column-major per line (Fc[line][col][row]); C as in the host set-up.
+template <int NPL>
+__global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ x,
+                                                    double2* __restrict__ y, int Ny, int Nxi,
+                                                    int nl, const double2* __restrict__ Fc,
+                                                    const double2* __restrict__ C,
+                                                    const int* __restrict__ skip) {
+  extern __shared__ double2 ys[];   // [nl][Ny]
+  if (skip && *skip) return;
+  const int b = blockIdx.x;
+  const int l = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nlines = 2 * Nxi;
+  const int nl_blk = min(nl, nlines - b * nl);
+  const bool active = l < nl_blk;
+  const int lg = b * nl + l;
+  const int f = active ? lg / Nxi : 0, k = active ? lg - f * Nxi : 0;
+  const int nc = 2 * Nxi;
+  const double2* Fl = Fc + (int64_t)(active ? lg : 0) * Ny * Ny;
+  const double2* Cl = C + (((int64_t)b * nl + l) * nl) * Ny;
+  double2 v[NPL];
+#pragma unroll
+  for (int s = 0; s < NPL; ++s) {
+    const int j = lane + 64 * s;
+    v[s] = (active && j < Ny) ? x[((int64_t)2 * j + f) * Nxi + k] : make_double2(0.0, 0.0);
+  }
+  const int steps = Ny + nl_blk - 1;
+  // forward: unit lower
+  for (int t = 0; t < steps; ++t) {
+    const int j = t - l;
+    if (active && j >= 0 && j < Ny) {
+      double2 cpl = make_double2(0.0, 0.0);
+      if (lane < l) {   // lanes 0..l-1 fetch coupling terms of earlier lines
+        cpl = cmul(Cl[(int64_t)lane * Ny + j], ys[lane * Ny + j]);
+      }
+      cpl.x = wave_sum(cpl.x);
+      cpl.y = wave_sum(cpl.y);
+      const int owner = j & 63, slot = j >> 6;
+      double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < NPL; ++s)
+        if (s == slot) mine = v[s];
+      double2 yj;
+      yj.x = __shfl(mine.x, owner, 64) - cpl.x;
+      yj.y = __shfl(mine.y, owner, 64) - cpl.y;
+      if (lane == owner) {
+        ys[l * Ny + j] = yj;
+#pragma unroll
+        for (int s = 0; s < NPL; ++s)
+          if (s == slot) v[s] = yj;
+      }
+      const double2* colj = Fl + (int64_t)j * Ny;
+#pragma unroll
+      for (int s = 0; s < NPL; ++s) {
+        const int q = lane + 64 * s;
+        if (q > j && q < Ny) v[s] = csub(v[s], cmul(colj[q], yj));
+      }
+    }
+    __syncthreads();
+  }
+  // backward: upper with diagonal; x(l,j) needs later lines l2 > l at node j
+  for (int t = 0; t < steps; ++t) {
+    const int j = (Ny - 1) - (t - (nl_blk - 1 - l));
+    if (active && j >= 0 && j < Ny) {
+      double2 cpl = make_double2(0.0, 0.0);
+      if (lane > l && lane < nl_blk) {
+        cpl = cmul(Cl[(int64_t)lane * Ny + j], ys[lane * Ny + j]);
+      }
+      cpl.x = wave_sum(cpl.x);
+      cpl.y = wave_sum(cpl.y);
+      const int owner = j & 63, slot = j >> 6;
+      double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < NPL; ++s)
+        if (s == slot) mine = v[s];
+      const double2* colj = Fl + (int64_t)j * Ny;
+      const double2 d = colj[j];
+      double2 num;
+      num.x = __shfl(mine.x, owner, 64) - cpl.x;
+      num.y = __shfl(mine.y, owner, 64) - cpl.y;
+      const double dd = d.x * d.x + d.y * d.y;
+      double2 xj;
+      xj.x = (num.x * d.x + num.y * d.y) / dd;
+      xj.y = (num.y * d.x - num.x * d.y) / dd;
+      if (lane == owner) {
+        ys[l * Ny + j] = xj;
+#pragma unroll
+        for (int s = 0; s < NPL; ++s)
+          if (s == slot) v[s] = xj;
+      }
+#pragma unroll
+      for (int s = 0; s < NPL; ++s) {
+        const int q = lane + 64 * s;
+        if (q < j) v[s] = csub(v[s], cmul(colj[q], xj));
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int s = 0; s < NPL; ++s) {
+      const int j = lane + 64 * s;
+      if (j < Ny) y[((int64_t)2 * j + f) * Nxi + k] = v[s];
+    }
+  }
+  (void)nc;
+}
+
+// ------------------------------------------------------- vector kernels ----
+
+// out[i] (=, +=, or (H^{-1} c)) for c_i = sum_t conj(S_i[t]) x[t], over up to two
+// segments of vectors (seg0: m0 vectors at s0, stride n; seg1: m1 at s1).
+// Each block reduces a contiguous slice of t for all vectors, writes partials,
+// and the last block sums the partials in block order.
+// mode: 0 out = c, 1 out += c, 2 out = Hinv * c (Hinv m x m row-major),
+//       3 out = c and also out[m] = sum |x|^2 (norm of x appended).
+__global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, int m0,
+                                              const double2* __restrict__ s1, int m1,
+                                              const double2* __restrict__ x, int64_t n, int chunk,
+                                              double2* __restrict__ partial,
+                                              unsigned int* __restrict__ counter,
+                                              double2* __restrict__ out, int mode,
+                                              const double2* __restrict__ Hinv,
+                                              double2* __restrict__ out2,
+                                              const int* __restrict__ skip) {
+  __shared__ double2 sh[4];
+  __shared__ bool last;
+  if (skip && *skip) return;
+  const int m = m0 + m1;
+  const int mtot = (mode == 3) ? m + 1 : m;
+  const int64_t t0 = (int64_t)blockIdx.x * chunk;
+  const int64_t t1 = min(n, t0 + chunk);
+  for (int g = 0; g < mtot; g += 8) {
+    double2 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+      const double2 xv = x[t];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = g + q;
+        if (i < m) {
+          const double2 sv = (i < m0) ? s0[(int64_t)i * n + t] : s1[(int64_t)(i - m0) * n + t];
+          acc[q] = cadd(acc[q], cmulc(sv, xv));
+        } else if (i == m && mode == 3) {
+          acc[q].x += xv.x * xv.x + xv.y * xv.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (g + q < mtot) {
+        const double2 sres = block_sum256(acc[q], sh);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * mtot + g + q] = sres;
+      }
+    }
+  }
+  __threadfence();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  __shared__ double2 cs[128];
+  for (int i = threadIdx.x; i < mtot; i += 256) {
+    double2 s = make_double2(0.0, 0.0);
+    for (unsigned bb = 0; bb < gridDim.x; ++bb) s = cadd(s, partial[(int64_t)bb * mtot + i]);
+    if (mode == 2) cs[i] = s;
+    else if (mode == 1) out[i] = cadd(out[i], s);
+    else out[i] = s;
+    if (out2 && i < m) out2[i] = cadd(out2[i], s);
+  }
+  if (mode == 2) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += 256) {
+      double2 s = make_double2(0.0, 0.0);
+      for (int q = 0; q < m; ++q) s = cadd(s, cmul(Hinv[i * m + q], cs[q]));
+      out[i] = s;
+    }
+  }
+  if (threadIdx.x == 0) *counter = 0u;
+}
+
+// x[t] -= sum_i S_i[t] c[i] over two segments (c on device; c[0..m0) for seg0,
+// c[m0..m0+m1) for seg1).  If dst != nullptr the result goes to dst instead.
+__global__ void __launch_bounds__(256) k_subm(const double2* __restrict__ s0, int m0,
+                                              const double2* __restrict__ s1, int m1,
+                                              const double2* __restrict__ c, double2* x,
+                                              double2* dst, int64_t n, double sign,
+                                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = 0; i < m0; ++i) acc = cadd(acc, cmul(s0[(int64_t)i * n + t], c[i]));
+  for (int i = 0; i < m1; ++i) acc = cadd(acc, cmul(s1[(int64_t)i * n + t], c[m0 + i]));
+  const double2 xv = x[t];
+  const double2 r = make_double2(xv.x - sign * acc.x, xv.y - sign * acc.y);
+  (dst ? dst : x)[t] = r;
+}
+
+// out_j[t] = sum_i S_i[t] coef[i * ldc + j] for j < k (basis rotation V <- V U),
+// coefficients on the device.  grid.y = output vector j.
+__global__ void __launch_bounds__(256) k_combine(const double2* __restrict__ S, int m, int64_t n,
+                                                 const double2* __restrict__ coef, int ldc,
+                                                 double2* __restrict__ out,
+                                                 const int* __restrict__ count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (t >= n) return;
+  const int mm = count ? min(m, *count) : m;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int i = 0; i < mm; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], coef[(int64_t)i * ldc + j]));
+  out[(int64_t)j * n + t] = acc;
+}
+
+// x *= 1 / sqrt(*nrm2) (nrm2 on device), optionally into dst.
+__global__ void k_scale_rsqrt(double2* x, double2* dst, int64_t n, const double2* __restrict__ nrm2,
+                              const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double s = 1.0 / sqrt(nrm2->x);
+  const double2 v = x[t];
+  (dst ? dst : x)[t] = make_double2(v.x * s, v.y * s);
+}
+
+// y = a x (+ y if accum), a host scalar.
+__global__ void k_axpby(const double2* __restrict__ x, double2* y, int64_t n, double are,
+                        double aim, int accum) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double2 xv = x[t];
+  double2 r = make_double2(are * xv.x - aim * xv.y, are * xv.y + aim * xv.x);
+  if (accum) r = cadd(r, y[t]);
+  y[t] = r;
+}
+
+// GMRES bookkeeping on the device (one thread): column j of the Hessenberg
+// (h[0..j] from Gram-Schmidt, h[j+1] = sqrt(nrm2)) gets the previous Givens
+// rotations, a new rotation zeroes h[j+1], g is rotated, and the residual
+// estimate |g[j+1]| decides whether the cycle is done.
+__global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ nrm2,
+                               double* __restrict__ cs, double2* __restrict__ sn,
+                               double2* __restrict__ g, int* __restrict__ done,
+                               int* __restrict__ steps, const double* __restrict__ beta, double rtol) {
+  if (*done) return;
+  const double tol_abs = rtol * (*beta);
+  double2* h = H + (int64_t)j * ldh;
+  h[j + 1] = make_double2(sqrt(nrm2->x), 0.0);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = h[i], b = h[i + 1];
+    // [c s; -conj(s) c]
+    const double2 sb = cmul(sn[i], b);
+    const double2 csa = cscale(a, cs[i]);
+    const double2 nsa = cmul(make_double2(-sn[i].x, sn[i].y), a);   // -conj(s) a
+    h[i] = cadd(csa, sb);
+    h[i + 1] = cadd(nsa, cscale(b, cs[i]));
+  }
+  const double2 a = h[j], b = h[j + 1];
+  const double af = sqrt(a.x * a.x + a.y * a.y), ag = sqrt(b.x * b.x + b.y * b.y);
+  double c;
+  double2 s;
+  if (ag == 0.0) { c = 1.0; s = make_double2(0.0, 0.0); }
+  else if (af == 0.0) { c = 0.0; s = make_double2(b.x / ag, -b.y / ag); }
+  else {
+    const double nrm = hypot(af, ag);
+    c = af / nrm;
+    const double2 ph = make_double2(a.x / af, a.y / af);
+    s = cscale(cmul(ph, make_double2(b.x, -b.y)), 1.0 / nrm);
+  }
+  cs[j] = c;
+  sn[j] = s;
+  h[j] = cadd(cscale(a, c), cmul(s, b));
+  h[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  g[j] = cscale(gj, c);
+  g[j + 1] = cmul(make_double2(-s.x, s.y), gj);
+  *steps = j + 1;
+  const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
+  if (res <= tol_abs || ag == 0.0) *done = 1;
+}
+
+// g[0] = sqrt(*nrm2); done = (g[0] == 0); steps = 0.
+__global__ void k_gmres_init(const double2* __restrict__ nrm2, double2* __restrict__ g, int* done,
+                             int* steps, double* beta_out) {
+  const double b = sqrt(nrm2->x);
+  g[0] = make_double2(b, 0.0);
+  *done = (b == 0.0) ? 1 : 0;
+  *steps = 0;
+  *beta_out = b;
+}
+
+// Back substitution R y = g with the rotated Hessenberg (steps x steps upper).
+__global__ void k_gmres_solve(const double2* __restrict__ H, int ldh, const double2* __restrict__ g,
+                              const int* __restrict__ steps, double2* __restrict__ yk) {
+  const int s = *steps;
+  for (int i = s - 1; i >= 0; --i) {
+    double2 acc = g[i];
+    for (int q = i + 1; q < s; ++q) acc = csub(acc, cmul(H[(int64_t)q * ldh + i], yk[q]));
+    const double2 d = H[(int64_t)i * ldh + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    yk[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+  }
+}
+
+// y = B x: copy with inflow entries zeroed.
+__global__ void k_mask_bc(const double2* __restrict__ x, double2* __restrict__ y, int64_t n, int Ny,
+                          int Nxi, const double* __restrict__ xi_x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int nc = 2 * Nxi;
+  const int j = (int)(i / nc);
+  const int k = (int)(i - (int64_t)j * nc) % Nxi;
+  const bool bc = (j == Ny - 1 && xi_x[k] > 0.0) || (j == 0 && xi_x[k] < 0.0);
+  y[i] = bc ? make_double2(0.0, 0.0) : x[i];
+}
+
+// Reset a flag.
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+// ------------------------------------------------------------- launchers ---
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                    const double* M, double2* mom, const int* skip) {
+  hipLaunchKernelGGL(k_moments, dim3(Ny, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, skip);
+}
+
+void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
+                  int r, double tre, double tim, double beta, const double* Dx, const double* xix,
+                  const double* xiy, const double* nu, const double* U, const double2* mom,
+                  const int* skip) {
+  constexpr int TC = 32;
+  const int nc = 2 * Nxi;
+  const int tiles = (nc + TC - 1) / TC;
+  // enough workgroups to cover the chip: split rows into groups of >= 8
+  int groups = 1;
+  while (tiles * groups * nvec < 1024 && Ny / (groups * 2) >= 8) groups *= 2;
+  const int rpg = (Ny + groups - 1) / groups;
+  const size_t lds = (size_t)Ny * TC * sizeof(double2);
+  hipLaunchKernelGGL(k_apply<TC>, dim3(tiles, groups, nvec), dim3(256), lds, st, x, y, n, Ny, Nxi, r,
+                     tre, tim, beta, Dx, xix, xiy, nu, U, mom, rpg, skip);
+}
+
+void launch_csr_build(hipStream_t st, int64_t* rowptr, int32_t* col, double2* val, int Ny, int Nxi,
+                      int r, double beta, const double* Dx, const double* xix, const double* xiy,
+                      const double* nu, const double* U, const double* M, int npos, int nneg) {
+  const int64_t n = 2LL * Ny * Nxi;
+  hipLaunchKernelGGL(k_csr_rowptr, dim3(nblk(n, 256)), dim3(256), 0, st, rowptr, Ny, Nxi, xix, npos, nneg);
+  hipLaunchKernelGGL(k_csr_fill, dim3(nblk(n * 64, 256)), dim3(256), 0, st, rowptr, col, val, Ny, Nxi, r,
+                     beta, Dx, xix, xiy, nu, U, M);
+}
+
+void launch_csr_spmv(hipStream_t st, const int64_t* rowptr, const int32_t* col, const double2* val,
+                     const double2* x, double2* y, int64_t n, int Ny, int Nxi, const double* xix,
+                     double tre, double tim, const int* skip) {
+  hipLaunchKernelGGL(k_csr_spmv, dim3(nblk(n * 64, 256)), dim3(256), 0, st, rowptr, col, val, x, y, n,
+                     Ny, Nxi, xix, tre, tim, skip);
+}
+
+void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
+                      int nblocks, const double2* Fc, const double2* C, const int* skip) {
+  const size_t lds = (size_t)nl * Ny * sizeof(double2);
+  const dim3 blk(64 * nl);
+  if (Ny <= 64)
+    hipLaunchKernelGGL(k_ilu_apply<1>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+  else if (Ny <= 128)
+    hipLaunchKernelGGL(k_ilu_apply<2>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+  else
+    hipLaunchKernelGGL(k_ilu_apply<4>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+}
+
+int dot_blocks(int64_t n, int* chunk) {
+  int c = 2048;
+  while ((n + c - 1) / c > 512) c *= 2;
+  *chunk = c;
+  return (int)((n + c - 1) / c);
+}
+
+void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
+                 int mode, const double2* Hinv, double2* out2, const int* skip) {
+  int chunk;
+  const int nb = dot_blocks(n, &chunk);
+  hipLaunchKernelGGL(k_dotm, dim3(nb), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk, partial, counter,
+                     out, mode, Hinv, out2, skip);
+}
+
+void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                 const double2* c, double2* x, double2* dst, int64_t n, double sign, const int* skip) {
+  hipLaunchKernelGGL(k_subm, dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, dst, n, sign,
+                     skip);
+}
+
+void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, double2* out, const int* count) {
+  hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out, count);
+}
+
+void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* nrm2,
+                        const int* skip) {
+  hipLaunchKernelGGL(k_scale_rsqrt, dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
+}
+
+void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
+                  int accum) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, are, aim, accum);
+}
+
+void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
+                       double* beta) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(1), 0, st, nrm2, g, done, steps, beta);
+}
+
+void launch_gmres_givens(hipStream_t st, double2* H, int ldh, int j, const double2* nrm2, double* cs,
+                         double2* sn, double2* g, int* done, int* steps, const double* beta, double rtol) {
+  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, st, H, ldh, j, nrm2, cs, sn, g, done, steps,
+                     beta, rtol);
+}
+
+void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2* g, const int* steps,
+                        double2* yk) {
+  hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(1), 0, st, H, ldh, g, steps, yk);
+}
+
+void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int Ny, int Nxi,
+                    const double* xix) {
+  hipLaunchKernelGGL(k_mask_bc, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, Ny, Nxi, xix);
+}
+
+void launch_set_int(hipStream_t st, int* p, int v) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+}
+
+}  // namespace dev
+}  // namespace klst

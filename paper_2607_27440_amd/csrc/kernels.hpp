@@ -1,0 +1,49 @@
+// Launchers of the device kernels (kernels.hip).  All pointers are device
+// pointers; complex FP64 vectors are double2 arrays of length n per vector.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace klst {
+namespace dev {
+
+void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                    const double* M, double2* mom, const int* skip);
+void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
+                  int r, double tre, double tim, double beta, const double* Dx, const double* xix,
+                  const double* xiy, const double* nu, const double* U, const double2* mom,
+                  const int* skip);
+void launch_csr_build(hipStream_t st, int64_t* rowptr, int32_t* col, double2* val, int Ny, int Nxi,
+                      int r, double beta, const double* Dx, const double* xix, const double* xiy,
+                      const double* nu, const double* U, const double* M, int npos, int nneg);
+void launch_csr_spmv(hipStream_t st, const int64_t* rowptr, const int32_t* col, const double2* val,
+                     const double2* x, double2* y, int64_t n, int Ny, int Nxi, const double* xix,
+                     double tre, double tim, const int* skip);
+void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
+                      int nblocks, const double2* Fc, const double2* C, const int* skip);
+int dot_blocks(int64_t n, int* chunk);
+// mode 0: out = S^H x; 1: out += S^H x; 2: out = Hinv (S^H x); 3: out = S^H x and out[m] = ||x||^2.
+// out2 (optional) += S^H x.
+void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
+                 int mode, const double2* Hinv, double2* out2, const int* skip);
+void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                 const double2* c, double2* x, double2* dst, int64_t n, double sign, const int* skip);
+void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, double2* out, const int* count);
+void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* nrm2,
+                        const int* skip);
+void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
+                  int accum);
+void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
+                       double* beta);
+void launch_gmres_givens(hipStream_t st, double2* H, int ldh, int j, const double2* nrm2, double* cs,
+                         double2* sn, double2* g, int* done, int* steps, const double* beta, double rtol);
+void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2* g, const int* steps,
+                        double2* yk);
+void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int Ny, int Nxi,
+                    const double* xix);
+void launch_set_int(hipStream_t st, int* p, int v);
+
+}  // namespace dev
+}  // namespace klst

@@ -1,0 +1,258 @@
+"""Thin ctypes binding of libklst (C ABI in include/klst.h).
+
+Argument marshalling only: every step of the eigen-solve runs in the native
+library.  Device vectors are passed as torch tensors (complex128, contiguous, on
+the context's device) through their data pointers; PyTorch is used for device
+memory and streams only.  Importing this module loads the library and raises if
+it has not been built (``python -m paper_2607_27440_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libklst.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libklst.so not built at {LIB_PATH}; run `python -m paper_2607_27440_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ECANCELLED, ESTATE = range(8)
+
+
+class Options(C.Structure):
+    _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("precision", C.c_int),
+                ("op_mode", C.c_int), ("lines_per_block", C.c_int), ("m_max", C.c_int),
+                ("m_min", C.c_int), ("gmres_m", C.c_int), ("max_it", C.c_int), ("tol", C.c_double),
+                ("inner_rtol", C.c_double), ("fix", C.c_double), ("seed", C.c_uint64)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("Ny", C.c_int), ("L", C.c_double), ("s_inf", C.c_double)]
+
+
+class Vel(C.Structure):
+    _fields_ = [("Nxi", C.c_int), ("xi_x", C.POINTER(C.c_double)), ("xi_y", C.POINTER(C.c_double)),
+                ("w", C.POINTER(C.c_double)), ("Dv", C.c_int)]
+
+
+class Base(C.Structure):
+    _fields_ = [("mode", C.c_int), ("rho", C.POINTER(C.c_double)), ("u", C.POINTER(C.c_double)),
+                ("T", C.POINTER(C.c_double)), ("g_c", C.POINTER(C.c_double)),
+                ("h_c", C.POINTER(C.c_double)), ("s_visc", C.c_double), ("nu_inf", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("outer_iterations", C.c_int), ("inner_iterations", C.c_int), ("restarts", C.c_int),
+                ("nconv", C.c_int), ("pivots_floored", C.c_int), ("seconds_total", C.c_double),
+                ("seconds_setup", C.c_double), ("seconds_op", C.c_double), ("seconds_pc", C.c_double),
+                ("op_applies", C.c_int64), ("pc_applies", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_D2 = C.POINTER(C.c_double)
+_sig = {
+    "klst_default_options": (None, [C.POINTER(Options)]),
+    "klst_strerror": (C.c_char_p, [C.c_int]),
+    "klst_last_error": (C.c_char_p, [_P]),
+    "klst_create": (C.c_int, [C.POINTER(_P), C.POINTER(Options)]),
+    "klst_destroy": (None, [_P]),
+    "klst_assemble": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double]),
+    "klst_dims": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+    "klst_apply": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_apply_many": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
+    "klst_apply_csr": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_precond_setup": (C.c_int, [_P, _D2]),
+    "klst_precond_apply": (C.c_int, [_P, _P, _P]),
+    "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
+    "klst_get_stats": (C.c_int, [_P, C.POINTER(Stats)]),
+    "klst_host_tables": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
+                                   _D2, _D2, _D2, _D2, C.POINTER(C.c_uint8)]),
+    "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+#: every entry point the header declares (checked by the CPU test suite)
+EXPORTS = tuple(_sig)
+
+
+class KlstError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_lib.klst_strerror(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(_D2)
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    _lib.klst_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _structs(wl):
+    """Marshal a workload-like object into (Grid, Vel, Base, keepalive)."""
+    keep = []
+
+    def arr(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return _dp(a)
+    g = Grid(int(wl.Ny), float(wl.L), float(wl.s_inf))
+    v = Vel(int(len(wl.xi_x)), arr(wl.xi_x), arr(wl.xi_y), arr(wl.w), int(wl.Dv))
+    null = C.POINTER(C.c_double)()
+    if wl.mode == 0:
+        b = Base(0, arr(wl.rho), arr(wl.u), arr(wl.T), null, null, float(wl.s_visc), float(wl.nu_inf))
+    else:
+        b = Base(1, null, null, null, arr(wl.g_c), arr(wl.h_c), float(wl.s_visc), float(wl.nu_inf))
+    return g, v, b, keep
+
+
+def host_tables(wl):
+    """Tables built by the library's host assembly (no device needed)."""
+    g, v, b, keep = _structs(wl)
+    Ny, Nxi = int(wl.Ny), len(wl.xi_x)
+    r = 4 if wl.Dv == 2 else 3
+    Dx = np.zeros(Ny * Ny)
+    nu = np.zeros(Ny)
+    U = np.zeros(Ny * 2 * r * Nxi)
+    M = np.zeros(Ny * r * 2 * Nxi)
+    bc = np.zeros(Ny * 2 * Nxi, np.uint8)
+    st = _lib.klst_host_tables(C.byref(g), C.byref(v), C.byref(b), float(wl.beta), _dp(Dx), _dp(nu),
+                               _dp(U), _dp(M), bc.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if st != OK:
+        raise KlstError(st, "host tables")
+    return dict(Dx=Dx.reshape(Ny, Ny), nu=nu, U=U.reshape(Ny, 2, r, Nxi), M=M.reshape(Ny, r, 2, Nxi),
+                bc=bc.reshape(Ny, 2, Nxi).astype(bool))
+
+
+def host_sorted_schur(G: np.ndarray):
+    """(U, T) with G U = U T, |T_00| >= |T_11| >= ...  (library host routine)."""
+    m = G.shape[0]
+    g = np.ascontiguousarray(G, dtype=np.complex128).view(np.float64).ravel()
+    U = np.zeros(2 * m * m)
+    T = np.zeros(2 * m * m)
+    st = _lib.klst_host_sorted_schur(m, _dp(g), _dp(U), _dp(T))
+    if st != OK:
+        raise KlstError(st, "sorted schur")
+    return U.view(np.complex128).reshape(m, m), T.view(np.complex128).reshape(m, m)
+
+
+class Context:
+    """One library context: a device, a stream, one assembled problem."""
+
+    def __init__(self, options: Optional[Options] = None, **kw):
+        opt = options if options is not None else default_options(**kw)
+        h = _P()
+        st = _lib.klst_create(C.byref(h), C.byref(opt))
+        if st != OK:
+            raise KlstError(st, "klst_create")
+        self._h = h
+        self.options = opt
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.klst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, what):
+        if st != OK:
+            raise KlstError(st, f"{what}: {_lib.klst_last_error(self._h).decode()}")
+
+    def assemble(self, wl):
+        g, v, b, keep = _structs(wl)
+        self._check(_lib.klst_assemble(self._h, C.byref(g), C.byref(v), C.byref(b), float(wl.beta)),
+                    "klst_assemble")
+        n = C.c_int64()
+        nnz = C.c_int64()
+        nbc = C.c_int()
+        self._check(_lib.klst_dims(self._h, C.byref(n), C.byref(nnz), C.byref(nbc)), "klst_dims")
+        self.n, self.nnz, self.n_bc = n.value, nnz.value, nbc.value
+        return self
+
+    @staticmethod
+    def _ptr(t):
+        import torch
+        assert t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous(), \
+            "device complex128 contiguous tensor expected"
+        return C.c_void_p(t.data_ptr())
+
+    def _tau(self, tau):
+        tau = complex(tau)
+        a = np.array([tau.real, tau.imag])
+        return a, _dp(a)
+
+    def apply(self, tau, x, y):
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply(self._h, p, self._ptr(x), self._ptr(y)), "klst_apply")
+
+    def apply_many(self, tau, nvec, x, y):
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply_many(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
+                    "klst_apply_many")
+
+    def apply_csr(self, tau, x, y):
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply_csr(self._h, p, self._ptr(x), self._ptr(y)), "klst_apply_csr")
+
+    def precond_setup(self, sigma):
+        a, p = self._tau(sigma)
+        self._check(_lib.klst_precond_setup(self._h, p), "klst_precond_setup")
+
+    def precond_apply(self, x, y):
+        self._check(_lib.klst_precond_apply(self._h, self._ptr(x), self._ptr(y)), "klst_precond_apply")
+
+    def solve(self, sigma, nev, X=None, want_vectors=True):
+        """Returns dict(lam, X, resid, nconv, status, stats).  X may be a device
+        tensor of nev * n complex128 to receive the eigenvectors in place."""
+        a, p = self._tau(sigma)
+        lam = np.zeros(2 * nev)
+        res = np.zeros(nev)
+        nconv = C.c_int()
+        if X is not None:
+            xp, on_dev = self._ptr(X), 1
+            hostX = None
+        elif want_vectors:
+            hostX = np.zeros(nev * self.n, np.complex128)
+            xp, on_dev = C.c_void_p(hostX.ctypes.data), 0
+        else:
+            hostX, xp, on_dev = None, None, 0
+        st = _lib.klst_solve(self._h, p, int(nev), _dp(lam), xp, on_dev, _dp(res), C.byref(nconv))
+        if st not in (OK, ENOCONV):
+            self._check(st, "klst_solve")
+        k = nconv.value
+        s = Stats()
+        _lib.klst_get_stats(self._h, C.byref(s))
+        out = dict(lam=lam.view(np.complex128)[:k].copy(), resid=res[:k].copy(), nconv=k, status=st,
+                   stats=s.as_dict())
+        if hostX is not None:
+            out["X"] = hostX.reshape(nev, self.n)[:k].T.copy()
+        elif X is not None:
+            out["X"] = X
+        return out

@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every input is seeded and synthetic (paper_2607_27440_amd.workloads); every
+expected value comes from oracle/.  Floating-point bounds are stated per test:
+entrywise results use the dot-product error bound c * u * (|A| |x|)_i, solves use
+the eigenpair matching rule of oracle.parity.
+"""
+import numpy as np
+import pytest
+
+from paper_2607_27440_amd import workloads as W
+from oracle import eig as E
+from oracle import jd as OJ
+from oracle import operator as O
+from oracle import parity as PAR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+DEV = "cuda:0"
+
+
+def _klst():
+    from paper_2607_27440_amd import klst
+    return klst
+
+
+def _ctx(wl, **kw):
+    klst = _klst()
+    print(f"[case] {wl.name} n={wl.n} opts={kw}", flush=True)
+    ctx = klst.Context(**kw)
+    ctx.assemble(wl)
+    return ctx
+
+
+def _abs_bound(P, x, tau):
+    """(|A - tau B| |x|)_i from the structured pieces (valid at every size)."""
+    wl = P.wl
+    ax = np.abs(x).reshape(P.Ny, 2, P.Nxi)
+    y = np.einsum("jm,mfk->jfk", np.abs(P.Dx), ax) * np.abs(wl.xi_x)[None, None, :]
+    y += np.abs(1j * wl.beta * wl.xi_y[None, None, :] + P.state["nu"][:, None, None] - tau) * ax
+    m = np.einsum("jafk,jfk->ja", np.abs(P.M), ax)
+    y += np.einsum("jfak,ja->jfk", np.abs(P.U), m)
+    y[P.bc] = ax[P.bc]
+    return y.ravel()
+
+
+def _gamma(P):
+    """Deterministic dot-product error bound factor gamma_L = L u for the longest
+    row (L = Ny - 1 + 2 Nxi entries plus the rank-r update)."""
+    return (P.Ny + 2 * P.Nxi + P.r + 4) * U
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+CONFIGS = {"c1": W.config1, "c2": W.config2}
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+@pytest.mark.parametrize("tau", [0.0, 0.3 - 0.7j])
+def test_apply_matches_oracle(cfg, tau):
+    wl = CONFIGS[cfg]()
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 11)
+    ctx = _ctx(wl)
+    xd = _dev(x)
+    yd = torch.empty_like(xd)
+    ctx.apply(tau, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = P.apply(x, tau)
+    bound = _gamma(P) * _abs_bound(P, x, tau) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2"])
+def test_apply_csr_matches_oracle(cfg):
+    wl = CONFIGS[cfg]()
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 12)
+    tau = 0.1 + 0.05j
+    ctx = _ctx(wl)
+    assert ctx.nnz == P.A.nnz == O.nnz_formula(P.Ny, P.Nxi, int(P.bc.sum()))
+    xd = _dev(x)
+    yd = torch.empty_like(xd)
+    ctx.apply_csr(tau, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = P.apply(x, tau)
+    bound = _gamma(P) * _abs_bound(P, x, tau) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+
+
+def test_apply_c3_full_shape():
+    """M=4, Ny=96, Nxi=1464 (n = 281,088): every entry of one matrix-free apply
+    against the oracle's structured apply."""
+    wl = W.config3()
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 13)
+    ctx = _ctx(wl)
+    xd = _dev(x)
+    yd = torch.empty_like(xd)
+    ctx.apply(0.0, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = P.apply_structured(x, 0.0)
+    bound = _gamma(P) * _abs_bound(P, x, 0.0) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+
+
+def test_apply_many_equals_single():
+    wl = W.config2()
+    ctx = _ctx(wl)
+    nvec = 5
+    x = np.stack([W.random_vector(wl.n, 20 + i) for i in range(nvec)])
+    xd = _dev(x.ravel())
+    yd = torch.empty_like(xd)
+    ctx.apply_many(0.2j, nvec, xd, yd)
+    y1 = torch.empty(wl.n, dtype=torch.complex128, device=DEV)
+    for i in range(nvec):
+        ctx.apply(0.2j, xd[i * wl.n:(i + 1) * wl.n], y1)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, yd[i * wl.n:(i + 1) * wl.n])
+
+
+@pytest.mark.parametrize("cfg,lines", [("c1", 1), ("c1", 4), ("c2", 3)])
+def test_precond_matches_oracle(cfg, lines):
+    wl = CONFIGS[cfg]()
+    P = O.Pencil(wl)
+    sigma = wl.sigma
+    K = OJ.LineBlockILU0(P, sigma, lines)
+    b = W.random_vector(wl.n, 30) * P.bdiag
+    ctx = _ctx(wl, lines_per_block=lines)
+    ctx.precond_setup(sigma)
+    bd = _dev(b)
+    yd = torch.empty_like(bd)
+    ctx.precond_apply(bd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = K.solve(b)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    assert err <= 1e-11, err
+
+
+def _check_solve(wl, out, ref_lam, kappa=None, normA=None, tol=1e-10):
+    lam = out["lam"]
+    assert out["nconv"] == wl.nev, out["stats"]
+    assert np.all(out["resid"] <= 1e-10), out["resid"]
+    res, skipped = PAR.match(lam, ref_lam, kappa, normA, sigma=wl.sigma, tol=tol)
+    bad = [r for r in res if not r["ok"]]
+    assert not bad, bad
+    assert not skipped, skipped
+
+
+def test_solve_c1_matches_qz():
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam_all, X, Y, ninf = E.qz_all(P)
+    assert ninf == int(P.bc.sum())
+    idx = E.order_nearest(lam_all, wl.sigma)[:wl.nev + 10]
+    kap = E.condition_numbers(P, lam_all[idx], X[:, idx], Y[:, idx])
+    normA = abs(P.A).sum(axis=0).max()
+    ctx = _ctx(wl, lines_per_block=4, m_max=40)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    _check_solve(wl, out, lam_all[idx], kap, normA)
+    # eigenvectors: residual with the oracle's explicit matrices
+    r = E.residuals(P, out["lam"], out["X"])
+    assert np.all(r <= 1e-10), r
+
+
+def test_solve_c2_matches_shift_invert():
+    wl = W.config2()
+    P = O.Pencil(wl)
+    ref, _ = E.si_nearest(P, wl.sigma, wl.nev + 10)
+    ctx = _ctx(wl, lines_per_block=3, m_max=60)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    r = E.residuals(P, out["lam"], out["X"])
+    assert np.all(r <= 1e-10), r
+    _check_solve(wl, out, ref, tol=2e-10)
