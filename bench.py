@@ -1,0 +1,206 @@
+"""Benchmark: Jacobi-Davidson eigenpairs/s for the kLST shock-stability pencil.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3]
+                    [--precision fp64|mixed] [--no-cpu-baseline]
+
+One step = the whole hot path on one synthetic input: assemble the operator
+(grids, coefficient tables, device upload) and solve for the nev eigenpairs
+nearest the target with Jacobi-Davidson (block-Jacobi ILU(0) set-up, GMRES
+correction solves, CGS2, projected problems, locking, eigenvectors).  The value
+counts only eigenpairs whose relative residual is <= 1e-10.  Inputs are seeded
+synthetic shock base flows (paper_2607_27440_amd.workloads).
+
+After the timed steps, the dominant kernel is re-timed with HIP events on the
+library's stream to report its roofline fraction, and the CPU oracle's
+Jacobi-Davidson is timed on a bounded sample for the cpu_baseline field.
+Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+RES_GATE = 1e-10
+
+# workload -> (generator, library options)
+WORKLOADS = {
+    # Plain FP64 JD, M = 3 bimodal shock, Ny = 64, Nxi = 96 (n = 12,288), 20 nearest 0.05i,
+    # block-Jacobi ILU(0) with 64 blocks (3 velocity lines each), GMRES(20).
+    "c2": ("config2", dict(lines_per_block=3, m_max=60, m_min=6, gmres_m=20)),
+    # M = 4 bimodal shock, Ny = 96, Nxi = 1464 (n = 281,088), 10 nearest 0.
+    "c3": ("config3", dict(lines_per_block=16, m_max=40, m_min=6, gmres_m=20)),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_roofline(ctx, wl, torch, reps):
+    """Time the block-Jacobi ILU(0) apply (the dominant kernel of the solve) with
+    HIP events on the library's stream.  Algorithmic bytes per launch: with the
+    stored block inverse (pc_kernel 1), every block's dense (nl Ny)^2 inverse read
+    once plus the input and output vectors (32 n); with the level-set sweeps
+    (pc_kernel 0), the factor tables (2 Nxi lines x Ny^2 + coupling entries)
+    plus 32 n.  Complex FP64 = 16 B per entry."""
+    n = wl.n
+    x = torch.randn(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    ctx.precond_setup(wl.sigma)
+    st = torch.cuda.current_stream()
+    for _ in range(5):
+        ctx.precond_apply(x, y)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        ctx.precond_apply(x, y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    nl = ctx.options.lines_per_block
+    nlines = 2 * wl.Nxi
+    nblocks = (nlines + nl - 1) // nl
+    if ctx.options.pc_kernel == 1:
+        sizes = [min(nl, nlines - b * nl) * wl.Ny for b in range(nblocks)]
+        nbytes = 16 * sum(s * s for s in sizes) + 32 * n
+        kname = "k_blockinv_apply (block-Jacobi ILU(0), stored block inverse)"
+    else:
+        nbytes = 16 * (nlines * wl.Ny * wl.Ny + nblocks * nl * nl * wl.Ny) + 32 * n
+        kname = "k_ilu_apply (block-Jacobi ILU(0) level-set sweeps)"
+    achieved = nbytes / sec / 1e9
+    return {"kernel": kname,
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_us": round(sec * 1e6, 3), "bytes_per_launch": nbytes}
+
+
+def op_apply_rate(ctx, wl, torch, reps):
+    """Matrix-free (A - tau B) x and CSR SpMV rates on this workload (events)."""
+    n = wl.n
+    x = torch.randn(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    st = torch.cuda.current_stream()
+    out = {}
+    for name, fn, nbytes in (
+            ("matrix_free", ctx.apply, 32 * n + 8 * 2 * 2 * 4 * wl.Nxi * wl.Ny),
+            ("csr", ctx.apply_csr, 20 * ctx.nnz + 8 * (n + 1) + 32 * n)):
+        for _ in range(3):
+            fn(0.0, x, y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn(0.0, x, y)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        out[name] = {"avg_us": round(sec * 1e6, 3), "GB/s": round(nbytes / sec / 1e9, 2),
+                     "bytes": nbytes}
+    return out
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle's plain CPU Jacobi-Davidson on the same workload, stopped after
+    `seconds` of work (a bounded sample); rate = converged eigenpairs / time."""
+    import numpy as np
+    from oracle import jd as OJ
+    from oracle import operator as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    P = O.Pencil(wl)
+    K = OJ.LineBlockILU0(P, wl.sigma, WORKLOADS["c2"][1]["lines_per_block"])
+    remaining = max(1.0, seconds - (time.perf_counter() - t0))
+    out = OJ.jd(P, wl.sigma, wl.nev, tol=RES_GATE, m_max=60, precond=K, time_limit=remaining)
+    el = time.perf_counter() - t0
+    good = int(np.sum(out["resid"] <= RES_GATE))
+    return {"value": round(good / el, 6), "unit": "eigenpairs/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"{wl.name}: CPU JD (same parameters) for {el:.1f} s incl. ILU(0) set-up; "
+                      f"{good} eigenpairs converged, {out['outer']} outer iterations"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2607_27440_amd import klst, workloads
+    gen, opts = WORKLOADS[a.workload]
+    wl = getattr(workloads, gen)()
+    prec = 0 if a.precision == "fp64" else 1
+    st = torch.cuda.current_stream()
+    ctx = klst.Context(stream=st.cuda_stream, precision=prec, **opts)
+    log(f"[bench] workload {wl.name} n={wl.n} nev={wl.nev} sigma={wl.sigma} opts={opts}")
+    good_total = 0
+    stats = None
+    for i in range(a.warmup):
+        ctx.assemble(wl)
+        out = ctx.solve(wl.sigma, wl.nev, want_vectors=False)
+        log(f"[bench] warmup {i}: nconv {out['nconv']} outer {out['stats']['outer_iterations']} "
+            f"{out['stats']['seconds_total']:.3f}s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ctx.assemble(wl)
+        out = ctx.solve(wl.sigma, wl.nev, want_vectors=False)
+        good_total += int(np.sum(out["resid"] <= RES_GATE))
+        stats = out["stats"]
+        log(f"[bench] step {i}: nconv {out['nconv']} outer {stats['outer_iterations']} "
+            f"inner {stats['inner_iterations']} {stats['seconds_total']:.3f}s")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = good_total / el
+    roof = kernel_roofline(ctx, wl, torch, a.kernel_reps)
+    ops = op_apply_rate(ctx, wl, torch, max(20, a.kernel_reps // 4))
+    line = {
+        "metric": "eigenpairs/s at rel. residual <= 1e-10",
+        "value": round(value, 4),
+        "unit": "eigenpairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * el / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128" if prec == 0 else "c64-inner/c128-outer",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "nev": wl.nev, "sigma": str(wl.sigma),
+                   "Ny": wl.Ny, "Nxi": wl.Nxi, "precision": a.precision, **opts},
+        "roofline": roof,
+        "op_apply": ops,
+        "solve_stats": stats,
+    }
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -55,7 +55,7 @@ typedef enum {
  * m_min, GMRES correction-equation solves of at most gmres_m steps. */
 typedef struct {
   int device;           /* HIP device ordinal                                        */
-  void* stream;         /* hipStream_t to order work on; NULL = library-owned stream */
+  void* stream;         /* hipStream_t to order work on; NULL = the default stream   */
   int precision;        /* 0 = FP64 everywhere; 1 = FP32 inner GMRES + preconditioner
                            inside an FP64 iterative refinement of the correction eq. */
   int op_mode;          /* 0 = matrix-free operator; 1 = explicit CSR (built on device) */
@@ -67,6 +67,9 @@ typedef struct {
   double inner_rtol;    /* GMRES relative tolerance                                  */
   double fix;           /* correction shift = sigma until rel. residual < fix        */
   uint64_t seed;        /* start vector: counter-based SplitMix64 stream             */
+  int pc_kernel;        /* preconditioner application: 0 = level-set triangular sweeps
+                           over the ILU(0) factors; 1 = the same (L U)^{-1} applied as
+                           a stored dense inverse per block (batched GEMV)           */
 } klst_options;
 
 /* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]

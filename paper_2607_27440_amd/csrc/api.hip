@@ -40,7 +40,9 @@ struct klst_ctx {
   double2* d_val = nullptr;
   // preconditioner
   klst::ILU0 ilu;
-  double2 *d_F = nullptr, *d_C = nullptr;
+  double2 *d_F = nullptr, *d_C = nullptr, *d_Kinv = nullptr;
+  int64_t* d_koff = nullptr;
+  int pc_kernel_built = -1;
   bool pc_ready = false;
   cd pc_sigma = 0.0;
   int pc_lines = 0;
@@ -94,7 +96,7 @@ klst_status dalloc(klst_ctx* ctx, void** p, size_t bytes) {
 void free_problem(klst_ctx* ctx) {
   dfree(ctx->d_Dx); dfree(ctx->d_xix); dfree(ctx->d_xiy); dfree(ctx->d_nu); dfree(ctx->d_U);
   dfree(ctx->d_M); dfree(ctx->d_mom); dfree(ctx->d_rowptr); dfree(ctx->d_col); dfree(ctx->d_val);
-  dfree(ctx->d_F); dfree(ctx->d_C);
+  dfree(ctx->d_F); dfree(ctx->d_C); dfree(ctx->d_Kinv); dfree(ctx->d_koff);
   ctx->mom_cap = 0;
   ctx->pc_ready = false;
   ctx->assembled = false;
@@ -157,10 +159,27 @@ klst_status op_apply(klst_ctx* ctx, cd tau, const double2* x, double2* y, int nv
 klst_status pc_setup(klst_ctx* ctx, cd sigma) {
   const klst::Problem& p = ctx->prob;
   const int lines = std::max(1, ctx->opt.lines_per_block);
-  if (ctx->pc_ready && ctx->pc_sigma == sigma && ctx->pc_lines == lines) return KLST_OK;
+  const int pk = ctx->opt.pc_kernel;
+  if (ctx->pc_ready && ctx->pc_sigma == sigma && ctx->pc_lines == lines && ctx->pc_kernel_built == pk)
+    return KLST_OK;
   ctx->pc_ready = false;
   const unsigned hw = std::thread::hardware_concurrency();
-  klst::build_ilu0(p, sigma, lines, ctx->ilu, (int)std::max(1u, std::min(hw, 16u)));
+  const int nth = (int)std::max(1u, std::min(hw, 16u));
+  klst::build_ilu0(p, sigma, lines, ctx->ilu, nth);
+  dfree(ctx->d_Kinv);
+  dfree(ctx->d_koff);
+  if (pk == 1) {
+    std::vector<cd> Kinv;
+    std::vector<int64_t> koff;
+    klst::build_block_inverse(ctx->ilu, Kinv, koff, nth);
+    ALLOC(ctx->d_Kinv, sizeof(double2) * Kinv.size());
+    ALLOC(ctx->d_koff, sizeof(int64_t) * koff.size());
+    HIPCHK(hipMemcpyAsync(ctx->d_Kinv, Kinv.data(), sizeof(double2) * Kinv.size(), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_koff, koff.data(), sizeof(int64_t) * koff.size(), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   // F column-major per line for the device sweeps
   const int Ny = p.Ny;
   std::vector<cd> Fc(ctx->ilu.F.size());
@@ -169,6 +188,8 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
     cd* Fo = &Fc[(size_t)l * Ny * Ny];
     for (int j = 0; j < Ny; ++j)
       for (int m = 0; m < Ny; ++m) Fo[(size_t)m * Ny + j] = Fr[(size_t)j * Ny + m];
+    // the device sweeps multiply by the reciprocal pivot
+    for (int j = 0; j < Ny; ++j) Fo[(size_t)j * Ny + j] = 1.0 / Fr[(size_t)j * Ny + j];
   }
   dfree(ctx->d_F);
   dfree(ctx->d_C);
@@ -182,14 +203,19 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
   ctx->pc_ready = true;
   ctx->pc_sigma = sigma;
   ctx->pc_lines = lines;
+  ctx->pc_kernel_built = pk;
   ctx->stats.pivots_floored = ctx->ilu.floored;
   return KLST_OK;
 }
 
 klst_status pc_apply(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
   const klst::Problem& p = ctx->prob;
-  klst::dev::launch_ilu_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks, ctx->d_F,
-                              ctx->d_C, skip);
+  if (ctx->pc_kernel_built == 1)
+    klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
+                                     ctx->d_Kinv, ctx->d_koff, skip);
+  else
+    klst::dev::launch_ilu_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks, ctx->d_F,
+                                ctx->d_C, skip);
   HIPCHK(hipGetLastError());
   ctx->stats.pc_applies += 1;
   return KLST_OK;
@@ -240,6 +266,7 @@ void klst_default_options(klst_options* o) {
   o->inner_rtol = 1e-6;
   o->fix = 0.01;
   o->seed = 0;
+  o->pc_kernel = 1;
 }
 
 const char* klst_strerror(klst_status s) {
@@ -265,7 +292,8 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   if (opt) o = *opt; else klst_default_options(&o);
   if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
-      (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120)
+      (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
+      (o.pc_kernel != 0 && o.pc_kernel != 1))
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -275,15 +303,10 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   klst_ctx* ctx = new klst_ctx();
   ctx->opt = o;
   if (hipSetDevice(o.device) != hipSuccess) { delete ctx; return KLST_EDEVICE; }
-  if (o.stream) {
-    ctx->stream = (hipStream_t)o.stream;
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return KLST_EDEVICE;
-    }
-    ctx->own_stream = true;
-  }
+  // NULL selects the device's default (null) stream, so work is ordered with
+  // anything else the caller issues there (torch's default stream included).
+  ctx->stream = (hipStream_t)o.stream;
+  ctx->own_stream = false;
   if (dalloc(ctx, (void**)&ctx->d_partial, sizeof(double2) * 512 * 256) != KLST_OK ||
       dalloc(ctx, (void**)&ctx->d_counter, sizeof(unsigned) * 4) != KLST_OK) {
     klst_destroy(ctx);
@@ -542,9 +565,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       dot(s0, m0, s1, m1, x, c, 0);
       sub(s0, m0, s1, m1, c, x);
       dot(s0, m0, s1, m1, x, d_c2, 0, nullptr, c);
-      sub(s0, m0, s1, m1, d_c2, x);
     }
-    dot(nullptr, 0, nullptr, 0, x, nrm, 3);
+    launch_subm_norm(st, s0, m0, s1, m1, d_c2, x, n, partial, counter, nrm, nullptr, 0, 0, nullptr,
+                     nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
   };
 
   // host mirrors of projected quantities
@@ -766,10 +789,8 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       dot(Gb, j + 1, nullptr, 0, gj1, hcol, 0, nullptr, nullptr, d_done);
       launch_subm(st, Gb, j + 1, nullptr, 0, hcol, gj1, nullptr, n, 1.0, d_done);
       dot(Gb, j + 1, nullptr, 0, gj1, d_c2, 0, nullptr, hcol, d_done);
-      launch_subm(st, Gb, j + 1, nullptr, 0, d_c2, gj1, nullptr, n, 1.0, d_done);
-      dot(nullptr, 0, nullptr, 0, gj1, d_small + 2, 3, nullptr, nullptr, d_done);
-      launch_gmres_givens(st, d_H, gm + 1, j, d_small + 2, d_cs, d_sn, d_g, d_done, d_steps, d_beta,
-                          o.inner_rtol);
+      launch_subm_norm(st, Gb, j + 1, nullptr, 0, d_c2, gj1, n, partial, counter, d_small + 2, d_H,
+                       gm + 1, j, d_cs, d_sn, d_g, d_done, d_steps, d_beta, o.inner_rtol);
       launch_scale_rsqrt(st, gj1, nullptr, n, d_small + 2, d_done);
     }
     launch_gmres_solve(st, d_H, gm + 1, d_g, d_steps, d_yk);

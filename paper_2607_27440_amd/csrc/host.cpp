@@ -313,6 +313,68 @@ void build_ilu0(const Problem& p, cd sigma, int lines_per_block, ILU0& f, int nt
   for (int v : floored) f.floored += v;
 }
 
+void build_block_inverse(const ILU0& f, std::vector<cd>& Kinv, std::vector<int64_t>& off,
+                         int nthreads) {
+  const int Ny = f.Ny, nl = f.nl;
+  off.assign(f.nblocks + 1, 0);
+  for (int b = 0; b < f.nblocks; ++b) {
+    const int nb = std::min(nl, f.nlines - b * nl) * Ny;
+    off[b + 1] = off[b] + (int64_t)nb * nb;
+  }
+  Kinv.assign(off[f.nblocks], cd(0.0));
+  auto work = [&](int t) {
+    std::vector<cd> L, U, col;
+    for (int b = t; b < f.nblocks; b += nthreads) {
+      const int nlb = std::min(nl, f.nlines - b * nl);
+      const int nb = nlb * Ny;
+      L.assign((size_t)nb * nb, cd(0.0));
+      U.assign((size_t)nb * nb, cd(0.0));
+      for (int l = 0; l < nlb; ++l) {
+        const cd* F = &f.F[(size_t)(b * nl + l) * Ny * Ny];
+        const cd* Cl = &f.C[(((size_t)b * nl + l) * nl) * Ny];
+        for (int j = 0; j < Ny; ++j) {
+          const size_t r = (size_t)(l * Ny + j) * nb;
+          for (int m = 0; m < Ny; ++m) {
+            if (m < j) L[r + l * Ny + m] = F[(size_t)j * Ny + m];
+            else U[r + l * Ny + m] = F[(size_t)j * Ny + m];
+          }
+          L[r + l * Ny + j] = 1.0;
+          for (int l2 = 0; l2 < nlb; ++l2) {
+            if (l2 < l) L[r + l2 * Ny + j] = Cl[(size_t)l2 * Ny + j];
+            else if (l2 > l) U[r + l2 * Ny + j] = Cl[(size_t)l2 * Ny + j];
+          }
+        }
+      }
+      cd* K = &Kinv[off[b]];
+      col.resize(nb);
+      for (int c = 0; c < nb; ++c) {
+        for (int i = 0; i < nb; ++i) col[i] = (i == c) ? cd(1.0) : cd(0.0);
+        for (int i = 0; i < nb; ++i) {               // L z = e_c
+          cd acc = col[i];
+          const cd* Li = &L[(size_t)i * nb];
+          for (int q = c; q < i; ++q) acc -= Li[q] * col[q];
+          col[i] = acc;
+        }
+        for (int i = nb - 1; i >= 0; --i) {          // U w = z
+          cd acc = col[i];
+          const cd* Ui = &U[(size_t)i * nb];
+          for (int q = i + 1; q < nb; ++q) acc -= Ui[q] * col[q];
+          col[i] = acc / Ui[i];
+        }
+        for (int i = 0; i < nb; ++i) K[(size_t)c * nb + i] = col[i];
+      }
+    }
+  };
+  nthreads = std::max(1, std::min(nthreads, f.nblocks));
+  if (nthreads == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nthreads; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+}
+
 // ---------------------------------------------------------------- dense ----
 
 namespace {

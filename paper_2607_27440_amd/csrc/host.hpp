@@ -48,6 +48,10 @@ struct ILU0 {
   int floored = 0;
 };
 void build_ilu0(const Problem& p, cd sigma, int lines_per_block, ILU0& f, int nthreads);
+// Dense inverse (L_b U_b)^{-1} of every block's ILU(0) factors, column-major over
+// the block's rows in (line, node) order; block b starts at Kinv[off[b]].
+void build_block_inverse(const ILU0& f, std::vector<cd>& Kinv, std::vector<int64_t>& off,
+                         int nthreads);
 
 // ---- small dense complex matrices, row-major m x m ----
 // Sorted Schur form: G U = U T, T upper triangular, |T_00| >= |T_11| >= ...

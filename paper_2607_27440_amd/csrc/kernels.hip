@@ -22,6 +22,23 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// sum_{i < m} S_i[t] c[coff + i] with the loads of eight vectors issued before
+// their products are accumulated (c indices are wave-uniform: scalar loads).
+__device__ __forceinline__ double2 lincomb(const double2* __restrict__ S, int m, int64_t n, int64_t t,
+                                           const double2* __restrict__ c, int cstride) {
+  double2 acc = make_double2(0.0, 0.0);
+  int i = 0;
+  for (; i + 8 <= m; i += 8) {
+    double2 sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = S[(int64_t)(i + u) * n + t];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(sv[u], c[(int64_t)(i + u) * cstride]));
+  }
+  for (; i < m; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], c[(int64_t)i * cstride]));
+  return acc;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
@@ -276,8 +293,32 @@ __global__ void __launch_bounds__(256) k_csr_spmv(const int64_t* __restrict__ ro
 // j = t - l (the level set l + j = t of the lower factor), taking the coupling
 // entries of earlier lines of the block at the same node from LDS, then updates
 // its later rows with column j of L (right-looking).  Backward sweep mirrors it.
+// The factor column and coupling entries of step t + 2 are loaded during step t,
+// so the per-step critical path is the barrier and the shuffles, not memory.
 // F is stored column-major per line (Fc[line][col][row]); C as in the host set-up.
 template <int NPL>
+__device__ __forceinline__ void load_col(double2 (&f)[NPL], const double2* __restrict__ col, int Ny,
+                                         int lane) {
+#pragma unroll
+  for (int s = 0; s < NPL; ++s) {
+    const int q = lane + 64 * s;
+    f[s] = (q < Ny) ? col[q] : make_double2(0.0, 0.0);
+  }
+}
+
+// Broadcast lane `src` (wave-uniform) of a double2 to the whole wavefront.
+__device__ __forceinline__ double2 bcast(double2 v, int src) {
+  double2 r;
+  const unsigned lo_x = __builtin_amdgcn_readlane((unsigned)(__double_as_longlong(v.x) & 0xffffffffULL), src);
+  const unsigned hi_x = __builtin_amdgcn_readlane((unsigned)((unsigned long long)__double_as_longlong(v.x) >> 32), src);
+  const unsigned lo_y = __builtin_amdgcn_readlane((unsigned)(__double_as_longlong(v.y) & 0xffffffffULL), src);
+  const unsigned hi_y = __builtin_amdgcn_readlane((unsigned)((unsigned long long)__double_as_longlong(v.y) >> 32), src);
+  r.x = __longlong_as_double((long long)(((unsigned long long)hi_x << 32) | lo_x));
+  r.y = __longlong_as_double((long long)(((unsigned long long)hi_y << 32) | lo_y));
+  return r;
+}
+
+template <int NPL, int PD>
 __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ x,
                                                     double2* __restrict__ y, int Ny, int Nxi,
                                                     int nl, const double2* __restrict__ Fc,
@@ -292,9 +333,8 @@ __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ 
   const bool active = l < nl_blk;
   const int lg = b * nl + l;
   const int f = active ? lg / Nxi : 0, k = active ? lg - f * Nxi : 0;
-  const int nc = 2 * Nxi;
   const double2* Fl = Fc + (int64_t)(active ? lg : 0) * Ny * Ny;
-  const double2* Cl = C + (((int64_t)b * nl + l) * nl) * Ny;
+  const double2* Cl = C + (((int64_t)b * nl + l) * nl) * Ny;   // Cl[l2 * Ny + j]
   double2 v[NPL];
 #pragma unroll
   for (int s = 0; s < NPL; ++s) {
@@ -302,76 +342,99 @@ __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ 
     v[s] = (active && j < Ny) ? x[((int64_t)2 * j + f) * Nxi + k] : make_double2(0.0, 0.0);
   }
   const int steps = Ny + nl_blk - 1;
-  // forward: unit lower
+  // ring of the factor columns (and lane-l2 coupling entries) of the next PD steps
+  double2 fr[PD][NPL], cr[PD];
+  const bool cl = active && lane < nl_blk && lane != l;
+  // ---- forward sweep, unit lower factor
+  if (active) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      if (d < Ny) {
+        load_col<NPL>(fr[d], Fl + (int64_t)d * Ny, Ny, lane);
+        cr[d] = cl ? Cl[(int64_t)lane * Ny + d] : make_double2(0.0, 0.0);
+      }
+    }
+  }
   for (int t = 0; t < steps; ++t) {
     const int j = t - l;
     if (active && j >= 0 && j < Ny) {
-      double2 cpl = make_double2(0.0, 0.0);
-      if (lane < l) {   // lanes 0..l-1 fetch coupling terms of earlier lines
-        cpl = cmul(Cl[(int64_t)lane * Ny + j], ys[lane * Ny + j]);
+      double2 f0[NPL];
+#pragma unroll
+      for (int s2 = 0; s2 < NPL; ++s2) f0[s2] = fr[0][s2];
+      const double2 c0 = cr[0];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+#pragma unroll
+        for (int s2 = 0; s2 < NPL; ++s2) fr[d][s2] = fr[d + 1][s2];
+        cr[d] = cr[d + 1];
       }
-      cpl.x = wave_sum(cpl.x);
-      cpl.y = wave_sum(cpl.y);
+      if (j + PD < Ny) {
+        load_col<NPL>(fr[PD - 1], Fl + (int64_t)(j + PD) * Ny, Ny, lane);
+        cr[PD - 1] = cl ? Cl[(int64_t)lane * Ny + j + PD] : make_double2(0.0, 0.0);
+      }
+      // coupling with earlier lines of the block at node j (same value in every lane)
+      double2 cpl = make_double2(0.0, 0.0);
+      for (int l2 = 0; l2 < l; ++l2) cpl = cadd(cpl, cmul(bcast(c0, l2), ys[l2 * Ny + j]));
       const int owner = j & 63, slot = j >> 6;
       double2 mine = make_double2(0.0, 0.0);
 #pragma unroll
       for (int s = 0; s < NPL; ++s)
         if (s == slot) mine = v[s];
-      double2 yj;
-      yj.x = __shfl(mine.x, owner, 64) - cpl.x;
-      yj.y = __shfl(mine.y, owner, 64) - cpl.y;
-      if (lane == owner) {
-        ys[l * Ny + j] = yj;
-#pragma unroll
-        for (int s = 0; s < NPL; ++s)
-          if (s == slot) v[s] = yj;
-      }
-      const double2* colj = Fl + (int64_t)j * Ny;
+      const double2 yj = csub(bcast(mine, owner), cpl);
+      if (lane == owner && nl_blk > 1) ys[l * Ny + j] = yj;
 #pragma unroll
       for (int s = 0; s < NPL; ++s) {
         const int q = lane + 64 * s;
-        if (q > j && q < Ny) v[s] = csub(v[s], cmul(colj[q], yj));
+        if (q == j) v[s] = yj;
+        else if (q > j && q < Ny) v[s] = csub(v[s], cmul(f0[s], yj));
       }
     }
-    __syncthreads();
+    if (nl_blk > 1) __syncthreads();
   }
-  // backward: upper with diagonal; x(l,j) needs later lines l2 > l at node j
+  // ---- backward sweep, upper factor; its diagonal is stored as the reciprocal
+  if (active) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      if (Ny - 1 - d >= 0) {
+        load_col<NPL>(fr[d], Fl + (int64_t)(Ny - 1 - d) * Ny, Ny, lane);
+        cr[d] = cl ? Cl[(int64_t)lane * Ny + Ny - 1 - d] : make_double2(0.0, 0.0);
+      }
+    }
+  }
   for (int t = 0; t < steps; ++t) {
     const int j = (Ny - 1) - (t - (nl_blk - 1 - l));
     if (active && j >= 0 && j < Ny) {
-      double2 cpl = make_double2(0.0, 0.0);
-      if (lane > l && lane < nl_blk) {
-        cpl = cmul(Cl[(int64_t)lane * Ny + j], ys[lane * Ny + j]);
+      double2 f0[NPL];
+#pragma unroll
+      for (int s2 = 0; s2 < NPL; ++s2) f0[s2] = fr[0][s2];
+      const double2 c0 = cr[0];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d) {
+#pragma unroll
+        for (int s2 = 0; s2 < NPL; ++s2) fr[d][s2] = fr[d + 1][s2];
+        cr[d] = cr[d + 1];
       }
-      cpl.x = wave_sum(cpl.x);
-      cpl.y = wave_sum(cpl.y);
+      if (j - PD >= 0) {
+        load_col<NPL>(fr[PD - 1], Fl + (int64_t)(j - PD) * Ny, Ny, lane);
+        cr[PD - 1] = cl ? Cl[(int64_t)lane * Ny + j - PD] : make_double2(0.0, 0.0);
+      }
+      double2 cpl = make_double2(0.0, 0.0);
+      for (int l2 = l + 1; l2 < nl_blk; ++l2) cpl = cadd(cpl, cmul(bcast(c0, l2), ys[l2 * Ny + j]));
       const int owner = j & 63, slot = j >> 6;
-      double2 mine = make_double2(0.0, 0.0);
+      double2 mine = make_double2(0.0, 0.0), dmine = make_double2(0.0, 0.0);
 #pragma unroll
       for (int s = 0; s < NPL; ++s)
-        if (s == slot) mine = v[s];
-      const double2* colj = Fl + (int64_t)j * Ny;
-      const double2 d = colj[j];
-      double2 num;
-      num.x = __shfl(mine.x, owner, 64) - cpl.x;
-      num.y = __shfl(mine.y, owner, 64) - cpl.y;
-      const double dd = d.x * d.x + d.y * d.y;
-      double2 xj;
-      xj.x = (num.x * d.x + num.y * d.y) / dd;
-      xj.y = (num.y * d.x - num.x * d.y) / dd;
-      if (lane == owner) {
-        ys[l * Ny + j] = xj;
-#pragma unroll
-        for (int s = 0; s < NPL; ++s)
-          if (s == slot) v[s] = xj;
-      }
+        if (s == slot) { mine = v[s]; dmine = f0[s]; }
+      const double2 xj = cmul(csub(bcast(mine, owner), cpl), bcast(dmine, owner));
+      if (lane == owner && nl_blk > 1) ys[l * Ny + j] = xj;
 #pragma unroll
       for (int s = 0; s < NPL; ++s) {
         const int q = lane + 64 * s;
-        if (q < j) v[s] = csub(v[s], cmul(colj[q], xj));
+        if (q == j) v[s] = xj;
+        else if (q < j) v[s] = csub(v[s], cmul(f0[s], xj));
       }
     }
-    __syncthreads();
+    if (nl_blk > 1) __syncthreads();
   }
   if (active) {
 #pragma unroll
@@ -380,17 +443,74 @@ __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ 
       if (j < Ny) y[((int64_t)2 * j + f) * Nxi + k] = v[s];
     }
   }
-  (void)nc;
+}
+
+// y_b = Kinv_b x_b for every block-Jacobi block b, with Kinv_b = (L_b U_b)^{-1}
+// the dense inverse of the block's ILU(0) factors (same preconditioner as the
+// sweeps above, applied as a bandwidth-bound batched GEMV).  Kinv_b is stored
+// column-major over the block's rows in velocity-major order (line, node).
+// grid (row tiles of 64, blocks), block 256: the 4 wavefronts split the columns,
+// lanes own rows (coalesced column reads), partial sums meet in LDS.
+__global__ void __launch_bounds__(256) k_blockinv_apply(const double2* __restrict__ x,
+                                                        double2* __restrict__ y, int Ny, int Nxi,
+                                                        int nl, const double2* __restrict__ Kinv,
+                                                        const int64_t* __restrict__ koff,
+                                                        const int* __restrict__ skip) {
+  extern __shared__ double2 xsb[];   // [nb] block input, then [4][64] partials
+  if (skip && *skip) return;
+  const int b = blockIdx.y;
+  const int nlines = 2 * Nxi;
+  const int nl_blk = min(nl, nlines - b * nl);
+  const int nb = nl_blk * Ny;
+  const int l0 = b * nl;
+  for (int c = threadIdx.x; c < nb; c += 256) {
+    const int lg = l0 + c / Ny, j = c % Ny;
+    const int f = lg / Nxi, k = lg - f * Nxi;
+    xsb[c] = x[((int64_t)2 * j + f) * Nxi + k];
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 64 + lane;
+  const double2* K = Kinv + koff[b];
+  double2 acc = make_double2(0.0, 0.0);
+  if (row < nb) {
+    const int cper = (nb + 3) / 4;
+    const int cb = wv * cper, ce = min(nb, cb + cper);
+    int c = cb;
+    for (; c + 8 <= ce; c += 8) {
+      double2 kv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kv[u] = K[(int64_t)(c + u) * nb + row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(kv[u], xsb[c + u]));
+    }
+    for (; c < ce; ++c) acc = cadd(acc, cmul(K[(int64_t)c * nb + row], xsb[c]));
+  }
+  __syncthreads();
+  double2* part = xsb + nb;
+  part[wv * 64 + lane] = acc;
+  __syncthreads();
+  if (wv == 0 && row < nb) {
+    double2 r = part[lane];
+    r = cadd(r, part[64 + lane]);
+    r = cadd(r, part[128 + lane]);
+    r = cadd(r, part[192 + lane]);
+    const int lg = l0 + row / Ny, j = row % Ny;
+    const int f = lg / Nxi, k = lg - f * Nxi;
+    y[((int64_t)2 * j + f) * Nxi + k] = r;
+  }
 }
 
 // ------------------------------------------------------- vector kernels ----
 
-// out[i] (=, +=, or (H^{-1} c)) for c_i = sum_t conj(S_i[t]) x[t], over up to two
+// out[i] (=, +=, or Hinv * c) for c_i = sum_t conj(S_i[t]) x[t], over up to two
 // segments of vectors (seg0: m0 vectors at s0, stride n; seg1: m1 at s1).
-// Each block reduces a contiguous slice of t for all vectors, writes partials,
-// and the last block sums the partials in block order.
+// Tall-skinny layout: one wavefront per (vector, chunk of t), lanes striding the
+// chunk, one wavefront reduction per partial; the last workgroup to finish sums
+// the partials of every vector over the chunks in chunk order (deterministic).
+// grid (nchunks, ceil(mtot / 4)), block 256 = 4 wavefronts.
 // mode: 0 out = c, 1 out += c, 2 out = Hinv * c (Hinv m x m row-major),
-//       3 out = c and also out[m] = sum |x|^2 (norm of x appended).
+//       3 out = c and out[m] = sum |x|^2.  out2 (optional) += c.
 __global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, int m0,
                                               const double2* __restrict__ s1, int m1,
                                               const double2* __restrict__ x, int64_t n, int chunk,
@@ -400,61 +520,71 @@ __global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, in
                                               const double2* __restrict__ Hinv,
                                               double2* __restrict__ out2,
                                               const int* __restrict__ skip) {
-  __shared__ double2 sh[4];
   __shared__ bool last;
+  __shared__ double2 cs[256];
   if (skip && *skip) return;
   const int m = m0 + m1;
   const int mtot = (mode == 3) ? m + 1 : m;
-  const int64_t t0 = (int64_t)blockIdx.x * chunk;
-  const int64_t t1 = min(n, t0 + chunk);
-  for (int g = 0; g < mtot; g += 8) {
-    double2 acc[8];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.y * 4 + wv;
+  const int nchunks = gridDim.x;
+  if (i < mtot) {
+    const int64_t t0 = (int64_t)blockIdx.x * chunk;
+    const int64_t t1 = min(n, t0 + chunk);
+    double ar = 0.0, ai = 0.0;
+    const double2* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
+    int64_t t = t0 + lane;
+    for (; t + 192 < t1; t += 256) {
+      double2 a[4], b[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = make_double2(0.0, 0.0);
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-      const double2 xv = x[t];
+      for (int u = 0; u < 4; ++u) { a[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int i = g + q;
-        if (i < m) {
-          const double2 sv = (i < m0) ? s0[(int64_t)i * n + t] : s1[(int64_t)(i - m0) * n + t];
-          acc[q] = cadd(acc[q], cmulc(sv, xv));
-        } else if (i == m && mode == 3) {
-          acc[q].x += xv.x * xv.x + xv.y * xv.y;
-        }
+      for (int u = 0; u < 4; ++u) {
+        ar = fma(a[u].x, b[u].x, ar); ar = fma(a[u].y, b[u].y, ar);
+        ai = fma(a[u].x, b[u].y, ai); ai = fma(-a[u].y, b[u].x, ai);
       }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (g + q < mtot) {
-        const double2 sres = block_sum256(acc[q], sh);
-        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * mtot + g + q] = sres;
-      }
+    for (; t < t1; t += 64) {
+      const double2 a = sv[t], b = x[t];
+      ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
+      ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
     }
+    if (i >= m) ai = 0.0;   // |x|^2 row: conj(x) x is real
+    ar = wave_sum(ar);
+    ai = wave_sum(ai);
+    if (lane == 0) partial[(int64_t)i * nchunks + blockIdx.x] = make_double2(ar, ai);
   }
   __threadfence();
+  __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
+    last = (prev == gridDim.x * gridDim.y - 1);
   }
   __syncthreads();
   if (!last) return;
   __threadfence();
-  __shared__ double2 cs[128];
-  for (int i = threadIdx.x; i < mtot; i += 256) {
-    double2 s = make_double2(0.0, 0.0);
-    for (unsigned bb = 0; bb < gridDim.x; ++bb) s = cadd(s, partial[(int64_t)bb * mtot + i]);
-    if (mode == 2) cs[i] = s;
-    else if (mode == 1) out[i] = cadd(out[i], s);
-    else out[i] = s;
-    if (out2 && i < m) out2[i] = cadd(out2[i], s);
+  // one wavefront per vector: lanes load the chunk partials (fixed assignment),
+  // then a fixed-shape wavefront tree sums them
+  for (int q = wv; q < mtot; q += 4) {
+    const double2* pq = partial + (int64_t)q * nchunks;
+    double sr = 0.0, si = 0.0;
+    for (int c = lane; c < nchunks; c += 64) { const double2 pv = pq[c]; sr += pv.x; si += pv.y; }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) {
+      const double2 sm = make_double2(sr, si);
+      if (mode == 2) cs[q] = sm;
+      else if (mode == 1) out[q] = cadd(out[q], sm);
+      else out[q] = sm;
+      if (out2 && q < m) out2[q] = cadd(out2[q], sm);
+    }
   }
   if (mode == 2) {
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += 256) {
-      double2 s = make_double2(0.0, 0.0);
-      for (int q = 0; q < m; ++q) s = cadd(s, cmul(Hinv[i * m + q], cs[q]));
-      out[i] = s;
+    for (int q = threadIdx.x; q < m; q += 256) {
+      double2 sm = make_double2(0.0, 0.0);
+      for (int p = 0; p < m; ++p) sm = cadd(sm, cmul(Hinv[q * m + p], cs[p]));
+      out[q] = sm;
     }
   }
   if (threadIdx.x == 0) *counter = 0u;
@@ -470,9 +600,7 @@ __global__ void __launch_bounds__(256) k_subm(const double2* __restrict__ s0, in
   if (skip && *skip) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int i = 0; i < m0; ++i) acc = cadd(acc, cmul(s0[(int64_t)i * n + t], c[i]));
-  for (int i = 0; i < m1; ++i) acc = cadd(acc, cmul(s1[(int64_t)i * n + t], c[m0 + i]));
+  const double2 acc = cadd(lincomb(s0, m0, n, t, c, 1), lincomb(s1, m1, n, t, c + m0, 1));
   const double2 xv = x[t];
   const double2 r = make_double2(xv.x - sign * acc.x, xv.y - sign * acc.y);
   (dst ? dst : x)[t] = r;
@@ -488,9 +616,7 @@ __global__ void __launch_bounds__(256) k_combine(const double2* __restrict__ S, 
   const int j = blockIdx.y;
   if (t >= n) return;
   const int mm = count ? min(m, *count) : m;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int i = 0; i < mm; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], coef[(int64_t)i * ldc + j]));
-  out[(int64_t)j * n + t] = acc;
+  out[(int64_t)j * n + t] = lincomb(S, mm, n, t, coef + j, ldc);
 }
 
 // x *= 1 / sqrt(*nrm2) (nrm2 on device), optionally into dst.
@@ -519,17 +645,16 @@ __global__ void k_axpby(const double2* __restrict__ x, double2* y, int64_t n, do
 // (h[0..j] from Gram-Schmidt, h[j+1] = sqrt(nrm2)) gets the previous Givens
 // rotations, a new rotation zeroes h[j+1], g is rotated, and the residual
 // estimate |g[j+1]| decides whether the cycle is done.
-__global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ nrm2,
-                               double* __restrict__ cs, double2* __restrict__ sn,
-                               double2* __restrict__ g, int* __restrict__ done,
-                               int* __restrict__ steps, const double* __restrict__ beta, double rtol) {
-  if (*done) return;
+__device__ void gmres_givens_body(double2* __restrict__ H, int ldh, int j, double nrm2,
+                                  double* __restrict__ cs, double2* __restrict__ sn,
+                                  double2* __restrict__ g, int* __restrict__ done,
+                                  int* __restrict__ steps, const double* __restrict__ beta,
+                                  double rtol) {
   const double tol_abs = rtol * (*beta);
   double2* h = H + (int64_t)j * ldh;
-  h[j + 1] = make_double2(sqrt(nrm2->x), 0.0);
+  h[j + 1] = make_double2(sqrt(nrm2), 0.0);
   for (int i = 0; i < j; ++i) {
     const double2 a = h[i], b = h[i + 1];
-    // [c s; -conj(s) c]
     const double2 sb = cmul(sn[i], b);
     const double2 csa = cscale(a, cs[i]);
     const double2 nsa = cmul(make_double2(-sn[i].x, sn[i].y), a);   // -conj(s) a
@@ -558,6 +683,61 @@ __global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const do
   *steps = j + 1;
   const double res = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y);
   if (res <= tol_abs || ag == 0.0) *done = 1;
+}
+
+__global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ nrm2,
+                               double* __restrict__ cs, double2* __restrict__ sn,
+                               double2* __restrict__ g, int* __restrict__ done,
+                               int* __restrict__ steps, const double* __restrict__ beta, double rtol) {
+  if (*done) return;
+  gmres_givens_body(H, ldh, j, nrm2->x, cs, sn, g, done, steps, beta, rtol);
+}
+
+// x[t] -= sum_i S_i[t] c[i] (two segments, c on device) and ||x||^2 of the result
+// into *nrm2 (partials per block, fixed-order sum by the last block).  When H is
+// given, the last block also performs the GMRES Givens update of column j.
+__global__ void __launch_bounds__(256) k_subm_norm(const double2* __restrict__ s0, int m0,
+                                                   const double2* __restrict__ s1, int m1,
+                                                   const double2* __restrict__ c, double2* x,
+                                                   int64_t n, double2* __restrict__ partial,
+                                                   unsigned* __restrict__ counter,
+                                                   double2* __restrict__ nrm2,
+                                                   double2* __restrict__ H, int ldh, int j,
+                                                   double* __restrict__ cs, double2* __restrict__ sn,
+                                                   double2* __restrict__ g, int* done,
+                                                   int* __restrict__ steps,
+                                                   const double* __restrict__ beta, double rtol) {
+  __shared__ double2 sh[4];
+  __shared__ bool last;
+  if (done && *done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double a2 = 0.0;
+  if (t < n) {
+    const double2 acc = cadd(lincomb(s0, m0, n, t, c, 1), lincomb(s1, m1, n, t, c + m0, 1));
+    const double2 xv = csub(x[t], acc);
+    x[t] = xv;
+    a2 = xv.x * xv.x + xv.y * xv.y;
+  }
+  const double2 bs = block_sum256(make_double2(a2, 0.0), sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double ps = 0.0;
+  for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += 256) ps += partial[bb].x;
+  const double2 tot = block_sum256(make_double2(ps, 0.0), sh);
+  if (threadIdx.x == 0) {
+    const double sm = tot.x;
+    *nrm2 = make_double2(sm, 0.0);
+    if (H) gmres_givens_body(H, ldh, j, sm, cs, sn, g, done, steps, beta, rtol);
+    *counter = 0u;
+  }
 }
 
 // g[0] = sqrt(*nrm2); done = (g[0] == 0); steps = 0.
@@ -644,15 +824,26 @@ void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int 
   const size_t lds = (size_t)nl * Ny * sizeof(double2);
   const dim3 blk(64 * nl);
   if (Ny <= 64)
-    hipLaunchKernelGGL(k_ilu_apply<1>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+    hipLaunchKernelGGL((k_ilu_apply<1, 4>), dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
   else if (Ny <= 128)
-    hipLaunchKernelGGL(k_ilu_apply<2>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+    hipLaunchKernelGGL((k_ilu_apply<2, 3>), dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
   else
-    hipLaunchKernelGGL(k_ilu_apply<4>, dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+    hipLaunchKernelGGL((k_ilu_apply<4, 2>), dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
+}
+
+// Chunk length for the tall-skinny reductions: at least 512 entries per
+// wavefront, at most 512 chunks (the partial buffer holds 512 x 256 values).
+void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
+                           int nblocks, const double2* Kinv, const int64_t* koff, const int* skip) {
+  const int nb = nl * Ny;
+  const size_t lds = (size_t)(nb + 256) * sizeof(double2);
+  hipLaunchKernelGGL(k_blockinv_apply, dim3((nb + 63) / 64, nblocks), dim3(256), lds, st, x, y, Ny, Nxi,
+                     nl, Kinv, koff, skip);
 }
 
 int dot_blocks(int64_t n, int* chunk) {
-  int c = 2048;
+  int c = 512;
+  while ((n + c - 1) / c > 128 && c < (1 << 20)) c *= 2;
   while ((n + c - 1) / c > 512) c *= 2;
   *chunk = c;
   return (int)((n + c - 1) / c);
@@ -663,8 +854,10 @@ void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, i
                  int mode, const double2* Hinv, double2* out2, const int* skip) {
   int chunk;
   const int nb = dot_blocks(n, &chunk);
-  hipLaunchKernelGGL(k_dotm, dim3(nb), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk, partial, counter,
-                     out, mode, Hinv, out2, skip);
+  const int mtot = m0 + m1 + (mode == 3 ? 1 : 0);
+  if (mtot == 0) return;
+  hipLaunchKernelGGL(k_dotm, dim3(nb, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk,
+                     partial, counter, out, mode, Hinv, out2, skip);
 }
 
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -686,6 +879,14 @@ void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, con
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum) {
   hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, are, aim, accum);
+}
+
+void launch_subm_norm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                      const double2* c, double2* x, int64_t n, double2* partial, unsigned* counter,
+                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                      int* done, int* steps, const double* beta, double rtol) {
+  hipLaunchKernelGGL(k_subm_norm, dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, n, partial,
+                     counter, nrm2, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
 }
 
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,

@@ -21,6 +21,8 @@ void launch_csr_spmv(hipStream_t st, const int64_t* rowptr, const int32_t* col, 
                      double tre, double tim, const int* skip);
 void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                       int nblocks, const double2* Fc, const double2* C, const int* skip);
+void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
+                           int nblocks, const double2* Kinv, const int64_t* koff, const int* skip);
 int dot_blocks(int64_t n, int* chunk);
 // mode 0: out = S^H x; 1: out += S^H x; 2: out = Hinv (S^H x); 3: out = S^H x and out[m] = ||x||^2.
 // out2 (optional) += S^H x.
@@ -35,6 +37,12 @@ void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, con
                         const int* skip);
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum);
+// x -= S c and *nrm2 = ||x||^2; with H != nullptr also the GMRES Givens update
+// of column j (skipped entirely when *done).  n / 256 <= 512 * 256 blocks.
+void launch_subm_norm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                      const double2* c, double2* x, int64_t n, double2* partial, unsigned* counter,
+                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                      int* done, int* steps, const double* beta, double rtol);
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
                        double* beta);
 void launch_gmres_givens(hipStream_t st, double2* H, int ldh, int j, const double2* nrm2, double* cs,
