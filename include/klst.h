@@ -175,6 +175,56 @@ klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* la
 /* Statistics of the last solve. */
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);
 
+/* ---------------------------------------------------------------------------
+ * Served / batched stability sweeps: many independent solves (different grids,
+ * wavenumbers, Mach numbers, base flows) sharing one GPU.  A server owns `slots`
+ * contexts, each on its own stream and worker thread.  Requests are admitted in
+ * submission order as soon as a slot is free and their modelled HBM footprint
+ * (klst_footprint_bytes) fits under the budget, so requests that arrive while
+ * others run overlap with them on the device (continuous batching).  Every
+ * request runs alone on its context with deterministic kernels: its result is the
+ * same whether it ran alone or in a mix.
+ * ------------------------------------------------------------------------- */
+typedef struct klst_server klst_server;
+
+/* Device bytes one solve of this shape allocates with these options (tables,
+ * preconditioner, workspace); the admission model. 0 for invalid sizes. */
+size_t      klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_options* opt);
+
+/* Start a server: `slots` concurrent solves (1..64) on opt->device, admitting
+ * requests while their summed footprints stay <= hbm_budget_bytes (0: 80% of the
+ * free device memory).  want_vectors = 0 keeps only eigenvalues and residuals.
+ * opt->stream is ignored (each slot creates its own default-priority stream).
+ * Errors: EINVAL, EDEVICE, ENOMEM. */
+klst_status klst_server_create(klst_server** out, const klst_options* opt, int slots,
+                               size_t hbm_budget_bytes, int want_vectors);
+/* Cancels everything queued or running, joins the workers, frees the device. */
+void        klst_server_destroy(klst_server* sv);
+
+/* Queue one solve (inputs are copied; the caller keeps ownership).  Returns a
+ * ticket.  Errors: EINVAL (bad input, as klst_assemble / klst_solve), ENOMEM
+ * (footprint larger than the whole budget), EBUSY (queue full). */
+klst_status klst_submit(klst_server* sv, const klst_grid* grid, const klst_vel* vel,
+                        const klst_base* base, double beta, const double sigma[2], int nev,
+                        uint64_t* ticket);
+/* state: 0 queued, 1 running, 2 done (OK or ENOCONV), 3 failed, 4 cancelled. */
+klst_status klst_poll(klst_server* sv, uint64_t ticket, int* state);
+/* Block until the request is finished (timeout_s < 0: no limit); EBUSY on timeout. */
+klst_status klst_wait(klst_server* sv, uint64_t ticket, double timeout_s);
+/* Ask a queued or running request to stop; a running solve stops at its next
+ * outer iteration and finishes with ECANCELLED. */
+klst_status klst_cancel(klst_server* sv, uint64_t ticket);
+/* Copy out the results of a finished request and forget it.  lambda [2*nev],
+ * X [nev*n] complex host (if vectors were kept), resid [nev], timing[3] =
+ * {queueing s, service s, latency s = completion - submission}.  Any output may be
+ * NULL.  Returns the request's own status (OK, ENOCONV, ECANCELLED, ...), or EBUSY
+ * if it has not finished. */
+klst_status klst_fetch(klst_server* sv, uint64_t ticket, double* lambda, void* X, double* resid,
+                       int* nconv, double timing[3], klst_stats* stats);
+/* Peak number of concurrently running solves, peak admitted footprint, budget. */
+klst_status klst_server_stats(klst_server* sv, int* peak_running, size_t* peak_bytes,
+                              size_t* budget);
+
 /* Host-only (no device needed): the tables klst_assemble builds, for testing
  * against an independent implementation.  Dx [Ny*Ny] row-major, nu [Ny],
  * U [Ny][2][r][Nxi] (coupling columns: G_a on g rows, H_a on h rows), M

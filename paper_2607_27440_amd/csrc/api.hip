@@ -9,11 +9,18 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "host.hpp"
@@ -30,8 +37,8 @@ struct klst_ctx {
   bool assembled = false;
   klst::Problem prob;
   // device tables
-  double *d_Dx = nullptr, *d_xix = nullptr, *d_xiy = nullptr, *d_nu = nullptr, *d_U = nullptr,
-         *d_M = nullptr;
+  double *d_Dx = nullptr, *d_DxT = nullptr, *d_xix = nullptr, *d_xiy = nullptr, *d_nu = nullptr,
+         *d_U = nullptr, *d_M = nullptr;
   double2* d_mom = nullptr;
   int mom_cap = 0;   // vectors
   // explicit CSR
@@ -46,10 +53,17 @@ struct klst_ctx {
   bool pc_ready = false;
   cd pc_sigma = 0.0;
   int pc_lines = 0;
+  // FP32 copies for the mixed-precision inner solve
+  float *d_Dx32 = nullptr, *d_DxT32 = nullptr, *d_xix32 = nullptr, *d_xiy32 = nullptr, *d_nu32 = nullptr,
+        *d_U32 = nullptr, *d_M32 = nullptr;
+  float2* d_mom32 = nullptr;
+  float2* d_Kinv32 = nullptr;
   // reductions
   double2* d_partial = nullptr;
+  double2* d_npart = nullptr;     // per-workgroup norm partials (<= 2^16 workgroups)
   unsigned* d_counter = nullptr;
   klst_stats stats{};
+  const volatile int* cancel = nullptr;   // set by the server: stop the current solve
 };
 
 namespace {
@@ -68,16 +82,19 @@ klst_status fail(klst_ctx* ctx, klst_status s, const std::string& msg) {
   return s;
 }
 
+// Device memory is stream-ordered (hipMallocAsync / hipFreeAsync on the
+// context's stream), so a context freeing its buffers never synchronises the
+// device under other contexts working concurrently (served mode).
 template <class T>
-void dfree(T*& p) {
-  if (p) hipFree(p);
+void dfree(klst_ctx* ctx, T*& p) {
+  if (p) (void)hipFreeAsync((void*)p, ctx->stream);
   p = nullptr;
 }
 
 klst_status dalloc(klst_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
-  const hipError_t e = hipMalloc(p, bytes);
+  const hipError_t e = hipMallocAsync(p, bytes, ctx->stream);
   if (e != hipSuccess) {
     *p = nullptr;
     ctx->err = "hipMalloc(" + std::to_string(bytes) + " bytes) failed: " + hipGetErrorString(e);
@@ -94,9 +111,11 @@ klst_status dalloc(klst_ctx* ctx, void** p, size_t bytes) {
   } while (0)
 
 void free_problem(klst_ctx* ctx) {
-  dfree(ctx->d_Dx); dfree(ctx->d_xix); dfree(ctx->d_xiy); dfree(ctx->d_nu); dfree(ctx->d_U);
-  dfree(ctx->d_M); dfree(ctx->d_mom); dfree(ctx->d_rowptr); dfree(ctx->d_col); dfree(ctx->d_val);
-  dfree(ctx->d_F); dfree(ctx->d_C); dfree(ctx->d_Kinv); dfree(ctx->d_koff);
+  dfree(ctx, ctx->d_Dx); dfree(ctx, ctx->d_DxT); dfree(ctx, ctx->d_xix); dfree(ctx, ctx->d_xiy); dfree(ctx, ctx->d_nu); dfree(ctx, ctx->d_U);
+  dfree(ctx, ctx->d_M); dfree(ctx, ctx->d_mom); dfree(ctx, ctx->d_rowptr); dfree(ctx, ctx->d_col); dfree(ctx, ctx->d_val);
+  dfree(ctx, ctx->d_F); dfree(ctx, ctx->d_C); dfree(ctx, ctx->d_Kinv); dfree(ctx, ctx->d_koff);
+  dfree(ctx, ctx->d_Dx32); dfree(ctx, ctx->d_DxT32); dfree(ctx, ctx->d_xix32); dfree(ctx, ctx->d_xiy32); dfree(ctx, ctx->d_nu32); dfree(ctx, ctx->d_U32);
+  dfree(ctx, ctx->d_M32); dfree(ctx, ctx->d_mom32); dfree(ctx, ctx->d_Kinv32);
   ctx->mom_cap = 0;
   ctx->pc_ready = false;
   ctx->assembled = false;
@@ -104,8 +123,8 @@ void free_problem(klst_ctx* ctx) {
 
 klst_status ensure_mom(klst_ctx* ctx, int nvec) {
   if (ctx->mom_cap >= nvec) return KLST_OK;
-  dfree(ctx->d_mom);
-  ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec);
+  dfree(ctx, ctx->d_mom);
+  ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 8);
   ctx->mom_cap = nvec;
   return KLST_OK;
 }
@@ -119,7 +138,7 @@ klst_status ensure_csr(klst_ctx* ctx) {
   ALLOC(ctx->d_col, sizeof(int32_t) * nnz);
   const klst_status s = dalloc(ctx, (void**)&ctx->d_val, sizeof(double2) * nnz);
   if (s != KLST_OK) {
-    dfree(ctx->d_rowptr); dfree(ctx->d_col);
+    dfree(ctx, ctx->d_rowptr); dfree(ctx, ctx->d_col);
     return s;
   }
   int npos = 0, nneg = 0;
@@ -148,7 +167,7 @@ klst_status op_apply(klst_ctx* ctx, cd tau, const double2* x, double2* y, int nv
     klst::dev::launch_moments(ctx->stream, x, p.n(), nvec, p.Ny, p.Nxi, p.r, ctx->d_M, ctx->d_mom,
                               skip);
     klst::dev::launch_apply(ctx->stream, x, y, p.n(), nvec, p.Ny, p.Nxi, p.r, tau.real(), tau.imag(),
-                            p.beta, ctx->d_Dx, ctx->d_xix, ctx->d_xiy, ctx->d_nu, ctx->d_U,
+                            p.beta, ctx->d_DxT, ctx->d_xix, ctx->d_xiy, ctx->d_nu, ctx->d_U,
                             ctx->d_mom, skip);
   }
   HIPCHK(hipGetLastError());
@@ -166,8 +185,8 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
   const unsigned hw = std::thread::hardware_concurrency();
   const int nth = (int)std::max(1u, std::min(hw, 16u));
   klst::build_ilu0(p, sigma, lines, ctx->ilu, nth);
-  dfree(ctx->d_Kinv);
-  dfree(ctx->d_koff);
+  dfree(ctx, ctx->d_Kinv);
+  dfree(ctx, ctx->d_koff);
   if (pk == 1) {
     std::vector<cd> Kinv;
     std::vector<int64_t> koff;
@@ -179,6 +198,16 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
     HIPCHK(hipMemcpyAsync(ctx->d_koff, koff.data(), sizeof(int64_t) * koff.size(), hipMemcpyHostToDevice,
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    dfree(ctx, ctx->d_Kinv32);
+    if (ctx->opt.precision == 1) {
+      std::vector<float2> K32(Kinv.size());
+      for (size_t i = 0; i < Kinv.size(); ++i)
+        K32[i] = make_float2((float)Kinv[i].real(), (float)Kinv[i].imag());
+      ALLOC(ctx->d_Kinv32, sizeof(float2) * K32.size());
+      HIPCHK(hipMemcpyAsync(ctx->d_Kinv32, K32.data(), sizeof(float2) * K32.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
   }
   // F column-major per line for the device sweeps
   const int Ny = p.Ny;
@@ -191,8 +220,8 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
     // the device sweeps multiply by the reciprocal pivot
     for (int j = 0; j < Ny; ++j) Fo[(size_t)j * Ny + j] = 1.0 / Fr[(size_t)j * Ny + j];
   }
-  dfree(ctx->d_F);
-  dfree(ctx->d_C);
+  dfree(ctx, ctx->d_F);
+  dfree(ctx, ctx->d_C);
   ALLOC(ctx->d_F, sizeof(double2) * Fc.size());
   ALLOC(ctx->d_C, sizeof(double2) * std::max<size_t>(1, ctx->ilu.C.size()));
   HIPCHK(hipMemcpyAsync(ctx->d_F, Fc.data(), sizeof(double2) * Fc.size(), hipMemcpyHostToDevice,
@@ -218,6 +247,59 @@ klst_status pc_apply(klst_ctx* ctx, const double2* x, double2* y, const int* ski
                                 ctx->d_C, skip);
   HIPCHK(hipGetLastError());
   ctx->stats.pc_applies += 1;
+  return KLST_OK;
+}
+
+// Precision-generic operator / preconditioner for the GMRES correction solve.
+klst_status op_v(klst_ctx* ctx, cd tau, const double2* x, double2* y, const int* skip) {
+  return op_apply(ctx, tau, x, y, 1, ctx->opt.op_mode, skip);
+}
+klst_status op_v(klst_ctx* ctx, cd tau, const float2* x, float2* y, const int* skip) {
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_moments(ctx->stream, x, p.n(), 1, p.Ny, p.Nxi, p.r, ctx->d_M32, ctx->d_mom32, skip);
+  klst::dev::launch_apply(ctx->stream, x, y, p.n(), 1, p.Ny, p.Nxi, p.r, tau.real(), tau.imag(), p.beta,
+                          ctx->d_DxT32, ctx->d_xix32, ctx->d_xiy32, ctx->d_nu32, ctx->d_U32, ctx->d_mom32,
+                          skip);
+  HIPCHK(hipGetLastError());
+  ctx->stats.op_applies += 1;
+  return KLST_OK;
+}
+klst_status pc_v(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
+  return pc_apply(ctx, x, y, skip);
+}
+klst_status pc_v(klst_ctx* ctx, const float2* x, float2* y, const int* skip) {
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
+                                   ctx->d_Kinv32, ctx->d_koff, skip);
+  HIPCHK(hipGetLastError());
+  ctx->stats.pc_applies += 1;
+  return KLST_OK;
+}
+
+// FP32 copies of the operator tables (mixed precision).
+klst_status upload_fp32_tables(klst_ctx* ctx) {
+  const klst::Problem& q = ctx->prob;
+  auto up = [&](float*& d, const std::vector<double>& h) -> klst_status {
+    std::vector<float> f(h.begin(), h.end());
+    ALLOC(d, sizeof(float) * std::max<size_t>(1, f.size()));
+    HIPCHK(hipMemcpyAsync(d, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return KLST_OK;
+  };
+  klst_status s;
+  if ((s = up(ctx->d_Dx32, q.Dx)) != KLST_OK) return s;
+  {
+    std::vector<double> DxT(q.Dx.size());
+    for (int j = 0; j < q.Ny; ++j)
+      for (int m = 0; m < q.Ny; ++m) DxT[(size_t)m * q.Ny + j] = q.Dx[(size_t)j * q.Ny + m];
+    if ((s = up(ctx->d_DxT32, DxT)) != KLST_OK) return s;
+  }
+  if ((s = up(ctx->d_xix32, q.xi_x)) != KLST_OK) return s;
+  if ((s = up(ctx->d_xiy32, q.xi_y)) != KLST_OK) return s;
+  if ((s = up(ctx->d_nu32, q.nu)) != KLST_OK) return s;
+  if ((s = up(ctx->d_U32, q.U)) != KLST_OK) return s;
+  if ((s = up(ctx->d_M32, q.M)) != KLST_OK) return s;
+  ALLOC(ctx->d_mom32, sizeof(float2) * (size_t)q.Ny * q.r * 8);
   return KLST_OK;
 }
 
@@ -293,7 +375,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
-      (o.pc_kernel != 0 && o.pc_kernel != 1))
+      (o.pc_kernel != 0 && o.pc_kernel != 1) || (o.precision == 1 && o.pc_kernel != 1))
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -308,6 +390,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   ctx->stream = (hipStream_t)o.stream;
   ctx->own_stream = false;
   if (dalloc(ctx, (void**)&ctx->d_partial, sizeof(double2) * 512 * 256) != KLST_OK ||
+      dalloc(ctx, (void**)&ctx->d_npart, sizeof(double2) * 65536) != KLST_OK ||
       dalloc(ctx, (void**)&ctx->d_counter, sizeof(unsigned) * 4) != KLST_OK) {
     klst_destroy(ctx);
     return KLST_ENOMEM;
@@ -326,8 +409,10 @@ void klst_destroy(klst_ctx* ctx) {
   hipSetDevice(ctx->opt.device);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   free_problem(ctx);
-  dfree(ctx->d_partial);
-  dfree(ctx->d_counter);
+  dfree(ctx, ctx->d_partial);
+  dfree(ctx, ctx->d_npart);
+  dfree(ctx, ctx->d_counter);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
   if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -369,6 +454,11 @@ klst_status klst_assemble(klst_ctx* ctx, const klst_grid* grid, const klst_vel* 
   ctx->prob = std::move(p);
   const klst::Problem& q = ctx->prob;
   ALLOC(ctx->d_Dx, sizeof(double) * q.Dx.size());
+  ALLOC(ctx->d_DxT, sizeof(double) * q.Dx.size());
+  std::vector<double> DxT(q.Dx.size());
+  for (int j = 0; j < q.Ny; ++j)
+    for (int m = 0; m < q.Ny; ++m) DxT[(size_t)m * q.Ny + j] = q.Dx[(size_t)j * q.Ny + m];
+  HIPCHK(hipMemcpyAsync(ctx->d_DxT, DxT.data(), sizeof(double) * DxT.size(), hipMemcpyHostToDevice, ctx->stream));
   ALLOC(ctx->d_xix, sizeof(double) * q.Nxi);
   ALLOC(ctx->d_xiy, sizeof(double) * q.Nxi);
   ALLOC(ctx->d_nu, sizeof(double) * q.Ny);
@@ -382,6 +472,7 @@ klst_status klst_assemble(klst_ctx* ctx, const klst_grid* grid, const klst_vel* 
   HIPCHK(hipMemcpyAsync(ctx->d_M, q.M.data(), sizeof(double) * q.M.size(), hipMemcpyHostToDevice, ctx->stream));
   klst_status s = ensure_mom(ctx, 1);
   if (s != KLST_OK) return s;
+  if (ctx->opt.precision == 1 && (s = upload_fp32_tables(ctx)) != KLST_OK) return s;
   if (ctx->opt.op_mode == 1) {
     s = ensure_csr(ctx);
     if (s != KLST_OK) return s;
@@ -452,13 +543,19 @@ struct Workspace {
   int64_t n;
   std::vector<void*> ptrs;
   ~Workspace() {
-    for (void* p : ptrs) hipFree(p);
+    for (void* p : ptrs) (void)hipFreeAsync(p, ctx->stream);
   }
   double2* vec(int count) {
     void* p = nullptr;
     if (dalloc(ctx, &p, sizeof(double2) * (size_t)count * n) != KLST_OK) return nullptr;
     ptrs.push_back(p);
     return (double2*)p;
+  }
+  float2* vec32(int count) {
+    void* p = nullptr;
+    if (dalloc(ctx, &p, sizeof(float2) * (size_t)count * n) != KLST_OK) return nullptr;
+    ptrs.push_back(p);
+    return (float2*)p;
   }
   template <class T>
   T* small(size_t count) {
@@ -519,7 +616,22 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   double2* rv = ws.vec(1);
   double2* av = ws.vec(1);
   double2* bv = ws.vec(1);
-  const int SM = 4 * 128 + 64;
+  const bool mixed = (o.precision == 1);
+  double2* rho64 = mixed ? ws.vec(1) : nullptr;
+  // FP32 mirrors for the mixed-precision inner solve: Krylov basis, [Q u], [K^-1 Z, K^-1 z]
+  float2 *Gb32 = nullptr, *Q32 = nullptr, *Y32 = nullptr, *a32 = nullptr, *b32 = nullptr,
+         *d32 = nullptr;
+  if (mixed) {
+    Gb32 = ws.vec32(gm + 1);
+    Q32 = ws.vec32(nev + 1);
+    Y32 = ws.vec32(nev + 1);
+    a32 = ws.vec32(1);
+    b32 = ws.vec32(1);
+    d32 = ws.vec32(1);
+    if (!Gb32 || !Q32 || !Y32 || !a32 || !b32 || !d32 || !rho64) return KLST_ENOMEM;
+  }
+  std::vector<cd> HQY32;   // Q32^H Y32 of the locked vectors (mixed precision)
+  const int SM = 1024;   // small device results gathered for one host transfer
   double2* d_c = ws.small<double2>(SM);        // coefficients of Gram-Schmidt passes
   double2* d_c2 = ws.small<double2>(SM);
   double2* d_cw = ws.small<double2>(SM);
@@ -542,10 +654,15 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   unsigned* counter = ctx->d_counter;
   std::vector<double2> hsmall(SM);
 
+  double2* npart = ctx->d_npart;
+  if (n > 256LL * 65536) return fail(ctx, KLST_EINVAL, "problem too large for the norm partial table");
+  // small results of S^H x (mode as launch_dot_reduce) written to `out` on the device
   auto dot = [&](const double2* s0, int m0, const double2* s1, int m1, const double2* x, double2* out,
                  int mode, const double2* Hinv = nullptr, double2* out2 = nullptr,
                  const int* skip = nullptr) {
-    launch_dotm(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
+    if (m0 + m1 + (mode == 3 ? 1 : 0) == 0) return;
+    const int nch = launch_dot_partial(st, s0, m0, s1, m1, x, n, partial, mode == 3 ? 1 : 0, skip);
+    launch_dot_reduce(st, partial, m0 + m1, nch, out, mode, Hinv, out2, skip);
   };
   auto sub = [&](const double2* s0, int m0, const double2* s1, int m1, const double2* c, double2* x,
                  const int* skip = nullptr) { launch_subm(st, s0, m0, s1, m1, c, x, nullptr, n, 1.0, skip); };
@@ -559,15 +676,26 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     return KLST_OK;
   };
   // CGS2 of x against (s0: m0, s1: m1); coefficients summed into c (device), norm^2 into nrm.
+  auto dot32 = [&](const float2* s0, int m0, const float2* s1, int m1, const float2* x, double2* out,
+                   int mode, const double2* Hinv = nullptr) {
+    if (m0 + m1 + (mode == 3 ? 1 : 0) == 0) return;
+    const int nch = launch_dot_partial(st, s0, m0, s1, m1, x, n, partial, mode == 3 ? 1 : 0, nullptr);
+    launch_dot_reduce(st, partial, m0 + m1, nch, out, mode, Hinv, nullptr, nullptr);
+  };
+  // CGS2 of x against (s0: m0, s1: m1): coefficients summed into c (device),
+  // ||x||^2 into nrm, x / ||x|| into dst
   auto cgs2 = [&](const double2* s0, int m0, const double2* s1, int m1, double2* x, double2* c,
-                  double2* nrm) {
+                  double2* nrm, double2* dst) {
     if (m0 + m1 > 0) {
-      dot(s0, m0, s1, m1, x, c, 0);
-      sub(s0, m0, s1, m1, c, x);
-      dot(s0, m0, s1, m1, x, d_c2, 0, nullptr, c);
+      int nch = launch_dot_partial(st, s0, m0, s1, m1, x, n, partial, 0, nullptr);
+      launch_subm_fused(st, s0, m0, s1, m1, partial, nch, nullptr, c, nullptr, x, n, nullptr, nullptr);
+      nch = launch_dot_partial(st, s0, m0, s1, m1, x, n, partial, 0, nullptr);
+      launch_subm_fused(st, s0, m0, s1, m1, partial, nch, nullptr, nullptr, c, x, n, npart, nullptr);
+    } else {
+      launch_subm_fused(st, s0, 0, s1, 0, partial, 1, nullptr, nullptr, nullptr, x, n, npart, nullptr);
     }
-    launch_subm_norm(st, s0, m0, s1, m1, d_c2, x, n, partial, counter, nrm, nullptr, 0, 0, nullptr,
-                     nullptr, nullptr, nullptr, nullptr, nullptr, 0.0);
+    launch_scale_norm(st, x, dst, n, npart, nrm, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr, 0.0);
   };
 
   // host mirrors of projected quantities
@@ -643,6 +771,7 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   klst_status status = KLST_OK;
   while (k < nev) {
     if (outer >= o.max_it) { status = KLST_ENOCONV; break; }
+    if (ctx->cancel && *ctx->cancel) { status = KLST_ECANCELLED; break; }
     ++outer;
     // ---- restart
     if (m >= m_max) {
@@ -656,11 +785,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     // ---- expansion: v = orth(t | Q, V); w = orth((A - sigma B) v | Z, W)
     double2* vnew = V + (size_t)m * n;
     double2* wnew = W + (size_t)m * n;
-    cgs2(Qb, k, V, m, tv, d_c, d_small + 0);
-    launch_scale_rsqrt(st, tv, vnew, n, d_small + 0, nullptr);
+    cgs2(Qb, k, V, m, tv, d_c, d_small + 0, vnew);
     if ((s = op_apply(ctx, sigma, vnew, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
-    cgs2(Zb, k, W, m, av, d_cw, d_small + 1);
-    launch_scale_rsqrt(st, av, wnew, n, d_small + 1, nullptr);
+    cgs2(Zb, k, W, m, av, d_cw, d_small + 1, wnew);
     // small results gathered for one transfer: [0] |v|^2, [1] |w|^2, [3] GMRES steps,
     // [4..] M_B column W^H v_new (m + 1), [132..] V^H w_new (m), [260..] Z,W coefficients
     dot(W, m + 1, nullptr, 0, vnew, d_small + 4, 0);
@@ -721,7 +848,21 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       dot(Zb, k + 1, nullptr, 0, bv, d_small + 128, 0);          // S_B column
       dot(Qb, k + 1, nullptr, 0, Yb + (size_t)k * n, d_small + 256, 0);   // Q^H y_new
       dot(Yb, k, nullptr, 0, Qb + (size_t)k * n, d_small + 384, 0);       // Y^H q_new
-      if ((s = fetch(384 + k)) != KLST_OK) return s;
+      if (mixed) {   // FP32 mirrors of the new locked pair for the inner solve
+        launch_narrow(st, uv, Q32 + (size_t)k * n, n);
+        launch_narrow(st, zv, a32, n);
+        if ((s = pc_v(ctx, a32, Y32 + (size_t)k * n, nullptr)) != KLST_OK) return s;
+        dot32(Q32, k + 1, nullptr, 0, Y32 + (size_t)k * n, d_small + 400, 0);
+        if (k > 0)
+          dot32(Y32, k, nullptr, 0, Q32 + (size_t)k * n, d_small + 500, 0);
+      }
+      if ((s = fetch(mixed ? 500 + k : 384 + k)) != KLST_OK) return s;
+      if (mixed) {
+        resize_sq(HQY32, k, k + 1);
+        for (int i = 0; i <= k; ++i) HQY32[(size_t)i * (k + 1) + k] = cd(hsmall[400 + i].x, hsmall[400 + i].y);
+        for (int i = 0; i < k; ++i)
+          HQY32[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[500 + i].x, hsmall[500 + i].y));
+      }
       resize_sq(SA, k, k + 1);
       resize_sq(SB, k, k + 1);
       resize_sq(HQY, k, k + 1);
@@ -752,50 +893,126 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       continue;
     }
     // ---- correction equation
-    // Qt = [Q, u], Zt = [Z, z], Yt = [Y, K^{-1} z], Ht = Qt^H Yt
-    double2* ynew = Yb + (size_t)k * n;
-    if ((s = pc_apply(ctx, zv, ynew, nullptr)) != KLST_OK) return s;
-    dot(Qb, k, uv, 1, ynew, d_small + 0, 0);                  // Qt^H y_new  (k + 1)
-    if (k > 0) dot(Yb, k, nullptr, 0, uv, d_small + 128, 0);  // Y^H u (k)
-    if ((s = fetch(128 + k)) != KLST_OK) return s;
-    {
+    // (I - Zt Zt^H)(A - shift B)(I - Qt Qt^H) t = -r, t _|_ Qt, Qt = [Q u], Zt = [Z z],
+    // left-preconditioned with K and the oblique projection I - Yt Ht^{-1} Qt^H,
+    // Yt = K^{-1} Zt, Ht = Qt^H Yt (Fokkema-Sleijpen-van der Vorst 1998).
+    const cd shift = (rel <= o.fix) ? theta : sigma;
+    // GMRES on the device for the projected preconditioned operator; vectors in the
+    // precision of V (double2 or float2); rhs in `a` (consumed), result to `tout`.
+    auto gmres = [&](auto* Gbp, auto* a, auto* bw, auto* Qt0, auto* ut, auto* Yt0, int kq, int budget,
+                     auto* tout) -> klst_status {
+      using V = std::remove_pointer_t<decltype(Gbp)>;
+      klst_status s2;
+      {
+        const int nch = launch_dot_partial(st, (const V*)nullptr, 0, (const V*)nullptr, 0, a, n, partial, 1,
+                                           nullptr);
+        launch_dot_reduce(st, partial, 0, nch, d_small, 3, nullptr, nullptr, nullptr);
+      }
+      launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta);
+      launch_scale_rsqrt(st, a, Gbp, n, d_small, d_done);
+      for (int j = 0; j < budget; ++j) {
+        V* gj = Gbp + (size_t)j * n;
+        V* gj1 = Gbp + (size_t)(j + 1) * n;
+        if ((s2 = op_v(ctx, shift, gj, bw, d_done)) != KLST_OK) return s2;
+        if ((s2 = pc_v(ctx, bw, gj1, d_done)) != KLST_OK) return s2;
+        // oblique projection: gj1 -= Yt Ht^{-1} Qt^H gj1
+        int nch = launch_dot_partial(st, Qt0, kq, ut, 1, gj1, n, partial, 0, d_done);
+        launch_subm_fused(st, Yt0, kq + 1, (const V*)nullptr, 0, partial, nch, d_Hinv, nullptr, nullptr,
+                          gj1, n, nullptr, d_done);
+        // CGS2 against the Krylov basis, coefficients into Hessenberg column j
+        double2* hcol = d_H + (size_t)j * (gm + 1);
+        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 0, d_done);
+        launch_subm_fused(st, Gbp, j + 1, (const V*)nullptr, 0, partial, nch, nullptr, hcol, nullptr, gj1, n,
+                          nullptr, d_done);
+        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 0, d_done);
+        launch_subm_fused(st, Gbp, j + 1, (const V*)nullptr, 0, partial, nch, nullptr, nullptr, hcol, gj1, n,
+                          npart, d_done);
+        // h[j+1] = ||gj1||, Givens update, gj1 /= ||gj1||
+        launch_scale_norm(st, gj1, (V*)nullptr, n, npart, d_small + 2, d_H, gm + 1, j, d_cs, d_sn, d_g,
+                          d_done, d_steps, d_beta, o.inner_rtol);
+      }
+      launch_gmres_solve(st, d_H, gm + 1, d_g, d_steps, d_yk);
+      launch_combine(st, Gbp, budget, n, d_yk, 1, 1, tout, d_steps);
+      HIPCHK(hipGetLastError());
+      return KLST_OK;
+    };
+    auto set_hinv = [&](const std::vector<cd>& HQ, const double2* col, const double2* row) -> klst_status {
       const int kt = k + 1;
       std::vector<cd> Ht((size_t)kt * kt), Hi((size_t)kt * kt);
       for (int i = 0; i < k; ++i)
-        for (int j = 0; j < k; ++j) Ht[(size_t)i * kt + j] = HQY[(size_t)i * k + j];
-      for (int i = 0; i < kt; ++i) Ht[(size_t)i * kt + k] = cd(hsmall[i].x, hsmall[i].y);
-      for (int j = 0; j < k; ++j) Ht[(size_t)k * kt + j] = std::conj(cd(hsmall[128 + j].x, hsmall[128 + j].y));
+        for (int j = 0; j < k; ++j) Ht[(size_t)i * kt + j] = HQ[(size_t)i * k + j];
+      for (int i = 0; i < kt; ++i) Ht[(size_t)i * kt + k] = cd(col[i].x, col[i].y);
+      for (int j = 0; j < k; ++j) Ht[(size_t)k * kt + j] = std::conj(cd(row[j].x, row[j].y));
       if (!klst::invert(kt, Ht.data(), Hi.data()))
         return fail(ctx, KLST_ENOCONV, "singular projected preconditioner (Q^H K^-1 Z)");
-      if ((s = upload(d_Hinv, Hi)) != KLST_OK) return s;
+      return upload(d_Hinv, Hi);
+    };
+    if (!mixed) {
+      double2* ynew = Yb + (size_t)k * n;
+      if ((s = pc_apply(ctx, zv, ynew, nullptr)) != KLST_OK) return s;
+      dot(Qb, k, uv, 1, ynew, d_small + 0, 0);                  // Qt^H y_new  (k + 1)
+      if (k > 0) dot(Yb, k, nullptr, 0, uv, d_small + 128, 0);  // Y^H u (k)
+      if ((s = fetch(128 + k)) != KLST_OK) return s;
+      if ((s = set_hinv(HQY, hsmall.data(), hsmall.data() + 128)) != KLST_OK) return s;
+      // rhs = -(I - Yt Ht^{-1} Qt^H) K^{-1} r
+      if ((s = pc_apply(ctx, rv, av, nullptr)) != KLST_OK) return s;
+      dot(Qb, k, uv, 1, av, d_c, 2, d_Hinv);
+      sub(Yb, k + 1, nullptr, 0, d_c, av);
+      launch_axpby(st, av, av, n, -1.0, 0.0, 0);
+      if ((s = gmres(Gb, av, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k, gm, tv)) !=
+          KLST_OK)
+        return s;
+    } else {
+      // Mixed precision: FP64 iterative refinement of the correction equation around
+      // FP32 GMRES solves (FP32 operator, preconditioner, Krylov vectors, FP32
+      // accumulation); the residual of the correction equation stays FP64.
+      float2* u32 = Q32 + (size_t)k * n;
+      float2* ynew = Y32 + (size_t)k * n;
+      launch_narrow(st, uv, u32, n);
+      launch_narrow(st, zv, a32, n);
+      if ((s = pc_v(ctx, a32, ynew, nullptr)) != KLST_OK) return s;
+      dot32(Q32, k, u32, 1, ynew, d_small + 0, 0);
+      if (k > 0)
+        dot32(Y32, k, nullptr, 0, u32, d_small + 128, 0);
+      // r <- (I - z z^H) r  (r is already orthogonal to Z)
+      dot(zv, 1, nullptr, 0, rv, d_c, 0);
+      sub(zv, 1, nullptr, 0, d_c, rv);
+      dot(nullptr, 0, nullptr, 0, rv, d_small + 300, 3);
+      if ((s = fetch(301)) != KLST_OK) return s;
+      if ((s = set_hinv(HQY32, hsmall.data(), hsmall.data() + 128)) != KLST_OK) return s;
+      const double rnorm = std::sqrt(hsmall[300].x);
+      HIPCHK(hipMemsetAsync(tv, 0, sizeof(double2) * n, st));
+      launch_axpby(st, rv, rho64, n, -1.0, 0.0, 0);               // rho = -r
+      int used = 0;
+      for (int sweep = 0; sweep < 3 && used < gm; ++sweep) {
+        launch_narrow(st, rho64, a32, n);
+        if ((s = pc_v(ctx, a32, b32, nullptr)) != KLST_OK) return s;
+        dot32(Q32, k, u32, 1, b32, d_c, 2, d_Hinv);
+        launch_subm(st, Y32, k + 1, (const float2*)nullptr, 0, d_c, b32, (float2*)nullptr, n, 1.0, nullptr);
+        if ((s = gmres(Gb32, b32, a32, (const float2*)Q32, (const float2*)u32, (const float2*)Y32, k,
+                       gm - used, d32)) != KLST_OK)
+          return s;
+        launch_widen(st, d32, tv, n, 1);                          // t += delta
+        int stp = 0;
+        HIPCHK(hipMemcpyAsync(&stp, d_steps, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        used += std::max(stp, 1);
+        if (used >= gm || sweep == 2) break;
+        // FP64 residual of the correction equation: rho = -r - Zt-proj (A - shift B) Qt-proj t
+        HIPCHK(hipMemcpyAsync(av, tv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+        dot(Qb, k, uv, 1, av, d_c, 0);
+        sub(Qb, k, uv, 1, d_c, av);
+        if ((s = op_apply(ctx, shift, av, bv, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+        dot(Zb, k, zv, 1, bv, d_c, 0);
+        sub(Zb, k, zv, 1, d_c, bv);
+        launch_axpby(st, rv, rho64, n, -1.0, 0.0, 0);
+        launch_axpby(st, bv, rho64, n, -1.0, 0.0, 1);
+        dot(nullptr, 0, nullptr, 0, rho64, d_small, 3);
+        if ((s = fetch(1)) != KLST_OK) return s;
+        if (std::sqrt(hsmall[0].x) <= o.inner_rtol * rnorm) break;
+      }
+      launch_set_int(st, d_steps, used);
     }
-    const cd shift = (rel <= o.fix) ? theta : sigma;
-    // rhs = -(I - Yt Ht^{-1} Qt^H) K^{-1} r
-    if ((s = pc_apply(ctx, rv, av, nullptr)) != KLST_OK) return s;
-    dot(Qb, k, uv, 1, av, d_c, 2, d_Hinv);
-    sub(Yb, k + 1, nullptr, 0, d_c, av);
-    launch_axpby(st, av, av, n, -1.0, 0.0, 0);
-    dot(nullptr, 0, nullptr, 0, av, d_small, 3);
-    launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta);
-    launch_scale_rsqrt(st, av, Gb, n, d_small, d_done);
-    for (int j = 0; j < gm; ++j) {
-      double2* gj = Gb + (size_t)j * n;
-      double2* gj1 = Gb + (size_t)(j + 1) * n;
-      if ((s = op_apply(ctx, shift, gj, bv, 1, o.op_mode, d_done)) != KLST_OK) return s;
-      if ((s = pc_apply(ctx, bv, gj1, d_done)) != KLST_OK) return s;
-      dot(Qb, k, uv, 1, gj1, d_c, 2, d_Hinv, nullptr, d_done);
-      launch_subm(st, Yb, k + 1, nullptr, 0, d_c, gj1, nullptr, n, 1.0, d_done);
-      double2* hcol = d_H + (size_t)j * (gm + 1);
-      dot(Gb, j + 1, nullptr, 0, gj1, hcol, 0, nullptr, nullptr, d_done);
-      launch_subm(st, Gb, j + 1, nullptr, 0, hcol, gj1, nullptr, n, 1.0, d_done);
-      dot(Gb, j + 1, nullptr, 0, gj1, d_c2, 0, nullptr, hcol, d_done);
-      launch_subm_norm(st, Gb, j + 1, nullptr, 0, d_c2, gj1, n, partial, counter, d_small + 2, d_H,
-                       gm + 1, j, d_cs, d_sn, d_g, d_done, d_steps, d_beta, o.inner_rtol);
-      launch_scale_rsqrt(st, gj1, nullptr, n, d_small + 2, d_done);
-    }
-    launch_gmres_solve(st, d_H, gm + 1, d_g, d_steps, d_yk);
-    launch_combine(st, Gb, gm, n, d_yk, 1, 1, tv, d_steps);
-    HIPCHK(hipGetLastError());
   }
   HIPCHK(hipStreamSynchronize(st));
   {
@@ -872,4 +1089,317 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   ctx->stats.seconds_total =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   return status;
+}
+
+// ================================================================ server ===
+//
+// Continuous batching of independent solves (stability sweeps).  `slots`
+// workers each own a context on their own non-blocking stream, so admitted
+// solves overlap on the device and their host-side work overlaps on the CPU.
+// A request is admitted (FIFO) when a worker is free and its modelled HBM
+// footprint fits under the budget; it then runs assemble + solve and keeps
+// its results until fetched.  Each request runs alone on its context with
+// deterministic kernels, so its result does not depend on what else is running.
+
+namespace {
+
+struct Request {
+  uint64_t ticket = 0;
+  klst_grid grid{};
+  int Nxi = 0, Dv = 2;
+  std::vector<double> xi_x, xi_y, w, rho, u, T, g_c, h_c;
+  int mode = 0;
+  double s_visc = 0, nu_inf = 0, beta = 0, sigma[2] = {0, 0};
+  int nev = 0;
+  size_t footprint = 0;
+  std::atomic<int> state{0};   // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
+  volatile int cancel = 0;
+  klst_status status = KLST_OK;
+  std::string err;
+  std::vector<double> lambda, resid, X;
+  int nconv = 0;
+  klst_stats stats{};
+  double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct klst_server {
+  klst_options opt{};
+  int slots = 1;
+  size_t budget = 0, in_use = 0, peak_bytes = 0;
+  int running = 0, peak_running = 0;
+  int max_queue = 1 << 16;
+  int want_vectors = 1;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+  std::vector<std::thread> workers;
+  std::vector<klst_ctx*> ctxs;
+  std::vector<hipStream_t> streams;
+  bool stop = false;
+  uint64_t next = 1;
+};
+
+extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_options* opt) {
+  klst_options o;
+  if (opt) o = *opt; else klst_default_options(&o);
+  if (Ny < 1 || Nxi < 1 || nev < 1) return 0;
+  const size_t n = 2ull * Ny * Nxi, r = 4, cvec = 16 * n;
+  const int m_max = std::max(o.m_max, o.m_min + 2), gm = o.gmres_m;
+  const int nl = std::max(1, std::min(o.lines_per_block, 2 * Nxi));
+  const size_t nblocks = (2ull * Nxi + nl - 1) / nl;
+  size_t b = 0;
+  b += 8ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 8ull * Ny * 2 * r * Nxi + 16ull * Ny * r * 8;  // tables
+  b += 16ull * 2 * Nxi * Ny * Ny + 16ull * nblocks * nl * nl * Ny;                       // ILU factors
+  if (o.pc_kernel == 1) b += 16ull * nblocks * (size_t)(nl * Ny) * (nl * Ny) + 8 * (nblocks + 1);
+  if (o.precision == 1) {
+    b += 4ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 4ull * Ny * 2 * r * Nxi + 8ull * Ny * r * 8;
+    b += 8ull * nblocks * (size_t)(nl * Ny) * (nl * Ny);
+    b += 8ull * n * ((gm + 1) + 2 * (nev + 1) + 3) + cvec;
+  }
+  if (o.op_mode == 1) {
+    const size_t nnz = n * (Ny - 1 + 2ull * Nxi);
+    b += 20 * nnz + 8 * (n + 1);
+  }
+  b += cvec * (2ull * (m_max + 1) + 3ull * (nev + 1) + (gm + 1) + m_max + 6 + nev);     // JD workspace
+  b += 16ull * 512 * 256 + 16ull * (4 * 1024 + 2 * 128 * 128 + (gm + 1) * (gm + 3));    // reductions, small
+  return b;
+}
+
+namespace {
+
+void serve_one(klst_server* sv, klst_ctx* ctx, Request& r) {
+  klst_vel vel{r.Nxi, r.xi_x.data(), r.xi_y.data(), r.w.data(), r.Dv};
+  klst_base base{};
+  base.mode = r.mode;
+  base.s_visc = r.s_visc;
+  base.nu_inf = r.nu_inf;
+  if (r.mode == 0) { base.rho = r.rho.data(); base.u = r.u.data(); base.T = r.T.data(); }
+  else { base.g_c = r.g_c.data(); base.h_c = r.h_c.data(); }
+  ctx->cancel = &r.cancel;
+  klst_status st = klst_assemble(ctx, &r.grid, &vel, &base, r.beta);
+  if (st == KLST_OK) {
+    r.lambda.assign(2 * r.nev, 0.0);
+    r.resid.assign(r.nev, 0.0);
+    if (sv->want_vectors) r.X.assign((size_t)2 * r.nev * ctx->prob.n(), 0.0);
+    st = klst_solve(ctx, r.sigma, r.nev, r.lambda.data(), sv->want_vectors ? r.X.data() : nullptr, 0,
+                    r.resid.data(), &r.nconv);
+    r.stats = ctx->stats;
+  }
+  if (st != KLST_OK) r.err = ctx->err;
+  ctx->cancel = nullptr;
+  r.status = st;
+}
+
+void worker_main(klst_server* sv, int wi) {
+  klst_ctx* ctx = sv->ctxs[wi];
+  hipSetDevice(sv->opt.device);
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv.wait(lk, [&] {
+        return sv->stop ||
+               (!sv->queue.empty() && sv->in_use + sv->queue.front()->footprint <= sv->budget);
+      });
+      if (sv->stop) return;
+      r = sv->queue.front();
+      sv->queue.pop_front();
+      if (r->cancel) {
+        r->state = 4;
+        r->status = KLST_ECANCELLED;
+        r->t_done = now_s();
+        sv->done_cv.notify_all();
+        sv->cv.notify_all();
+        continue;
+      }
+      sv->in_use += r->footprint;
+      sv->running += 1;
+      sv->peak_bytes = std::max(sv->peak_bytes, sv->in_use);
+      sv->peak_running = std::max(sv->peak_running, sv->running);
+      r->t_start = now_s();
+      r->state = 1;
+    }
+    serve_one(sv, ctx, *r);
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->in_use -= r->footprint;
+      sv->running -= 1;
+      r->t_done = now_s();
+      r->state = (r->status == KLST_OK || r->status == KLST_ENOCONV) ? 2
+                 : (r->status == KLST_ECANCELLED ? 4 : 3);
+    }
+    sv->done_cv.notify_all();
+    sv->cv.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" klst_status klst_server_create(klst_server** out, const klst_options* opt, int slots,
+                                          size_t hbm_budget_bytes, int want_vectors) {
+  if (!out || slots < 1 || slots > 64) return KLST_EINVAL;
+  *out = nullptr;
+  klst_server* sv = new klst_server();
+  if (opt) sv->opt = *opt; else klst_default_options(&sv->opt);
+  sv->slots = slots;
+  sv->want_vectors = want_vectors ? 1 : 0;
+  if (hipSetDevice(sv->opt.device) != hipSuccess) { delete sv; return KLST_EDEVICE; }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) { delete sv; return KLST_EDEVICE; }
+  sv->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
+  for (int i = 0; i < slots; ++i) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { klst_server_destroy(sv); return KLST_EDEVICE; }
+    sv->streams.push_back(s);
+    klst_options o = sv->opt;
+    o.stream = s;
+    klst_ctx* c = nullptr;
+    const klst_status st = klst_create(&c, &o);
+    if (st != KLST_OK) { klst_server_destroy(sv); return st; }
+    sv->ctxs.push_back(c);
+  }
+  for (int i = 0; i < slots; ++i) sv->workers.emplace_back(worker_main, sv, i);
+  *out = sv;
+  return KLST_OK;
+}
+
+extern "C" void klst_server_destroy(klst_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stop = true;
+    for (auto& q : sv->queue) q->cancel = 1;
+    for (auto& kv : sv->all) kv.second->cancel = 1;
+  }
+  sv->cv.notify_all();
+  for (auto& t : sv->workers) t.join();
+  for (klst_ctx* c : sv->ctxs) klst_destroy(c);
+  for (hipStream_t s : sv->streams) hipStreamDestroy(s);
+  delete sv;
+}
+
+extern "C" klst_status klst_submit(klst_server* sv, const klst_grid* grid, const klst_vel* vel,
+                                   const klst_base* base, double beta, const double sigma[2], int nev,
+                                   uint64_t* ticket) {
+  if (!sv || !grid || !vel || !base || !sigma || !ticket || nev < 1) return KLST_EINVAL;
+  // validate the inputs once on the host (same checks as klst_assemble)
+  {
+    klst::Problem p;
+    if (!klst::build_problem(grid, vel, base, beta, p).empty()) return KLST_EINVAL;
+    if (nev > p.n() - p.n_bc) return KLST_EINVAL;
+  }
+  auto r = std::make_shared<Request>();
+  r->grid = *grid;
+  r->Nxi = vel->Nxi;
+  r->Dv = vel->Dv;
+  r->xi_x.assign(vel->xi_x, vel->xi_x + vel->Nxi);
+  r->xi_y.assign(vel->xi_y, vel->xi_y + vel->Nxi);
+  r->w.assign(vel->w, vel->w + vel->Nxi);
+  r->mode = base->mode;
+  if (base->mode == 0) {
+    r->rho.assign(base->rho, base->rho + grid->Ny);
+    r->u.assign(base->u, base->u + grid->Ny);
+    r->T.assign(base->T, base->T + grid->Ny);
+  } else {
+    r->g_c.assign(base->g_c, base->g_c + (size_t)grid->Ny * vel->Nxi);
+    r->h_c.assign(base->h_c, base->h_c + (size_t)grid->Ny * vel->Nxi);
+  }
+  r->s_visc = base->s_visc;
+  r->nu_inf = base->nu_inf;
+  r->beta = beta;
+  r->sigma[0] = sigma[0];
+  r->sigma[1] = sigma[1];
+  r->nev = nev;
+  r->footprint = klst_footprint_bytes(grid->Ny, vel->Nxi, nev, &sv->opt);
+  if (r->footprint > sv->budget) return KLST_ENOMEM;   // would never be admitted
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if ((int)sv->queue.size() >= sv->max_queue) return KLST_EBUSY;
+    r->ticket = sv->next++;
+    r->t_submit = now_s();
+    sv->queue.push_back(r);
+    sv->all[r->ticket] = r;
+    *ticket = r->ticket;
+  }
+  sv->cv.notify_all();
+  return KLST_OK;
+}
+
+extern "C" klst_status klst_poll(klst_server* sv, uint64_t ticket, int* state) {
+  if (!sv || !state) return KLST_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return KLST_EINVAL;
+  *state = it->second->state.load();
+  return KLST_OK;
+}
+
+extern "C" klst_status klst_wait(klst_server* sv, uint64_t ticket, double timeout_s) {
+  if (!sv) return KLST_EINVAL;
+  std::unique_lock<std::mutex> lk(sv->mu);
+  auto it = sv->all.find(ticket);
+  if (it == sv->all.end()) return KLST_EINVAL;
+  auto r = it->second;
+  auto pred = [&] { return r->state.load() >= 2; };
+  if (timeout_s < 0) sv->done_cv.wait(lk, pred);
+  else if (!sv->done_cv.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return KLST_EBUSY;
+  return KLST_OK;
+}
+
+extern "C" klst_status klst_cancel(klst_server* sv, uint64_t ticket) {
+  if (!sv) return KLST_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(ticket);
+    if (it == sv->all.end()) return KLST_EINVAL;
+    it->second->cancel = 1;
+  }
+  sv->cv.notify_all();
+  return KLST_OK;
+}
+
+extern "C" klst_status klst_fetch(klst_server* sv, uint64_t ticket, double* lambda, void* X,
+                                  double* resid, int* nconv, double timing[3], klst_stats* stats) {
+  if (!sv) return KLST_EINVAL;
+  std::shared_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->all.find(ticket);
+    if (it == sv->all.end()) return KLST_EINVAL;
+    r = it->second;
+    if (r->state.load() < 2) return KLST_EBUSY;
+    sv->all.erase(it);
+  }
+  const int k = r->nconv;
+  if (lambda && !r->lambda.empty()) std::memcpy(lambda, r->lambda.data(), sizeof(double) * 2 * k);
+  if (resid && !r->resid.empty()) std::memcpy(resid, r->resid.data(), sizeof(double) * k);
+  if (X && !r->X.empty()) {
+    const size_t nn = 2ull * r->grid.Ny * r->Nxi;
+    std::memcpy(X, r->X.data(), sizeof(double) * 2 * nn * k);
+  }
+  if (nconv) *nconv = k;
+  if (timing) {
+    timing[0] = r->t_start > 0 ? r->t_start - r->t_submit : 0.0;   // queueing
+    timing[1] = r->t_start > 0 ? r->t_done - r->t_start : 0.0;     // service
+    timing[2] = r->t_done - r->t_submit;                           // latency
+  }
+  if (stats) *stats = r->stats;
+  return r->status;
+}
+
+extern "C" klst_status klst_server_stats(klst_server* sv, int* peak_running, size_t* peak_bytes,
+                                         size_t* budget) {
+  if (!sv) return KLST_EINVAL;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (peak_running) *peak_running = sv->peak_running;
+  if (peak_bytes) *peak_bytes = sv->peak_bytes;
+  if (budget) *budget = sv->budget;
+  return KLST_OK;
 }

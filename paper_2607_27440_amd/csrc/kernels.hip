@@ -5,12 +5,27 @@
 // a fixed-order final sum done by the last workgroup to finish ("last block"
 // pattern with one global counter that the last block resets).
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.hpp"
 
 namespace klst {
 namespace dev {
+
+// complex vector type of a real type
+template <class R> struct cvec;
+template <> struct cvec<double> { using type = double2; };
+template <> struct cvec<float> { using type = float2; };
+template <class R> using cv = typename cvec<R>::type;
+
+template <class R> __device__ __forceinline__ cv<R> mk(R a, R b) { cv<R> v; v.x = a; v.y = b; return v; }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+template <class R> __device__ __forceinline__ cv<R> narrow(double2 c) { return mk<R>((R)c.x, (R)c.y); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -22,20 +37,22 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
-// sum_{i < m} S_i[t] c[coff + i] with the loads of eight vectors issued before
+// sum_{i < m} S_i[t] c[i * cstride] with the loads of eight vectors issued before
 // their products are accumulated (c indices are wave-uniform: scalar loads).
-__device__ __forceinline__ double2 lincomb(const double2* __restrict__ S, int m, int64_t n, int64_t t,
-                                           const double2* __restrict__ c, int cstride) {
-  double2 acc = make_double2(0.0, 0.0);
+// Vectors of real type R, coefficients in FP64 (narrowed to R), accumulation in R.
+template <class R>
+__device__ __forceinline__ cv<R> lincomb(const cv<R>* __restrict__ S, int m, int64_t n, int64_t t,
+                                         const double2* __restrict__ c, int cstride) {
+  cv<R> acc = mk<R>(0, 0);
   int i = 0;
   for (; i + 8 <= m; i += 8) {
-    double2 sv[8];
+    cv<R> sv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) sv[u] = S[(int64_t)(i + u) * n + t];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(sv[u], c[(int64_t)(i + u) * cstride]));
+    for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(sv[u], narrow<R>(c[(int64_t)(i + u) * cstride])));
   }
-  for (; i < m; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], c[(int64_t)i * cstride]));
+  for (; i < m; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], narrow<R>(c[(int64_t)i * cstride])));
   return acc;
 }
 
@@ -62,32 +79,48 @@ __device__ __forceinline__ double2 block_sum256(double2 v, double2* sh /*[4]*/) 
 // ------------------------------------------------------------ operator ----
 
 // Perturbation moments m_a(j) = sum_{f,p} M[j][a][f][p] x[j][f][p] (rank r <= 4)
-// for each node j and vector v.  grid (Ny, nvec), block 256.
-__global__ void __launch_bounds__(256) k_moments(const double2* __restrict__ x, int64_t n, int Ny,
-                                                 int Nxi, int r, const double* __restrict__ M,
-                                                 double2* __restrict__ mom, const int* __restrict__ skip) {
+// for each node j and vector v, split over S column parts: workgroup
+// (j * S + part, v) writes the partial sums of its part to mom[((v Ny + j) S +
+// part) r + a]; the operator kernels add the S parts in fixed order.
+template <class R>
+__global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, int64_t n, int Ny,
+                                                 int Nxi, int r, const R* __restrict__ M,
+                                                 cv<R>* __restrict__ mom, int S,
+                                                 const int* __restrict__ skip) {
   __shared__ double2 sh[4];
   if (skip && *skip) return;
-  const int j = blockIdx.x, v = blockIdx.y;
+  const int j = blockIdx.x / S, part = blockIdx.x - j * S, v = blockIdx.y;
   const int nc = 2 * Nxi;
-  const double2* xj = x + (int64_t)v * n + (int64_t)j * nc;
-  double2 acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  for (int c = threadIdx.x; c < nc; c += 256) {
-    const double2 xv = xj[c];
+  const int per = (nc + S - 1) / S;
+  const int cbeg = part * per, cend = min(nc, cbeg + per);
+  const cv<R>* xj = x + (int64_t)v * n + (int64_t)j * nc;
+  R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+  for (int c = cbeg + threadIdx.x; c < cend; c += 256) {
+    const cv<R> xv = xj[c];
     for (int a = 0; a < 4; ++a) {
       if (a < r) {
-        const double mw = M[((int64_t)j * r + a) * nc + c];
-        acc[a].x += mw * xv.x;
-        acc[a].y += mw * xv.y;
+        const R mw = M[((int64_t)j * r + a) * nc + c];
+        ar[a] += mw * xv.x;
+        ai[a] += mw * xv.y;
       }
     }
   }
   for (int a = 0; a < 4; ++a) {
     if (a < r) {
-      const double2 s = block_sum256(acc[a], sh);
-      if (threadIdx.x == 0) mom[((int64_t)v * Ny + j) * r + a] = s;
+      const double2 sres = block_sum256(make_double2((double)ar[a], (double)ai[a]), sh);
+      if (threadIdx.x == 0) mom[(((int64_t)v * Ny + j) * S + part) * r + a] = mk<R>((R)sres.x, (R)sres.y);
     }
   }
+}
+
+// m_a(j) of vector v from the S partial sums (fixed order).
+template <class R>
+__device__ __forceinline__ cv<R> mom_at(const cv<R>* __restrict__ mom, int64_t v, int Ny, int j, int a, int r,
+                                        int S) {
+  const cv<R>* p = mom + ((v * Ny + j) * S) * r + a;
+  cv<R> s = p[0];
+  for (int q = 1; q < S; ++q) s = cadd(s, p[(int64_t)q * r]);
+  return s;
 }
 
 // y = (A - tau B) x, matrix-free.  The streaming term is a real GEMM
@@ -96,65 +129,196 @@ __global__ void __launch_bounds__(256) k_moments(const double2* __restrict__ x, 
 // rows [row0, row1) of the tile.  Epilogue per entry: xi_x scaling, diagonal
 // (nu_j + i beta xi_y - tau), rank-r moment update, identity inflow rows.
 // grid (col tiles, row groups, nvec), block 256, dynamic LDS Ny * TC * 16 B.
-template <int TC>
-__global__ void __launch_bounds__(256) k_apply(const double2* __restrict__ x, double2* __restrict__ y,
-                                               int64_t n, int Ny, int Nxi, int r, double tau_re,
-                                               double tau_im, double beta,
-                                               const double* __restrict__ Dx,
-                                               const double* __restrict__ xi_x,
-                                               const double* __restrict__ xi_y,
-                                               const double* __restrict__ nu,
-                                               const double* __restrict__ U,
-                                               const double2* __restrict__ mom, int rows_per_group,
+template <class R, int RB>
+__global__ void __launch_bounds__(256) k_apply(const cv<R>* __restrict__ x, cv<R>* __restrict__ y,
+                                               int64_t n, int Ny, int Nxi, int r, R tau_re,
+                                               R tau_im, R beta,
+                                               const R* __restrict__ DxT,
+                                               const R* __restrict__ xi_x,
+                                               const R* __restrict__ xi_y,
+                                               const R* __restrict__ nu,
+                                               const R* __restrict__ U,
+                                               const cv<R>* __restrict__ mom, int S,
                                                const int* __restrict__ skip) {
-  extern __shared__ double2 xs[];   // [Ny][TC]
   if (skip && *skip) return;
   const int nc = 2 * Nxi;
-  const int c0 = blockIdx.x * TC;
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * RB;
   const int v = blockIdx.z;
-  const double2* xv = x + (int64_t)v * n;
-  double2* yv = y + (int64_t)v * n;
-  for (int idx = threadIdx.x; idx < Ny * TC; idx += 256) {
-    const int m = idx / TC, cc = idx % TC;
-    const int c = c0 + cc;
-    xs[idx] = (c < nc) ? xv[(int64_t)m * nc + c] : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int cc = threadIdx.x % TC;
-  const int c = c0 + cc;
   if (c >= nc) return;
+  const cv<R>* xv = x + (int64_t)v * n;
+  cv<R>* yv = y + (int64_t)v * n;
+  // streaming: acc[rr] = sum_m D_x[j0 + rr, m] X[m, c]; the D_x column slice is
+  // wave-uniform (scalar loads from the transposed table), X is read once per
+  // row group and reused for all RB rows from registers
+  R ar[RB], ai[RB];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) { ar[rr] = 0; ai[rr] = 0; }
+  const int jn = min(RB, Ny - j0);
+  int m = 0;
+  for (; m + 4 <= Ny; m += 4) {
+    cv<R> xm[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xm[u] = xv[(int64_t)(m + u) * nc + c];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const R* dcol = DxT + (int64_t)(m + u) * Ny + j0;
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) {
+        const R d = (rr < jn) ? dcol[rr] : (R)0;
+        ar[rr] = fma(d, xm[u].x, ar[rr]);
+        ai[rr] = fma(d, xm[u].y, ai[rr]);
+      }
+    }
+  }
+  for (; m < Ny; ++m) {
+    const cv<R> xm = xv[(int64_t)m * nc + c];
+    const R* dcol = DxT + (int64_t)m * Ny + j0;
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      const R d = (rr < jn) ? dcol[rr] : (R)0;
+      ar[rr] = fma(d, xm.x, ar[rr]);
+      ai[rr] = fma(d, xm.y, ai[rr]);
+    }
+  }
+  // epilogue: xi_x scaling, diagonal, rank-r moment update, identity inflow rows
   const int f = c / Nxi, k = c - f * Nxi;
-  const double xik = xi_x[k], bxy = beta * xi_y[k];
-  const int row0 = blockIdx.y * rows_per_group;
-  const int row1 = min(Ny, row0 + rows_per_group);
-  const double2* momv = mom + (int64_t)v * Ny * r;
-  for (int j = row0 + threadIdx.x / TC; j < row1; j += 256 / TC) {
-    const double2 xjc = xs[j * TC + cc];
-    const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
-    double2 out;
+  const R xik = xi_x[k], bxy = beta * xi_y[k];
+#pragma unroll
+  for (int rr = 0; rr < RB; ++rr) {
+    const int j = j0 + rr;
+    if (j >= Ny) break;
+    const cv<R> xjc = xv[(int64_t)j * nc + c];
+    const bool bc = (j == Ny - 1 && xik > 0) || (j == 0 && xik < 0);
+    cv<R> out;
     if (bc) {
       out = xjc;
     } else {
-      const double* drow = Dx + (int64_t)j * Ny;
-      double sr = 0.0, si = 0.0;
-      for (int m = 0; m < Ny; ++m) {
-        const double d = drow[m];
-        const double2 xm = xs[m * TC + cc];
-        sr = fma(d, xm.x, sr);
-        si = fma(d, xm.y, si);
-      }
-      const double dre = nu[j] - tau_re, dim = bxy - tau_im;
-      out.x = xik * sr + dre * xjc.x - dim * xjc.y;
-      out.y = xik * si + dre * xjc.y + dim * xjc.x;
-      const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+      const R dre = nu[j] - tau_re, dim = bxy - tau_im;
+      out.x = xik * ar[rr] + dre * xjc.x - dim * xjc.y;
+      out.y = xik * ai[rr] + dre * xjc.y + dim * xjc.x;
+      const R* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
       for (int a = 0; a < r; ++a) {
-        const double ua = Uj[(int64_t)a * Nxi];
-        const double2 ma = momv[j * r + a];
+        const R ua = Uj[(int64_t)a * Nxi];
+        const cv<R> ma = mom_at<R>(mom, v, Ny, j, a, r, S);
         out.x -= ua * ma.x;
         out.y -= ua * ma.y;
       }
     }
     yv[(int64_t)j * nc + c] = out;
+  }
+}
+
+// y = (A - tau B) x with the streaming GEMM on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64).  One wavefront per tile of 16 complex columns x RT*16
+// rows; the real and imaginary parts of X are two B operands sharing the D_x
+// fragment.  Operand layouts (gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, D[i][j] for lane l, register q at i = l/16 + 4q, j = l%16.
+// grid (ceil(2Nxi/16), ceil(ceil(Ny/16)/RT), nvec), block 64.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+// NW wavefronts per workgroup, each a column tile of 16; with NW > 1 the D_x^T
+// row slice of the workgroup is staged once in LDS and shared.  The moments of
+// the workgroup's rows are summed from their S parts once into LDS.
+template <int RT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restrict__ x,
+                                                        double2* __restrict__ y, int64_t n, int Ny,
+                                                        int Nxi, int r, double tau_re, double tau_im,
+                                                        double beta, const double* __restrict__ DxT,
+                                                        const double* __restrict__ xi_x,
+                                                        const double* __restrict__ xi_y,
+                                                        const double* __restrict__ nu,
+                                                        const double* __restrict__ U,
+                                                        const double2* __restrict__ mom, int S,
+                                                        const int* __restrict__ skip) {
+  extern __shared__ unsigned char lds_raw[];
+  double2* ms = reinterpret_cast<double2*>(lds_raw);                 // [RT*16][4] moments
+  double* As = reinterpret_cast<double*>(lds_raw + RT * 16 * 4 * sizeof(double2));  // [Ny4][RT*16]
+  if (skip && *skip) return;
+  const int nc = 2 * Nxi;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nrt = (Ny + 15) / 16;
+  const int rt0 = blockIdx.y * RT;
+  const int v = blockIdx.z;
+  const int W = RT * 16;
+  for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
+    const int jl = idx / r, a = idx - jl * r;
+    const int j = rt0 * 16 + jl;
+    double2 sm = make_double2(0.0, 0.0);
+    if (j < Ny) {
+      const double2* p = mom + (((int64_t)v * Ny + j) * S) * r + a;
+      for (int q = 0; q < S; ++q) sm = cadd(sm, p[(int64_t)q * r]);
+    }
+    ms[jl * 4 + a] = sm;
+  }
+  if (NW > 1) {
+    const int Ny4 = (Ny + 3) & ~3;
+    for (int idx = threadIdx.x; idx < Ny4 * W; idx += 64 * NW) {
+      const int m = idx / W, rl = idx - m * W;
+      const int row = rt0 * 16 + rl;
+      As[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int c0 = (blockIdx.x * NW + wv) * 16;
+  if (c0 >= nc) return;
+  const double2* xv = x + (int64_t)v * n;
+  double2* yv = y + (int64_t)v * n;
+  const int li = lane & 15, lk = lane >> 4;
+  const int cb = c0 + li;
+  dbl4 are[RT], aim[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
+  double2 xb = (lk < Ny && cb < nc) ? xv[(int64_t)lk * nc + cb] : make_double2(0.0, 0.0);
+  for (int m0 = 0; m0 < Ny; m0 += 4) {
+    const int m = m0 + lk;
+    const int mn = m + 4;
+    const double2 xn = (mn < Ny && cb < nc) ? xv[(int64_t)mn * nc + cb] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      double a;
+      if (NW > 1) {
+        a = As[m * W + t * 16 + li];
+      } else {
+        const int row = (rt0 + t) * 16 + li;
+        a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+      }
+      are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.x, are[t], 0, 0, 0);
+      aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.y, aim[t], 0, 0, 0);
+    }
+    xb = xn;
+  }
+  // epilogue on the accumulator layout: column c, rows j = tile*16 + lk + 4q
+  const int c = c0 + li;
+  if (c >= nc) return;
+  const int f = c / Nxi, k = c - f * Nxi;
+  const double xik = xi_x[k], bxy = beta * xi_y[k];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+    if (rt0 + t >= nrt) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jl = t * 16 + lk + 4 * q;
+      const int j = rt0 * 16 + jl;
+      if (j >= Ny) continue;
+      const double2 xjc = xv[(int64_t)j * nc + c];
+      const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
+      double2 out;
+      if (bc) {
+        out = xjc;
+      } else {
+        const double dre = nu[j] - tau_re, dim = bxy - tau_im;
+        out.x = xik * are[t][q] + dre * xjc.x - dim * xjc.y;
+        out.y = xik * aim[t][q] + dre * xjc.y + dim * xjc.x;
+        const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+        for (int a = 0; a < r; ++a) {
+          const double ua = Uj[(int64_t)a * Nxi];
+          const double2 ma = ms[jl * 4 + a];
+          out.x -= ua * ma.x;
+          out.y -= ua * ma.y;
+        }
+      }
+      yv[(int64_t)j * nc + c] = out;
+    }
   }
 }
 
@@ -451,12 +615,14 @@ __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ 
 // column-major over the block's rows in velocity-major order (line, node).
 // grid (row tiles of 64, blocks), block 256: the 4 wavefronts split the columns,
 // lanes own rows (coalesced column reads), partial sums meet in LDS.
-__global__ void __launch_bounds__(256) k_blockinv_apply(const double2* __restrict__ x,
-                                                        double2* __restrict__ y, int Ny, int Nxi,
-                                                        int nl, const double2* __restrict__ Kinv,
+template <class R>
+__global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict__ x,
+                                                        cv<R>* __restrict__ y, int Ny, int Nxi,
+                                                        int nl, const cv<R>* __restrict__ Kinv,
                                                         const int64_t* __restrict__ koff,
                                                         const int* __restrict__ skip) {
-  extern __shared__ double2 xsb[];   // [nb] block input, then [4][64] partials
+  extern __shared__ unsigned char lds_raw[];
+  cv<R>* xsb = reinterpret_cast<cv<R>*>(lds_raw);   // [nb] block input, then [4][64] partials
   if (skip && *skip) return;
   const int b = blockIdx.y;
   const int nlines = 2 * Nxi;
@@ -471,14 +637,14 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const double2* __restric
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = blockIdx.x * 64 + lane;
-  const double2* K = Kinv + koff[b];
-  double2 acc = make_double2(0.0, 0.0);
+  const cv<R>* K = Kinv + koff[b];
+  cv<R> acc = mk<R>(0, 0);
   if (row < nb) {
     const int cper = (nb + 3) / 4;
     const int cb = wv * cper, ce = min(nb, cb + cper);
     int c = cb;
     for (; c + 8 <= ce; c += 8) {
-      double2 kv[8];
+      cv<R> kv[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) kv[u] = K[(int64_t)(c + u) * nb + row];
 #pragma unroll
@@ -487,17 +653,17 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const double2* __restric
     for (; c < ce; ++c) acc = cadd(acc, cmul(K[(int64_t)c * nb + row], xsb[c]));
   }
   __syncthreads();
-  double2* part = xsb + nb;
+  cv<R>* part = xsb + nb;
   part[wv * 64 + lane] = acc;
   __syncthreads();
   if (wv == 0 && row < nb) {
-    double2 r = part[lane];
-    r = cadd(r, part[64 + lane]);
-    r = cadd(r, part[128 + lane]);
-    r = cadd(r, part[192 + lane]);
+    cv<R> rr = part[lane];
+    rr = cadd(rr, part[64 + lane]);
+    rr = cadd(rr, part[128 + lane]);
+    rr = cadd(rr, part[192 + lane]);
     const int lg = l0 + row / Ny, j = row % Ny;
     const int f = lg / Nxi, k = lg - f * Nxi;
-    y[((int64_t)2 * j + f) * Nxi + k] = r;
+    y[((int64_t)2 * j + f) * Nxi + k] = rr;
   }
 }
 
@@ -511,9 +677,10 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const double2* __restric
 // grid (nchunks, ceil(mtot / 4)), block 256 = 4 wavefronts.
 // mode: 0 out = c, 1 out += c, 2 out = Hinv * c (Hinv m x m row-major),
 //       3 out = c and out[m] = sum |x|^2.  out2 (optional) += c.
-__global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, int m0,
-                                              const double2* __restrict__ s1, int m1,
-                                              const double2* __restrict__ x, int64_t n, int chunk,
+template <class R>
+__global__ void __launch_bounds__(256) k_dotm(const cv<R>* __restrict__ s0, int m0,
+                                              const cv<R>* __restrict__ s1, int m1,
+                                              const cv<R>* __restrict__ x, int64_t n, int chunk,
                                               double2* __restrict__ partial,
                                               unsigned int* __restrict__ counter,
                                               double2* __restrict__ out, int mode,
@@ -531,11 +698,11 @@ __global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, in
   if (i < mtot) {
     const int64_t t0 = (int64_t)blockIdx.x * chunk;
     const int64_t t1 = min(n, t0 + chunk);
-    double ar = 0.0, ai = 0.0;
-    const double2* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
+    R ar = 0, ai = 0;
+    const cv<R>* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
     int64_t t = t0 + lane;
     for (; t + 192 < t1; t += 256) {
-      double2 a[4], b[4];
+      cv<R> a[4], b[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) { a[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
 #pragma unroll
@@ -545,14 +712,14 @@ __global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, in
       }
     }
     for (; t < t1; t += 64) {
-      const double2 a = sv[t], b = x[t];
+      const cv<R> a = sv[t], b = x[t];
       ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
       ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
     }
-    if (i >= m) ai = 0.0;   // |x|^2 row: conj(x) x is real
-    ar = wave_sum(ar);
-    ai = wave_sum(ai);
-    if (lane == 0) partial[(int64_t)i * nchunks + blockIdx.x] = make_double2(ar, ai);
+    if (i >= m) ai = 0;   // |x|^2 row: conj(x) x is real
+    double dr = wave_sum((double)ar);
+    double di = wave_sum((double)ai);
+    if (lane == 0) partial[(int64_t)i * nchunks + blockIdx.x] = make_double2(dr, di);
   }
   __threadfence();
   __syncthreads();
@@ -590,53 +757,248 @@ __global__ void __launch_bounds__(256) k_dotm(const double2* __restrict__ s0, in
   if (threadIdx.x == 0) *counter = 0u;
 }
 
+// ---- two-phase deterministic reductions (no cross-workgroup synchronisation) ----
+//
+// Phase 1 (k_dot_partial): one wavefront per (vector, chunk of t) writes the
+// chunk's partial sum.  Phase 2 happens in the consumer: every workgroup of the
+// next kernel reduces the partials of each vector with one wavefront in a fixed
+// order, so all workgroups obtain bit-identical coefficients.
+
+// partial[q * nch + chunk] = sum_{t in chunk} conj(S_q[t]) x[t] for q < m; with
+// with_norm, row q = m holds sum |x[t]|^2.  grid (nch, ceil(mtot / 4)), block 256.
+template <class R>
+__global__ void __launch_bounds__(256) k_dot_partial(const cv<R>* __restrict__ s0, int m0,
+                                                     const cv<R>* __restrict__ s1, int m1,
+                                                     const cv<R>* __restrict__ x, int64_t n, int chunk,
+                                                     double2* __restrict__ partial, int with_norm,
+                                                     const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int m = m0 + m1;
+  const int mtot = m + (with_norm ? 1 : 0);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.y * 4 + wv;
+  if (i >= mtot) return;
+  const int64_t t0 = (int64_t)blockIdx.x * chunk;
+  const int64_t t1 = min(n, t0 + chunk);
+  R ar = 0, ai = 0;
+  const cv<R>* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
+  int64_t t = t0 + lane;
+  for (; t + 192 < t1; t += 256) {
+    cv<R> a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { a[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      ar = fma(a[u].x, b[u].x, ar); ar = fma(a[u].y, b[u].y, ar);
+      ai = fma(a[u].x, b[u].y, ai); ai = fma(-a[u].y, b[u].x, ai);
+    }
+  }
+  for (; t < t1; t += 64) {
+    const cv<R> a = sv[t], b = x[t];
+    ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
+    ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
+  }
+  if (i >= m) ai = 0;
+  const double dr = wave_sum((double)ar);
+  const double di = wave_sum((double)ai);
+  if (lane == 0) partial[(int64_t)i * gridDim.x + blockIdx.x] = make_double2(dr, di);
+}
+
+// c[q] = sum over chunks of partial[q * nch + chunk], q < mtot, into LDS; one
+// wavefront per q, lanes over chunks, fixed tree: identical in every workgroup.
+__device__ __forceinline__ void reduce_partials(const double2* __restrict__ partial, int mtot, int nch,
+                                                double2* c) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int q = wv; q < mtot; q += nw) {
+    const double2* pq = partial + (int64_t)q * nch;
+    double sr = 0.0, si = 0.0;
+    for (int cc = lane; cc < nch; cc += 64) { const double2 pv = pq[cc]; sr += pv.x; si += pv.y; }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) c[q] = make_double2(sr, si);
+  }
+  __syncthreads();
+}
+
+// Final reduction of k_dot_partial into out (single workgroup).  mode 0 out = c,
+// 1 out += c, 2 out = Hinv c, 3 as 0 plus out[m] = ||x||^2; out2 (optional) += c.
+__global__ void __launch_bounds__(256) k_dot_reduce(const double2* __restrict__ partial, int m, int nch,
+                                                    double2* __restrict__ out, int mode,
+                                                    const double2* __restrict__ Hinv,
+                                                    double2* __restrict__ out2, const int* __restrict__ skip) {
+  __shared__ double2 c[256];
+  if (skip && *skip) return;
+  const int mtot = (mode == 3) ? m + 1 : m;
+  reduce_partials(partial, mtot, nch, c);
+  for (int q = threadIdx.x; q < mtot; q += 256) {
+    double2 v = c[q];
+    if (mode == 2) {
+      v = make_double2(0.0, 0.0);
+      for (int p = 0; p < m; ++p) v = cadd(v, cmul(Hinv[q * m + p], c[p]));
+      out[q] = v;
+    } else if (mode == 1) {
+      out[q] = cadd(out[q], v);
+    } else {
+      out[q] = v;
+    }
+    if (out2 && q < m) out2[q] = cadd(out2[q], c[q]);
+  }
+}
+
+// x -= sum_i S_i c_i where c comes from the dot partials of the previous kernel
+// (c = Hinv * sums when Hinv != nullptr).  Workgroup 0 stores c to coef_set
+// and/or adds it to coef_add.  With norm_part, each workgroup writes the partial
+// ||x_new||^2 of its slice.  grid ceil(n / 256), block 256.
+template <class R>
+__global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0, int m0,
+                                                    const cv<R>* __restrict__ s1, int m1,
+                                                    const double2* __restrict__ partial, int nch,
+                                                    const double2* __restrict__ Hinv,
+                                                    double2* __restrict__ coef_set,
+                                                    double2* __restrict__ coef_add, cv<R>* x, int64_t n,
+                                                    double2* __restrict__ norm_part,
+                                                    const int* __restrict__ skip) {
+  __shared__ double2 cr[256], cc[256];
+  __shared__ double2 sh[4];
+  if (skip && *skip) return;
+  const int m = m0 + m1;
+  reduce_partials(partial, m, nch, cr);
+  const double2* c = cr;
+  if (Hinv) {
+    for (int q = threadIdx.x; q < m; q += 256) {
+      double2 v = make_double2(0.0, 0.0);
+      for (int p = 0; p < m; ++p) v = cadd(v, cmul(Hinv[q * m + p], cr[p]));
+      cc[q] = v;
+    }
+    __syncthreads();
+    c = cc;
+  }
+  if (blockIdx.x == 0) {
+    for (int q = threadIdx.x; q < m; q += 256) {
+      if (coef_set) coef_set[q] = c[q];
+      if (coef_add) coef_add[q] = cadd(coef_add[q], c[q]);
+    }
+  }
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  R a2 = 0;
+  if (t < n) {
+    cv<R> acc = mk<R>(0, 0);
+    for (int i = 0; i < m0; ++i) acc = cadd(acc, cmul(s0[(int64_t)i * n + t], narrow<R>(c[i])));
+    for (int i = 0; i < m1; ++i) acc = cadd(acc, cmul(s1[(int64_t)i * n + t], narrow<R>(c[m0 + i])));
+    const cv<R> xv = csub(x[t], acc);
+    x[t] = xv;
+    a2 = xv.x * xv.x + xv.y * xv.y;
+  }
+  if (norm_part) {
+    const double2 bs = block_sum256(make_double2((double)a2, 0.0), sh);
+    if (threadIdx.x == 0) norm_part[blockIdx.x] = bs;
+  }
+}
+
+// nrm2 = sum of the nb norm partials (fixed order, every workgroup); x (or dst)
+// = x / sqrt(nrm2).  Workgroup 0 stores nrm2 and, when H is given, performs the
+// GMRES Givens update of column j (which may set *done).
+__device__ void gmres_givens_body(double2* __restrict__ H, int ldh, int j, double nrm2,
+                                  double* __restrict__ cs, double2* __restrict__ sn,
+                                  double2* __restrict__ g, int* __restrict__ done,
+                                  int* __restrict__ steps, const double* __restrict__ beta,
+                                  double rtol);
+template <class R>
+__global__ void __launch_bounds__(256) k_scale_norm(cv<R>* x, cv<R>* dst, int64_t n,
+                                                    const double2* __restrict__ norm_part, int nb,
+                                                    double2* __restrict__ nrm2_out,
+                                                    double2* __restrict__ H, int ldh, int j,
+                                                    double* __restrict__ cs, double2* __restrict__ sn,
+                                                    double2* __restrict__ g, int* done,
+                                                    int* __restrict__ steps,
+                                                    const double* __restrict__ beta, double rtol) {
+  __shared__ double2 sh[4];
+  __shared__ double tot;
+  if (done && *done) return;
+  double ps = 0.0;
+  for (int b = threadIdx.x; b < nb; b += 256) ps += norm_part[b].x;
+  const double2 s2 = block_sum256(make_double2(ps, 0.0), sh);
+  if (threadIdx.x == 0) {
+    tot = s2.x;
+    if (blockIdx.x == 0) {
+      *nrm2_out = make_double2(s2.x, 0.0);
+      if (H) gmres_givens_body(H, ldh, j, s2.x, cs, sn, g, done, steps, beta, rtol);
+    }
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const R sc = (R)(1.0 / sqrt(tot));
+  const cv<R> v = x[t];
+  (dst ? dst : x)[t] = mk<R>(v.x * sc, v.y * sc);
+}
+
 // x[t] -= sum_i S_i[t] c[i] over two segments (c on device; c[0..m0) for seg0,
 // c[m0..m0+m1) for seg1).  If dst != nullptr the result goes to dst instead.
-__global__ void __launch_bounds__(256) k_subm(const double2* __restrict__ s0, int m0,
-                                              const double2* __restrict__ s1, int m1,
-                                              const double2* __restrict__ c, double2* x,
-                                              double2* dst, int64_t n, double sign,
+template <class R>
+__global__ void __launch_bounds__(256) k_subm(const cv<R>* __restrict__ s0, int m0,
+                                              const cv<R>* __restrict__ s1, int m1,
+                                              const double2* __restrict__ c, cv<R>* x,
+                                              cv<R>* dst, int64_t n, R sign,
                                               const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const double2 acc = cadd(lincomb(s0, m0, n, t, c, 1), lincomb(s1, m1, n, t, c + m0, 1));
-  const double2 xv = x[t];
-  const double2 r = make_double2(xv.x - sign * acc.x, xv.y - sign * acc.y);
+  const cv<R> acc = cadd(lincomb<R>(s0, m0, n, t, c, 1), lincomb<R>(s1, m1, n, t, c + m0, 1));
+  const cv<R> xv = x[t];
+  const cv<R> r = mk<R>(xv.x - sign * acc.x, xv.y - sign * acc.y);
   (dst ? dst : x)[t] = r;
 }
 
 // out_j[t] = sum_i S_i[t] coef[i * ldc + j] for j < k (basis rotation V <- V U),
 // coefficients on the device.  grid.y = output vector j.
-__global__ void __launch_bounds__(256) k_combine(const double2* __restrict__ S, int m, int64_t n,
+template <class R>
+__global__ void __launch_bounds__(256) k_combine(const cv<R>* __restrict__ S, int m, int64_t n,
                                                  const double2* __restrict__ coef, int ldc,
-                                                 double2* __restrict__ out,
+                                                 cv<R>* __restrict__ out,
                                                  const int* __restrict__ count) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (t >= n) return;
   const int mm = count ? min(m, *count) : m;
-  out[(int64_t)j * n + t] = lincomb(S, mm, n, t, coef + j, ldc);
+  out[(int64_t)j * n + t] = lincomb<R>(S, mm, n, t, coef + j, ldc);
 }
 
 // x *= 1 / sqrt(*nrm2) (nrm2 on device), optionally into dst.
-__global__ void k_scale_rsqrt(double2* x, double2* dst, int64_t n, const double2* __restrict__ nrm2,
+template <class R>
+__global__ void k_scale_rsqrt(cv<R>* x, cv<R>* dst, int64_t n, const double2* __restrict__ nrm2,
                               const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const double s = 1.0 / sqrt(nrm2->x);
-  const double2 v = x[t];
-  (dst ? dst : x)[t] = make_double2(v.x * s, v.y * s);
+  const R sc = (R)(1.0 / sqrt(nrm2->x));
+  const cv<R> v = x[t];
+  (dst ? dst : x)[t] = mk<R>(v.x * sc, v.y * sc);
 }
 
 // y = a x (+ y if accum), a host scalar.
-__global__ void k_axpby(const double2* __restrict__ x, double2* y, int64_t n, double are,
-                        double aim, int accum) {
+template <class R>
+__global__ void k_axpby(const cv<R>* __restrict__ x, cv<R>* y, int64_t n, R are, R aim, int accum) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
-  const double2 xv = x[t];
-  double2 r = make_double2(are * xv.x - aim * xv.y, are * xv.y + aim * xv.x);
+  const cv<R> xv = x[t];
+  cv<R> r = mk<R>(are * xv.x - aim * xv.y, are * xv.y + aim * xv.x);
+  if (accum) r = cadd(r, y[t]);
+  y[t] = r;
+}
+
+// Precision conversion: y32 = (float) x64, or y64 (+)= (double) x32.
+__global__ void k_narrow(const double2* __restrict__ x, float2* __restrict__ y, int64_t n) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double2 v = x[t];
+  y[t] = make_float2((float)v.x, (float)v.y);
+}
+__global__ void k_widen(const float2* __restrict__ x, double2* __restrict__ y, int64_t n, int accum) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const float2 v = x[t];
+  double2 r = make_double2((double)v.x, (double)v.y);
   if (accum) r = cadd(r, y[t]);
   y[t] = r;
 }
@@ -696,9 +1058,10 @@ __global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const do
 // x[t] -= sum_i S_i[t] c[i] (two segments, c on device) and ||x||^2 of the result
 // into *nrm2 (partials per block, fixed-order sum by the last block).  When H is
 // given, the last block also performs the GMRES Givens update of column j.
-__global__ void __launch_bounds__(256) k_subm_norm(const double2* __restrict__ s0, int m0,
-                                                   const double2* __restrict__ s1, int m1,
-                                                   const double2* __restrict__ c, double2* x,
+template <class R>
+__global__ void __launch_bounds__(256) k_subm_norm(const cv<R>* __restrict__ s0, int m0,
+                                                   const cv<R>* __restrict__ s1, int m1,
+                                                   const double2* __restrict__ c, cv<R>* x,
                                                    int64_t n, double2* __restrict__ partial,
                                                    unsigned* __restrict__ counter,
                                                    double2* __restrict__ nrm2,
@@ -711,14 +1074,14 @@ __global__ void __launch_bounds__(256) k_subm_norm(const double2* __restrict__ s
   __shared__ bool last;
   if (done && *done) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double a2 = 0.0;
+  R a2 = 0;
   if (t < n) {
-    const double2 acc = cadd(lincomb(s0, m0, n, t, c, 1), lincomb(s1, m1, n, t, c + m0, 1));
-    const double2 xv = csub(x[t], acc);
+    const cv<R> acc = cadd(lincomb<R>(s0, m0, n, t, c, 1), lincomb<R>(s1, m1, n, t, c + m0, 1));
+    const cv<R> xv = csub(x[t], acc);
     x[t] = xv;
     a2 = xv.x * xv.x + xv.y * xv.y;
   }
-  const double2 bs = block_sum256(make_double2(a2, 0.0), sh);
+  const double2 bs = block_sum256(make_double2((double)a2, 0.0), sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
   __threadfence();
   __syncthreads();
@@ -782,25 +1145,84 @@ __global__ void k_set_int(int* p, int v) { *p = v; }
 
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
-                    const double* M, double2* mom, const int* skip) {
-  hipLaunchKernelGGL(k_moments, dim3(Ny, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, skip);
+// Column parts of the moment reduction: enough workgroups per vector to fill
+// the chip.  A function of the grid only (not of the batch size), so a vector
+// gets bit-identical results alone and in a batch.
+int moment_splits(int Ny, int nvec, int Nxi) {
+  (void)nvec;
+  (void)Ny;
+  return std::max(1, std::min(8, (2 * Nxi) / 512));
 }
 
+template <class R>
+static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                      const R* M, cv<R>* mom, const int* skip) {
+  const int S = moment_splits(Ny, nvec, Nxi);
+  hipLaunchKernelGGL((k_moments<R>), dim3(Ny * S, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S,
+                     skip);
+}
+void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                    const double* M, double2* mom, const int* skip) {
+  moments_t<double>(st, x, n, nvec, Ny, Nxi, r, M, mom, skip);
+}
+void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                    const float* M, float2* mom, const int* skip) {
+  moments_t<float>(st, x, n, nvec, Ny, Nxi, r, M, mom, skip);
+}
+
+template <class R>
+static void apply_t(hipStream_t st, const cv<R>* x, cv<R>* y, int64_t n, int nvec, int Ny, int Nxi,
+                    int r, double tre, double tim, double beta, const R* DxT, const R* xix, const R* xiy,
+                    const R* nu, const R* U, const cv<R>* mom, const int* skip) {
+  const int nc = 2 * Nxi;
+  const int cblocks = (nc + 255) / 256;
+  const int S = moment_splits(Ny, nvec, Nxi);
+  // rows per thread: as many as possible while keeping >= ~1024 wavefronts busy
+  const int64_t waves16 = (int64_t)((nc + 63) / 64) * ((Ny + 15) / 16) * nvec;
+  const int64_t waves8 = (int64_t)((nc + 63) / 64) * ((Ny + 7) / 8) * nvec;
+  if (waves16 >= 1024) {
+    hipLaunchKernelGGL((k_apply<R, 16>), dim3(cblocks, (Ny + 15) / 16, nvec), dim3(256), 0, st, x, y, n, Ny,
+                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+  } else if (waves8 >= 512) {
+    hipLaunchKernelGGL((k_apply<R, 8>), dim3(cblocks, (Ny + 7) / 8, nvec), dim3(256), 0, st, x, y, n, Ny,
+                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+  } else {
+    hipLaunchKernelGGL((k_apply<R, 4>), dim3(cblocks, (Ny + 3) / 4, nvec), dim3(256), 0, st, x, y, n, Ny,
+                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+  }
+}
 void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const double* Dx, const double* xix,
                   const double* xiy, const double* nu, const double* U, const double2* mom,
                   const int* skip) {
-  constexpr int TC = 32;
+  // FP64: streaming GEMM on the matrix cores.  Large launches use workgroups of
+  // 4 wavefronts sharing an LDS copy of their D_x row slice; small ones use one
+  // wavefront per workgroup (more workgroups, D_x from L2).  Row tiles per
+  // workgroup are chosen for >= ~1024 wavefronts when the problem allows it.
   const int nc = 2 * Nxi;
-  const int tiles = (nc + TC - 1) / TC;
-  // enough workgroups to cover the chip: split rows into groups of >= 8
-  int groups = 1;
-  while (tiles * groups * nvec < 1024 && Ny / (groups * 2) >= 8) groups *= 2;
-  const int rpg = (Ny + groups - 1) / groups;
-  const size_t lds = (size_t)Ny * TC * sizeof(double2);
-  hipLaunchKernelGGL(k_apply<TC>, dim3(tiles, groups, nvec), dim3(256), lds, st, x, y, n, Ny, Nxi, r,
-                     tre, tim, beta, Dx, xix, xiy, nu, U, mom, rpg, skip);
+  const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
+  const int S = moment_splits(Ny, nvec, Nxi);
+  int rt = 6;
+  while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
+  const bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512 &&
+                    (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) <= 96 * 1024;
+  const size_t lds_m = (size_t)rt * 16 * 4 * sizeof(double2);
+  const size_t lds = lds_m + (wide ? (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) : 0);
+  const dim3 g(wide ? (ctiles + 3) / 4 : ctiles, (nrt + rt - 1) / rt, nvec);
+#define KLST_MF(RT_, NW_) hipLaunchKernelGGL((k_apply_mfma<RT_, NW_>), g, dim3(64 * NW_), lds, st, x, y, n, Ny, \
+                                             Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, skip)
+  if (wide) {
+    if (rt == 6) KLST_MF(6, 4); else if (rt == 3) KLST_MF(3, 4); else if (rt == 2) KLST_MF(2, 4); else KLST_MF(1, 4);
+  } else {
+    if (rt == 6) KLST_MF(6, 1); else if (rt == 3) KLST_MF(3, 1); else if (rt == 2) KLST_MF(2, 1); else KLST_MF(1, 1);
+  }
+#undef KLST_MF
+}
+void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi,
+                  int r, double tre, double tim, double beta, const float* Dx, const float* xix,
+                  const float* xiy, const float* nu, const float* U, const float2* mom,
+                  const int* skip) {
+  apply_t<float>(st, x, y, n, nvec, Ny, Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, skip);
 }
 
 void launch_csr_build(hipStream_t st, int64_t* rowptr, int32_t* col, double2* val, int Ny, int Nxi,
@@ -831,16 +1253,25 @@ void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int 
     hipLaunchKernelGGL((k_ilu_apply<4, 2>), dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
 }
 
-// Chunk length for the tall-skinny reductions: at least 512 entries per
-// wavefront, at most 512 chunks (the partial buffer holds 512 x 256 values).
+template <class R>
+static void blockinv_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int nl, int nblocks,
+                       const cv<R>* Kinv, const int64_t* koff, const int* skip) {
+  const int nb = nl * Ny;
+  const size_t lds = (size_t)(nb + 256) * sizeof(cv<R>);
+  hipLaunchKernelGGL((k_blockinv_apply<R>), dim3((nb + 63) / 64, nblocks), dim3(256), lds, st, x, y, Ny,
+                     Nxi, nl, Kinv, koff, skip);
+}
 void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                            int nblocks, const double2* Kinv, const int64_t* koff, const int* skip) {
-  const int nb = nl * Ny;
-  const size_t lds = (size_t)(nb + 256) * sizeof(double2);
-  hipLaunchKernelGGL(k_blockinv_apply, dim3((nb + 63) / 64, nblocks), dim3(256), lds, st, x, y, Ny, Nxi,
-                     nl, Kinv, koff, skip);
+  blockinv_t<double>(st, x, y, Ny, Nxi, nl, nblocks, Kinv, koff, skip);
+}
+void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int nl,
+                           int nblocks, const float2* Kinv, const int64_t* koff, const int* skip) {
+  blockinv_t<float>(st, x, y, Ny, Nxi, nl, nblocks, Kinv, koff, skip);
 }
 
+// Chunk length for the tall-skinny reductions: at least 512 entries per
+// wavefront, at most 512 chunks (the partial buffer holds 512 x 256 values).
 int dot_blocks(int64_t n, int* chunk) {
   int c = 512;
   while ((n + c - 1) / c > 128 && c < (1 << 20)) c *= 2;
@@ -849,44 +1280,167 @@ int dot_blocks(int64_t n, int* chunk) {
   return (int)((n + c - 1) / c);
 }
 
-void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
-                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
-                 int mode, const double2* Hinv, double2* out2, const int* skip) {
+template <class R>
+static void dotm_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1, const cv<R>* x,
+                   int64_t n, double2* partial, unsigned* counter, double2* out, int mode,
+                   const double2* Hinv, double2* out2, const int* skip) {
   int chunk;
   const int nb = dot_blocks(n, &chunk);
   const int mtot = m0 + m1 + (mode == 3 ? 1 : 0);
   if (mtot == 0) return;
-  hipLaunchKernelGGL(k_dotm, dim3(nb, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk,
+  hipLaunchKernelGGL((k_dotm<R>), dim3(nb, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk,
                      partial, counter, out, mode, Hinv, out2, skip);
+}
+void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
+                 int mode, const double2* Hinv, double2* out2, const int* skip) {
+  dotm_t<double>(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
+}
+void launch_dotm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                 const float2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
+                 int mode, const double2* Hinv, double2* out2, const int* skip) {
+  dotm_t<float>(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
+}
+
+// Chunking for k_dot_partial: about 2048 wavefronts in total, at least 256
+// entries per chunk, at most 512 chunks.
+int partial_chunks(int64_t n, int mtot, int* chunk) {
+  int64_t want = std::max<int64_t>(1, 2048 / std::max(1, mtot));
+  want = std::min<int64_t>(want, 512);
+  int64_t c = std::max<int64_t>(256, (n + want - 1) / want);
+  c = (c + 63) / 64 * 64;
+  while ((n + c - 1) / c > 512) c += 64;
+  *chunk = (int)c;
+  return (int)((n + c - 1) / c);
+}
+
+template <class R>
+static int dot_partial_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1, const cv<R>* x,
+                         int64_t n, double2* partial, int with_norm, const int* skip) {
+  const int mtot = m0 + m1 + (with_norm ? 1 : 0);
+  int chunk;
+  const int nch = partial_chunks(n, mtot, &chunk);
+  if (mtot > 0)
+    hipLaunchKernelGGL((k_dot_partial<R>), dim3(nch, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n,
+                       chunk, partial, with_norm, skip);
+  return nch;
+}
+int launch_dot_partial(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                       const double2* x, int64_t n, double2* partial, int with_norm, const int* skip) {
+  return dot_partial_t<double>(st, s0, m0, s1, m1, x, n, partial, with_norm, skip);
+}
+int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const float2* x, int64_t n, double2* partial, int with_norm, const int* skip) {
+  return dot_partial_t<float>(st, s0, m0, s1, m1, x, n, partial, with_norm, skip);
+}
+void launch_dot_reduce(hipStream_t st, const double2* partial, int m, int nch, double2* out, int mode,
+                       const double2* Hinv, double2* out2, const int* skip) {
+  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), 0, st, partial, m, nch, out, mode, Hinv, out2, skip);
+}
+template <class R>
+static void subm_fused_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1,
+                         const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                         double2* coef_add, cv<R>* x, int64_t n, double2* norm_part, const int* skip) {
+  hipLaunchKernelGGL((k_subm_fused<R>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, partial, nch,
+                     Hinv, coef_set, coef_add, x, n, norm_part, skip);
+}
+void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, double2* x, int64_t n, double2* norm_part, const int* skip) {
+  subm_fused_t<double>(st, s0, m0, s1, m1, partial, nch, Hinv, coef_set, coef_add, x, n, norm_part, skip);
+}
+void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, float2* x, int64_t n, double2* norm_part, const int* skip) {
+  subm_fused_t<float>(st, s0, m0, s1, m1, partial, nch, Hinv, coef_set, coef_add, x, n, norm_part, skip);
+}
+template <class R>
+static void scale_norm_t(hipStream_t st, cv<R>* x, cv<R>* dst, int64_t n, const double2* norm_part,
+                         double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                         int* done, int* steps, const double* beta, double rtol) {
+  hipLaunchKernelGGL((k_scale_norm<R>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, norm_part,
+                     (int)nblk(n, 256), nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+}
+void launch_scale_norm(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol) {
+  scale_norm_t<double>(st, x, dst, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+}
+void launch_scale_norm(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol) {
+  scale_norm_t<float>(st, x, dst, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
 }
 
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
                  const double2* c, double2* x, double2* dst, int64_t n, double sign, const int* skip) {
-  hipLaunchKernelGGL(k_subm, dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, dst, n, sign,
-                     skip);
+  hipLaunchKernelGGL((k_subm<double>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, dst, n,
+                     sign, skip);
+}
+void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                 const double2* c, float2* x, float2* dst, int64_t n, double sign, const int* skip) {
+  hipLaunchKernelGGL((k_subm<float>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, dst, n,
+                     (float)sign, skip);
 }
 
 void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, double2* out, const int* count) {
-  hipLaunchKernelGGL(k_combine, dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out, count);
+  hipLaunchKernelGGL((k_combine<double>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
+                     count);
+}
+void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, float2* out, const int* count) {
+  hipLaunchKernelGGL((k_combine<float>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
+                     count);
 }
 
 void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* nrm2,
                         const int* skip) {
-  hipLaunchKernelGGL(k_scale_rsqrt, dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
+  hipLaunchKernelGGL((k_scale_rsqrt<double>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
+}
+void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* nrm2,
+                        const int* skip) {
+  hipLaunchKernelGGL((k_scale_rsqrt<float>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
 }
 
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum) {
-  hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, are, aim, accum);
+  hipLaunchKernelGGL((k_axpby<double>), dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, are, aim, accum);
+}
+void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double are, double aim,
+                  int accum) {
+  hipLaunchKernelGGL((k_axpby<float>), dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, (float)are,
+                     (float)aim, accum);
 }
 
+void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n) {
+  hipLaunchKernelGGL(k_narrow, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n);
+}
+void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int accum) {
+  hipLaunchKernelGGL(k_widen, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, accum);
+}
+
+template <class R>
+static void subm_norm_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1,
+                        const double2* c, cv<R>* x, int64_t n, double2* partial, unsigned* counter,
+                        double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                        int* done, int* steps, const double* beta, double rtol) {
+  hipLaunchKernelGGL((k_subm_norm<R>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, n,
+                     partial, counter, nrm2, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+}
 void launch_subm_norm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
                       const double2* c, double2* x, int64_t n, double2* partial, unsigned* counter,
                       double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                       int* done, int* steps, const double* beta, double rtol) {
-  hipLaunchKernelGGL(k_subm_norm, dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, n, partial,
-                     counter, nrm2, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+  subm_norm_t<double>(st, s0, m0, s1, m1, c, x, n, partial, counter, nrm2, H, ldh, j, cs, sn, g, done,
+                      steps, beta, rtol);
+}
+void launch_subm_norm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                      const double2* c, float2* x, int64_t n, double2* partial, unsigned* counter,
+                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                      int* done, int* steps, const double* beta, double rtol) {
+  subm_norm_t<float>(st, s0, m0, s1, m1, c, x, n, partial, counter, nrm2, H, ldh, j, cs, sn, g, done,
+                     steps, beta, rtol);
 }
 
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,

@@ -7,6 +7,7 @@
 namespace klst {
 namespace dev {
 
+// Moment partial sums: mom must hold Ny * r * nvec * 8 entries (up to 8 column parts).
 void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                     const double* M, double2* mom, const int* skip);
 void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
@@ -52,6 +53,55 @@ void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2
 void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int Ny, int Nxi,
                     const double* xix);
 void launch_set_int(hipStream_t st, int* p, int v);
+
+// ---- FP32 overloads (mixed-precision inner solve); coefficients stay FP64 ----
+void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                    const float* M, float2* mom, const int* skip);
+void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi,
+                  int r, double tre, double tim, double beta, const float* Dx, const float* xix,
+                  const float* xiy, const float* nu, const float* U, const float2* mom,
+                  const int* skip);
+void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int nl,
+                           int nblocks, const float2* Kinv, const int64_t* koff, const int* skip);
+void launch_dotm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                 const float2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
+                 int mode, const double2* Hinv, double2* out2, const int* skip);
+void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                 const double2* c, float2* x, float2* dst, int64_t n, double sign, const int* skip);
+void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, float2* out, const int* count);
+void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* nrm2,
+                        const int* skip);
+void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double are, double aim,
+                  int accum);
+void launch_subm_norm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                      const double2* c, float2* x, int64_t n, double2* partial, unsigned* counter,
+                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                      int* done, int* steps, const double* beta, double rtol);
+// precision conversion of n complex entries: y32 = x64; y64 = x32 (+ y64 if accum)
+void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n);
+void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int accum);
+
+// ---- two-phase reductions (partials + consumer-side fixed-order reduction) ----
+// Returns the number of chunks (columns of the partial table) for the consumer.
+int launch_dot_partial(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                       const double2* x, int64_t n, double2* partial, int with_norm, const int* skip);
+int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const float2* x, int64_t n, double2* partial, int with_norm, const int* skip);
+void launch_dot_reduce(hipStream_t st, const double2* partial, int m, int nch, double2* out, int mode,
+                       const double2* Hinv, double2* out2, const int* skip);
+void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, double2* x, int64_t n, double2* norm_part, const int* skip);
+void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, float2* x, int64_t n, double2* norm_part, const int* skip);
+void launch_scale_norm(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol);
+void launch_scale_norm(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol);
 
 }  // namespace dev
 }  // namespace klst

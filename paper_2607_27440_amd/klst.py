@@ -74,6 +74,16 @@ _sig = {
     "klst_precond_apply": (C.c_int, [_P, _P, _P]),
     "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_get_stats": (C.c_int, [_P, C.POINTER(Stats)]),
+    "klst_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.POINTER(Options)]),
+    "klst_server_create": (C.c_int, [C.POINTER(_P), C.POINTER(Options), C.c_int, C.c_size_t, C.c_int]),
+    "klst_server_destroy": (None, [_P]),
+    "klst_submit": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double, _D2,
+                              C.c_int, C.POINTER(C.c_uint64)]),
+    "klst_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int)]),
+    "klst_wait": (C.c_int, [_P, C.c_uint64, C.c_double]),
+    "klst_cancel": (C.c_int, [_P, C.c_uint64]),
+    "klst_fetch": (C.c_int, [_P, C.c_uint64, _D2, _P, _D2, C.POINTER(C.c_int), _D2, C.POINTER(Stats)]),
+    "klst_server_stats": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "klst_host_tables": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
                                    _D2, _D2, _D2, _D2, C.POINTER(C.c_uint8)]),
     "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
@@ -256,4 +266,108 @@ class Context:
             out["X"] = hostX.reshape(nev, self.n)[:k].T.copy()
         elif X is not None:
             out["X"] = X
+        return out
+
+
+def footprint_bytes(Ny, Nxi, nev, options: Optional[Options] = None) -> int:
+    """Device bytes one solve of this shape allocates (the server's admission model)."""
+    o = options if options is not None else default_options()
+    return int(_lib.klst_footprint_bytes(int(Ny), int(Nxi), int(nev), C.byref(o)))
+
+
+QUEUED, RUNNING, DONE, FAILED, CANCELLED = range(5)
+
+
+class Server:
+    """Continuous-batching server of independent solves (native worker threads,
+    one context and stream per slot, admission by HBM footprint)."""
+
+    def __init__(self, slots=4, hbm_budget=0, want_vectors=False, options: Optional[Options] = None,
+                 **kw):
+        opt = options if options is not None else default_options(**kw)
+        h = _P()
+        st = _lib.klst_server_create(C.byref(h), C.byref(opt), int(slots), C.c_size_t(int(hbm_budget)),
+                                     1 if want_vectors else 0)
+        if st != OK:
+            raise KlstError(st, "klst_server_create")
+        self._h = h
+        self.options = opt
+        self.want_vectors = want_vectors
+        self._meta = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.klst_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def submit(self, wl, sigma=None, nev=None):
+        g, v, b, keep = _structs(wl)
+        sig = complex(wl.sigma if sigma is None else sigma)
+        nev = int(wl.nev if nev is None else nev)
+        sa = np.array([sig.real, sig.imag])
+        t = C.c_uint64()
+        st = _lib.klst_submit(self._h, C.byref(g), C.byref(v), C.byref(b), float(wl.beta), _dp(sa), nev,
+                              C.byref(t))
+        if st != OK:
+            raise KlstError(st, "klst_submit")
+        self._meta[t.value] = (nev, 2 * int(wl.Ny) * len(wl.xi_x))
+        return t.value
+
+    def poll(self, ticket):
+        s = C.c_int()
+        st = _lib.klst_poll(self._h, C.c_uint64(ticket), C.byref(s))
+        if st != OK:
+            raise KlstError(st, "klst_poll")
+        return s.value
+
+    def wait(self, ticket, timeout=-1.0):
+        st = _lib.klst_wait(self._h, C.c_uint64(ticket), float(timeout))
+        return st == OK
+
+    def cancel(self, ticket):
+        st = _lib.klst_cancel(self._h, C.c_uint64(ticket))
+        if st != OK:
+            raise KlstError(st, "klst_cancel")
+
+    def fetch(self, ticket):
+        nev, n = self._meta.pop(ticket)
+        lam = np.zeros(2 * nev)
+        res = np.zeros(nev)
+        X = np.zeros(nev * n, np.complex128) if self.want_vectors else None
+        nconv = C.c_int()
+        timing = np.zeros(3)
+        stats = Stats()
+        st = _lib.klst_fetch(self._h, C.c_uint64(ticket), _dp(lam),
+                             C.c_void_p(X.ctypes.data) if X is not None else None, _dp(res),
+                             C.byref(nconv), _dp(timing), C.byref(stats))
+        k = nconv.value
+        out = dict(status=st, lam=lam.view(np.complex128)[:k].copy(), resid=res[:k].copy(), nconv=k,
+                   queue_s=timing[0], service_s=timing[1], latency_s=timing[2], stats=stats.as_dict())
+        if X is not None:
+            out["X"] = X.reshape(nev, n)[:k].T.copy()
+        return out
+
+    def stats(self):
+        pr = C.c_int()
+        pb = C.c_size_t()
+        bd = C.c_size_t()
+        _lib.klst_server_stats(self._h, C.byref(pr), C.byref(pb), C.byref(bd))
+        return dict(peak_running=pr.value, peak_bytes=pb.value, budget=bd.value)
+
+    def solve_all(self, workloads, nev=None):
+        """Submit every workload, wait for all, return results in order."""
+        tickets = [self.submit(wl, nev=nev) for wl in workloads]
+        out = []
+        for t in tickets:
+            self.wait(t)
+            out.append(self.fetch(t))
         return out

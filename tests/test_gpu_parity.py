@@ -202,3 +202,32 @@ def test_solve_c2_matches_shift_invert(pc_kernel, c2_reference):
     r = E.residuals(P, out["lam"], out["X"])
     assert np.all(r <= 1e-10), r
     _check_solve(wl, out, ref, kap, normA, tol=1e-10)
+
+
+def test_solve_c1_mixed_precision():
+    """FP32 inner GMRES (operator, preconditioner, Krylov vectors) inside FP64
+    refinement: eigenpairs still meet the FP64 residual gate and match QZ."""
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam_all, X, Y, _ = E.qz_all(P)
+    idx = E.order_nearest(lam_all, wl.sigma)[:wl.nev + 10]
+    kap = E.condition_numbers(P, lam_all[idx], X[:, idx], Y[:, idx])
+    normA = abs(P.A).sum(axis=0).max()
+    ctx = _ctx(wl, lines_per_block=4, m_max=40, precision=1)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    _check_solve(wl, out, lam_all[idx], kap, normA, tol=1e-8)
+    res, _ = PAR.match(out["lam"], lam_all[idx], kap, normA, sigma=wl.sigma, tol=1e-8)
+    print("mixed rel. errors:", [f"{r['err']:.2e}" for r in res], flush=True)
+
+
+def test_solve_c2_mixed_precision(c2_reference):
+    wl, P, ref, kap, normA = c2_reference
+    ctx = _ctx(wl, lines_per_block=3, m_max=60, precision=1)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    r = E.residuals(P, out["lam"], out["X"])
+    assert np.all(r <= 1e-10), r
+    _check_solve(wl, out, ref, kap, normA, tol=1e-8)
+    res, _ = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-8)
+    print("mixed rel. errors:", [f"{r['err']:.2e}" for r in res], flush=True)

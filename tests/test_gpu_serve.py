@@ -1,0 +1,112 @@
+"""Served / batched stability sweeps on the GPU (through the C ABI server).
+
+Inputs: the seeded sweep distribution (Ny in {24..64}, Nxi in {16..128}, beta,
+Mach, base type drawn per solve).  Checks: every result is bit-identical alone
+and in a concurrent mix; admission never exceeds the HBM budget; cancellation;
+served eigenpairs match the oracle."""
+import numpy as np
+import pytest
+
+from paper_2607_27440_amd import workloads as W
+from oracle import eig as E
+from oracle import operator as O
+from oracle import parity as PAR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _klst():
+    from paper_2607_27440_amd import klst
+    return klst
+
+
+def _small_sweep(k=8, nev=6):
+    wls = sorted(W.sweep(seed=4, count=64, nev=nev), key=lambda w: w.n)[:k]
+    return wls
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_results_identical_alone_and_in_mix(precision):
+    klst = _klst()
+    wls = _small_sweep()
+    print("[case] sizes", [w.n for w in wls], "precision", precision, flush=True)
+    opts = dict(lines_per_block=2, m_max=30, precision=precision)
+    with klst.Server(slots=1, **opts) as alone:
+        ref = [alone.solve_all([wl])[0] for wl in wls]
+    with klst.Server(slots=4, **opts) as mix:
+        got = mix.solve_all(wls)
+        st = mix.stats()
+    print("peak running", st["peak_running"], flush=True)
+    for a, b, wl in zip(ref, got, wls):
+        assert a["status"] == b["status"] == 0, (wl.name, a["status"], b["status"])
+        assert a["nconv"] == b["nconv"] == wl.nev
+        assert np.array_equal(a["lam"], b["lam"]), wl.name
+        assert np.array_equal(a["resid"], b["resid"]), wl.name
+        assert np.all(b["resid"] <= 1e-10)
+
+
+def test_admission_respects_hbm_budget():
+    """Admitted footprints never exceed the budget; with identical requests and a
+    budget of 2.2 footprints, at most 2 of the 4 slots run at once."""
+    klst = _klst()
+    o = klst.default_options(lines_per_block=2, m_max=30)
+    wls = _small_sweep(6)
+    fps = [klst.footprint_bytes(w.Ny, w.Nxi, w.nev, o) for w in wls]
+    budget = int(2.2 * max(fps))
+    with klst.Server(slots=4, hbm_budget=budget, options=o) as sv:
+        res = sv.solve_all(wls)
+        st = sv.stats()
+    print("footprints", fps, "budget", budget, st, flush=True)
+    assert st["peak_bytes"] <= budget
+    assert all(r["status"] == 0 for r in res)
+    same = [wls[-1]] * 6
+    with klst.Server(slots=4, hbm_budget=budget, options=o) as sv:
+        res = sv.solve_all(same)
+        st = sv.stats()
+    assert st["peak_running"] <= 2 and st["peak_bytes"] <= budget, st
+    assert all(np.array_equal(r["lam"], res[0]["lam"]) for r in res)
+
+
+def test_submit_rejects_request_larger_than_budget():
+    klst = _klst()
+    wl = W.config2()
+    o = klst.default_options(lines_per_block=3, m_max=60)
+    with klst.Server(slots=1, hbm_budget=1 << 20, options=o) as sv:
+        with pytest.raises(klst.KlstError) as ei:
+            sv.submit(wl)
+        assert ei.value.status == klst.ENOMEM
+
+
+def test_cancel_running_and_queued():
+    klst = _klst()
+    wl = W.config2()
+    with klst.Server(slots=1, lines_per_block=3, m_max=60) as sv:
+        t1 = sv.submit(wl)
+        t2 = sv.submit(wl)
+        sv.cancel(t2)
+        sv.cancel(t1)
+        sv.wait(t1)
+        sv.wait(t2)
+        r1, r2 = sv.fetch(t1), sv.fetch(t2)
+    assert r2["status"] == klst.ECANCELLED
+    assert r1["status"] in (klst.ECANCELLED, klst.OK)
+
+
+def test_served_eigenpairs_match_oracle():
+    klst = _klst()
+    wls = _small_sweep(3)
+    with klst.Server(slots=3, want_vectors=True, lines_per_block=2, m_max=30, precision=1) as sv:
+        res = sv.solve_all(wls)
+    for wl, r in zip(wls, res):
+        P = O.Pencil(wl)
+        ref, X = E.si_nearest(P, wl.sigma, wl.nev + 8)
+        Y = E.left_vectors_si(P, ref, wl.sigma)
+        kap = np.linalg.norm(Y, axis=0) * np.linalg.norm(X, axis=0) / np.abs(
+            np.einsum("ij,ij->j", Y.conj(), P.bdiag[:, None] * X))
+        normA = abs(P.A).sum(axis=0).max()
+        assert r["nconv"] == wl.nev
+        assert np.all(E.residuals(P, r["lam"], r["X"]) <= 1e-10)
+        m, skipped = PAR.match(r["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-8)
+        assert all(x["ok"] for x in m), (wl.name, m)
+        assert not skipped
