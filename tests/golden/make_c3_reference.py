@@ -1,0 +1,61 @@
+"""Write tests/golden/c3_m4_reference.txt: the eigenvalues of the M=4 bimodal
+shock pencil (Ny = 96, Nxi = 61 x 24, n = 281,088, beta = 0.5) nearest sigma = 0,
+with their relative residuals and condition numbers, computed by the oracle only
+(exact structured shift-invert Arnoldi for right vectors, the adjoint structured
+inverse for left vectors).  Takes about 20 minutes on 8 cores.
+
+    python tests/golden/make_c3_reference.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import eig as E          # noqa: E402
+from oracle import operator as O     # noqa: E402
+from paper_2607_27440_amd import workloads as W   # noqa: E402
+
+K = 24          # eigenvalues kept (the cluster begins at position 9)
+NCV = 400
+
+
+def arnoldi(S, n, Bd, k, ncv):
+    op = spla.LinearOperator((n, n), matvec=lambda x: S.solve(Bd * x.ravel()), dtype=complex)
+    return spla.eigs(op, k=k, which="LM", ncv=ncv, tol=1e-12, maxiter=5000)
+
+
+def main():
+    wl = W.config3()
+    P = O.Pencil(wl)
+    t0 = time.time()
+    S = E.ShiftInvert(P, wl.sigma)
+    mu, X = arnoldi(S, P.n, P.bdiag, K + 16, NCV)
+    lam = wl.sigma + 1.0 / mu
+    idx = E.order_nearest(lam, wl.sigma)[:K]
+    lam, X = lam[idx], X[:, idx]
+    res = E.residuals(P, lam, X)
+    Sa = E.ShiftInvert(P, wl.sigma, adjoint=True)
+    mua, Y = arnoldi(Sa, P.n, P.bdiag, K + 16, NCV)
+    laml = np.conj(np.conj(wl.sigma) + 1.0 / mua)
+    kap = np.empty(K)
+    for i, l in enumerate(lam):
+        j = int(np.argmin(np.abs(laml - l)))
+        y = Y[:, j]
+        kap[i] = np.linalg.norm(y) * np.linalg.norm(X[:, i]) / abs(np.vdot(y, P.bdiag * X[:, i]))
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "c3_m4_reference.txt")
+    with open(out, "w") as f:
+        f.write("# oracle eigenvalues of the M=4 bimodal shock pencil (n = 281,088) nearest 0,\n")
+        f.write(f"# written by tests/golden/make_c3_reference.py in {time.time() - t0:.0f} s\n")
+        f.write("# columns: Re(lambda) Im(lambda) rel_residual kappa\n")
+        for l, r, k in zip(lam, res, kap):
+            f.write(f"{l.real:.17e} {l.imag:.17e} {r:.3e} {k:.3e}\n")
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()
