@@ -47,6 +47,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--count", type=int, default=64, help="batched: number of sweep solves")
+    ap.add_argument("--requests", type=int, default=80, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="served: arrivals per second (0: 0.7 x the measured saturated rate)")
+    ap.add_argument("--max-it", type=int, default=2000, help="batched/served: outer-iteration cap")
     return ap.parse_args()
 
 
@@ -142,11 +149,128 @@ def cpu_baseline(wl, seconds):
                       f"{good} eigenpairs converged, {out['outer']} outer iterations"}
 
 
+SWEEP_OPTS = dict(lines_per_block=2, m_max=30, m_min=6, gmres_m=20)
+
+
+def _common(metric, unit, value, a, el, nsteps, dtype, config, extra):
+    line = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": nsteps,
+            "warmup": a.warmup, "ms_per_step": round(1e3 * el / max(1, nsteps), 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+    line.update(extra)
+    return line
+
+
+def run_batched(a):
+    """Batched stability sweep: `count` independent solves (seeded sweep draws:
+    Ny in {24..64}, Nxi in {16..128}, beta, Mach, base type), 8 eigenpairs
+    nearest 0 each.  Baseline: the same solves one after another with the plain
+    FP64 GPU JD; measured: FP32-inner / FP64-outer JD over concurrent slots."""
+    import numpy as np
+    from paper_2607_27440_amd import klst, workloads
+    wls = workloads.sweep(seed=4, count=a.count, nev=8)
+
+    def run(slots, prec):
+        with klst.Server(slots=slots, precision=prec, max_it=a.max_it, **SWEEP_OPTS) as sv:
+            if a.warmup:
+                sv.solve_all(wls[:2])
+            t = time.perf_counter()
+            res = sv.solve_all(wls)
+            el = time.perf_counter() - t
+            st = sv.stats()
+        good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in res)
+        return good, el, res, st
+    log(f"[bench] batched: {len(wls)} solves, serial plain FP64 baseline")
+    g0, e0, _, _ = run(1, 0)
+    log(f"[bench] baseline {g0} eigenpairs in {e0:.2f}s; now {a.slots} slots, mixed precision")
+    g1, e1, res, st = run(a.slots, 1)
+    lat = [r["service_s"] for r in res]
+    cfg = {"workload": f"sweep_seed4_{len(wls)}_solves_nev8", "slots": a.slots, "precision": "mixed",
+           "max_it": a.max_it, **SWEEP_OPTS}
+    return _common("eigenpairs/s at rel. residual <= 1e-10 (batched sweep)", "eigenpairs/s", g1 / e1, a, e1,
+                   len(wls), "c64-inner/c128-outer", cfg,
+                   {"plain_fp64_serial": {"value": round(g0 / e0, 4), "seconds": round(e0, 3),
+                                          "eigenpairs": g0},
+                    "speedup_vs_plain_fp64_serial": round((g1 / e1) / (g0 / e0), 3),
+                    "eigenpairs": g1, "seconds": round(e1, 3), "peak_running": st["peak_running"],
+                    "service_p50_s": round(float(np.percentile(lat, 50)), 4),
+                    "unconverged_solves": int(sum(1 for r in res if r["status"] != 0))})
+
+
+def run_served(a):
+    """Served stability sweep: Poisson arrivals, 95% from the sweep distribution and
+    5% at the config-2 shape (Ny = 64, Nxi = 96), 8 eigenpairs each, admitted by
+    HBM footprint into concurrent slots.  Baseline: the same trace served by one
+    plain FP64 solver in arrival order (service times measured, queueing replayed)."""
+    import numpy as np
+    from paper_2607_27440_amd import klst, workloads
+    rng = np.random.default_rng(5)
+    pool = workloads.sweep(seed=5, count=a.requests, nev=8)
+    c2 = workloads.config2()
+    c2.nev = 8
+    reqs = [c2 if rng.uniform() < 0.05 else pool[i] for i in range(a.requests)]
+    # saturated throughput (requests/s) of the served configuration, from a short batch
+    rate = a.rate
+    with klst.Server(slots=a.slots, precision=1, max_it=a.max_it, **SWEEP_OPTS) as sv:
+        if rate <= 0:
+            cal = reqs[: min(16, len(reqs))]
+            t = time.perf_counter()
+            sv.solve_all(cal)
+            rate = 0.7 * len(cal) / (time.perf_counter() - t)
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        arrive = np.cumsum(gaps) - gaps[0]
+        log(f"[bench] served: {len(reqs)} requests at {rate:.3f}/s on {a.slots} slots")
+        tickets = []
+        t0 = time.perf_counter()
+        for wl, ta in zip(reqs, arrive):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(sv.submit(wl))
+        res = []
+        for t in tickets:
+            sv.wait(t)
+            res.append(sv.fetch(t))
+        el = time.perf_counter() - t0
+        st = sv.stats()
+    lat = np.array([r["latency_s"] for r in res])
+    good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in res)
+    # baseline: plain FP64, one request at a time in arrival order
+    with klst.Server(slots=1, precision=0, max_it=a.max_it, **SWEEP_OPTS) as sb:
+        serv, goodb = [], 0
+        for wl in reqs:
+            r = sb.solve_all([wl])[0]
+            serv.append(r["service_s"])
+            goodb += int(np.sum(r["resid"] <= RES_GATE))
+    done, lat_b = 0.0, []
+    for ta, sv_s in zip(arrive, serv):
+        start = max(ta, done)
+        done = start + sv_s
+        lat_b.append(done - ta)
+    lat_b = np.array(lat_b)
+    cfg = {"workload": f"served_poisson_seed5_{len(reqs)}req_95pct_sweep_5pct_ny64_nxi96_nev8",
+           "slots": a.slots, "rate_per_s": round(rate, 4), "precision": "mixed", "max_it": a.max_it,
+           **SWEEP_OPTS}
+    return _common("eigenpairs/s at rel. residual <= 1e-10 (served sweep)", "eigenpairs/s", good / el, a,
+                   el, len(reqs), "c64-inner/c128-outer", cfg,
+                   {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                    "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                    "eigenpairs": good, "seconds": round(el, 3), "peak_running": st["peak_running"],
+                    "serial_plain_fp64": {"value": round(goodb / max(done, 1e-9), 4),
+                                          "p50_latency_s": round(float(np.percentile(lat_b, 50)), 4),
+                                          "p99_latency_s": round(float(np.percentile(lat_b, 99)), 4)}})
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if a.mode != "single":
+        import torch  # noqa: F401  (device initialisation)
+        line = run_batched(a) if a.mode == "batched" else run_served(a)
+        print(json.dumps(line), flush=True)
+        return
     import numpy as np
     import torch
     from paper_2607_27440_amd import klst, workloads
