@@ -52,7 +52,8 @@ typedef enum {
 /* Solver options (defaults from klst_default_options).  Paper defaults for the
  * JD solve are listed in its Appendix C; the values here follow the same
  * scheme: tol on ||A u - theta B u|| / (|theta| ||u||), restart from m_max to
- * m_min, GMRES correction-equation solves of at most gmres_m steps. */
+ * m_min, correction equations solved by GMRES restarted every gmres_m steps,
+ * up to inner_max_it steps or a residual reduction of inner_rtol. */
 typedef struct {
   int device;           /* HIP device ordinal                                        */
   void* stream;         /* hipStream_t to order work on; NULL = the default stream   */
@@ -61,15 +62,17 @@ typedef struct {
   int op_mode;          /* 0 = matrix-free operator; 1 = explicit CSR (built on device) */
   int lines_per_block;  /* block-Jacobi block = this many whole velocity lines       */
   int m_max, m_min;     /* search-space size before / after a restart               */
-  int gmres_m;          /* GMRES steps per correction-equation solve                 */
+  int gmres_m;          /* GMRES restart length (Krylov vectors per cycle)           */
   int max_it;           /* outer-iteration budget                                    */
   double tol;           /* eigenpair acceptance: relative residual                   */
-  double inner_rtol;    /* GMRES relative tolerance                                  */
+  double inner_rtol;    /* correction-equation relative tolerance                    */
   double fix;           /* correction shift = sigma until rel. residual < fix        */
   uint64_t seed;        /* start vector: counter-based SplitMix64 stream             */
   int pc_kernel;        /* preconditioner application: 0 = level-set triangular sweeps
                            over the ILU(0) factors; 1 = the same (L U)^{-1} applied as
                            a stored dense inverse per block (batched GEMV)           */
+  int inner_max_it;     /* GMRES steps per correction equation, over all restarts;
+                           values <= gmres_m give one unrestarted cycle              */
 } klst_options;
 
 /* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]
@@ -174,6 +177,15 @@ klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* la
 
 /* Statistics of the last solve. */
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);
+
+/* Convergence history of the last solve: one record of KLST_HISTORY_FIELDS
+ * doubles per outer iteration that ended in a correction equation, namely
+ * (outer iteration, pairs locked so far, relative residual ||r|| / |theta| of the
+ * selected Petrov pair, Re theta, Im theta, 1 if the correction equation was
+ * shifted by theta rather than sigma).  Copies min(cap, count) records into rec
+ * (host, caller-owned); *count receives the total.  Errors: EINVAL. */
+#define KLST_HISTORY_FIELDS 6
+klst_status klst_get_history(const klst_ctx* ctx, double* rec, int cap, int* count);
 
 /* ---------------------------------------------------------------------------
  * Served / batched stability sweeps: many independent solves (different grids,

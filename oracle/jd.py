@@ -114,9 +114,31 @@ def gmres(apply, b, m, rtol):
     return x, steps
 
 
+def gmres_restarted(apply, b, m, rtol, max_steps):
+    """Restarted GMRES(m) from x0 = 0: cycles of at most m steps, each started
+    from the true residual b - apply(x), until ||b - apply(x)|| <= rtol ||b|| or
+    max_steps steps in total.  Returns (x, steps)."""
+    x, steps = gmres(apply, b, min(m, max_steps), rtol)
+    bnorm = np.linalg.norm(b)
+    while steps < max_steps:
+        res = b - apply(x)
+        rn = np.linalg.norm(res)
+        if rn <= rtol * bnorm:
+            break
+        dx, st = gmres(apply, res, min(m, max_steps - steps), rtol * bnorm / rn)
+        x = x + dx
+        steps += max(st, 1)
+    return x, steps
+
+
 def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-6,
-       max_it=10000, seed=0, time_limit=None, verbose=False, fix=0.01, precond=None):
-    """Returns dict(lam, X, resid, outer, inner, nconv)."""
+       max_it=10000, seed=0, time_limit=None, verbose=False, fix=0.01, precond=None,
+       inner_max_it=None):
+    """Returns dict(lam, X, resid, outer, inner, nconv).  The correction equation
+    is solved by GMRES restarted every gmres_m steps, until its residual is below
+    inner_rtol times the initial one or inner_max_it steps are spent (App. C sets
+    a restart length, a relative tolerance and an iteration cap); by default
+    inner_max_it = gmres_m, one cycle."""
     import time
     t_start = time.perf_counter()
     n = P.n
@@ -231,7 +253,7 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
             return proj(K.solve(op(x, shift)))
 
         rhs = -proj(K.solve(r))
-        t, steps = gmres(F, rhs, gmres_m, inner_rtol)
+        t, steps = gmres_restarted(F, rhs, gmres_m, inner_rtol, inner_max_it or gmres_m)
         inner += steps
     # eigenpairs of the upper-triangular pencil (S_A, S_B), mapped back through Q
     k = Q.shape[1]

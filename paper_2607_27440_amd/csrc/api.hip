@@ -61,8 +61,8 @@ struct klst_ctx {
   // reductions
   double2* d_partial = nullptr;
   double2* d_npart = nullptr;     // per-workgroup norm partials (<= 2^16 workgroups)
-  unsigned* d_counter = nullptr;
   klst_stats stats{};
+  std::vector<double> history;   // per outer iteration: outer, nconv, rel residual, Re/Im theta, shift flag
   const volatile int* cancel = nullptr;   // set by the server: stop the current solve
 };
 
@@ -349,6 +349,7 @@ void klst_default_options(klst_options* o) {
   o->fix = 0.01;
   o->seed = 0;
   o->pc_kernel = 1;
+  o->inner_max_it = 20;
 }
 
 const char* klst_strerror(klst_status s) {
@@ -375,7 +376,8 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
-      (o.pc_kernel != 0 && o.pc_kernel != 1) || (o.precision == 1 && o.pc_kernel != 1))
+      (o.pc_kernel != 0 && o.pc_kernel != 1) || (o.precision == 1 && o.pc_kernel != 1) ||
+      o.inner_max_it < 1 || o.inner_max_it > 100000)
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -390,13 +392,11 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   ctx->stream = (hipStream_t)o.stream;
   ctx->own_stream = false;
   if (dalloc(ctx, (void**)&ctx->d_partial, sizeof(double2) * 512 * 256) != KLST_OK ||
-      dalloc(ctx, (void**)&ctx->d_npart, sizeof(double2) * 65536) != KLST_OK ||
-      dalloc(ctx, (void**)&ctx->d_counter, sizeof(unsigned) * 4) != KLST_OK) {
+      dalloc(ctx, (void**)&ctx->d_npart, sizeof(double2) * 65536) != KLST_OK) {
     klst_destroy(ctx);
     return KLST_ENOMEM;
   }
-  if (hipMemsetAsync(ctx->d_counter, 0, sizeof(unsigned) * 4, ctx->stream) != hipSuccess ||
-      hipStreamSynchronize(ctx->stream) != hipSuccess) {
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
     klst_destroy(ctx);
     return KLST_EDEVICE;
   }
@@ -411,7 +411,6 @@ void klst_destroy(klst_ctx* ctx) {
   free_problem(ctx);
   dfree(ctx, ctx->d_partial);
   dfree(ctx, ctx->d_npart);
-  dfree(ctx, ctx->d_counter);
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   if (ctx->own_stream && ctx->stream) hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -532,6 +531,15 @@ klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out) {
   return KLST_OK;
 }
 
+klst_status klst_get_history(const klst_ctx* ctx, double* rec, int cap, int* count) {
+  if (!ctx || !count || cap < 0 || (cap > 0 && !rec)) return KLST_EINVAL;
+  const int total = (int)(ctx->history.size() / KLST_HISTORY_FIELDS);
+  *count = total;
+  const int nrec = std::min(cap, total);
+  std::copy(ctx->history.begin(), ctx->history.begin() + (size_t)nrec * KLST_HISTORY_FIELDS, rec);
+  return KLST_OK;
+}
+
 }  // extern "C"
 
 // ================================================================ solver ===
@@ -593,9 +601,11 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   const int m_max = std::max(o.m_max, o.m_min + 2);
   const int m_min = o.m_min;
   const int gm = o.gmres_m;
+  const int imax = std::max(o.inner_max_it, 1);
   const cd sigma(sigma_in[0], sigma_in[1]);
   hipStream_t st = ctx->stream;
   ctx->stats = klst_stats{};
+  ctx->history.clear();
 
   klst_status s = pc_setup(ctx, sigma);
   if (s != KLST_OK) return s;
@@ -651,7 +661,6 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       !d_steps || !d_beta)
     return KLST_ENOMEM;
   double2* partial = ctx->d_partial;
-  unsigned* counter = ctx->d_counter;
   std::vector<double2> hsmall(SM);
 
   double2* npart = ctx->d_npart;
@@ -897,10 +906,12 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     // left-preconditioned with K and the oblique projection I - Yt Ht^{-1} Qt^H,
     // Yt = K^{-1} Zt, Ht = Qt^H Yt (Fokkema-Sleijpen-van der Vorst 1998).
     const cd shift = (rel <= o.fix) ? theta : sigma;
+    ctx->history.insert(ctx->history.end(),
+                        {(double)outer, (double)k, rel, theta.real(), theta.imag(), rel <= o.fix ? 1.0 : 0.0});
     // GMRES on the device for the projected preconditioned operator; vectors in the
     // precision of V (double2 or float2); rhs in `a` (consumed), result to `tout`.
     auto gmres = [&](auto* Gbp, auto* a, auto* bw, auto* Qt0, auto* ut, auto* Yt0, int kq, int budget,
-                     auto* tout) -> klst_status {
+                     auto* tout, bool first) -> klst_status {
       using V = std::remove_pointer_t<decltype(Gbp)>;
       klst_status s2;
       {
@@ -908,7 +919,7 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
                                            nullptr);
         launch_dot_reduce(st, partial, 0, nch, d_small, 3, nullptr, nullptr, nullptr);
       }
-      launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta);
+      launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta, first ? 1 : 0);
       launch_scale_rsqrt(st, a, Gbp, n, d_small, d_done);
       for (int j = 0; j < budget; ++j) {
         V* gj = Gbp + (size_t)j * n;
@@ -959,13 +970,43 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       dot(Qb, k, uv, 1, av, d_c, 2, d_Hinv);
       sub(Yb, k + 1, nullptr, 0, d_c, av);
       launch_axpby(st, av, av, n, -1.0, 0.0, 0);
-      if ((s = gmres(Gb, av, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k, gm, tv)) !=
-          KLST_OK)
+      // Restarted GMRES(gm): cycles of at most gm steps until the projected
+      // preconditioned residual is below inner_rtol times its initial norm or
+      // inner_max_it steps are spent; each restart recomputes the residual from t.
+      if ((s = gmres(Gb, av, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
+                     std::min(gm, imax), tv, true)) != KLST_OK)
         return s;
+      if (imax > gm) {
+        double2* resv = Tmp;                 // the rotation buffer is free here
+        double2* dt = Tmp + (size_t)n;
+        int used = 0;
+        while (true) {
+          int flags[2] = {0, 0};
+          HIPCHK(hipMemcpyAsync(&flags[0], d_done, sizeof(int), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipMemcpyAsync(&flags[1], d_steps, sizeof(int), hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          used += std::max(flags[1], 1);
+          if (flags[0] || used >= imax) break;
+          // resv = rhs - (I - Yt Ht^{-1} Qt^H) K^{-1} (A - shift B) t
+          if ((s = op_apply(ctx, shift, tv, bv, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+          if ((s = pc_apply(ctx, bv, resv, nullptr)) != KLST_OK) return s;
+          dot(Qb, k, uv, 1, resv, d_c, 2, d_Hinv);
+          sub(Yb, k + 1, nullptr, 0, d_c, resv);
+          launch_axpby(st, resv, resv, n, -1.0, 0.0, 0);
+          launch_axpby(st, av, resv, n, 1.0, 0.0, 1);
+          if ((s = gmres(Gb, resv, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
+                         std::min(gm, imax - used), dt, false)) != KLST_OK)
+            return s;
+          launch_axpby(st, dt, tv, n, 1.0, 0.0, 1);
+        }
+        launch_set_int(st, d_steps, used);
+      }
     } else {
       // Mixed precision: FP64 iterative refinement of the correction equation around
       // FP32 GMRES solves (FP32 operator, preconditioner, Krylov vectors, FP32
-      // accumulation); the residual of the correction equation stays FP64.
+      // accumulation); the residual of the correction equation stays FP64.  Each
+      // refinement sweep is one GMRES cycle of at most gmres_m steps, so the sweeps
+      // form a restarted GMRES whose restarts use the FP64 residual.
       float2* u32 = Q32 + (size_t)k * n;
       float2* ynew = Y32 + (size_t)k * n;
       launch_narrow(st, uv, u32, n);
@@ -984,20 +1025,20 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       HIPCHK(hipMemsetAsync(tv, 0, sizeof(double2) * n, st));
       launch_axpby(st, rv, rho64, n, -1.0, 0.0, 0);               // rho = -r
       int used = 0;
-      for (int sweep = 0; sweep < 3 && used < gm; ++sweep) {
+      while (used < imax) {
         launch_narrow(st, rho64, a32, n);
         if ((s = pc_v(ctx, a32, b32, nullptr)) != KLST_OK) return s;
         dot32(Q32, k, u32, 1, b32, d_c, 2, d_Hinv);
         launch_subm(st, Y32, k + 1, (const float2*)nullptr, 0, d_c, b32, (float2*)nullptr, n, 1.0, nullptr);
         if ((s = gmres(Gb32, b32, a32, (const float2*)Q32, (const float2*)u32, (const float2*)Y32, k,
-                       gm - used, d32)) != KLST_OK)
+                       std::min(gm, imax - used), d32, true)) != KLST_OK)
           return s;
         launch_widen(st, d32, tv, n, 1);                          // t += delta
         int stp = 0;
         HIPCHK(hipMemcpyAsync(&stp, d_steps, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         used += std::max(stp, 1);
-        if (used >= gm || sweep == 2) break;
+        if (used >= imax) break;
         // FP64 residual of the correction equation: rho = -r - Zt-proj (A - shift B) Qt-proj t
         HIPCHK(hipMemcpyAsync(av, tv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
         dot(Qb, k, uv, 1, av, d_c, 0);

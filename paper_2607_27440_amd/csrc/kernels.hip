@@ -1,9 +1,9 @@
 // HIP kernels for gfx950 (CDNA4, 64-wide wavefronts).
 //
 // Vectors are complex FP64 stored as double2 (re, im), unknown (j, f, k) at
-// (2 j + f) * Nxi + k.  All reductions are deterministic: fixed partitions and
-// a fixed-order final sum done by the last workgroup to finish ("last block"
-// pattern with one global counter that the last block resets).
+// (2 j + f) * Nxi + k.  All reductions are deterministic: fixed partitions whose
+// partial sums are combined in a fixed order by the kernel that consumes them,
+// with no cross-workgroup synchronisation.
 #include <hip/hip_runtime.h>
 #include <algorithm>
 #include <cstdint>
@@ -669,94 +669,6 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict_
 
 // ------------------------------------------------------- vector kernels ----
 
-// out[i] (=, +=, or Hinv * c) for c_i = sum_t conj(S_i[t]) x[t], over up to two
-// segments of vectors (seg0: m0 vectors at s0, stride n; seg1: m1 at s1).
-// Tall-skinny layout: one wavefront per (vector, chunk of t), lanes striding the
-// chunk, one wavefront reduction per partial; the last workgroup to finish sums
-// the partials of every vector over the chunks in chunk order (deterministic).
-// grid (nchunks, ceil(mtot / 4)), block 256 = 4 wavefronts.
-// mode: 0 out = c, 1 out += c, 2 out = Hinv * c (Hinv m x m row-major),
-//       3 out = c and out[m] = sum |x|^2.  out2 (optional) += c.
-template <class R>
-__global__ void __launch_bounds__(256) k_dotm(const cv<R>* __restrict__ s0, int m0,
-                                              const cv<R>* __restrict__ s1, int m1,
-                                              const cv<R>* __restrict__ x, int64_t n, int chunk,
-                                              double2* __restrict__ partial,
-                                              unsigned int* __restrict__ counter,
-                                              double2* __restrict__ out, int mode,
-                                              const double2* __restrict__ Hinv,
-                                              double2* __restrict__ out2,
-                                              const int* __restrict__ skip) {
-  __shared__ bool last;
-  __shared__ double2 cs[256];
-  if (skip && *skip) return;
-  const int m = m0 + m1;
-  const int mtot = (mode == 3) ? m + 1 : m;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.y * 4 + wv;
-  const int nchunks = gridDim.x;
-  if (i < mtot) {
-    const int64_t t0 = (int64_t)blockIdx.x * chunk;
-    const int64_t t1 = min(n, t0 + chunk);
-    R ar = 0, ai = 0;
-    const cv<R>* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
-    int64_t t = t0 + lane;
-    for (; t + 192 < t1; t += 256) {
-      cv<R> a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) { a[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        ar = fma(a[u].x, b[u].x, ar); ar = fma(a[u].y, b[u].y, ar);
-        ai = fma(a[u].x, b[u].y, ai); ai = fma(-a[u].y, b[u].x, ai);
-      }
-    }
-    for (; t < t1; t += 64) {
-      const cv<R> a = sv[t], b = x[t];
-      ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
-      ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
-    }
-    if (i >= m) ai = 0;   // |x|^2 row: conj(x) x is real
-    double dr = wave_sum((double)ar);
-    double di = wave_sum((double)ai);
-    if (lane == 0) partial[(int64_t)i * nchunks + blockIdx.x] = make_double2(dr, di);
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x * gridDim.y - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // one wavefront per vector: lanes load the chunk partials (fixed assignment),
-  // then a fixed-shape wavefront tree sums them
-  for (int q = wv; q < mtot; q += 4) {
-    const double2* pq = partial + (int64_t)q * nchunks;
-    double sr = 0.0, si = 0.0;
-    for (int c = lane; c < nchunks; c += 64) { const double2 pv = pq[c]; sr += pv.x; si += pv.y; }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) {
-      const double2 sm = make_double2(sr, si);
-      if (mode == 2) cs[q] = sm;
-      else if (mode == 1) out[q] = cadd(out[q], sm);
-      else out[q] = sm;
-      if (out2 && q < m) out2[q] = cadd(out2[q], sm);
-    }
-  }
-  if (mode == 2) {
-    __syncthreads();
-    for (int q = threadIdx.x; q < m; q += 256) {
-      double2 sm = make_double2(0.0, 0.0);
-      for (int p = 0; p < m; ++p) sm = cadd(sm, cmul(Hinv[q * m + p], cs[p]));
-      out[q] = sm;
-    }
-  }
-  if (threadIdx.x == 0) *counter = 0u;
-}
-
 // ---- two-phase deterministic reductions (no cross-workgroup synchronisation) ----
 //
 // Phase 1 (k_dot_partial): one wavefront per (vector, chunk of t) writes the
@@ -1047,70 +959,16 @@ __device__ void gmres_givens_body(double2* __restrict__ H, int ldh, int j, doubl
   if (res <= tol_abs || ag == 0.0) *done = 1;
 }
 
-__global__ void k_gmres_givens(double2* __restrict__ H, int ldh, int j, const double2* __restrict__ nrm2,
-                               double* __restrict__ cs, double2* __restrict__ sn,
-                               double2* __restrict__ g, int* __restrict__ done,
-                               int* __restrict__ steps, const double* __restrict__ beta, double rtol) {
-  if (*done) return;
-  gmres_givens_body(H, ldh, j, nrm2->x, cs, sn, g, done, steps, beta, rtol);
-}
-
-// x[t] -= sum_i S_i[t] c[i] (two segments, c on device) and ||x||^2 of the result
-// into *nrm2 (partials per block, fixed-order sum by the last block).  When H is
-// given, the last block also performs the GMRES Givens update of column j.
-template <class R>
-__global__ void __launch_bounds__(256) k_subm_norm(const cv<R>* __restrict__ s0, int m0,
-                                                   const cv<R>* __restrict__ s1, int m1,
-                                                   const double2* __restrict__ c, cv<R>* x,
-                                                   int64_t n, double2* __restrict__ partial,
-                                                   unsigned* __restrict__ counter,
-                                                   double2* __restrict__ nrm2,
-                                                   double2* __restrict__ H, int ldh, int j,
-                                                   double* __restrict__ cs, double2* __restrict__ sn,
-                                                   double2* __restrict__ g, int* done,
-                                                   int* __restrict__ steps,
-                                                   const double* __restrict__ beta, double rtol) {
-  __shared__ double2 sh[4];
-  __shared__ bool last;
-  if (done && *done) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  R a2 = 0;
-  if (t < n) {
-    const cv<R> acc = cadd(lincomb<R>(s0, m0, n, t, c, 1), lincomb<R>(s1, m1, n, t, c + m0, 1));
-    const cv<R> xv = csub(x[t], acc);
-    x[t] = xv;
-    a2 = xv.x * xv.x + xv.y * xv.y;
-  }
-  const double2 bs = block_sum256(make_double2((double)a2, 0.0), sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double ps = 0.0;
-  for (unsigned bb = threadIdx.x; bb < gridDim.x; bb += 256) ps += partial[bb].x;
-  const double2 tot = block_sum256(make_double2(ps, 0.0), sh);
-  if (threadIdx.x == 0) {
-    const double sm = tot.x;
-    *nrm2 = make_double2(sm, 0.0);
-    if (H) gmres_givens_body(H, ldh, j, sm, cs, sn, g, done, steps, beta, rtol);
-    *counter = 0u;
-  }
-}
-
-// g[0] = sqrt(*nrm2); done = (g[0] == 0); steps = 0.
+// g[0] = sqrt(*nrm2); done = (g[0] == 0); steps = 0.  The first cycle of a
+// restarted solve records its initial residual norm in *beta_out, which later
+// cycles keep, so that every cycle stops at rtol times the initial residual.
 __global__ void k_gmres_init(const double2* __restrict__ nrm2, double2* __restrict__ g, int* done,
-                             int* steps, double* beta_out) {
+                             int* steps, double* beta_out, int first) {
   const double b = sqrt(nrm2->x);
   g[0] = make_double2(b, 0.0);
   *done = (b == 0.0) ? 1 : 0;
   *steps = 0;
-  *beta_out = b;
+  if (first) *beta_out = b;
 }
 
 // Back substitution R y = g with the rotated Hessenberg (steps x steps upper).
@@ -1270,38 +1128,6 @@ void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, i
   blockinv_t<float>(st, x, y, Ny, Nxi, nl, nblocks, Kinv, koff, skip);
 }
 
-// Chunk length for the tall-skinny reductions: at least 512 entries per
-// wavefront, at most 512 chunks (the partial buffer holds 512 x 256 values).
-int dot_blocks(int64_t n, int* chunk) {
-  int c = 512;
-  while ((n + c - 1) / c > 128 && c < (1 << 20)) c *= 2;
-  while ((n + c - 1) / c > 512) c *= 2;
-  *chunk = c;
-  return (int)((n + c - 1) / c);
-}
-
-template <class R>
-static void dotm_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1, const cv<R>* x,
-                   int64_t n, double2* partial, unsigned* counter, double2* out, int mode,
-                   const double2* Hinv, double2* out2, const int* skip) {
-  int chunk;
-  const int nb = dot_blocks(n, &chunk);
-  const int mtot = m0 + m1 + (mode == 3 ? 1 : 0);
-  if (mtot == 0) return;
-  hipLaunchKernelGGL((k_dotm<R>), dim3(nb, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n, chunk,
-                     partial, counter, out, mode, Hinv, out2, skip);
-}
-void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
-                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
-                 int mode, const double2* Hinv, double2* out2, const int* skip) {
-  dotm_t<double>(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
-}
-void launch_dotm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
-                 const float2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
-                 int mode, const double2* Hinv, double2* out2, const int* skip) {
-  dotm_t<float>(st, s0, m0, s1, m1, x, n, partial, counter, out, mode, Hinv, out2, skip);
-}
-
 // Chunking for k_dot_partial: about 2048 wavefronts in total, at least 256
 // entries per chunk, at most 512 chunks.
 int partial_chunks(int64_t n, int mtot, int* chunk) {
@@ -1354,6 +1180,7 @@ void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s
                        double2* coef_add, float2* x, int64_t n, double2* norm_part, const int* skip) {
   subm_fused_t<float>(st, s0, m0, s1, m1, partial, nch, Hinv, coef_set, coef_add, x, n, norm_part, skip);
 }
+
 template <class R>
 static void scale_norm_t(hipStream_t st, cv<R>* x, cv<R>* dst, int64_t n, const double2* norm_part,
                          double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
@@ -1420,38 +1247,9 @@ void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int ac
   hipLaunchKernelGGL(k_widen, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, accum);
 }
 
-template <class R>
-static void subm_norm_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1,
-                        const double2* c, cv<R>* x, int64_t n, double2* partial, unsigned* counter,
-                        double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
-                        int* done, int* steps, const double* beta, double rtol) {
-  hipLaunchKernelGGL((k_subm_norm<R>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, c, x, n,
-                     partial, counter, nrm2, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
-}
-void launch_subm_norm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
-                      const double2* c, double2* x, int64_t n, double2* partial, unsigned* counter,
-                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
-                      int* done, int* steps, const double* beta, double rtol) {
-  subm_norm_t<double>(st, s0, m0, s1, m1, c, x, n, partial, counter, nrm2, H, ldh, j, cs, sn, g, done,
-                      steps, beta, rtol);
-}
-void launch_subm_norm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
-                      const double2* c, float2* x, int64_t n, double2* partial, unsigned* counter,
-                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
-                      int* done, int* steps, const double* beta, double rtol) {
-  subm_norm_t<float>(st, s0, m0, s1, m1, c, x, n, partial, counter, nrm2, H, ldh, j, cs, sn, g, done,
-                     steps, beta, rtol);
-}
-
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
-                       double* beta) {
-  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(1), 0, st, nrm2, g, done, steps, beta);
-}
-
-void launch_gmres_givens(hipStream_t st, double2* H, int ldh, int j, const double2* nrm2, double* cs,
-                         double2* sn, double2* g, int* done, int* steps, const double* beta, double rtol) {
-  hipLaunchKernelGGL(k_gmres_givens, dim3(1), dim3(1), 0, st, H, ldh, j, nrm2, cs, sn, g, done, steps,
-                     beta, rtol);
+                       double* beta, int first) {
+  hipLaunchKernelGGL(k_gmres_init, dim3(1), dim3(1), 0, st, nrm2, g, done, steps, beta, first);
 }
 
 void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2* g, const int* steps,

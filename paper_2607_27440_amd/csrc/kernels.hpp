@@ -24,12 +24,6 @@ void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int 
                       int nblocks, const double2* Fc, const double2* C, const int* skip);
 void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                            int nblocks, const double2* Kinv, const int64_t* koff, const int* skip);
-int dot_blocks(int64_t n, int* chunk);
-// mode 0: out = S^H x; 1: out += S^H x; 2: out = Hinv (S^H x); 3: out = S^H x and out[m] = ||x||^2.
-// out2 (optional) += S^H x.
-void launch_dotm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
-                 const double2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
-                 int mode, const double2* Hinv, double2* out2, const int* skip);
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
                  const double2* c, double2* x, double2* dst, int64_t n, double sign, const int* skip);
 void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
@@ -38,16 +32,9 @@ void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, con
                         const int* skip);
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum);
-// x -= S c and *nrm2 = ||x||^2; with H != nullptr also the GMRES Givens update
-// of column j (skipped entirely when *done).  n / 256 <= 512 * 256 blocks.
-void launch_subm_norm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
-                      const double2* c, double2* x, int64_t n, double2* partial, unsigned* counter,
-                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
-                      int* done, int* steps, const double* beta, double rtol);
+// First cycle (first != 0): *beta = ||r0||; later restart cycles keep it.
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
-                       double* beta);
-void launch_gmres_givens(hipStream_t st, double2* H, int ldh, int j, const double2* nrm2, double* cs,
-                         double2* sn, double2* g, int* done, int* steps, const double* beta, double rtol);
+                       double* beta, int first);
 void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2* g, const int* steps,
                         double2* yk);
 void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int Ny, int Nxi,
@@ -63,9 +50,6 @@ void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nve
                   const int* skip);
 void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int nl,
                            int nblocks, const float2* Kinv, const int64_t* koff, const int* skip);
-void launch_dotm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
-                 const float2* x, int64_t n, double2* partial, unsigned* counter, double2* out,
-                 int mode, const double2* Hinv, double2* out2, const int* skip);
 void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
                  const double2* c, float2* x, float2* dst, int64_t n, double sign, const int* skip);
 void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
@@ -74,10 +58,6 @@ void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const
                         const int* skip);
 void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double are, double aim,
                   int accum);
-void launch_subm_norm(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
-                      const double2* c, float2* x, int64_t n, double2* partial, unsigned* counter,
-                      double2* nrm2, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
-                      int* done, int* steps, const double* beta, double rtol);
 // precision conversion of n complex entries: y32 = x64; y64 = x32 (+ y64 if accum)
 void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n);
 void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int accum);

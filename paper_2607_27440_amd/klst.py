@@ -22,6 +22,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBUSY, ECANCELLED, ESTATE = range(8)
+HISTORY_FIELDS = 6
 
 
 class Options(C.Structure):
@@ -29,7 +30,7 @@ class Options(C.Structure):
                 ("op_mode", C.c_int), ("lines_per_block", C.c_int), ("m_max", C.c_int),
                 ("m_min", C.c_int), ("gmres_m", C.c_int), ("max_it", C.c_int), ("tol", C.c_double),
                 ("inner_rtol", C.c_double), ("fix", C.c_double), ("seed", C.c_uint64),
-                ("pc_kernel", C.c_int)]
+                ("pc_kernel", C.c_int), ("inner_max_it", C.c_int)]
 
 
 class Grid(C.Structure):
@@ -74,6 +75,7 @@ _sig = {
     "klst_precond_apply": (C.c_int, [_P, _P, _P]),
     "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_get_stats": (C.c_int, [_P, C.POINTER(Stats)]),
+    "klst_get_history": (C.c_int, [_P, _D2, C.c_int, C.POINTER(C.c_int)]),
     "klst_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.POINTER(Options)]),
     "klst_server_create": (C.c_int, [C.POINTER(_P), C.POINTER(Options), C.c_int, C.c_size_t, C.c_int]),
     "klst_server_destroy": (None, [_P]),
@@ -267,6 +269,16 @@ class Context:
         elif X is not None:
             out["X"] = X
         return out
+
+    def history(self) -> np.ndarray:
+        """Convergence history of the last solve, one row per outer iteration:
+        (outer, locked, relative residual, Re theta, Im theta, theta-shifted)."""
+        cnt = C.c_int(0)
+        self._check(_lib.klst_get_history(self._h, None, 0, C.byref(cnt)), "klst_get_history")
+        rec = np.zeros((cnt.value, HISTORY_FIELDS), np.float64)
+        if cnt.value:
+            self._check(_lib.klst_get_history(self._h, _dp(rec), cnt.value, C.byref(cnt)), "klst_get_history")
+        return rec
 
 
 def footprint_bytes(Ny, Nxi, nev, options: Optional[Options] = None) -> int:

@@ -173,6 +173,31 @@ def test_solve_c1_matches_qz():
     # eigenvectors: residual with the oracle's explicit matrices
     r = E.residuals(P, out["lam"], out["X"])
     assert np.all(r <= 1e-10), r
+    # convergence history: one row per correction equation, locked count never
+    # decreasing, every recorded residual above the acceptance tolerance
+    h = ctx.history()
+    assert h.shape[1] == 6 and 0 < len(h) <= out["stats"]["outer_iterations"]
+    assert np.all(np.diff(h[:, 1]) >= 0) and h[-1, 1] < wl.nev
+    assert np.all(h[:, 2] > 1e-10)
+    assert np.all((h[:, 5] == 1) == (h[:, 2] <= 0.01))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_c1_restarted_gmres(precision):
+    """Correction equations by GMRES(8) restarted up to 40 steps (FP64 residual
+    restarts in mixed precision) reach the same eigenpairs as QZ."""
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam_all, X, Y, _ = E.qz_all(P)
+    idx = E.order_nearest(lam_all, wl.sigma)[:wl.nev + 10]
+    kap = E.condition_numbers(P, lam_all[idx], X[:, idx], Y[:, idx])
+    normA = abs(P.A).sum(axis=0).max()
+    ctx = _ctx(wl, lines_per_block=4, m_max=40, gmres_m=8, inner_max_it=40, precision=precision)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    _check_solve(wl, out, lam_all[idx], kap, normA, tol=1e-10 if precision == 0 else 1e-8)
+    r = E.residuals(P, out["lam"], out["X"])
+    assert np.all(r <= 1e-10), r
 
 
 @pytest.fixture(scope="module")

@@ -283,6 +283,25 @@ def test_gmres_exact_in_n_steps():
     assert np.allclose(x, np.linalg.solve(Am, b), atol=1e-10)
 
 
+def test_restarted_gmres_reaches_direct_solve():
+    """GMRES(4) restarted many times solves a well-conditioned system to the
+    requested tolerance; capped at one cycle it stops after 4 steps with a
+    residual that restarting then strictly reduces (each cycle minimises the
+    residual over a Krylov space that contains 0)."""
+    rng = np.random.default_rng(10)
+    n = 40
+    Am = 0.3 * (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(n) + np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, steps = J.gmres_restarted(lambda v: Am @ v, b, 4, 1e-12, 400)
+    assert np.linalg.norm(Am @ x - b) <= 1e-12 * np.linalg.norm(b) * 1.01
+    assert np.allclose(x, np.linalg.solve(Am, b), rtol=1e-10, atol=1e-12)
+    x1, s1 = J.gmres_restarted(lambda v: Am @ v, b, 4, 1e-12, 4)
+    x2, s2 = J.gmres_restarted(lambda v: Am @ v, b, 4, 1e-12, 8)
+    assert s1 == 4 and s2 == 8
+    r1, r2 = np.linalg.norm(Am @ x1 - b), np.linalg.norm(Am @ x2 - b)
+    assert r2 < r1 < np.linalg.norm(b)
+
+
 def test_sorted_schur():
     rng = np.random.default_rng(9)
     Gm = rng.standard_normal((9, 9)) + 1j * rng.standard_normal((9, 9))
