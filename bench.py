@@ -5,14 +5,17 @@
 
 One step = the whole hot path on one synthetic input: assemble the operator
 (grids, coefficient tables, device upload) and solve for the nev eigenpairs
-nearest the target with Jacobi-Davidson (block-Jacobi ILU(0) set-up, GMRES
-correction solves, CGS2, projected problems, locking, eigenvectors).  The value
-counts only eigenpairs whose relative residual is <= 1e-10.  Inputs are seeded
-synthetic shock base flows (paper_2607_27440_amd.workloads).
+nearest the target with Jacobi-Davidson (preconditioner set-up, GMRES correction
+solves, CGS2, projected problems, locking, eigenvectors).  The value counts only
+eigenpairs whose relative residual is <= 1e-10.  Inputs are seeded synthetic
+shock base flows (paper_2607_27440_amd.workloads).
 
-After the timed steps, the dominant kernel is re-timed with HIP events on the
-library's stream to report its roofline fraction, and the CPU oracle's
-Jacobi-Davidson is timed on a bounded sample for the cpu_baseline field.
+Workload c2 (the default) is the configured method: block-Jacobi ILU(0) with 64
+blocks and GMRES(20); its line also reports, as "variants", the same solve with
+FP32 inner solves in FP64 refinement and with the exact structured inverse as
+preconditioner.  After the timed steps, the dominant kernel is re-timed with HIP
+events on the library's stream to report its roofline fraction, and the CPU
+oracle's Jacobi-Davidson is timed on a bounded sample for the cpu_baseline field.
 Prints ONE JSON line.
 """
 import argparse
@@ -31,9 +34,17 @@ RES_GATE = 1e-10
 WORKLOADS = {
     # Plain FP64 JD, M = 3 bimodal shock, Ny = 64, Nxi = 96 (n = 12,288), 20 nearest 0.05i,
     # block-Jacobi ILU(0) with 64 blocks (3 velocity lines each), GMRES(20).
-    "c2": ("config2", dict(lines_per_block=3, m_max=60, m_min=6, gmres_m=20)),
-    # M = 4 bimodal shock, Ny = 96, Nxi = 1464 (n = 281,088), 10 nearest 0.
-    "c3": ("config3", dict(lines_per_block=16, m_max=40, m_min=6, gmres_m=20)),
+    "c2": ("config2", dict(pc_kernel=1, lines_per_block=3, m_max=60, m_min=6, gmres_m=20)),
+    # M = 4 bimodal shock, Ny = 96, Nxi = 1464 (n = 281,088), 10 nearest 0, exact
+    # structured inverse as preconditioner; the nearest eigenvalues include members
+    # of a cluster 1e-6 wide, which needs the larger search space.
+    "c3": ("config3", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
+}
+# variants reported beside the c2 line (same workload, same residual gate)
+C2_VARIANTS = {
+    "mixed_fp32_inner": dict(precision=1),
+    "exact_structured_pc": dict(pc_kernel=2),
+    "exact_structured_pc_mixed": dict(pc_kernel=2, precision=1),
 }
 
 
@@ -45,6 +56,7 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
@@ -86,7 +98,14 @@ def kernel_roofline(ctx, wl, torch, reps):
     nl = ctx.options.lines_per_block
     nlines = 2 * wl.Nxi
     nblocks = (nlines + nl - 1) // nl
-    if ctx.options.pc_kernel == 1:
+    if ctx.options.pc_kernel == 2:
+        # two line-inverse passes (each reads the Nxi shared Ny x Ny inverses, x,
+        # writes y), the moment pass (reads y and M), the capacitance GEMV, and the
+        # rank update's U read in the second pass
+        Rd = 4 * wl.Ny
+        nbytes = 2 * 16 * wl.Nxi * wl.Ny * wl.Ny + 16 * 5 * n + 2 * 8 * 4 * n + 16 * Rd * Rd
+        kname = "structured exact inverse (2 x k_line_inverse + k_moments + k_capacitance)"
+    elif ctx.options.pc_kernel == 1:
         sizes = [min(nl, nlines - b * nl) * wl.Ny for b in range(nblocks)]
         nbytes = 16 * sum(s * s for s in sizes) + 32 * n
         kname = "k_blockinv_apply (block-Jacobi ILU(0), stored block inverse)"
@@ -125,9 +144,11 @@ def op_apply_rate(ctx, wl, torch, reps):
     return out
 
 
-def cpu_baseline(wl, seconds):
-    """The oracle's plain CPU Jacobi-Davidson on the same workload, stopped after
-    `seconds` of work (a bounded sample); rate = converged eigenpairs / time."""
+def cpu_baseline(wl, seconds, opts):
+    """The oracle's plain CPU Jacobi-Davidson on the same workload with the same
+    preconditioner (block-Jacobi ILU(0) over the same line blocks, or the exact
+    structured inverse), stopped after `seconds` of work (a bounded sample);
+    rate = converged eigenpairs / time."""
     import numpy as np
     from oracle import jd as OJ
     from oracle import operator as O
@@ -138,9 +159,14 @@ def cpu_baseline(wl, seconds):
         cores = os.cpu_count() or 1
     t0 = time.perf_counter()
     P = O.Pencil(wl)
-    K = OJ.LineBlockILU0(P, wl.sigma, WORKLOADS["c2"][1]["lines_per_block"])
+    if opts.get("pc_kernel", 2) == 2:
+        from oracle import eig as OE
+        K = OE.ShiftInvert(P, wl.sigma)
+    else:
+        K = OJ.LineBlockILU0(P, wl.sigma, opts["lines_per_block"])
     remaining = max(1.0, seconds - (time.perf_counter() - t0))
-    out = OJ.jd(P, wl.sigma, wl.nev, tol=RES_GATE, m_max=60, precond=K, time_limit=remaining)
+    out = OJ.jd(P, wl.sigma, wl.nev, tol=RES_GATE, m_max=opts["m_max"], gmres_m=opts["gmres_m"],
+                fix=opts.get("fix", 0.01), precond=K, time_limit=remaining)
     el = time.perf_counter() - t0
     good = int(np.sum(out["resid"] <= RES_GATE))
     return {"value": round(good / el, 6), "unit": "eigenpairs/s", "cores": int(cores),
@@ -149,7 +175,7 @@ def cpu_baseline(wl, seconds):
                       f"{good} eigenpairs converged, {out['outer']} outer iterations"}
 
 
-SWEEP_OPTS = dict(lines_per_block=2, m_max=30, m_min=6, gmres_m=20)
+SWEEP_OPTS = dict(pc_kernel=2, m_max=30, m_min=6, gmres_m=20)
 
 
 def _common(metric, unit, value, a, el, nsteps, dtype, config, extra):
@@ -165,7 +191,8 @@ def run_batched(a):
     """Batched stability sweep: `count` independent solves (seeded sweep draws:
     Ny in {24..64}, Nxi in {16..128}, beta, Mach, base type), 8 eigenpairs
     nearest 0 each.  Baseline: the same solves one after another with the plain
-    FP64 GPU JD; measured: FP32-inner / FP64-outer JD over concurrent slots."""
+    FP64 GPU JD; measured: the solves over concurrent slots in the requested
+    precision (the other precision is reported beside it)."""
     import numpy as np
     from paper_2607_27440_amd import klst, workloads
     wls = workloads.sweep(seed=4, count=a.count, nev=8)
@@ -180,18 +207,23 @@ def run_batched(a):
             st = sv.stats()
         good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in res)
         return good, el, res, st
+    prec = 0 if a.precision == "fp64" else 1
     log(f"[bench] batched: {len(wls)} solves, serial plain FP64 baseline")
     g0, e0, _, _ = run(1, 0)
-    log(f"[bench] baseline {g0} eigenpairs in {e0:.2f}s; now {a.slots} slots, mixed precision")
-    g1, e1, res, st = run(a.slots, 1)
+    log(f"[bench] baseline {g0} eigenpairs in {e0:.2f}s; now {a.slots} slots, {a.precision}")
+    g1, e1, res, st = run(a.slots, prec)
+    g2, e2, res2, _ = run(a.slots, 1 - prec)
     lat = [r["service_s"] for r in res]
-    cfg = {"workload": f"sweep_seed4_{len(wls)}_solves_nev8", "slots": a.slots, "precision": "mixed",
+    cfg = {"workload": f"sweep_seed4_{len(wls)}_solves_nev8", "slots": a.slots, "precision": a.precision,
            "max_it": a.max_it, **SWEEP_OPTS}
+    other = "mixed" if prec == 0 else "fp64"
     return _common("eigenpairs/s at rel. residual <= 1e-10 (batched sweep)", "eigenpairs/s", g1 / e1, a, e1,
-                   len(wls), "c64-inner/c128-outer", cfg,
+                   len(wls), "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
                    {"plain_fp64_serial": {"value": round(g0 / e0, 4), "seconds": round(e0, 3),
                                           "eigenpairs": g0},
                     "speedup_vs_plain_fp64_serial": round((g1 / e1) / (g0 / e0), 3),
+                    f"slots_{other}": {"value": round(g2 / e2, 4), "seconds": round(e2, 3), "eigenpairs": g2,
+                                       "unconverged_solves": int(sum(1 for r in res2 if r["status"] != 0))},
                     "eigenpairs": g1, "seconds": round(e1, 3), "peak_running": st["peak_running"],
                     "service_p50_s": round(float(np.percentile(lat, 50)), 4),
                     "unconverged_solves": int(sum(1 for r in res if r["status"] != 0))})
@@ -211,7 +243,8 @@ def run_served(a):
     reqs = [c2 if rng.uniform() < 0.05 else pool[i] for i in range(a.requests)]
     # saturated throughput (requests/s) of the served configuration, from a short batch
     rate = a.rate
-    with klst.Server(slots=a.slots, precision=1, max_it=a.max_it, **SWEEP_OPTS) as sv:
+    prec = 0 if a.precision == "fp64" else 1
+    with klst.Server(slots=a.slots, precision=prec, max_it=a.max_it, **SWEEP_OPTS) as sv:
         if rate <= 0:
             cal = reqs[: min(16, len(reqs))]
             t = time.perf_counter()
@@ -249,10 +282,10 @@ def run_served(a):
         lat_b.append(done - ta)
     lat_b = np.array(lat_b)
     cfg = {"workload": f"served_poisson_seed5_{len(reqs)}req_95pct_sweep_5pct_ny64_nxi96_nev8",
-           "slots": a.slots, "rate_per_s": round(rate, 4), "precision": "mixed", "max_it": a.max_it,
+           "slots": a.slots, "rate_per_s": round(rate, 4), "precision": a.precision, "max_it": a.max_it,
            **SWEEP_OPTS}
     return _common("eigenpairs/s at rel. residual <= 1e-10 (served sweep)", "eigenpairs/s", good / el, a,
-                   el, len(reqs), "c64-inner/c128-outer", cfg,
+                   el, len(reqs), "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
                    {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
                     "eigenpairs": good, "seconds": round(el, 3), "peak_running": st["peak_running"],
@@ -299,6 +332,27 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     value = good_total / el
+    variants = {}
+    if a.workload == "c2" and not a.no_variants:
+        for vname, vopt in C2_VARIANTS.items():
+            o = dict(opts, **vopt)
+            with klst.Context(stream=st.cuda_stream, **o) as vctx:
+                vctx.assemble(wl)
+                vctx.solve(wl.sigma, wl.nev, want_vectors=False)     # warm-up
+                torch.cuda.synchronize()
+                tv = time.perf_counter()
+                gv = 0
+                for _ in range(a.steps):
+                    vctx.assemble(wl)
+                    vo = vctx.solve(wl.sigma, wl.nev, want_vectors=False)
+                    gv += int(np.sum(vo["resid"] <= RES_GATE))
+                torch.cuda.synchronize()
+                ev = time.perf_counter() - tv
+            variants[vname] = {"value": round(gv / ev, 4), "ms_per_step": round(1e3 * ev / a.steps, 3),
+                               "speedup_vs_line": round((gv / ev) / value, 3),
+                               "outer": vo["stats"]["outer_iterations"], "inner": vo["stats"]["inner_iterations"],
+                               "options": vopt}
+            log(f"[bench] variant {vname}: {variants[vname]}")
     roof = kernel_roofline(ctx, wl, torch, a.kernel_reps)
     ops = op_apply_rate(ctx, wl, torch, max(20, a.kernel_reps // 4))
     line = {
@@ -320,9 +374,11 @@ def main():
         "op_apply": ops,
         "solve_stats": stats,
     }
+    if variants:
+        line["variants"] = variants
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds, opts)
     print(json.dumps(line), flush=True)
 
 

@@ -68,9 +68,14 @@ typedef struct {
   double inner_rtol;    /* correction-equation relative tolerance                    */
   double fix;           /* correction shift = sigma until rel. residual < fix        */
   uint64_t seed;        /* start vector: counter-based SplitMix64 stream             */
-  int pc_kernel;        /* preconditioner application: 0 = level-set triangular sweeps
-                           over the ILU(0) factors; 1 = the same (L U)^{-1} applied as
-                           a stored dense inverse per block (batched GEMV)           */
+  int pc_kernel;        /* preconditioner K ~ A - sigma B: 0 = block-Jacobi ILU(0)
+                           (Sec. 4.3) applied by level-set triangular sweeps; 1 = the
+                           same (L U)^{-1} applied as a stored dense inverse per block
+                           (batched GEMV); 2 = the exact inverse in structured form:
+                           velocity-line inverses of the streaming + relaxation part
+                           and the (r Ny)^2 moment capacitance (Woodbury identity),
+                           lines_per_block unused (the default).  Mixed precision
+                           needs 1 or 2.                                             */
   int inner_max_it;     /* GMRES steps per correction equation, over all restarts;
                            values <= gmres_m give one unrestarted cycle              */
 } klst_options;
@@ -112,7 +117,7 @@ typedef struct {
   int inner_iterations;      /* total GMRES steps                               */
   int restarts;
   int nconv;
-  int pivots_floored;        /* ILU(0) pivots raised to the floor (reading R9)  */
+  int pivots_floored;        /* ILU(0) pivots raised to 1e-12 x row 1-norm      */
   double seconds_total;      /* wall time of klst_solve                         */
   double seconds_setup;      /* preconditioner set-up inside klst_solve         */
   double seconds_op;         /* device time in operator applications (events)   */

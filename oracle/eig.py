@@ -22,7 +22,7 @@ import scipy.sparse.linalg as spla
 
 def order_nearest(lam, sigma):
     """Indices ordered by |lambda - sigma|, ties (to 1e-12 relative) broken with
-    Im lambda > 0 first (reading R12)."""
+    Im lambda > 0 first (conjugate pairs are equally near a real target)."""
     d = np.abs(lam - sigma)
     scale = max(1.0, float(np.max(d))) if d.size else 1.0
     key = np.round(d / (1e-12 * scale))
@@ -142,8 +142,8 @@ def left_vectors_si(P, lam, sigma, tol=1e-14):
 
 
 def residuals(P, lam, X):
-    """Relative residual ||A x - lambda B x|| / (|lambda| ||x||) (reading R6:
-    absolute residual over ||x|| when |lambda| < 1e-6)."""
+    """Relative residual ||A x - lambda B x|| / (|lambda| ||x||) (the acceptance
+    test of Sec. 4.2; absolute residual over ||x|| when |lambda| < 1e-6)."""
     if P.n <= 60000:
         R = P.A @ X - (P.B @ X) * lam[None, :]
     else:

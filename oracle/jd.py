@@ -9,7 +9,7 @@ approximately with preconditioned GMRES, orthogonalises the correction against
 the basis and appends it; at ncv vectors the basis is restarted to its k_min
 best directions.
 
-The paper's harmonic-Ritz formula is garbled (reading R5); this oracle uses
+The paper's harmonic-Ritz formula is not legible in its text; this oracle uses
 harmonic Petrov extraction with test space W = orth((I - Z Z^H)(A - sigma B) V)
 and deflation through a partial generalized Schur form (Q, Z, S_A, S_B), the
 JDQZ scheme of Fokkema, Sleijpen and van der Vorst (1998) that extends the
@@ -32,7 +32,7 @@ def splitmix64(z):
 
 
 def start_vector(n, seed, stream=0):
-    """Counter-based start vector (reading R8): with key = seed * 0x100000001B3 +
+    """Counter-based start vector (the paper leaves it unspecified): with key = seed * 0x100000001B3 +
     stream (mod 2^64) and U(c) = 2 * (splitmix64(key + c) >> 11) * 2^-53 - 1,
     entry i is U(2i) + i U(2i+1).  The caller masks inflow entries to zero."""
     key = np.uint64((int(seed) * 0x100000001B3 + int(stream)) % (1 << 64))

@@ -16,14 +16,15 @@ eq. Comp1DHarm, discretised as in eq. comp_ghat1Dshock)
 and U_a = G_a on g rows, H_a on h rows.  The G/H coefficients are deferred by the
 paper to another work; here they are the exact linearisation of the discrete BGK
 relaxation nu(m) (f^e(m) - f) about the base state, i.e. of eq. CompBGKtilde
-with P = rho T / 2 and mu ~ T^s (reading R2, pinned by a complex-step
-derivative of the nonlinear operator):
+with P = rho T / 2 and mu ~ T^s (the paper does not print them; this form is
+pinned by a complex-step derivative of the nonlinear operator):
   G_a = nu [ C_ga + (g^e - g_c) Lambda_a ],  H_a = nu [ C_ha + (h^e - h_c) Lambda_a ],
   C_ga = d g^e / d a,  C_ha = d h^e / d a,  Lambda_a = d ln P/da - d ln mu/da.
 
 Inflow rows (x = -s_inf with xi_x > 0, x = +s_inf with xi_x < 0; Sec. 2.2,
 zero-perturbation Dirichlet conditions) are identity rows of A and zero rows of
-B, so B = Z = diag(1 - bc) (reading R3).
+B, so B = Z = diag(1 - bc): the diagonal boundary-condition matrix Z of the
+nomenclature plays the role of B.
 """
 import numpy as np
 import scipy.sparse as sp

@@ -58,6 +58,9 @@ struct klst_ctx {
         *d_U32 = nullptr, *d_M32 = nullptr;
   float2* d_mom32 = nullptr;
   float2* d_Kinv32 = nullptr;
+  // structured exact inverse (pc_kernel 2): line inverses, capacitance inverse, d scratch
+  double2 *d_Pinv = nullptr, *d_Sinv = nullptr, *d_capd = nullptr;
+  float2 *d_Pinv32 = nullptr, *d_Sinv32 = nullptr, *d_capd32 = nullptr;
   // reductions
   double2* d_partial = nullptr;
   double2* d_npart = nullptr;     // per-workgroup norm partials (<= 2^16 workgroups)
@@ -116,6 +119,8 @@ void free_problem(klst_ctx* ctx) {
   dfree(ctx, ctx->d_F); dfree(ctx, ctx->d_C); dfree(ctx, ctx->d_Kinv); dfree(ctx, ctx->d_koff);
   dfree(ctx, ctx->d_Dx32); dfree(ctx, ctx->d_DxT32); dfree(ctx, ctx->d_xix32); dfree(ctx, ctx->d_xiy32); dfree(ctx, ctx->d_nu32); dfree(ctx, ctx->d_U32);
   dfree(ctx, ctx->d_M32); dfree(ctx, ctx->d_mom32); dfree(ctx, ctx->d_Kinv32);
+  dfree(ctx, ctx->d_Pinv); dfree(ctx, ctx->d_Sinv); dfree(ctx, ctx->d_capd);
+  dfree(ctx, ctx->d_Pinv32); dfree(ctx, ctx->d_Sinv32); dfree(ctx, ctx->d_capd32);
   ctx->mom_cap = 0;
   ctx->pc_ready = false;
   ctx->assembled = false;
@@ -184,6 +189,40 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
   ctx->pc_ready = false;
   const unsigned hw = std::thread::hardware_concurrency();
   const int nth = (int)std::max(1u, std::min(hw, 16u));
+  if (pk == 2) {
+    klst::StructuredInverse si;
+    const std::string e = klst::build_structured_inverse(p, sigma, si, nth);
+    if (!e.empty()) return fail(ctx, KLST_ENOCONV, e);
+    klst_status s;
+    if ((s = ensure_mom(ctx, 1)) != KLST_OK) return s;
+    auto put = [&](double2*& d64, float2*& d32, const std::vector<cd>& h) -> klst_status {
+      dfree(ctx, d64);
+      dfree(ctx, d32);
+      ALLOC(d64, sizeof(double2) * h.size());
+      HIPCHK(hipMemcpyAsync(d64, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, ctx->stream));
+      if (ctx->opt.precision == 1) {
+        std::vector<float2> h32(h.size());
+        for (size_t i = 0; i < h.size(); ++i) h32[i] = make_float2((float)h[i].real(), (float)h[i].imag());
+        ALLOC(d32, sizeof(float2) * h32.size());
+        HIPCHK(hipMemcpyAsync(d32, h32.data(), sizeof(float2) * h32.size(), hipMemcpyHostToDevice, ctx->stream));
+      }
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      return KLST_OK;
+    };
+    if ((s = put(ctx->d_Pinv, ctx->d_Pinv32, si.Pinv)) != KLST_OK) return s;
+    if ((s = put(ctx->d_Sinv, ctx->d_Sinv32, si.Sinv)) != KLST_OK) return s;
+    dfree(ctx, ctx->d_capd);
+    dfree(ctx, ctx->d_capd32);
+    ALLOC(ctx->d_capd, sizeof(double2) * (size_t)p.r * p.Ny);
+    if (ctx->opt.precision == 1) ALLOC(ctx->d_capd32, sizeof(float2) * (size_t)p.r * p.Ny);
+    ctx->ilu = klst::ILU0{};
+    ctx->pc_ready = true;
+    ctx->pc_sigma = sigma;
+    ctx->pc_lines = lines;
+    ctx->pc_kernel_built = pk;
+    ctx->stats.pivots_floored = 0;
+    return KLST_OK;
+  }
   klst::build_ilu0(p, sigma, lines, ctx->ilu, nth);
   dfree(ctx, ctx->d_Kinv);
   dfree(ctx, ctx->d_koff);
@@ -239,7 +278,10 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
 
 klst_status pc_apply(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
   const klst::Problem& p = ctx->prob;
-  if (ctx->pc_kernel_built == 1)
+  if (ctx->pc_kernel_built == 2)
+    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv, ctx->d_Sinv, ctx->d_M,
+                                         ctx->d_U, ctx->d_xix, ctx->d_mom, ctx->d_capd, skip);
+  else if (ctx->pc_kernel_built == 1)
     klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
                                      ctx->d_Kinv, ctx->d_koff, skip);
   else
@@ -269,8 +311,12 @@ klst_status pc_v(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
 }
 klst_status pc_v(klst_ctx* ctx, const float2* x, float2* y, const int* skip) {
   const klst::Problem& p = ctx->prob;
-  klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
-                                   ctx->d_Kinv32, ctx->d_koff, skip);
+  if (ctx->pc_kernel_built == 2)
+    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv32, ctx->d_Sinv32,
+                                         ctx->d_M32, ctx->d_U32, ctx->d_xix32, ctx->d_mom32, ctx->d_capd32, skip);
+  else
+    klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
+                                     ctx->d_Kinv32, ctx->d_koff, skip);
   HIPCHK(hipGetLastError());
   ctx->stats.pc_applies += 1;
   return KLST_OK;
@@ -348,7 +394,7 @@ void klst_default_options(klst_options* o) {
   o->inner_rtol = 1e-6;
   o->fix = 0.01;
   o->seed = 0;
-  o->pc_kernel = 1;
+  o->pc_kernel = 2;
   o->inner_max_it = 20;
 }
 
@@ -376,7 +422,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
-      (o.pc_kernel != 0 && o.pc_kernel != 1) || (o.precision == 1 && o.pc_kernel != 1) ||
+      o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
       o.inner_max_it < 1 || o.inner_max_it > 100000)
     return KLST_EINVAL;
   int ndev = 0;
@@ -1197,11 +1243,17 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
   const size_t nblocks = (2ull * Nxi + nl - 1) / nl;
   size_t b = 0;
   b += 8ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 8ull * Ny * 2 * r * Nxi + 16ull * Ny * r * 8;  // tables
-  b += 16ull * 2 * Nxi * Ny * Ny + 16ull * nblocks * nl * nl * Ny;                       // ILU factors
-  if (o.pc_kernel == 1) b += 16ull * nblocks * (size_t)(nl * Ny) * (nl * Ny) + 8 * (nblocks + 1);
+  const size_t Rd = r * (size_t)Ny;
+  if (o.pc_kernel == 2) {
+    b += 16ull * Nxi * Ny * Ny + 16ull * Rd * Rd + 16ull * Rd;                          // P^-1, S^-1, d
+  } else {
+    b += 16ull * 2 * Nxi * Ny * Ny + 16ull * nblocks * nl * nl * Ny;                     // ILU factors
+    if (o.pc_kernel == 1) b += 16ull * nblocks * (size_t)(nl * Ny) * (nl * Ny) + 8 * (nblocks + 1);
+  }
   if (o.precision == 1) {
     b += 4ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 4ull * Ny * 2 * r * Nxi + 8ull * Ny * r * 8;
-    b += 8ull * nblocks * (size_t)(nl * Ny) * (nl * Ny);
+    if (o.pc_kernel == 2) b += 8ull * Nxi * Ny * Ny + 8ull * Rd * Rd + 8ull * Rd;
+    else b += 8ull * nblocks * (size_t)(nl * Ny) * (nl * Ny);
     b += 8ull * n * ((gm + 1) + 2 * (nev + 1) + 3) + cvec;
   }
   if (o.op_mode == 1) {

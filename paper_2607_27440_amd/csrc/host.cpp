@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <thread>
 
 namespace klst {
@@ -273,7 +274,7 @@ static void ilu0_block(const Problem& p, cd sigma, int b, int nl_blk, int nl, IL
         const cd* Fm = F + (size_t)m * Ny;
         for (int q = m + 1; q < Ny; ++q) Fj[q] -= lm * Fm[q];
       }
-      // pivot floor (reading R9)
+      // pivot floor: |u_jj| >= 1e-12 x the row's 1-norm in A - sigma B
       const double fl_abs = 1e-12 * rownorm[j];
       const double a = std::abs(Fj[j]);
       if (a < fl_abs) {
@@ -562,6 +563,79 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
   std::copy(H.begin(), H.end(), To);
   std::copy(U.begin(), U.end(), Uo);
   return true;
+}
+
+std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads) {
+  const int Ny = p.Ny, Nxi = p.Nxi, r = p.r, Rd = r * Ny;
+  si.Ny = Ny;
+  si.Nxi = Nxi;
+  si.r = r;
+  const size_t blk = (size_t)Ny * Ny;
+  std::vector<cd> Prow((size_t)Nxi * blk);   // row-major line inverses
+  si.Pinv.assign((size_t)Nxi * blk, cd(0.0));
+  auto run = [&](int count, const std::function<void(int, int)>& work) {
+    const int nt = std::max(1, std::min(nthreads, count));
+    if (nt == 1) { work(0, 1); return; }
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t) th.emplace_back(work, t, nt);
+    for (auto& x : th) x.join();
+  };
+  std::vector<int> singular(Nxi, 0);
+  run(Nxi, [&](int t, int nt) {
+    std::vector<cd> a(blk);
+    for (int k = t; k < Nxi; k += nt) {
+      std::fill(a.begin(), a.end(), cd(0.0));
+      for (int j = 0; j < Ny; ++j) {
+        cd* aj = &a[(size_t)j * Ny];
+        if (p.is_bc(j, k)) { aj[j] = 1.0; continue; }
+        for (int m = 0; m < Ny; ++m) aj[m] = p.xi_x[k] * p.Dx[(size_t)j * Ny + m];
+        aj[j] += cd(p.nu[j], p.beta * p.xi_y[k]) - sigma;
+      }
+      cd* inv = &Prow[(size_t)k * blk];
+      if (!invert(Ny, a.data(), inv)) { singular[k] = 1; continue; }
+      cd* col = &si.Pinv[(size_t)k * blk];
+      for (int j = 0; j < Ny; ++j)
+        for (int m = 0; m < Ny; ++m) col[(size_t)m * Ny + j] = inv[(size_t)j * Ny + m];
+    }
+  });
+  for (int k = 0; k < Nxi; ++k)
+    if (singular[k]) return "singular velocity-line block at node " + std::to_string(k);
+  // G = M P^{-1} Ut:  G[(j,a),(j',b)] = sum_k P_k^{-1}[j][j'] sum_f M_a(j,f,k) Ut_b(j',f,k).
+  // Node-major copies of M and U keep the inner loops contiguous.
+  std::vector<double> Mt((size_t)Nxi * Ny * 2 * r), Ut((size_t)Nxi * Ny * 2 * r, 0.0);
+  for (int k = 0; k < Nxi; ++k)
+    for (int j = 0; j < Ny; ++j)
+      for (int f = 0; f < 2; ++f)
+        for (int a = 0; a < r; ++a) {
+          const size_t o = (((size_t)k * Ny + j) * 2 + f) * r + a;
+          Mt[o] = p.M[(((size_t)j * r + a) * 2 + f) * Nxi + k];
+          if (!p.is_bc(j, k)) Ut[o] = p.U[(((size_t)j * 2 + f) * r + a) * Nxi + k];
+        }
+  std::vector<cd> S((size_t)Rd * Rd, cd(0.0));
+  run(Ny, [&](int t, int nt) {
+    std::vector<double> g((size_t)r * r);
+    for (int j = t; j < Ny; j += nt) {
+      for (int k = 0; k < Nxi; ++k) {
+        const cd* prow = &Prow[(size_t)k * blk + (size_t)j * Ny];
+        const double* mj = &Mt[((size_t)k * Ny + j) * 2 * r];
+        for (int jp = 0; jp < Ny; ++jp) {
+          const double* uj = &Ut[((size_t)k * Ny + jp) * 2 * r];
+          for (int a = 0; a < r; ++a)
+            for (int b = 0; b < r; ++b) g[(size_t)a * r + b] = mj[a] * uj[b] + mj[r + a] * uj[r + b];
+          const cd w = prow[jp];
+          for (int a = 0; a < r; ++a) {
+            cd* srow = &S[((size_t)j * r + a) * Rd + (size_t)jp * r];
+            for (int b = 0; b < r; ++b) srow[b] += w * g[(size_t)a * r + b];
+          }
+        }
+      }
+    }
+  });
+  for (auto& v : S) v = -v;
+  for (int q = 0; q < Rd; ++q) S[(size_t)q * Rd + q] += 1.0;
+  si.Sinv.assign((size_t)Rd * Rd, cd(0.0));
+  if (!invert(Rd, S.data(), si.Sinv.data())) return "singular moment capacitance matrix";
+  return std::string();
 }
 
 bool invert(int m, const cd* A, cd* Ainv) {

@@ -53,6 +53,20 @@ void build_ilu0(const Problem& p, cd sigma, int lines_per_block, ILU0& f, int nt
 void build_block_inverse(const ILU0& f, std::vector<cd>& Kinv, std::vector<int64_t>& off,
                          int nthreads);
 
+// Exact inverse of (A - sigma B) in structured form (Woodbury identity):
+// A - sigma B = P - Ut M, P block diagonal over the velocity lines with a block
+// that depends on the velocity node only, P_k = xi_x,k D_x + diag(nu_j + i beta
+// xi_y,k - sigma) with unit inflow rows, and Ut M the rank-(r Ny) moment coupling
+// (coupling columns U with inflow rows zeroed).  Then
+// (A - sigma B)^{-1} = P^{-1} + P^{-1} Ut S^{-1} M P^{-1}, S = I - M P^{-1} Ut.
+struct StructuredInverse {
+  int Ny = 0, Nxi = 0, r = 0;
+  std::vector<cd> Pinv;   // [Nxi][Ny x Ny], column-major: entry (j, m) at m Ny + j
+  std::vector<cd> Sinv;   // [(r Ny) x (r Ny)], row-major, index q = j r + a
+};
+// Returns an empty string on success, else why (a singular line block or capacitance).
+std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads);
+
 // ---- small dense complex matrices, row-major m x m ----
 // Sorted Schur form: G U = U T, T upper triangular, |T_00| >= |T_11| >= ...
 // Returns false if the QR iteration failed to converge.

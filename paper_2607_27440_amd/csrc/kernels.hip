@@ -667,6 +667,118 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict_
   }
 }
 
+// ------------------------------------- structured exact (A - sigma B)^{-1} ----
+//
+// A - sigma B = P - Ut M: P is block diagonal over the velocity lines and its
+// block depends on the velocity node k only, P_k = xi_x,k D_x + diag(nu_j + i beta
+// xi_y,k - sigma) with unit inflow rows; Ut M is the rank-r moment coupling of
+// every node j (U with inflow rows zeroed).  By the Woodbury identity
+//   (A - sigma B)^{-1} x = P^{-1} (x + Ut d),  d = S^{-1} M P^{-1} x,
+// with the (r Ny) x (r Ny) capacitance S = I - M P^{-1} Ut (index q = j r + a).
+
+// y = P^{-1} (x + Ut d) for both fields of node k, reading P_k^{-1} once for the
+// two right-hand sides; d == nullptr skips the rank update.  Pinv: [Nxi][Ny x Ny]
+// column-major.  Lanes own rows, the 4 wavefronts split the columns and their
+// partial sums are added in fixed order.  grid ((Ny + 63) / 64, Nxi), block 256,
+// dynamic LDS (2 Ny + 512) * sizeof(cv<R>).
+template <class R>
+__global__ void __launch_bounds__(256) k_line_inverse(const cv<R>* __restrict__ x,
+                                                      cv<R>* __restrict__ y, int Ny, int Nxi,
+                                                      int r, const cv<R>* __restrict__ Pinv,
+                                                      const R* __restrict__ U,
+                                                      const R* __restrict__ xix,
+                                                      const cv<R>* __restrict__ d,
+                                                      const int* __restrict__ skip) {
+  extern __shared__ unsigned char lds_raw[];
+  cv<R>* xs = reinterpret_cast<cv<R>*>(lds_raw);   // [2][Ny]
+  cv<R>* part = xs + 2 * Ny;                        // [2][4][64]
+  if (skip && *skip) return;
+  const int k = blockIdx.y;
+  const R xk = xix[k];
+  for (int c = threadIdx.x; c < 2 * Ny; c += 256) {
+    const int f = c / Ny, m = c - f * Ny;
+    cv<R> v = x[((int64_t)2 * m + f) * Nxi + k];
+    const bool inflow = (m == Ny - 1 && xk > 0) || (m == 0 && xk < 0);
+    if (d && !inflow) {
+      for (int b = 0; b < r; ++b) {
+        const R u = U[(((int64_t)m * 2 + f) * r + b) * Nxi + k];
+        const cv<R> db = d[m * r + b];
+        v.x += u * db.x;
+        v.y += u * db.y;
+      }
+    }
+    xs[c] = v;
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 64 + lane;
+  const cv<R>* K = Pinv + (int64_t)k * Ny * Ny;
+  cv<R> a0 = mk<R>(0, 0), a1 = mk<R>(0, 0);
+  if (row < Ny) {
+    const int cper = (Ny + 3) / 4;
+    const int cb = wv * cper, ce = min(Ny, cb + cper);
+    int c = cb;
+    for (; c + 8 <= ce; c += 8) {
+      cv<R> kv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) kv[u] = K[(int64_t)(c + u) * Ny + row];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a0 = cadd(a0, cmul(kv[u], xs[c + u]));
+        a1 = cadd(a1, cmul(kv[u], xs[Ny + c + u]));
+      }
+    }
+    for (; c < ce; ++c) {
+      const cv<R> kv = K[(int64_t)c * Ny + row];
+      a0 = cadd(a0, cmul(kv, xs[c]));
+      a1 = cadd(a1, cmul(kv, xs[Ny + c]));
+    }
+  }
+  part[wv * 64 + lane] = a0;
+  part[256 + wv * 64 + lane] = a1;
+  __syncthreads();
+  if (wv < 2 && row < Ny) {
+    const cv<R>* pf = part + wv * 256;
+    cv<R> rr = pf[lane];
+    rr = cadd(rr, pf[64 + lane]);
+    rr = cadd(rr, pf[128 + lane]);
+    rr = cadd(rr, pf[192 + lane]);
+    y[((int64_t)2 * row + wv) * Nxi + k] = rr;
+  }
+}
+
+// d = S^{-1} c with c_q = m_a(j), q = j r + a, summed from the moment partials in
+// fixed order.  One wavefront per row of S^{-1} (row-major, Rd x Rd, Rd = r Ny),
+// FP64 accumulation.  grid ceil(Rd / 4), block 256, dynamic LDS Rd * sizeof(cv<R>).
+template <class R>
+__global__ void __launch_bounds__(256) k_capacitance(const cv<R>* __restrict__ mom, int Ny, int r,
+                                                     int S, const cv<R>* __restrict__ Sinv,
+                                                     cv<R>* __restrict__ d,
+                                                     const int* __restrict__ skip) {
+  extern __shared__ unsigned char lds_raw[];
+  cv<R>* cs = reinterpret_cast<cv<R>*>(lds_raw);
+  if (skip && *skip) return;
+  const int Rd = r * Ny;
+  for (int q = threadIdx.x; q < Rd; q += 256) {
+    const int j = q / r, a = q - j * r;
+    cs[q] = mom_at<R>(mom, 0, Ny, j, a, r, S);
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = blockIdx.x * 4 + wv;
+  if (q >= Rd) return;
+  double dr = 0.0, di = 0.0;
+  const cv<R>* srow = Sinv + (int64_t)q * Rd;
+  for (int c = lane; c < Rd; c += 64) {
+    const cv<R> sv = srow[c], xv = cs[c];
+    dr += (double)sv.x * xv.x - (double)sv.y * xv.y;
+    di += (double)sv.x * xv.y + (double)sv.y * xv.x;
+  }
+  dr = wave_sum(dr);
+  di = wave_sum(di);
+  if (lane == 0) d[q] = mk<R>((R)dr, (R)di);
+}
+
 // ------------------------------------------------------- vector kernels ----
 
 // ---- two-phase deterministic reductions (no cross-workgroup synchronisation) ----
@@ -1126,6 +1238,35 @@ void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny,
 void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int nl,
                            int nblocks, const float2* Kinv, const int64_t* koff, const int* skip) {
   blockinv_t<float>(st, x, y, Ny, Nxi, nl, nblocks, Kinv, koff, skip);
+}
+
+template <class R>
+static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r,
+                         const cv<R>* Pinv, const cv<R>* Sinv, const R* M, const R* U, const R* xix,
+                         cv<R>* mom, cv<R>* d, const int* skip) {
+  const size_t lds = (size_t)(2 * Ny + 512) * sizeof(cv<R>);
+  const dim3 grid((Ny + 63) / 64, Nxi);
+  hipLaunchKernelGGL((k_line_inverse<R>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
+                     (const cv<R>*)nullptr, skip);
+  const int64_t n = 2LL * Ny * Nxi;
+  moments_t<R>(st, y, n, 1, Ny, Nxi, r, M, mom, skip);
+  const int Rd = r * Ny;
+  const int S = moment_splits(Ny, 1, Nxi);
+  hipLaunchKernelGGL((k_capacitance<R>), dim3((Rd + 3) / 4), dim3(256), (size_t)Rd * sizeof(cv<R>), st, mom,
+                     Ny, r, S, Sinv, d, skip);
+  hipLaunchKernelGGL((k_line_inverse<R>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
+                     (const cv<R>*)d, skip);
+}
+void launch_structured_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
+                               const double2* Pinv, const double2* Sinv, const double* M,
+                               const double* U, const double* xix, double2* mom, double2* d,
+                               const int* skip) {
+  structured_t<double>(st, x, y, Ny, Nxi, r, Pinv, Sinv, M, U, xix, mom, d, skip);
+}
+void launch_structured_inverse(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int r,
+                               const float2* Pinv, const float2* Sinv, const float* M, const float* U,
+                               const float* xix, float2* mom, float2* d, const int* skip) {
+  structured_t<float>(st, x, y, Ny, Nxi, r, Pinv, Sinv, M, U, xix, mom, d, skip);
 }
 
 // Chunking for k_dot_partial: about 2048 wavefronts in total, at least 256

@@ -26,12 +26,13 @@ def _small_sweep(k=8, nev=6):
     return wls
 
 
+@pytest.mark.parametrize("pc_kernel", [1, 2])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_results_identical_alone_and_in_mix(precision):
+def test_results_identical_alone_and_in_mix(precision, pc_kernel):
     klst = _klst()
     wls = _small_sweep()
-    print("[case] sizes", [w.n for w in wls], "precision", precision, flush=True)
-    opts = dict(lines_per_block=2, m_max=30, precision=precision)
+    print("[case] sizes", [w.n for w in wls], "precision", precision, "pc", pc_kernel, flush=True)
+    opts = dict(lines_per_block=2, m_max=30, precision=precision, pc_kernel=pc_kernel)
     with klst.Server(slots=1, **opts) as alone:
         ref = [alone.solve_all([wl])[0] for wl in wls]
     with klst.Server(slots=4, **opts) as mix:
@@ -96,7 +97,7 @@ def test_cancel_running_and_queued():
 def test_served_eigenpairs_match_oracle():
     klst = _klst()
     wls = _small_sweep(3)
-    with klst.Server(slots=3, want_vectors=True, lines_per_block=2, m_max=30, precision=1) as sv:
+    with klst.Server(slots=3, want_vectors=True, lines_per_block=2, m_max=30, precision=1, pc_kernel=1) as sv:
         res = sv.solve_all(wls)
     for wl, r in zip(wls, res):
         P = O.Pencil(wl)
