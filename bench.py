@@ -35,6 +35,9 @@ WORKLOADS = {
     # Plain FP64 JD, M = 3 bimodal shock, Ny = 64, Nxi = 96 (n = 12,288), 20 nearest 0.05i,
     # block-Jacobi ILU(0) with 64 blocks (3 velocity lines each), GMRES(20).
     "c2": ("config2", dict(pc_kernel=1, lines_per_block=3, m_max=60, m_min=6, gmres_m=20)),
+    # config 2 with the exact structured inverse as preconditioner (the variant of
+    # the c2 line, selectable on its own for profiling)
+    "c2x": ("config2", dict(pc_kernel=2, m_max=60, m_min=6, gmres_m=20)),
     # M = 4 bimodal shock, Ny = 96, Nxi = 1464 (n = 281,088), 10 nearest 0, exact
     # structured inverse as preconditioner; the nearest eigenvalues include members
     # of a cluster 1e-6 wide, which needs the larger search space.
@@ -59,7 +62,7 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served"])
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "profile"])
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--count", type=int, default=64, help="batched: number of sweep solves")
     ap.add_argument("--requests", type=int, default=80, help="served: number of requests")
@@ -119,15 +122,22 @@ def kernel_roofline(ctx, wl, torch, reps):
             "avg_us": round(sec * 1e6, 3), "bytes_per_launch": nbytes}
 
 
-def op_apply_rate(ctx, wl, torch, reps):
-    """Matrix-free (A - tau B) x and CSR SpMV rates on this workload (events)."""
+def op_apply_rate(ctx, wl, torch, reps, nvec=64):
+    """Matrix-free (A - tau B) x (one vector, and nvec vectors in one launch so the
+    working set exceeds the 256 MB Infinity Cache) and CSR SpMV rates on this
+    workload (events).  Bytes: vectors in and out, U and M tables once per launch
+    (CSR: 20 B per stored entry)."""
     n = wl.n
     x = torch.randn(n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
+    xm = torch.randn(nvec * n, dtype=torch.complex128, device="cuda")
+    ym = torch.empty_like(xm)
     st = torch.cuda.current_stream()
     out = {}
+    tables = 8 * 2 * 2 * 4 * wl.Nxi * wl.Ny
     for name, fn, nbytes in (
-            ("matrix_free", ctx.apply, 32 * n + 8 * 2 * 2 * 4 * wl.Nxi * wl.Ny),
+            ("matrix_free", ctx.apply, 32 * n + tables),
+            (f"matrix_free_x{nvec}", lambda t, a, b: ctx.apply_many(t, nvec, xm, ym), 32 * n * nvec + tables),
             ("csr", ctx.apply_csr, 20 * ctx.nnz + 8 * (n + 1) + 32 * n)):
         for _ in range(3):
             fn(0.0, x, y)
@@ -294,6 +304,46 @@ def run_served(a):
                                           "p99_latency_s": round(float(np.percentile(lat_b, 99)), 4)}})
 
 
+def run_profile(a):
+    """Kernel-only run for rocprofv3 (timing and HBM counters): the workload's
+    preconditioner apply and matrix-free operator apply, `kernel_reps` times each,
+    then a plain 256 MiB device copy (`kernel_reps` times) whose known traffic
+    (read 256 MiB, write 256 MiB per dispatch) calibrates FETCH_SIZE / WRITE_SIZE.
+    Prints one JSON line with the event-timed averages."""
+    import torch
+    from paper_2607_27440_amd import klst, workloads
+    gen, opts = WORKLOADS[a.workload]
+    wl = getattr(workloads, gen)()
+    st = torch.cuda.current_stream()
+    out = {"mode": "profile", "workload": wl.name, "options": opts}
+    with klst.Context(stream=st.cuda_stream, **opts) as ctx:
+        ctx.assemble(wl)
+        out["precond"] = kernel_roofline(ctx, wl, torch, a.kernel_reps)
+        x = torch.randn(wl.n, dtype=torch.complex128, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            ctx.apply(0.0, x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(a.kernel_reps):
+            ctx.apply(0.0, x, y)
+        e1.record(st)
+        torch.cuda.synchronize()
+        out["apply_us"] = round(e0.elapsed_time(e1) * 1e3 / a.kernel_reps, 3)
+    src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    dst.copy_(src)
+    e0.record(st)
+    for _ in range(a.kernel_reps):
+        dst.copy_(src)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / a.kernel_reps
+    out["copy_256MiB"] = {"avg_us": round(sec * 1e6, 3), "GB/s": round(2 * (256 << 20) / sec / 1e9, 1)}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -301,7 +351,10 @@ def main():
         sys.exit(2)
     if a.mode != "single":
         import torch  # noqa: F401  (device initialisation)
-        line = run_batched(a) if a.mode == "batched" else run_served(a)
+        if a.mode == "profile":
+            line = run_profile(a)
+        else:
+            line = run_batched(a) if a.mode == "batched" else run_served(a)
         print(json.dumps(line), flush=True)
         return
     import numpy as np
@@ -348,7 +401,12 @@ def main():
                     gv += int(np.sum(vo["resid"] <= RES_GATE))
                 torch.cuda.synchronize()
                 ev = time.perf_counter() - tv
+            diff = None
+            if vo["nconv"] == out["nconv"] and out["nconv"] > 0:
+                d = [np.min(np.abs(out["lam"] - lv)) / abs(lv) for lv in vo["lam"]]
+                diff = float(max(d))
             variants[vname] = {"value": round(gv / ev, 4), "ms_per_step": round(1e3 * ev / a.steps, 3),
+                               "max_rel_eig_diff_vs_line": diff,
                                "speedup_vs_line": round((gv / ev) / value, 3),
                                "outer": vo["stats"]["outer_iterations"], "inner": vo["stats"]["inner_iterations"],
                                "options": vopt}

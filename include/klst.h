@@ -78,6 +78,10 @@ typedef struct {
                            needs 1 or 2.                                             */
   int inner_max_it;     /* GMRES steps per correction equation, over all restarts;
                            values <= gmres_m give one unrestarted cycle              */
+  int reorth;           /* GMRES Arnoldi orthogonalisation: 0 = classical Gram-Schmidt
+                           twice (CGS2, the default); 1 = second pass only when the
+                           first keeps less than 1/sqrt(2) of the norm (DGKS test,
+                           on the device)                                            */
 } klst_options;
 
 /* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]
@@ -170,13 +174,18 @@ klst_status klst_precond_setup(klst_ctx* ctx, const double sigma[2]);
 klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
 
 /* Jacobi-Davidson solve for the nev eigenvalues nearest sigma (Sec. 4.2).
+ * Pairs are locked as they converge; once nev are locked the iteration goes on
+ * until a newly locked eigenvalue is not nearer sigma than the nev-th nearest
+ * locked one (at most min(2 nev, 100, 250 - m_max) pairs are locked), and the
+ * nev nearest are returned, ordered by |lambda - sigma| (ties: Im lambda > 0
+ * first).
  * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at
  * X + 2 n i doubles), on the host or the device (X_on_device), or NULL.
  * Eigenvectors are scaled to unit 2-norm with the largest entry real positive.
  * resid: [nev] host relative residuals ||A x - lambda B x|| / (|lambda| ||x||),
  * or NULL.  nconv: converged count.  Returns ENOCONV (with nconv < nev valid
- * results) when max_it is reached.  Errors: ESTATE, EINVAL (nev < 1 or
- * nev > n - n_bc or nev + m_min > m_max), ENOMEM, EDEVICE. */
+ * results) when max_it is reached before nev pairs converge.  Errors: ESTATE,
+ * EINVAL (nev < 1, nev > min(100, n - n_bc), nev + m_max > 250), ENOMEM, EDEVICE. */
 klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* lambda,
                        void* X, int X_on_device, double* resid, int* nconv);
 

@@ -162,7 +162,18 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
     t = Bd * start_vector(n, seed)
     outer = inner = 0
     restarts = 0
-    while Q.shape[1] < nev and outer < max_it:
+    # the result is the nev eigenvalues nearest sigma, and JD locks pairs in the
+    # order they converge: after nev are locked, go on until a newly locked
+    # eigenvalue is not nearer than the nev-th nearest locked one (beyond it, or
+    # tied as a conjugate partner is for a real target), then keep the nev nearest
+    kcap = min(2 * nev, 100, 250 - m_max)
+    complete = False
+
+    def passed_nearest():
+        d = np.abs(np.diag(SA) / np.diag(SB) - sigma)
+        return d[-1] >= np.sort(d)[nev - 1] * (1 - 1e-12)
+
+    while not complete and outer < max_it:
         if time_limit is not None and time.perf_counter() - t_start > time_limit:
             break
         outer += 1
@@ -226,12 +237,14 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
             W = W @ UL[:, 1:]
             R = SR[1:, 1:]
             MB = MBr[1:, 1:]
-            if Q.shape[1] >= nev:
+            k = Q.shape[1]
+            if k >= kcap or (k > nev and passed_nearest()) or (k >= nev and V.shape[1] == 0):
+                complete = True
                 break
             if V.shape[1] == 0:
                 rn = None
                 break
-        if Q.shape[1] >= nev:
+        if complete:
             break
         if rn is None:            # search space emptied by deflation: fresh start
             t = Bd * start_vector(n, seed, stream=outer)
@@ -255,7 +268,8 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
         rhs = -proj(K.solve(r))
         t, steps = gmres_restarted(F, rhs, gmres_m, inner_rtol, inner_max_it or gmres_m)
         inner += steps
-    # eigenpairs of the upper-triangular pencil (S_A, S_B), mapped back through Q
+    # eigenpairs of the upper-triangular pencil (S_A, S_B), mapped back through Q;
+    # the nev nearest the target are returned
     k = Q.shape[1]
     lam = np.array([SA[i, i] / SB[i, i] for i in range(k)])
     X = np.zeros((n, k), complex)
@@ -270,10 +284,31 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
         imax = int(np.argmax(np.abs(x)))
         x = x * (abs(x[imax]) / x[imax])
         X[:, i] = x
+    keep = _nearest_first(lam, sigma)[:nev]
+    lam, X = lam[keep], X[:, keep]
     res = np.linalg.norm(A @ X - (Bd[:, None] * X) * lam[None, :], axis=0)
     res = res / np.where(np.abs(lam) < 1e-6, 1.0, np.abs(lam))
-    return dict(lam=lam, X=X, resid=res, outer=outer, inner=inner, nconv=k,
+    return dict(lam=lam, X=X, resid=res, outer=outer, inner=inner, nconv=len(lam),
                 restarts=restarts, seconds=time.perf_counter() - t_start)
+
+
+def _nearest_first(lam, sigma):
+    """Indices by |lambda - sigma|; within 1e-12 relative, Im lambda > 0 first,
+    then the given order."""
+    d = np.abs(np.asarray(lam) - sigma)
+    keys = [(d[i], i) for i in range(len(d))]
+    out = []
+    for _, i in sorted(keys):
+        out.append(i)
+    # stable pass for ties: group within 1e-12 relative, positive imaginary first
+    res, g = [], []
+    for i in out:
+        if g and abs(d[i] - d[g[0]]) > 1e-12 * max(d[i], d[g[0]]):
+            res += sorted(g, key=lambda j: (not np.imag(lam[j]) > 0, g.index(j)))
+            g = []
+        g.append(i)
+    res += sorted(g, key=lambda j: (not np.imag(lam[j]) > 0, g.index(j)))
+    return np.array(res, dtype=int)
 
 
 class LineBlockILU0:

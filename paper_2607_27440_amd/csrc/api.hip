@@ -189,6 +189,16 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma) {
   ctx->pc_ready = false;
   const unsigned hw = std::thread::hardware_concurrency();
   const int nth = (int)std::max(1u, std::min(hw, 16u));
+  // dynamic LDS of the apply kernels stays within 64 KiB per workgroup: the block
+  // GEMV stages nl Ny inputs plus up to 16 x 64 partial sums, the line inverse 2 Ny
+  // inputs plus 2 x 16 x 64, the capacitance GEMV its r Ny right-hand side
+  const size_t lds_max = 64 * 1024;
+  if (pk == 2 && (16 * (2 * (size_t)p.Ny + 2048) > lds_max || 16 * (size_t)p.r * p.Ny > lds_max))
+    return fail(ctx, KLST_EINVAL, "Ny too large for the structured inverse (Ny <= 1024)");
+  if (pk == 0 && 16 * (size_t)lines * p.Ny > lds_max)
+    return fail(ctx, KLST_EINVAL, "lines_per_block * Ny too large for the level-set sweeps (<= 4096)");
+  if (pk == 1 && 16 * ((size_t)lines * p.Ny + 1024) > lds_max)
+    return fail(ctx, KLST_EINVAL, "lines_per_block * Ny too large for the stored block inverse (<= 3072)");
   if (pk == 2) {
     klst::StructuredInverse si;
     const std::string e = klst::build_structured_inverse(p, sigma, si, nth);
@@ -396,6 +406,7 @@ void klst_default_options(klst_options* o) {
   o->seed = 0;
   o->pc_kernel = 2;
   o->inner_max_it = 20;
+  o->reorth = 0;
 }
 
 const char* klst_strerror(klst_status s) {
@@ -423,7 +434,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
       o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
-      o.inner_max_it < 1 || o.inner_max_it > 100000)
+      o.inner_max_it < 1 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1))
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -661,9 +672,13 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   Workspace ws{ctx, n, {}};
   double2* V = ws.vec(m_max + 1);
   double2* W = ws.vec(m_max + 1);
-  double2* Qb = ws.vec(nev + 1);
-  double2* Zb = ws.vec(nev + 1);
-  double2* Yb = ws.vec(nev + 1);
+  // up to kcap pairs are locked: after nev, JD goes on until a newly locked
+  // eigenvalue is not nearer than the nev-th nearest locked one (it has moved past
+  // the nev nearest, so none of them was skipped), then returns the nev nearest
+  const int kcap = std::min({2 * nev, 100, 250 - m_max});
+  double2* Qb = ws.vec(kcap + 1);
+  double2* Zb = ws.vec(kcap + 1);
+  double2* Yb = ws.vec(kcap + 1);
   double2* Gb = ws.vec(gm + 1);
   double2* Tmp = ws.vec(m_max);
   double2* tv = ws.vec(1);
@@ -679,8 +694,8 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
          *d32 = nullptr;
   if (mixed) {
     Gb32 = ws.vec32(gm + 1);
-    Q32 = ws.vec32(nev + 1);
-    Y32 = ws.vec32(nev + 1);
+    Q32 = ws.vec32(kcap + 1);
+    Y32 = ws.vec32(kcap + 1);
     a32 = ws.vec32(1);
     b32 = ws.vec32(1);
     d32 = ws.vec32(1);
@@ -701,10 +716,11 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   double2* d_yk = ws.small<double2>(gm + 1);
   int* d_done = ws.small<int>(4);
   int* d_steps = ws.small<int>(4);
+  int* d_reorth = ws.small<int>(4);   // skip flag of the second Gram-Schmidt pass
   double* d_beta = ws.small<double>(2);
   if (!V || !W || !Qb || !Zb || !Yb || !Gb || !Tmp || !tv || !uv || !zv || !rv || !av || !bv || !d_c || !d_cw ||
       !d_c2 || !d_small || !d_coef || !d_Hinv || !d_H || !d_cs || !d_sn || !d_g || !d_yk || !d_done ||
-      !d_steps || !d_beta)
+      !d_steps || !d_beta || !d_reorth)
     return KLST_ENOMEM;
   double2* partial = ctx->d_partial;
   std::vector<double2> hsmall(SM);
@@ -823,8 +839,18 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     R.swap(Rn);
   };
 
+  // is the last locked eigenvalue not nearer than the nev-th nearest of those
+  // locked (beyond it, or tied with it as a conjugate partner is for a real target)?
+  auto passed_nearest = [&]() {
+    std::vector<double> d(k);
+    for (int i = 0; i < k; ++i) d[i] = std::abs(SA[(size_t)i * k + i] / SB[(size_t)i * k + i] - sigma);
+    const double last = d[k - 1];
+    std::nth_element(d.begin(), d.begin() + (nev - 1), d.end());
+    return last >= d[nev - 1] * (1.0 - 1e-12);
+  };
   klst_status status = KLST_OK;
-  while (k < nev) {
+  bool complete = false;
+  while (!complete) {
     if (outer >= o.max_it) { status = KLST_ENOCONV; break; }
     if (ctx->cancel && *ctx->cancel) { status = KLST_ECANCELLED; break; }
     ++outer;
@@ -935,10 +961,10 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       }
       project(1, m - 1);
       --m;
-      if (k >= nev) break;
+      if (k >= kcap || (k > nev && passed_nearest()) || (k >= nev && m == 0)) { complete = true; break; }
       if (m == 0) break;
     }
-    if (k >= nev) break;
+    if (complete) break;
     if (!have_pair) {
       // search space emptied by deflation: start again from a fresh vector
       start_vector(p, o.seed, (uint64_t)outer, h_t);
@@ -976,14 +1002,22 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
         int nch = launch_dot_partial(st, Qt0, kq, ut, 1, gj1, n, partial, 0, d_done);
         launch_subm_fused(st, Yt0, kq + 1, (const V*)nullptr, 0, partial, nch, d_Hinv, nullptr, nullptr,
                           gj1, n, nullptr, d_done);
-        // CGS2 against the Krylov basis, coefficients into Hessenberg column j
+        // Classical Gram-Schmidt against the Krylov basis, coefficients into
+        // Hessenberg column j; with reorth = 1 the second pass runs only when the
+        // DGKS test on the device asks for it (the first pass kept less than
+        // 1/sqrt(2) of ||x||), with reorth = 0 always
         double2* hcol = d_H + (size_t)j * (gm + 1);
-        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 0, d_done);
+        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 1, d_done);
         launch_subm_fused(st, Gbp, j + 1, (const V*)nullptr, 0, partial, nch, nullptr, hcol, nullptr, gj1, n,
-                          nullptr, d_done);
-        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 0, d_done);
-        launch_subm_fused(st, Gbp, j + 1, (const V*)nullptr, 0, partial, nch, nullptr, nullptr, hcol, gj1, n,
                           npart, d_done);
+        const int* skip2 = d_done;
+        if (o.reorth == 1) {
+          launch_reorth_test(st, partial, j + 1, nch, n, npart, 0.5, d_done, d_reorth);
+          skip2 = d_reorth;
+        }
+        nch = launch_dot_partial(st, Gbp, j + 1, (const V*)nullptr, 0, gj1, n, partial, 0, skip2);
+        launch_subm_fused(st, Gbp, j + 1, (const V*)nullptr, 0, partial, nch, nullptr, nullptr, hcol, gj1, n,
+                          npart, skip2);
         // h[j+1] = ||gj1||, Givens update, gj1 /= ||gj1||
         launch_scale_norm(st, gj1, (V*)nullptr, n, npart, d_small + 2, d_H, gm + 1, j, d_cs, d_sn, d_g,
                           d_done, d_steps, d_beta, o.inner_rtol);
@@ -1108,26 +1142,42 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     if (status == KLST_ENOCONV && !need_fresh) inner += st_prev;
   }
 
-  // ---- eigenpairs of the triangular pencil (S_A, S_B), x_i = Q s_i
-  const int nconv = k;
-  std::vector<cd> lam(nconv), Sv((size_t)nconv * nconv, 0.0);
-  for (int i = 0; i < nconv; ++i) {
-    lam[i] = SA[(size_t)i * k + i] / SB[(size_t)i * k + i];
-    Sv[(size_t)i * nconv + i] = 1.0;
+  // nev converged pairs count as success even if max_it stopped the completion check
+  if (status == KLST_ENOCONV && k >= nev) status = KLST_OK;
+  // ---- eigenpairs of the triangular pencil (S_A, S_B), x_i = Q s_i, of all k locked
+  std::vector<cd> lam_all(k), Sv((size_t)k * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    lam_all[i] = SA[(size_t)i * k + i] / SB[(size_t)i * k + i];
+    Sv[(size_t)i * k + i] = 1.0;
     for (int q = i - 1; q >= 0; --q) {
       cd acc = 0.0;
       for (int t = q + 1; t <= i; ++t)
-        acc += (SA[(size_t)q * k + t] - lam[i] * SB[(size_t)q * k + t]) * Sv[(size_t)t * nconv + i];
-      const cd d = SA[(size_t)q * k + q] - lam[i] * SB[(size_t)q * k + q];
-      Sv[(size_t)q * nconv + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
+        acc += (SA[(size_t)q * k + t] - lam_all[i] * SB[(size_t)q * k + t]) * Sv[(size_t)t * k + i];
+      const cd d = SA[(size_t)q * k + q] - lam_all[i] * SB[(size_t)q * k + q];
+      Sv[(size_t)q * k + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
     }
+  }
+  // the min(k, nev) nearest the target, by distance (ties within 1e-12 relative:
+  // Im lambda > 0 first, then locking order)
+  std::vector<int> order(k);
+  for (int i = 0; i < k; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double da = std::abs(lam_all[a] - sigma), db = std::abs(lam_all[b] - sigma);
+    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
+    return (lam_all[a].imag() > 0) && !(lam_all[b].imag() > 0);
+  });
+  const int nconv = std::min(k, nev);
+  std::vector<cd> lam(nconv), Cs((size_t)std::max(1, k) * std::max(1, nconv), 0.0);
+  for (int o2 = 0; o2 < nconv; ++o2) {
+    lam[o2] = lam_all[order[o2]];
+    for (int q = 0; q < k; ++q) Cs[(size_t)q * nconv + o2] = Sv[(size_t)q * k + order[o2]];
   }
   std::vector<double> res(nconv, 0.0);
   if (nconv > 0) {
     double2* Xd = ws.vec(nconv);
     if (!Xd) return KLST_ENOMEM;
-    if ((s = upload(d_coef, Sv)) != KLST_OK) return s;
-    launch_combine(st, Qb, nconv, n, d_coef, nconv, nconv, Xd, nullptr);
+    if ((s = upload(d_coef, Cs)) != KLST_OK) return s;
+    launch_combine(st, Qb, k, n, d_coef, nconv, nconv, Xd, nullptr);
     std::vector<cd> hx((size_t)nconv * n);
     HIPCHK(hipMemcpyAsync(hx.data(), Xd, sizeof(double2) * hx.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1239,6 +1289,7 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
   if (Ny < 1 || Nxi < 1 || nev < 1) return 0;
   const size_t n = 2ull * Ny * Nxi, r = 4, cvec = 16 * n;
   const int m_max = std::max(o.m_max, o.m_min + 2), gm = o.gmres_m;
+  const int kcap = std::max(nev, std::min({2 * nev, 100, 250 - m_max}));
   const int nl = std::max(1, std::min(o.lines_per_block, 2 * Nxi));
   const size_t nblocks = (2ull * Nxi + nl - 1) / nl;
   size_t b = 0;
@@ -1254,13 +1305,13 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
     b += 4ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 4ull * Ny * 2 * r * Nxi + 8ull * Ny * r * 8;
     if (o.pc_kernel == 2) b += 8ull * Nxi * Ny * Ny + 8ull * Rd * Rd + 8ull * Rd;
     else b += 8ull * nblocks * (size_t)(nl * Ny) * (nl * Ny);
-    b += 8ull * n * ((gm + 1) + 2 * (nev + 1) + 3) + cvec;
+    b += 8ull * n * ((gm + 1) + 2 * (kcap + 1) + 3) + cvec;
   }
   if (o.op_mode == 1) {
     const size_t nnz = n * (Ny - 1 + 2ull * Nxi);
     b += 20 * nnz + 8 * (n + 1);
   }
-  b += cvec * (2ull * (m_max + 1) + 3ull * (nev + 1) + (gm + 1) + m_max + 6 + nev);     // JD workspace
+  b += cvec * (2ull * (m_max + 1) + 3ull * (kcap + 1) + (gm + 1) + m_max + 6 + nev);    // JD workspace
   b += 16ull * 512 * 256 + 16ull * (4 * 1024 + 2 * 128 * 128 + (gm + 1) * (gm + 3));    // reductions, small
   return b;
 }

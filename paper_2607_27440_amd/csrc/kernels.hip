@@ -615,32 +615,46 @@ __global__ void __launch_bounds__(1024) k_ilu_apply(const double2* __restrict__ 
 // column-major over the block's rows in velocity-major order (line, node).
 // grid (row tiles of 64, blocks), block 256: the 4 wavefronts split the columns,
 // lanes own rows (coalesced column reads), partial sums meet in LDS.
-template <class R>
-__global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict__ x,
-                                                        cv<R>* __restrict__ y, int Ny, int Nxi,
-                                                        int nl, const cv<R>* __restrict__ Kinv,
-                                                        const int64_t* __restrict__ koff,
-                                                        const int* __restrict__ skip) {
+// XCD-aware workgroup order.  Workgroups are dispatched round-robin over the 8
+// XCDs (linear id L runs on XCD L mod 8), each with its own L2.  Mapping L to the
+// logical index q = (L mod 8) * (nfull / 8) + L / 8 (a bijection on the first
+// nfull = 8 floor(nwg / 8) ids, identity on the tail) gives every XCD a contiguous
+// range of logical workgroups, so neighbouring velocity nodes, whose strided 16 B
+// vector entries share 128 B lines, are served by the same L2.
+__device__ __forceinline__ int xcd_logical_id() {
+  const int nwg = gridDim.x * gridDim.y;
+  const int L = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nfull = nwg & ~7;
+  return (L < nfull) ? (L & 7) * (nfull >> 3) + (L >> 3) : L;
+}
+
+template <class R, int NW>
+__global__ void __launch_bounds__(64 * NW) k_blockinv_apply(const cv<R>* __restrict__ x,
+                                                            cv<R>* __restrict__ y, int Ny, int Nxi,
+                                                            int nl, const cv<R>* __restrict__ Kinv,
+                                                            const int64_t* __restrict__ koff,
+                                                            const int* __restrict__ skip) {
   extern __shared__ unsigned char lds_raw[];
-  cv<R>* xsb = reinterpret_cast<cv<R>*>(lds_raw);   // [nb] block input, then [4][64] partials
+  cv<R>* xsb = reinterpret_cast<cv<R>*>(lds_raw);   // [nb] block input, then [NW][64] partials
   if (skip && *skip) return;
-  const int b = blockIdx.y;
+  const int q = xcd_logical_id();
+  const int b = q / gridDim.x, tile = q - b * gridDim.x;
   const int nlines = 2 * Nxi;
   const int nl_blk = min(nl, nlines - b * nl);
   const int nb = nl_blk * Ny;
   const int l0 = b * nl;
-  for (int c = threadIdx.x; c < nb; c += 256) {
+  for (int c = threadIdx.x; c < nb; c += 64 * NW) {
     const int lg = l0 + c / Ny, j = c % Ny;
     const int f = lg / Nxi, k = lg - f * Nxi;
     xsb[c] = x[((int64_t)2 * j + f) * Nxi + k];
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 64 + lane;
+  const int row = tile * 64 + lane;
   const cv<R>* K = Kinv + koff[b];
   cv<R> acc = mk<R>(0, 0);
   if (row < nb) {
-    const int cper = (nb + 3) / 4;
+    const int cper = (nb + NW - 1) / NW;
     const int cb = wv * cper, ce = min(nb, cb + cper);
     int c = cb;
     for (; c + 8 <= ce; c += 8) {
@@ -658,9 +672,8 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict_
   __syncthreads();
   if (wv == 0 && row < nb) {
     cv<R> rr = part[lane];
-    rr = cadd(rr, part[64 + lane]);
-    rr = cadd(rr, part[128 + lane]);
-    rr = cadd(rr, part[192 + lane]);
+#pragma unroll
+    for (int w = 1; w < NW; ++w) rr = cadd(rr, part[w * 64 + lane]);
     const int lg = l0 + row / Ny, j = row % Ny;
     const int f = lg / Nxi, k = lg - f * Nxi;
     y[((int64_t)2 * j + f) * Nxi + k] = rr;
@@ -678,24 +691,25 @@ __global__ void __launch_bounds__(256) k_blockinv_apply(const cv<R>* __restrict_
 
 // y = P^{-1} (x + Ut d) for both fields of node k, reading P_k^{-1} once for the
 // two right-hand sides; d == nullptr skips the rank update.  Pinv: [Nxi][Ny x Ny]
-// column-major.  Lanes own rows, the 4 wavefronts split the columns and their
-// partial sums are added in fixed order.  grid ((Ny + 63) / 64, Nxi), block 256,
-// dynamic LDS (2 Ny + 512) * sizeof(cv<R>).
-template <class R>
-__global__ void __launch_bounds__(256) k_line_inverse(const cv<R>* __restrict__ x,
-                                                      cv<R>* __restrict__ y, int Ny, int Nxi,
-                                                      int r, const cv<R>* __restrict__ Pinv,
-                                                      const R* __restrict__ U,
-                                                      const R* __restrict__ xix,
-                                                      const cv<R>* __restrict__ d,
-                                                      const int* __restrict__ skip) {
+// column-major.  Lanes own rows, the NW wavefronts split the columns and their
+// partial sums are added in fixed order.  grid ((Ny + 63) / 64, Nxi), block 64 NW,
+// dynamic LDS (2 Ny + 128 NW) * sizeof(cv<R>).
+template <class R, int NW>
+__global__ void __launch_bounds__(64 * NW) k_line_inverse(const cv<R>* __restrict__ x,
+                                                          cv<R>* __restrict__ y, int Ny, int Nxi,
+                                                          int r, const cv<R>* __restrict__ Pinv,
+                                                          const R* __restrict__ U,
+                                                          const R* __restrict__ xix,
+                                                          const cv<R>* __restrict__ d,
+                                                          const int* __restrict__ skip) {
   extern __shared__ unsigned char lds_raw[];
   cv<R>* xs = reinterpret_cast<cv<R>*>(lds_raw);   // [2][Ny]
-  cv<R>* part = xs + 2 * Ny;                        // [2][4][64]
+  cv<R>* part = xs + 2 * Ny;                        // [2][NW][64]
   if (skip && *skip) return;
-  const int k = blockIdx.y;
+  const int q = xcd_logical_id();
+  const int k = q / gridDim.x, tile = q - k * gridDim.x;
   const R xk = xix[k];
-  for (int c = threadIdx.x; c < 2 * Ny; c += 256) {
+  for (int c = threadIdx.x; c < 2 * Ny; c += 64 * NW) {
     const int f = c / Ny, m = c - f * Ny;
     cv<R> v = x[((int64_t)2 * m + f) * Nxi + k];
     const bool inflow = (m == Ny - 1 && xk > 0) || (m == 0 && xk < 0);
@@ -711,11 +725,11 @@ __global__ void __launch_bounds__(256) k_line_inverse(const cv<R>* __restrict__ 
   }
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 64 + lane;
+  const int row = tile * 64 + lane;
   const cv<R>* K = Pinv + (int64_t)k * Ny * Ny;
   cv<R> a0 = mk<R>(0, 0), a1 = mk<R>(0, 0);
   if (row < Ny) {
-    const int cper = (Ny + 3) / 4;
+    const int cper = (Ny + NW - 1) / NW;
     const int cb = wv * cper, ce = min(Ny, cb + cper);
     int c = cb;
     for (; c + 8 <= ce; c += 8) {
@@ -735,14 +749,13 @@ __global__ void __launch_bounds__(256) k_line_inverse(const cv<R>* __restrict__ 
     }
   }
   part[wv * 64 + lane] = a0;
-  part[256 + wv * 64 + lane] = a1;
+  part[NW * 64 + wv * 64 + lane] = a1;
   __syncthreads();
   if (wv < 2 && row < Ny) {
-    const cv<R>* pf = part + wv * 256;
+    const cv<R>* pf = part + wv * NW * 64;
     cv<R> rr = pf[lane];
-    rr = cadd(rr, pf[64 + lane]);
-    rr = cadd(rr, pf[128 + lane]);
-    rr = cadd(rr, pf[192 + lane]);
+#pragma unroll
+    for (int w = 1; w < NW; ++w) rr = cadd(rr, pf[w * 64 + lane]);
     y[((int64_t)2 * row + wv) * Nxi + k] = rr;
   }
 }
@@ -917,6 +930,27 @@ __global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0
     const double2 bs = block_sum256(make_double2((double)a2, 0.0), sh);
     if (threadIdx.x == 0) norm_part[blockIdx.x] = bs;
   }
+}
+
+// Is a second Gram-Schmidt pass needed?  DGKS criterion (Daniel, Gragg, Kaufman
+// and Stewart 1976): reorthogonalise when the first pass leaves less than eta of
+// the norm, ||x_after||^2 < eta2 ||x_before||^2.  before^2 is row m of the dot
+// partials (nch chunks, written with with_norm), after^2 the first pass's norm
+// partials (nb workgroups).  *skip_out = done || not needed.  grid 1, block 256.
+__global__ void __launch_bounds__(256) k_reorth_test(const double2* __restrict__ partial, int m, int nch,
+                                                     const double2* __restrict__ norm_part, int nb,
+                                                     double eta2, const int* __restrict__ done,
+                                                     int* __restrict__ skip_out) {
+  __shared__ double2 sh[4];
+  if (done && *done) {
+    if (threadIdx.x == 0) *skip_out = 1;
+    return;
+  }
+  double before = 0.0, after = 0.0;
+  for (int c = threadIdx.x; c < nch; c += 256) before += partial[(int64_t)m * nch + c].x;
+  for (int c = threadIdx.x; c < nb; c += 256) after += norm_part[c].x;
+  const double2 s = block_sum256(make_double2(before, after), sh);
+  if (threadIdx.x == 0) *skip_out = (s.y >= eta2 * s.x) ? 1 : 0;
 }
 
 // nrm2 = sum of the nb norm partials (fixed order, every workgroup); x (or dst)
@@ -1223,13 +1257,26 @@ void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int 
     hipLaunchKernelGGL((k_ilu_apply<4, 2>), dim3(nblocks), blk, lds, st, x, y, Ny, Nxi, nl, Fc, C, skip);
 }
 
+// Wavefronts per workgroup for the block GEMVs: enough loads in flight when the
+// grid alone cannot fill the 256 CUs (few or small blocks).
+static int gemv_waves(int64_t workgroups) {
+  return workgroups >= 1024 ? 4 : (workgroups >= 512 ? 8 : 16);
+}
+
 template <class R>
 static void blockinv_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int nl, int nblocks,
                        const cv<R>* Kinv, const int64_t* koff, const int* skip) {
   const int nb = nl * Ny;
-  const size_t lds = (size_t)(nb + 256) * sizeof(cv<R>);
-  hipLaunchKernelGGL((k_blockinv_apply<R>), dim3((nb + 63) / 64, nblocks), dim3(256), lds, st, x, y, Ny,
-                     Nxi, nl, Kinv, koff, skip);
+  const dim3 grid((nb + 63) / 64, nblocks);
+  const int nw = gemv_waves((int64_t)grid.x * grid.y);
+  const size_t lds = (size_t)(nb + 64 * nw) * sizeof(cv<R>);
+  if (nw == 4)
+    hipLaunchKernelGGL((k_blockinv_apply<R, 4>), grid, dim3(256), lds, st, x, y, Ny, Nxi, nl, Kinv, koff, skip);
+  else if (nw == 8)
+    hipLaunchKernelGGL((k_blockinv_apply<R, 8>), grid, dim3(512), lds, st, x, y, Ny, Nxi, nl, Kinv, koff, skip);
+  else
+    hipLaunchKernelGGL((k_blockinv_apply<R, 16>), grid, dim3(1024), lds, st, x, y, Ny, Nxi, nl, Kinv, koff,
+                       skip);
 }
 void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                            int nblocks, const double2* Kinv, const int64_t* koff, const int* skip) {
@@ -1244,18 +1291,28 @@ template <class R>
 static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r,
                          const cv<R>* Pinv, const cv<R>* Sinv, const R* M, const R* U, const R* xix,
                          cv<R>* mom, cv<R>* d, const int* skip) {
-  const size_t lds = (size_t)(2 * Ny + 512) * sizeof(cv<R>);
   const dim3 grid((Ny + 63) / 64, Nxi);
-  hipLaunchKernelGGL((k_line_inverse<R>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
-                     (const cv<R>*)nullptr, skip);
+  const int nw = gemv_waves((int64_t)grid.x * grid.y);
+  const size_t lds = (size_t)(2 * Ny + 128 * nw) * sizeof(cv<R>);
+  auto pass = [&](const cv<R>* dd) {
+    if (nw == 4)
+      hipLaunchKernelGGL((k_line_inverse<R, 4>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix, dd,
+                         skip);
+    else if (nw == 8)
+      hipLaunchKernelGGL((k_line_inverse<R, 8>), grid, dim3(512), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix, dd,
+                         skip);
+    else
+      hipLaunchKernelGGL((k_line_inverse<R, 16>), grid, dim3(1024), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
+                         dd, skip);
+  };
+  pass(nullptr);
   const int64_t n = 2LL * Ny * Nxi;
   moments_t<R>(st, y, n, 1, Ny, Nxi, r, M, mom, skip);
   const int Rd = r * Ny;
   const int S = moment_splits(Ny, 1, Nxi);
   hipLaunchKernelGGL((k_capacitance<R>), dim3((Rd + 3) / 4), dim3(256), (size_t)Rd * sizeof(cv<R>), st, mom,
                      Ny, r, S, Sinv, d, skip);
-  hipLaunchKernelGGL((k_line_inverse<R>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
-                     (const cv<R>*)d, skip);
+  pass(d);
 }
 void launch_structured_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
                                const double2* Pinv, const double2* Sinv, const double* M,
@@ -1386,6 +1443,12 @@ void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n) {
 }
 void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int accum) {
   hipLaunchKernelGGL(k_widen, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n, accum);
+}
+
+void launch_reorth_test(hipStream_t st, const double2* partial, int m, int nch, int64_t n,
+                        const double2* norm_part, double eta2, const int* done, int* skip_out) {
+  hipLaunchKernelGGL(k_reorth_test, dim3(1), dim3(256), 0, st, partial, m, nch, norm_part, (int)nblk(n, 256),
+                     eta2, done, skip_out);
 }
 
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,

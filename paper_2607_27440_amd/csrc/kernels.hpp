@@ -43,6 +43,11 @@ void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, con
                         const int* skip);
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum);
+// *skip_out = done || ||x||^2 after a Gram-Schmidt pass (norm partials of the
+// pass's k_subm_fused over n) >= eta2 x ||x||^2 before it (row m of the with_norm
+// dot partials): the DGKS test for a second pass.
+void launch_reorth_test(hipStream_t st, const double2* partial, int m, int nch, int64_t n,
+                        const double2* norm_part, double eta2, const int* done, int* skip_out);
 // First cycle (first != 0): *beta = ||r0||; later restart cycles keep it.
 void launch_gmres_init(hipStream_t st, const double2* nrm2, double2* g, int* done, int* steps,
                        double* beta, int first);

@@ -30,7 +30,8 @@ class Options(C.Structure):
                 ("op_mode", C.c_int), ("lines_per_block", C.c_int), ("m_max", C.c_int),
                 ("m_min", C.c_int), ("gmres_m", C.c_int), ("max_it", C.c_int), ("tol", C.c_double),
                 ("inner_rtol", C.c_double), ("fix", C.c_double), ("seed", C.c_uint64),
-                ("pc_kernel", C.c_int), ("inner_max_it", C.c_int)]
+                ("pc_kernel", C.c_int), ("inner_max_it", C.c_int),
+                ("reorth", C.c_int)]
 
 
 class Grid(C.Structure):
