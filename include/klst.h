@@ -124,8 +124,8 @@ typedef struct {
   int pivots_floored;        /* ILU(0) pivots raised to 1e-12 x row 1-norm      */
   double seconds_total;      /* wall time of klst_solve                         */
   double seconds_setup;      /* preconditioner set-up inside klst_solve         */
-  double seconds_op;         /* device time in operator applications (events)   */
-  double seconds_pc;         /* device time in preconditioner applications      */
+  double seconds_host;       /* host time in the projected dense problems       */
+  double seconds_wait;       /* host time blocked on device results (syncs)     */
   int64_t op_applies;
   int64_t pc_applies;
 } klst_stats;

@@ -32,6 +32,9 @@ def flags():
     return ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
             # packed FP32 arithmetic is kept off in device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # host complex arithmetic without the IEEE inf/nan recovery calls
+            # (__muldc3/__divdc3): the projected problems hold moderate values
+            "-fcx-limited-range",
             "-I", os.path.join(ROOT, "include"), "-I", CSRC,
             "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument"]
 

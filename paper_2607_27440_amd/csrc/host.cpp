@@ -382,10 +382,12 @@ namespace {
 
 // Givens rotation (c real, s complex) with [c s; -conj(s) c] [f; g] = [r; 0].
 void givens(cd f, cd g, double& c, cd& s) {
-  const double af = std::abs(f), ag = std::abs(g);
-  if (ag == 0.0) { c = 1.0; s = 0.0; return; }
-  if (af == 0.0) { c = 0.0; s = std::conj(g) / ag; return; }
-  const double nrm = std::hypot(af, ag);
+  // squared moduli and sqrt instead of hypot: the projected problems hold values
+  // far from the over/underflow range
+  const double f2 = std::norm(f), g2 = std::norm(g);
+  if (g2 == 0.0) { c = 1.0; s = 0.0; return; }
+  if (f2 == 0.0) { c = 0.0; s = std::conj(g) / std::sqrt(g2); return; }
+  const double af = std::sqrt(f2), nrm = std::sqrt(f2 + g2);
   c = af / nrm;
   s = (f / af) * std::conj(g) / nrm;
 }
@@ -434,13 +436,27 @@ void qr_square(int m, const cd* A, cd* Qm, cd* Rm) {
 // (Golub & Van Loan, Matrix Computations, Sec. 7.4-7.5), then a selection sort
 // of the diagonal by adjacent swaps of 1x1 blocks (the exchange of Bai & Demmel
 // used by LAPACK's ZTREXC).
-bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
-  std::vector<cd> H(G, G + (size_t)m * m), U((size_t)m * m, cd(0.0));
-  for (int i = 0; i < m; ++i) U[(size_t)i * m + i] = 1.0;
+static inline double cabs1(cd z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
+
+bool sorted_schur(int m, const cd* G, cd* Uo, cd* To, int nsort) {
+  // H row-major (row operations contiguous); the Schur vectors are kept
+  // column-major in Uc so that rotating two columns is contiguous.
+  std::vector<cd> H(G, G + (size_t)m * m), Uc((size_t)m * m, cd(0.0));
+  for (int i = 0; i < m; ++i) Uc[(size_t)i * m + i] = 1.0;
   auto h = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
-  auto u = [&](int i, int j) -> cd& { return U[(size_t)i * m + j]; };
-  // Hessenberg reduction
-  std::vector<cd> v(m);
+  auto ucol = [&](int j) -> cd* { return &Uc[(size_t)j * m]; };
+  auto rot_cols = [&](int k, double cs, cd sn) {   // U[:, k], U[:, k+1] <- (x, y) G^H
+    cd* x = ucol(k);
+    cd* y = ucol(k + 1);
+    const cd snc = std::conj(sn);
+    for (int ir = 0; ir < m; ++ir) {
+      const cd a = x[ir], b = y[ir];
+      x[ir] = cs * a + snc * b;
+      y[ir] = -sn * a + cs * b;
+    }
+  };
+  // Hessenberg reduction by Householder reflectors P = I - 2 v v^H / (v^H v)
+  std::vector<cd> v(m), t(m);
   for (int k = 0; k < m - 2; ++k) {
     double nrm = 0;
     for (int i = k + 1; i < m; ++i) nrm += std::norm(h(i, k));
@@ -454,17 +470,37 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
     double vn = 0;
     for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
     if (vn == 0.0) continue;
-    for (int jc = 0; jc < m; ++jc) {          // H <- P H
-      cd s = 0;
-      for (int i = k + 1; i < m; ++i) s += std::conj(v[i]) * h(i, jc);
-      s *= 2.0 / vn;
-      for (int i = k + 1; i < m; ++i) h(i, jc) -= s * v[i];
+    const double f = 2.0 / vn;
+    // H <- P H: t = v^H H (row vector), H -= v t
+    std::fill(t.begin(), t.end(), cd(0.0));
+    for (int i = k + 1; i < m; ++i) {
+      const cd vc = std::conj(v[i]);
+      const cd* hi = &h(i, 0);
+      for (int jc = 0; jc < m; ++jc) t[jc] += vc * hi[jc];
     }
-    for (int ir = 0; ir < m; ++ir) {          // H <- H P, U <- U P
-      cd s = 0, t = 0;
-      for (int i = k + 1; i < m; ++i) { s += h(ir, i) * v[i]; t += u(ir, i) * v[i]; }
-      s *= 2.0 / vn; t *= 2.0 / vn;
-      for (int i = k + 1; i < m; ++i) { h(ir, i) -= s * std::conj(v[i]); u(ir, i) -= t * std::conj(v[i]); }
+    for (int i = k + 1; i < m; ++i) {
+      const cd vi = v[i] * f;
+      cd* hi = &h(i, 0);
+      for (int jc = 0; jc < m; ++jc) hi[jc] -= vi * t[jc];
+    }
+    // H <- H P (rows), U <- U P (columns of Uc)
+    for (int ir = 0; ir < m; ++ir) {
+      cd sum = 0;
+      cd* hr = &h(ir, 0);
+      for (int i = k + 1; i < m; ++i) sum += hr[i] * v[i];
+      sum *= f;
+      for (int i = k + 1; i < m; ++i) hr[i] -= sum * std::conj(v[i]);
+    }
+    std::fill(t.begin(), t.end(), cd(0.0));
+    for (int i = k + 1; i < m; ++i) {
+      const cd vi = v[i];
+      const cd* ui = ucol(i);
+      for (int ir = 0; ir < m; ++ir) t[ir] += ui[ir] * vi;
+    }
+    for (int i = k + 1; i < m; ++i) {
+      const cd vc = std::conj(v[i]) * f;
+      cd* ui = ucol(i);
+      for (int ir = 0; ir < m; ++ir) ui[ir] -= t[ir] * vc;
     }
     for (int i = k + 2; i < m; ++i) h(i, k) = 0.0;
   }
@@ -476,8 +512,9 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
     if (++iter > 100 * m + 1000) return false;
     int lo = hi;
     while (lo > 0) {
-      const double sub = std::abs(h(lo, lo - 1));
-      double scale = std::abs(h(lo, lo)) + std::abs(h(lo - 1, lo - 1));
+      // |re| + |im| as the magnitude in the deflation test (as LAPACK does)
+      const double sub = cabs1(h(lo, lo - 1));
+      double scale = cabs1(h(lo, lo)) + cabs1(h(lo - 1, lo - 1));
       if (scale == 0.0) scale = 1.0;
       if (sub <= eps * scale) { h(lo, lo - 1) = 0.0; break; }
       --lo;
@@ -506,25 +543,24 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
       else { f0 = h(k, k - 1); g0 = h(k + 1, k - 1); }
       double cs; cd sn;
       givens(f0, g0, cs, sn);
+      const cd snc = std::conj(sn);
       // rows k, k+1 from column (k == lo ? lo : k-1)
+      cd* rk = &h(k, 0);
+      cd* rk1 = &h(k + 1, 0);
       for (int jc = (k == lo ? lo : k - 1); jc < m; ++jc) {
-        const cd x = h(k, jc), y = h(k + 1, jc);
-        h(k, jc) = cs * x + sn * y;
-        h(k + 1, jc) = -std::conj(sn) * x + cs * y;
+        const cd x = rk[jc], y = rk1[jc];
+        rk[jc] = cs * x + sn * y;
+        rk1[jc] = -snc * x + cs * y;
       }
       if (k > lo) h(k + 1, k - 1) = 0.0;
       // columns k, k+1 of H rows 0..min(k+2, hi), and of U
       const int rmax = std::min(k + 2, hi);
       for (int ir = 0; ir <= rmax; ++ir) {
         const cd x = h(ir, k), y = h(ir, k + 1);
-        h(ir, k) = cs * x + std::conj(sn) * y;
+        h(ir, k) = cs * x + snc * y;
         h(ir, k + 1) = -sn * x + cs * y;
       }
-      for (int ir = 0; ir < m; ++ir) {
-        const cd x = u(ir, k), y = u(ir, k + 1);
-        u(ir, k) = cs * x + std::conj(sn) * y;
-        u(ir, k + 1) = -sn * x + cs * y;
-      }
+      rot_cols(k, cs, sn);
     }
   }
   for (int i = 0; i < m; ++i)
@@ -534,34 +570,174 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To) {
     const cd t11 = h(k, k), t22 = h(k + 1, k + 1);
     double cs; cd sn;
     givens(h(k, k + 1), t22 - t11, cs, sn);
+    const cd snc = std::conj(sn);
+    cd* rk = &h(k, 0);
+    cd* rk1 = &h(k + 1, 0);
     for (int jc = k + 2; jc < m; ++jc) {       // rows k, k+1
-      const cd x = h(k, jc), y = h(k + 1, jc);
-      h(k, jc) = cs * x + sn * y;
-      h(k + 1, jc) = -std::conj(sn) * x + cs * y;
+      const cd x = rk[jc], y = rk1[jc];
+      rk[jc] = cs * x + sn * y;
+      rk1[jc] = -snc * x + cs * y;
     }
     for (int ir = 0; ir < k; ++ir) {           // columns k, k+1
       const cd x = h(ir, k), y = h(ir, k + 1);
-      h(ir, k) = cs * x + std::conj(sn) * y;
+      h(ir, k) = cs * x + snc * y;
       h(ir, k + 1) = -sn * x + cs * y;
     }
     h(k, k) = t22;
     h(k + 1, k + 1) = t11;
-    for (int ir = 0; ir < m; ++ir) {
-      const cd x = u(ir, k), y = u(ir, k + 1);
-      u(ir, k) = cs * x + std::conj(sn) * y;
-      u(ir, k + 1) = -sn * x + cs * y;
-    }
+    rot_cols(k, cs, sn);
   };
-  for (int pos = 0; pos < m; ++pos) {
+  // selection by adjacent swaps: the largest |T_ii| into position 0, 1, ...,
+  // for the first nsort positions (all when nsort <= 0 or >= m)
+  const int npos = (nsort <= 0 || nsort >= m) ? m : nsort;
+  for (int pos = 0; pos < npos; ++pos) {
     int best = pos;
     for (int i = pos + 1; i < m; ++i)
-      if (std::abs(h(i, i)) > std::abs(h(best, best))) best = i;
+      if (std::norm(h(i, i)) > std::norm(h(best, best))) best = i;
     for (int k = best - 1; k >= pos; --k) swap_adj(k);
   }
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < i; ++j) h(i, j) = 0.0;
   std::copy(H.begin(), H.end(), To);
-  std::copy(U.begin(), U.end(), Uo);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) Uo[(size_t)i * m + j] = Uc[(size_t)j * m + i];
+  return true;
+}
+
+bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
+  std::vector<cd> H(G, G + (size_t)m * m);
+  auto h = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
+  // Hessenberg reduction (similarity only: no transformation is kept)
+  std::vector<cd> v(m), t(m);
+  for (int k = 0; k < m - 2; ++k) {
+    double nrm = 0;
+    for (int i = k + 1; i < m; ++i) nrm += std::norm(h(i, k));
+    nrm = std::sqrt(nrm);
+    if (nrm == 0.0) continue;
+    const cd x0 = h(k + 1, k);
+    const cd ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cd(1.0);
+    for (int i = k + 1; i < m; ++i) v[i] = h(i, k);
+    v[k + 1] += ph * nrm;
+    double vn = 0;
+    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    const double f = 2.0 / vn;
+    std::fill(t.begin() + k, t.end(), cd(0.0));
+    for (int i = k + 1; i < m; ++i) {
+      const cd vc = std::conj(v[i]);
+      const cd* hi = &h(i, 0);
+      for (int jc = k; jc < m; ++jc) t[jc] += vc * hi[jc];
+    }
+    for (int i = k + 1; i < m; ++i) {
+      const cd vi = v[i] * f;
+      cd* hi = &h(i, 0);
+      for (int jc = k; jc < m; ++jc) hi[jc] -= vi * t[jc];
+    }
+    for (int ir = 0; ir < m; ++ir) {
+      cd sum = 0;
+      cd* hr = &h(ir, 0);
+      for (int i = k + 1; i < m; ++i) sum += hr[i] * v[i];
+      sum *= f;
+      for (int i = k + 1; i < m; ++i) hr[i] -= sum * std::conj(v[i]);
+    }
+    for (int i = k + 2; i < m; ++i) h(i, k) = 0.0;
+  }
+  // eigenvalues only: single-shift QR restricted to the active window
+  const double eps = 2.220446049250313e-16;
+  int hi = m - 1, iter = 0, since = 0;
+  while (hi > 0) {
+    if (++iter > 100 * m + 1000) return false;
+    int lo = hi;
+    while (lo > 0) {
+      // |re| + |im| as the magnitude in the deflation test (as LAPACK does)
+      const double sub = cabs1(h(lo, lo - 1));
+      double scale = cabs1(h(lo, lo)) + cabs1(h(lo - 1, lo - 1));
+      if (scale == 0.0) scale = 1.0;
+      if (sub <= eps * scale) { h(lo, lo - 1) = 0.0; break; }
+      --lo;
+    }
+    if (lo == hi) { --hi; since = 0; continue; }
+    ++since;
+    cd sh;
+    const cd a = h(hi - 1, hi - 1), bb = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+    if (since % 11 == 10) {
+      sh = d + cd(0.75 * std::abs(c), 0.0);
+    } else {
+      const cd tr = 0.5 * (a - d);
+      const cd disc = std::sqrt(tr * tr + bb * c);
+      const cd e1 = d - (bb * c) / (tr + disc), e2 = d - (bb * c) / (tr - disc);
+      const bool ok1 = std::abs(tr + disc) > 0, ok2 = std::abs(tr - disc) > 0;
+      if (ok1 && ok2) sh = (std::abs(e1 - d) < std::abs(e2 - d)) ? e1 : e2;
+      else if (ok1) sh = e1;
+      else if (ok2) sh = e2;
+      else sh = d;
+    }
+    for (int k = lo; k < hi; ++k) {
+      cd f0, g0;
+      if (k == lo) { f0 = h(lo, lo) - sh; g0 = h(lo + 1, lo); }
+      else { f0 = h(k, k - 1); g0 = h(k + 1, k - 1); }
+      double cs; cd sn;
+      givens(f0, g0, cs, sn);
+      const cd snc = std::conj(sn);
+      cd* rk = &h(k, 0);
+      cd* rk1 = &h(k + 1, 0);
+      for (int jc = (k == lo ? lo : k - 1); jc <= hi; ++jc) {
+        const cd xx = rk[jc], yy = rk1[jc];
+        rk[jc] = cs * xx + sn * yy;
+        rk1[jc] = -snc * xx + cs * yy;
+      }
+      if (k > lo) h(k + 1, k - 1) = 0.0;
+      const int rmax = std::min(k + 2, hi);
+      for (int ir = lo; ir <= rmax; ++ir) {
+        const cd xx = h(ir, k), yy = h(ir, k + 1);
+        h(ir, k) = cs * xx + snc * yy;
+        h(ir, k + 1) = -sn * xx + cs * yy;
+      }
+    }
+  }
+  int best = 0;
+  for (int i = 1; i < m; ++i)
+    if (std::norm(h(i, i)) > std::norm(h(best, best))) best = i;
+  mu = h(best, best);
+  // eigenvector by inverse iteration with G - mu I (LU, partial pivoting; an
+  // exactly zero pivot is replaced by eps ||G||)
+  double gn = 0;
+  for (size_t q = 0; q < (size_t)m * m; ++q) gn = std::max(gn, std::abs(G[q]));
+  std::vector<cd> Lu(G, G + (size_t)m * m);
+  for (int i = 0; i < m; ++i) Lu[(size_t)i * m + i] -= mu;
+  std::vector<int> piv(m);
+  for (int k = 0; k < m; ++k) {
+    int p = k;
+    for (int i = k + 1; i < m; ++i)
+      if (std::abs(Lu[(size_t)i * m + k]) > std::abs(Lu[(size_t)p * m + k])) p = i;
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < m; ++j) std::swap(Lu[(size_t)p * m + j], Lu[(size_t)k * m + j]);
+    cd& pk = Lu[(size_t)k * m + k];
+    if (std::abs(pk) == 0.0) pk = eps * std::max(gn, 1e-300);
+    for (int i = k + 1; i < m; ++i) {
+      const cd l = Lu[(size_t)i * m + k] / pk;
+      Lu[(size_t)i * m + k] = l;
+      if (l == 0.0) continue;
+      for (int j = k + 1; j < m; ++j) Lu[(size_t)i * m + j] -= l * Lu[(size_t)k * m + j];
+    }
+  }
+  std::vector<cd> y(m, cd(1.0));
+  for (int it = 0; it < 2; ++it) {
+    for (int k = 0; k < m; ++k) std::swap(y[k], y[piv[k]]);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < i; ++j) y[i] -= Lu[(size_t)i * m + j] * y[j];
+    for (int i = m - 1; i >= 0; --i) {
+      for (int j = i + 1; j < m; ++j) y[i] -= Lu[(size_t)i * m + j] * y[j];
+      y[i] /= Lu[(size_t)i * m + i];
+    }
+    double nn = 0;
+    for (int i = 0; i < m; ++i) nn += std::norm(y[i]);
+    nn = std::sqrt(nn);
+    if (!(nn > 0) || !std::isfinite(nn)) return false;
+    for (int i = 0; i < m; ++i) y[i] /= nn;
+  }
+  std::copy(y.begin(), y.end(), x);
   return true;
 }
 

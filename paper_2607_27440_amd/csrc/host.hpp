@@ -68,9 +68,15 @@ struct StructuredInverse {
 std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads);
 
 // ---- small dense complex matrices, row-major m x m ----
-// Sorted Schur form: G U = U T, T upper triangular, |T_00| >= |T_11| >= ...
+// Schur form G U = U T, T upper triangular, with the diagonal ordered by
+// decreasing |T_ii| in the first nsort positions (each holds the largest
+// remaining magnitude; all positions when nsort <= 0).  U row-major.
 // Returns false if the QR iteration failed to converge.
-bool sorted_schur(int m, const cd* G, cd* U, cd* T);
+bool sorted_schur(int m, const cd* G, cd* U, cd* T, int nsort = 0);
+// The eigenvalue mu of G of largest modulus (first on ties in the QR order) and
+// a unit eigenvector x (inverse iteration): the first column of a sorted Schur
+// form, without computing the rest of it.  Returns false on failure.
+bool dominant_eig(int m, const cd* G, cd& mu, cd* x);
 // Householder QR of an m x m matrix A = Qm Rm.
 void qr_square(int m, const cd* A, cd* Qm, cd* Rm);
 // Inverse of an m x m matrix by LU with partial pivoting; false if singular.

@@ -52,7 +52,7 @@ class Base(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("outer_iterations", C.c_int), ("inner_iterations", C.c_int), ("restarts", C.c_int),
                 ("nconv", C.c_int), ("pivots_floored", C.c_int), ("seconds_total", C.c_double),
-                ("seconds_setup", C.c_double), ("seconds_op", C.c_double), ("seconds_pc", C.c_double),
+                ("seconds_setup", C.c_double), ("seconds_host", C.c_double), ("seconds_wait", C.c_double),
                 ("op_applies", C.c_int64), ("pc_applies", C.c_int64)]
 
     def as_dict(self):
