@@ -28,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+# HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
+# each scaled by the same counter's reading for a 256 MiB copy (profiles/
+# jd_solve_c2_m3_ny64_nxi96_bjilu_fp64.md, jd_solve_c3_m4_ny96_nxi1464_exact_pc_fp64.md);
+# keyed by (workload, pc_kernel), valid for the kernels as they were counted
+TRAFFIC_BYTES = {("c2", 1): 45476516, ("c3", 2): 546081877}
 RES_GATE = 1e-10
 
 # workload -> (generator, library options)
@@ -76,7 +81,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_roofline(ctx, wl, torch, reps):
+def kernel_roofline(ctx, wl, torch, reps, workload=None):
     """Time the block-Jacobi ILU(0) apply (the dominant kernel of the solve) with
     HIP events on the library's stream.  Algorithmic bytes per launch: with the
     stored block inverse (pc_kernel 1), every block's dense (nl Ny)^2 inverse read
@@ -118,7 +123,8 @@ def kernel_roofline(ctx, wl, torch, reps):
     achieved = nbytes / sec / 1e9
     return {"kernel": kname,
             "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": TRAFFIC_BYTES.get((workload, ctx.options.pc_kernel)),
             "avg_us": round(sec * 1e6, 3), "bytes_per_launch": nbytes}
 
 
@@ -318,7 +324,7 @@ def run_profile(a):
     out = {"mode": "profile", "workload": wl.name, "options": opts}
     with klst.Context(stream=st.cuda_stream, **opts) as ctx:
         ctx.assemble(wl)
-        out["precond"] = kernel_roofline(ctx, wl, torch, a.kernel_reps)
+        out["precond"] = kernel_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
         x = torch.randn(wl.n, dtype=torch.complex128, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
@@ -411,7 +417,7 @@ def main():
                                "outer": vo["stats"]["outer_iterations"], "inner": vo["stats"]["inner_iterations"],
                                "options": vopt}
             log(f"[bench] variant {vname}: {variants[vname]}")
-    roof = kernel_roofline(ctx, wl, torch, a.kernel_reps)
+    roof = kernel_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
     ops = op_apply_rate(ctx, wl, torch, max(20, a.kernel_reps // 4))
     line = {
         "metric": "eigenpairs/s at rel. residual <= 1e-10",
