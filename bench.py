@@ -48,11 +48,19 @@ WORKLOADS = {
     # of a cluster 1e-6 wide, which needs the larger search space.
     "c3": ("config3", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
 }
-# variants reported beside the c2 line (same workload, same residual gate)
-C2_VARIANTS = {
-    "mixed_fp32_inner": dict(precision=1),
-    "exact_structured_pc": dict(pc_kernel=2),
-    "exact_structured_pc_mixed": dict(pc_kernel=2, precision=1),
+# variants reported beside a line (same workload, same residual gate): FP32 inner
+# solves, the exact structured inverse as JD preconditioner, and shift-invert
+# Krylov-Schur with that inverse as operator (method 1)
+VARIANTS = {
+    "c2": {
+        "mixed_fp32_inner": dict(precision=1),
+        "exact_structured_pc": dict(pc_kernel=2),
+        "exact_structured_pc_mixed": dict(pc_kernel=2, precision=1),
+        "shift_invert_exact": dict(method=1),
+    },
+    "c3": {
+        "shift_invert_exact": dict(method=1, m_max=120, max_it=100),
+    },
 }
 
 
@@ -213,8 +221,8 @@ def run_batched(a):
     from paper_2607_27440_amd import klst, workloads
     wls = workloads.sweep(seed=4, count=a.count, nev=8)
 
-    def run(slots, prec):
-        with klst.Server(slots=slots, precision=prec, max_it=a.max_it, **SWEEP_OPTS) as sv:
+    def run(slots, prec, method=0):
+        with klst.Server(slots=slots, precision=prec, max_it=a.max_it, method=method, **SWEEP_OPTS) as sv:
             if a.warmup:
                 sv.solve_all(wls[:2])
             t = time.perf_counter()
@@ -229,6 +237,7 @@ def run_batched(a):
     log(f"[bench] baseline {g0} eigenpairs in {e0:.2f}s; now {a.slots} slots, {a.precision}")
     g1, e1, res, st = run(a.slots, prec)
     g2, e2, res2, _ = run(a.slots, 1 - prec)
+    g3, e3, res3, _ = run(a.slots, prec, method=1)
     lat = [r["service_s"] for r in res]
     cfg = {"workload": f"sweep_seed4_{len(wls)}_solves_nev8", "slots": a.slots, "precision": a.precision,
            "max_it": a.max_it, **SWEEP_OPTS}
@@ -240,6 +249,10 @@ def run_batched(a):
                     "speedup_vs_plain_fp64_serial": round((g1 / e1) / (g0 / e0), 3),
                     f"slots_{other}": {"value": round(g2 / e2, 4), "seconds": round(e2, 3), "eigenpairs": g2,
                                        "unconverged_solves": int(sum(1 for r in res2 if r["status"] != 0))},
+                    "slots_shift_invert_exact": {"value": round(g3 / e3, 4), "seconds": round(e3, 3),
+                                                 "eigenpairs": g3,
+                                                 "unconverged_solves": int(sum(1 for r in res3
+                                                                               if r["status"] != 0))},
                     "eigenpairs": g1, "seconds": round(e1, 3), "peak_running": st["peak_running"],
                     "service_p50_s": round(float(np.percentile(lat, 50)), 4),
                     "unconverged_solves": int(sum(1 for r in res if r["status"] != 0))})
@@ -392,8 +405,8 @@ def main():
     el = time.perf_counter() - t0
     value = good_total / el
     variants = {}
-    if a.workload == "c2" and not a.no_variants:
-        for vname, vopt in C2_VARIANTS.items():
+    if not a.no_variants:
+        for vname, vopt in VARIANTS.get(a.workload, {}).items():
             o = dict(opts, **vopt)
             with klst.Context(stream=st.cuda_stream, **o) as vctx:
                 vctx.assemble(wl)

@@ -82,6 +82,8 @@ typedef struct {
                            twice (CGS2, the default); 1 = second pass only when the
                            first keeps less than 1/sqrt(2) of the norm (DGKS test,
                            on the device)                                            */
+  int method;           /* klst_solve's eigensolver: 0 = Jacobi-Davidson (default);
+                           1 = shift-invert Krylov-Schur (klst_solve_shift_invert)  */
 } klst_options;
 
 /* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]
@@ -188,6 +190,19 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
  * EINVAL (nev < 1, nev > min(100, n - n_bc), nev + m_max > 250), ENOMEM, EDEVICE. */
 klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* lambda,
                        void* X, int X_on_device, double* resid, int* nconv);
+
+/* Shift-invert Krylov-Schur solve for the nev eigenvalues nearest sigma: Arnoldi
+ * on (A - sigma B)^{-1} B as in the paper's Method 1 (Sec. 4.1), with the exact
+ * structured inverse (pc_kernel 2's factorization) in place of a sparse LU, and
+ * Krylov-Schur restarts that keep the min(m_max - 2, nev + (m_max - nev) / 2)
+ * leading Schur vectors.  m_max is the search-space size (at least nev + 2),
+ * max_it the number of restarts, tol the acceptance gate on the FP64 pencil
+ * residual of all nev leading Ritz pairs.  Outputs as klst_solve (nev nearest,
+ * ordered by distance); stats count restarts as outer iterations and operator
+ * applications as inner ones.  Errors: as klst_solve; ENOCONV also on a Krylov
+ * breakdown. */
+klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma[2], int nev, double* lambda,
+                                    void* X, int X_on_device, double* resid, int* nconv);
 
 /* Statistics of the last solve. */
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);

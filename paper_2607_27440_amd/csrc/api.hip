@@ -180,10 +180,11 @@ klst_status op_apply(klst_ctx* ctx, cd tau, const double2* x, double2* y, int nv
   return KLST_OK;
 }
 
-klst_status pc_setup(klst_ctx* ctx, cd sigma) {
+// pk_override >= 0 selects the preconditioner kind instead of opt.pc_kernel.
+klst_status pc_setup(klst_ctx* ctx, cd sigma, int pk_override = -1) {
   const klst::Problem& p = ctx->prob;
   const int lines = std::max(1, ctx->opt.lines_per_block);
-  const int pk = ctx->opt.pc_kernel;
+  const int pk = pk_override >= 0 ? pk_override : ctx->opt.pc_kernel;
   if (ctx->pc_ready && ctx->pc_sigma == sigma && ctx->pc_lines == lines && ctx->pc_kernel_built == pk)
     return KLST_OK;
   ctx->pc_ready = false;
@@ -407,6 +408,7 @@ void klst_default_options(klst_options* o) {
   o->pc_kernel = 2;
   o->inner_max_it = 20;
   o->reorth = 0;
+  o->method = 0;
 }
 
 const char* klst_strerror(klst_status s) {
@@ -434,7 +436,8 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
       o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
-      o.inner_max_it < 1 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1))
+      o.inner_max_it < 1 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1) ||
+      (o.method != 0 && o.method != 1))
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -643,9 +646,15 @@ void trsm_upper(int m, const std::vector<cd>& R, std::vector<cd>& B, int ncols) 
 
 }  // namespace
 
+extern "C" klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma_in[2], int nev,
+                                               double* lambda, void* X, int X_on_device, double* resid,
+                                               int* nconv_out);
+
 extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int nev, double* lambda,
                                   void* X, int X_on_device, double* resid, int* nconv_out) {
   using namespace klst::dev;
+  if (ctx && ctx->opt.method == 1)
+    return klst_solve_shift_invert(ctx, sigma_in, nev, lambda, X, X_on_device, resid, nconv_out);
   if (!ctx || !sigma_in || !lambda) return KLST_EINVAL;
   if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_solve before klst_assemble");
   HIPCHK(hipSetDevice(ctx->opt.device));
@@ -784,8 +793,6 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   launch_set_int(st, d_steps, 0);
 
   int outer = 0, inner = 0, restarts = 0;
-  const int lines_ok = 1;
-  (void)lines_ok;
   std::vector<cd> U, T, UL, SR, G, coef;
   cd theta = 0.0;
   bool need_fresh = false;
@@ -1276,6 +1283,247 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   return status;
 }
 
+// ===================================================== shift-invert solver ===
+//
+// Krylov-Schur iteration on S = (A - sigma B)^{-1} B (the paper's Method 1,
+// Sec. 4.1, with the exact structured inverse in place of a sparse LU).  Arnoldi
+// steps run on the device, CGS2 coefficients and norms collect in device memory;
+// at each restart the host forms the Schur form of the Rayleigh quotient sorted by
+// |mu| (mu = 1 / (lambda - sigma)), keeps the leading Schur vectors and the next
+// Arnoldi vector (S V_k = V_k T_k + v_{m+1} b^T), and accepts the nev leading Ritz
+// pairs once their FP64 pencil residuals are below tol.
+extern "C" klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma_in[2], int nev,
+                                               double* lambda, void* X, int X_on_device, double* resid,
+                                               int* nconv_out) {
+  using namespace klst::dev;
+  if (!ctx || !sigma_in || !lambda) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_solve_shift_invert before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const auto t_start = std::chrono::steady_clock::now();
+  const klst::Problem& p = ctx->prob;
+  const klst_options& o = ctx->opt;
+  const int64_t n = p.n();
+  const int ncv = std::max(o.m_max, nev + 2);
+  if (nev < 1 || nev > 100 || nev > n - p.n_bc || ncv > 250 || ncv > n - p.n_bc)
+    return fail(ctx, KLST_EINVAL, "nev or search-space size out of range");
+  const cd sigma(sigma_in[0], sigma_in[1]);
+  hipStream_t st = ctx->stream;
+  ctx->stats = klst_stats{};
+  ctx->history.clear();
+  klst_status s = pc_setup(ctx, sigma, 2);
+  if (s != KLST_OK) return s;
+  const double t_setup = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+
+  Workspace ws{ctx, n, {}};
+  double2* V = ws.vec(ncv + 1);
+  double2* av = ws.vec(1);
+  double2* Tmp = ws.vec(ncv);
+  double2* d_H = ws.small<double2>((size_t)(ncv + 1) * ncv);   // column j at d_H + j (ncv + 1)
+  double2* d_nrm = ws.small<double2>(ncv + 1);
+  double2* d_coef = ws.small<double2>((size_t)ncv * ncv);
+  double2* d_small = ws.small<double2>(256);
+  if (!V || !av || !Tmp || !d_H || !d_nrm || !d_coef || !d_small) return KLST_ENOMEM;
+  double2* partial = ctx->d_partial;
+  double2* npart = ctx->d_npart;
+  if (n > 256LL * 65536) return fail(ctx, KLST_EINVAL, "problem too large for the norm partial table");
+  double t_host = 0.0, t_wait = 0.0;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto secs = [](std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
+    return std::chrono::duration<double>(b - a).count();
+  };
+  auto cgs2 = [&](int m0, double2* x, double2* c, double2* nrm) {
+    int nch = launch_dot_partial(st, V, m0, (const double2*)nullptr, 0, x, n, partial, 0, nullptr);
+    launch_subm_fused(st, V, m0, (const double2*)nullptr, 0, partial, nch, nullptr, c, nullptr, x, n, nullptr,
+                      nullptr);
+    nch = launch_dot_partial(st, V, m0, (const double2*)nullptr, 0, x, n, partial, 0, nullptr);
+    launch_subm_fused(st, V, m0, (const double2*)nullptr, 0, partial, nch, nullptr, nullptr, c, x, n, npart,
+                      nullptr);
+    launch_scale_norm(st, x, (double2*)nullptr, n, npart, nrm, nullptr, 0, 0, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, nullptr, 0.0);
+  };
+  auto apply_S = [&](const double2* x, double2* y) -> klst_status {
+    launch_mask_bc(st, x, av, n, p.Ny, p.Nxi, ctx->d_xix);
+    return pc_apply(ctx, av, y, nullptr);
+  };
+  // start: S applied to a seeded vector (no component in the null space of B)
+  {
+    std::vector<cd> h;
+    start_vector(p, o.seed, 0, h);
+    HIPCHK(hipMemcpyAsync(V + n, h.data(), sizeof(double2) * n, hipMemcpyHostToDevice, st));
+    if ((s = apply_S(V + n, V)) != KLST_OK) return s;
+    launch_subm_fused(st, V, 0, (const double2*)nullptr, 0, partial, 1, nullptr, nullptr, nullptr, V, n, npart,
+                      nullptr);
+    launch_scale_norm(st, V, (double2*)nullptr, n, npart, d_nrm, nullptr, 0, 0, nullptr, nullptr, nullptr,
+                      nullptr, nullptr, nullptr, 0.0);
+  }
+  std::vector<cd> Hm((size_t)ncv * ncv, 0.0), U, T, Y, Z, lam;
+  std::vector<double2> hH((size_t)(ncv + 1) * ncv), hn(ncv + 1);
+  const int kkeep = std::min(ncv - 2, nev + (ncv - nev) / 2);
+  int kcur = 0, restarts = 0, steps = 0;
+  bool done = false;
+  klst_status status = KLST_OK;
+  std::vector<double> res(nev, 0.0);
+  double2* Xd = Tmp;   // candidate Ritz vectors (nev <= ncv - 2 columns of the scratch)
+  while (!done) {
+    if (restarts >= o.max_it) { status = KLST_ENOCONV; break; }
+    if (ctx->cancel && *ctx->cancel) { status = KLST_ECANCELLED; break; }
+    // ---- Arnoldi steps kcur .. ncv - 1
+    for (int j = kcur; j < ncv; ++j) {
+      double2* w = V + (size_t)(j + 1) * n;
+      if ((s = apply_S(V + (size_t)j * n, w)) != KLST_OK) return s;
+      cgs2(j + 1, w, d_H + (size_t)j * (ncv + 1), d_nrm + j);
+      ++steps;
+    }
+    {
+      const auto t0 = now();
+      HIPCHK(hipMemcpyAsync(hH.data(), d_H, sizeof(double2) * hH.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(hn.data(), d_nrm, sizeof(double2) * hn.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      t_wait += secs(t0, now());
+    }
+    for (int j = kcur; j < ncv; ++j)
+      if (!(hn[j].x > 0) || !std::isfinite(hn[j].x))
+        return fail(ctx, KLST_ENOCONV, "Krylov space breakdown (zero or non-finite Arnoldi vector)");
+    const auto th = now();
+    for (int j = kcur; j < ncv; ++j) {
+      for (int i = 0; i <= j; ++i) Hm[(size_t)i * ncv + j] = cd(hH[(size_t)j * (ncv + 1) + i].x, hH[(size_t)j * (ncv + 1) + i].y);
+      if (j + 1 < ncv) Hm[(size_t)(j + 1) * ncv + j] = std::sqrt(hn[j].x);
+    }
+    const double beta = std::sqrt(hn[ncv - 1].x);
+    U.assign((size_t)ncv * ncv, 0.0);
+    T.assign((size_t)ncv * ncv, 0.0);
+    if (!klst::sorted_schur(ncv, Hm.data(), U.data(), T.data(), kkeep))
+      return fail(ctx, KLST_ENOCONV, "Rayleigh quotient Schur form did not converge");
+    // eigenvectors of the leading triangular block, Ritz residual estimates
+    Y.assign((size_t)nev * nev, 0.0);
+    lam.assign(nev, 0.0);
+    double est = 0.0;
+    for (int i = 0; i < nev; ++i) {
+      const cd mu = T[(size_t)i * ncv + i];
+      Y[(size_t)i * nev + i] = 1.0;
+      for (int q = i - 1; q >= 0; --q) {
+        cd acc = 0.0;
+        for (int t = q + 1; t <= i; ++t) acc += T[(size_t)q * ncv + t] * Y[(size_t)t * nev + i];
+        const cd d = T[(size_t)q * ncv + q] - mu;
+        Y[(size_t)q * nev + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
+      }
+      cd zl = 0.0;
+      double zn = 0.0;
+      for (int q = 0; q <= i; ++q) zl += U[(size_t)(ncv - 1) * ncv + q] * Y[(size_t)q * nev + i];
+      for (int r2 = 0; r2 < ncv; ++r2) {
+        cd zr = 0.0;
+        for (int q = 0; q <= i; ++q) zr += U[(size_t)r2 * ncv + q] * Y[(size_t)q * nev + i];
+        zn += std::norm(zr);
+      }
+      est = std::max(est, beta * std::abs(zl) / (std::abs(mu) * std::sqrt(zn)));
+      lam[i] = sigma + 1.0 / mu;
+    }
+    t_host += secs(th, now());
+    ctx->history.insert(ctx->history.end(),
+                        {(double)restarts, 0.0, est, lam[0].real(), lam[0].imag(), 0.0});
+    if (est <= 1e-10) {
+      // explicit FP64 pencil residuals of the candidates x_i = V U Y[:, i]
+      Z.assign((size_t)ncv * nev, 0.0);
+      for (int r2 = 0; r2 < ncv; ++r2)
+        for (int i = 0; i < nev; ++i) {
+          cd acc = 0.0;
+          for (int q = 0; q <= i; ++q) acc += U[(size_t)r2 * ncv + q] * Y[(size_t)q * nev + i];
+          Z[(size_t)r2 * nev + i] = acc;
+        }
+      HIPCHK(hipMemcpyAsync(d_coef, Z.data(), sizeof(double2) * Z.size(), hipMemcpyHostToDevice, st));
+      launch_combine(st, V, ncv, n, d_coef, nev, nev, Xd, nullptr);
+      for (int i = 0; i < nev; ++i) {
+        if ((s = op_apply(ctx, lam[i], Xd + (size_t)i * n, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
+        int nch = launch_dot_partial(st, (const double2*)nullptr, 0, (const double2*)nullptr, 0, av, n, partial,
+                                     1, nullptr);
+        launch_dot_reduce(st, partial, 0, nch, d_small + 2 * i, 3, nullptr, nullptr, nullptr);
+        nch = launch_dot_partial(st, (const double2*)nullptr, 0, (const double2*)nullptr, 0, Xd + (size_t)i * n,
+                                 n, partial, 1, nullptr);
+        launch_dot_reduce(st, partial, 0, nch, d_small + 2 * i + 1, 3, nullptr, nullptr, nullptr);
+      }
+      std::vector<double2> hs(2 * nev);
+      const auto t0 = now();
+      HIPCHK(hipMemcpyAsync(hs.data(), d_small, sizeof(double2) * 2 * nev, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      t_wait += secs(t0, now());
+      bool ok = true;
+      for (int i = 0; i < nev; ++i) {
+        const double sc = std::abs(lam[i]) >= 1e-6 ? std::abs(lam[i]) : 1.0;
+        res[i] = std::sqrt(hs[2 * i].x) / (sc * std::sqrt(hs[2 * i + 1].x));
+        ok = ok && (res[i] <= o.tol);
+      }
+      if (ok) { done = true; break; }
+    }
+    // ---- restart: keep the kkeep leading Schur vectors and the next Arnoldi vector
+    ++restarts;
+    {
+      std::vector<cd> cf((size_t)ncv * kkeep);
+      for (int r2 = 0; r2 < ncv; ++r2)
+        for (int c2 = 0; c2 < kkeep; ++c2) cf[(size_t)r2 * kkeep + c2] = U[(size_t)r2 * ncv + c2];
+      HIPCHK(hipMemcpyAsync(d_coef, cf.data(), sizeof(double2) * cf.size(), hipMemcpyHostToDevice, st));
+      launch_combine(st, V, ncv, n, d_coef, kkeep, kkeep, Tmp, nullptr);
+      HIPCHK(hipMemcpyAsync(V, Tmp, sizeof(double2) * (size_t)kkeep * n, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(V + (size_t)kkeep * n, V + (size_t)ncv * n, sizeof(double2) * n,
+                            hipMemcpyDeviceToDevice, st));
+      std::vector<cd> Hn((size_t)ncv * ncv, 0.0);
+      for (int i = 0; i < kkeep; ++i)
+        for (int j = i; j < kkeep; ++j) Hn[(size_t)i * ncv + j] = T[(size_t)i * ncv + j];
+      for (int j = 0; j < kkeep; ++j) Hn[(size_t)kkeep * ncv + j] = beta * U[(size_t)(ncv - 1) * ncv + j];
+      Hm.swap(Hn);
+      kcur = kkeep;
+    }
+  }
+  // ---- output: the converged candidates (or the current ones), nearest first
+  const int nconv = done ? nev : 0;
+  std::vector<int> order(nconv);
+  for (int i = 0; i < nconv; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double da = std::abs(lam[a] - sigma), db = std::abs(lam[b] - sigma);
+    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
+    return (lam[a].imag() > 0) && !(lam[b].imag() > 0);
+  });
+  if (nconv > 0) {
+    std::vector<cd> hx((size_t)nconv * n);
+    HIPCHK(hipMemcpyAsync(hx.data(), Xd, sizeof(double2) * hx.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<cd> ho((size_t)nconv * n);
+    for (int o2 = 0; o2 < nconv; ++o2) {
+      const cd* xi = &hx[(size_t)order[o2] * n];
+      double nrm = 0.0, big = -1.0;
+      int64_t ib = 0;
+      for (int64_t t = 0; t < n; ++t) {
+        const double a = std::norm(xi[t]);
+        nrm += a;
+        if (a > big * (1.0 + 1e-12)) { big = a; ib = t; }
+      }
+      const cd ph = std::conj(xi[ib]) / std::abs(xi[ib]) / std::sqrt(nrm);
+      cd* xo = &ho[(size_t)o2 * n];
+      for (int64_t t = 0; t < n; ++t) xo[t] = xi[t] * ph;
+      lambda[2 * o2] = lam[order[o2]].real();
+      lambda[2 * o2 + 1] = lam[order[o2]].imag();
+      if (resid) resid[o2] = res[order[o2]];
+    }
+    if (X) {
+      if (X_on_device) {
+        HIPCHK(hipMemcpyAsync(X, ho.data(), sizeof(double2) * ho.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+      } else {
+        std::memcpy(X, ho.data(), sizeof(double2) * ho.size());
+      }
+    }
+  }
+  if (nconv_out) *nconv_out = nconv;
+  ctx->stats.outer_iterations = restarts;
+  ctx->stats.inner_iterations = steps;
+  ctx->stats.restarts = restarts;
+  ctx->stats.nconv = nconv;
+  ctx->stats.seconds_setup = t_setup;
+  ctx->stats.seconds_host = t_host;
+  ctx->stats.seconds_wait = t_wait;
+  ctx->stats.seconds_total = secs(t_start, now());
+  return status;
+}
+
 // ================================================================ server ===
 //
 // Continuous batching of independent solves (stability sweeps).  `slots`
@@ -1343,6 +1591,14 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
   size_t b = 0;
   b += 8ull * (2 * Ny * Ny + 2 * Nxi + Ny) + 2 * 8ull * Ny * 2 * r * Nxi + 16ull * Ny * r * 8;  // tables
   const size_t Rd = r * (size_t)Ny;
+  if (o.method == 1) {   // shift-invert: structured inverse, basis, scratch
+    const int ncv = std::max(o.m_max, nev + 2);
+    b += 16ull * Nxi * Ny * Ny + 16ull * Rd * Rd + 16ull * Rd;
+    if (o.op_mode == 1) b += 20 * n * (Ny - 1 + 2ull * Nxi) + 8 * (n + 1);
+    b += cvec * (2ull * ncv + 2 + nev) + 16ull * ((size_t)(ncv + 1) * ncv + ncv * ncv + 512);
+    b += 16ull * 512 * 256;
+    return b;
+  }
   if (o.pc_kernel == 2) {
     b += 16ull * Nxi * Ny * Ny + 16ull * Rd * Rd + 16ull * Rd;                          // P^-1, S^-1, d
   } else {

@@ -31,7 +31,7 @@ class Options(C.Structure):
                 ("m_min", C.c_int), ("gmres_m", C.c_int), ("max_it", C.c_int), ("tol", C.c_double),
                 ("inner_rtol", C.c_double), ("fix", C.c_double), ("seed", C.c_uint64),
                 ("pc_kernel", C.c_int), ("inner_max_it", C.c_int),
-                ("reorth", C.c_int)]
+                ("reorth", C.c_int), ("method", C.c_int)]
 
 
 class Grid(C.Structure):
@@ -77,6 +77,7 @@ _sig = {
     "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_get_stats": (C.c_int, [_P, C.POINTER(Stats)]),
     "klst_get_history": (C.c_int, [_P, _D2, C.c_int, C.POINTER(C.c_int)]),
+    "klst_solve_shift_invert": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.POINTER(Options)]),
     "klst_server_create": (C.c_int, [C.POINTER(_P), C.POINTER(Options), C.c_int, C.c_size_t, C.c_int]),
     "klst_server_destroy": (None, [_P]),
@@ -242,9 +243,12 @@ class Context:
     def precond_apply(self, x, y):
         self._check(_lib.klst_precond_apply(self._h, self._ptr(x), self._ptr(y)), "klst_precond_apply")
 
-    def solve(self, sigma, nev, X=None, want_vectors=True):
+    def solve(self, sigma, nev, X=None, want_vectors=True, method="jd"):
         """Returns dict(lam, X, resid, nconv, status, stats).  X may be a device
-        tensor of nev * n complex128 to receive the eigenvectors in place."""
+        tensor of nev * n complex128 to receive the eigenvectors in place.
+        method "jd" (klst_solve) or "shift_invert" (klst_solve_shift_invert)."""
+        fn = {"jd": _lib.klst_solve, "shift_invert": _lib.klst_solve_shift_invert}[method]
+        # (klst_solve itself follows options.method; "shift_invert" selects it per call)
         a, p = self._tau(sigma)
         lam = np.zeros(2 * nev)
         res = np.zeros(nev)
@@ -257,9 +261,9 @@ class Context:
             xp, on_dev = C.c_void_p(hostX.ctypes.data), 0
         else:
             hostX, xp, on_dev = None, None, 0
-        st = _lib.klst_solve(self._h, p, int(nev), _dp(lam), xp, on_dev, _dp(res), C.byref(nconv))
+        st = fn(self._h, p, int(nev), _dp(lam), xp, on_dev, _dp(res), C.byref(nconv))
         if st not in (OK, ENOCONV):
-            self._check(st, "klst_solve")
+            self._check(st, fn.__name__)
         k = nconv.value
         s = Stats()
         _lib.klst_get_stats(self._h, C.byref(s))

@@ -379,3 +379,69 @@ def test_solve_c3_matches_oracle_reference():
     assert all(r["ok"] for r in res), res
     assert not skipped, skipped
     assert sorted(r["j"] for r in res)[:8] == list(range(8))
+
+
+# ---- shift-invert Krylov-Schur with the exact structured inverse --------------
+
+def test_shift_invert_c1_matches_qz():
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam_all, X, Y, _ = E.qz_all(P)
+    idx = E.order_nearest(lam_all, wl.sigma)[:wl.nev + 10]
+    kap = E.condition_numbers(P, lam_all[idx], X[:, idx], Y[:, idx])
+    normA = abs(P.A).sum(axis=0).max()
+    ctx = _ctx(wl, m_max=30, max_it=200)
+    out = ctx.solve(wl.sigma, wl.nev, method="shift_invert")
+    print(out["stats"], flush=True)
+    _check_solve(wl, out, lam_all[idx], kap, normA)
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    d = np.abs(out["lam"] - wl.sigma)
+    assert np.all(np.diff(d) >= -1e-12 * d[1:])          # ordered by distance
+
+
+def test_shift_invert_c2_matches_oracle(c2_reference):
+    """Through klst_solve with method = 1 (options), config 2's 20 pairs."""
+    wl, P, ref, kap, normA = c2_reference
+    ctx = _ctx(wl, m_max=60, method=1)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    _check_solve(wl, out, ref, kap, normA, tol=1e-10)
+
+
+@pytest.mark.parametrize("draw", [7, 27, 40, 57])
+def test_shift_invert_sweep_draws(draw):
+    wl = W.sweep(seed=4, count=64, nev=8)[draw]
+    P = O.Pencil(wl)
+    ref, X = E.si_nearest(P, wl.sigma, wl.nev + 6)
+    Y = E.left_vectors_si(P, ref, wl.sigma)
+    kap = np.linalg.norm(Y, axis=0) * np.linalg.norm(X, axis=0) / np.abs(
+        np.einsum("ij,ij->j", Y.conj(), P.bdiag[:, None] * X))
+    normA = abs(P.A).sum(axis=0).max()
+    ctx = _ctx(wl, m_max=30, max_it=200)
+    out = ctx.solve(wl.sigma, wl.nev, method="shift_invert")
+    print(out["stats"], flush=True)
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    _check_solve(wl, out, ref, kap, normA, tol=1e-10)
+
+
+def test_shift_invert_c3_matches_oracle_reference():
+    """The 281,088-unknown Mach 4 pencil by shift-invert Krylov-Schur (search
+    space 120, enough to resolve the 1e-6-wide cluster that holds the 9th and
+    10th eigenvalues), against the stored oracle eigenvalues: the 8 nearest
+    exactly, the rest as distinct cluster members."""
+    wl = W.config3()
+    P = O.Pencil(wl)
+    ref, kap = _c3_reference()
+    normA = _norm1_bound(P)
+    ctx = _ctx(wl, m_max=120, max_it=100)
+    out = ctx.solve(wl.sigma, wl.nev, method="shift_invert")
+    print(out["stats"], flush=True)
+    assert out["nconv"] == wl.nev, out["stats"]
+    assert np.all(out["resid"] <= 1e-10), out["resid"]
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    res, skipped = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-10, tie=1e-5)
+    print("C3 rel. errors:", [f"{r['err']:.2e}/{r['bound']:.1e}" for r in res], flush=True)
+    assert all(r["ok"] for r in res), res
+    assert not skipped, skipped
+    assert sorted(r["j"] for r in res)[:8] == list(range(8))

@@ -26,13 +26,14 @@ def _small_sweep(k=8, nev=6):
     return wls
 
 
-@pytest.mark.parametrize("pc_kernel", [1, 2])
-@pytest.mark.parametrize("precision", [0, 1])
-def test_results_identical_alone_and_in_mix(precision, pc_kernel):
+@pytest.mark.parametrize("pc_kernel,precision,method", [(1, 0, 0), (1, 1, 0), (2, 0, 0), (2, 1, 0), (2, 0, 1)])
+def test_results_identical_alone_and_in_mix(precision, pc_kernel, method):
     klst = _klst()
     wls = _small_sweep()
-    print("[case] sizes", [w.n for w in wls], "precision", precision, "pc", pc_kernel, flush=True)
-    opts = dict(lines_per_block=2, m_max=30, precision=precision, pc_kernel=pc_kernel, max_it=1500)
+    print("[case] sizes", [w.n for w in wls], "precision", precision, "pc", pc_kernel, "method", method,
+          flush=True)
+    opts = dict(lines_per_block=2, m_max=30, precision=precision, pc_kernel=pc_kernel, max_it=1500,
+                method=method)
     with klst.Server(slots=1, **opts) as alone:
         ref = [alone.solve_all([wl])[0] for wl in wls]
     with klst.Server(slots=4, **opts) as mix:
