@@ -47,7 +47,23 @@ WORKLOADS = {
     # structured inverse as preconditioner; the nearest eigenvalues include members
     # of a cluster 1e-6 wide, which needs the larger search space.
     "c3": ("config3", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
+    # Shapes of the paper's benchmark table (Sec. 4.3): M = 1.2, Ny = 81, Q x Q
+    # Gauss-Hermite velocities, beta = 16, 50 eigenvalues nearest 1e-2, search
+    # space 150 (the paper's ncv); exact structured inverse as preconditioner.
+    "pb_q20": ("paper_benchmark:20", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
+    "pb_q24": ("paper_benchmark:24", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
+    "pb_q32": ("paper_benchmark:32", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
+    # Shape of the paper's Mach 4 run (Sec. 4.4): Ny = 61, 48 x 48 Gauss-Hermite
+    # velocities (n = 281,088), 10 nearest 0.
+    "m4_gh48": ("paper_mach4", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
 }
+
+
+def make_workload(workloads, gen):
+    """Generator spec "name" or "name:int_arg" -> workload."""
+    name, _, arg = gen.partition(":")
+    fn = getattr(workloads, name)
+    return fn(int(arg)) if arg else fn()
 # variants reported beside a line (same workload, same residual gate): FP32 inner
 # solves, the exact structured inverse as JD preconditioner, and shift-invert
 # Krylov-Schur with that inverse as operator (method 1)
@@ -332,7 +348,7 @@ def run_profile(a):
     import torch
     from paper_2607_27440_amd import klst, workloads
     gen, opts = WORKLOADS[a.workload]
-    wl = getattr(workloads, gen)()
+    wl = make_workload(workloads, gen)
     st = torch.cuda.current_stream()
     out = {"mode": "profile", "workload": wl.name, "options": opts}
     with klst.Context(stream=st.cuda_stream, **opts) as ctx:
@@ -380,7 +396,7 @@ def main():
     import torch
     from paper_2607_27440_amd import klst, workloads
     gen, opts = WORKLOADS[a.workload]
-    wl = getattr(workloads, gen)()
+    wl = make_workload(workloads, gen)
     prec = 0 if a.precision == "fp64" else 1
     st = torch.cuda.current_stream()
     ctx = klst.Context(stream=st.cuda_stream, precision=prec, **opts)

@@ -61,7 +61,7 @@ typedef struct {
                            inside an FP64 iterative refinement of the correction eq. */
   int op_mode;          /* 0 = matrix-free operator; 1 = explicit CSR (built on device) */
   int lines_per_block;  /* block-Jacobi block = this many whole velocity lines       */
-  int m_max, m_min;     /* search-space size before / after a restart               */
+  int m_max, m_min;     /* search-space size before / after a restart (m_max <= 248) */
   int gmres_m;          /* GMRES restart length (Krylov vectors per cycle)           */
   int max_it;           /* outer-iteration budget                                    */
   double tol;           /* eigenpair acceptance: relative residual                   */

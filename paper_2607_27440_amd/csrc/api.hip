@@ -434,7 +434,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   if (opt) o = *opt; else klst_default_options(&o);
   if (o.m_min < 1 || o.m_max < o.m_min + 2 || o.gmres_m < 1 || o.gmres_m > 256 || o.max_it < 1 ||
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
-      (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 120 ||
+      (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 248 ||
       o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
       o.inner_max_it < 1 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1) ||
       (o.method != 0 && o.method != 1))
@@ -711,13 +711,21 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     if (!Gb32 || !Q32 || !Y32 || !a32 || !b32 || !d32 || !rho64) return KLST_ENOMEM;
   }
   std::vector<cd> HQY32;   // Q32^H Y32 of the locked vectors (mixed precision)
-  const int SM = 1024;   // small device results gathered for one host transfer
+  // Small device results gathered for one host transfer.  Every column count below
+  // is at most kcap + m_max <= 250 (expansion) or kcap + 1 <= 101 (locking), so
+  // each region of the expansion layout holds 256 entries and each region of the
+  // locking layout 128; regions of one layout never overlap.
+  const int SM = 1024;
+  enum { X_MB = 4, X_VW = 260, X_CW = 516 };                       // expansion
+  enum { L_SA = 0, L_SB = 128, L_QY = 256, L_YQ = 384, L_QY32 = 512, L_YQ32 = 640 };   // locking
   double2* d_c = ws.small<double2>(SM);        // coefficients of Gram-Schmidt passes
   double2* d_c2 = ws.small<double2>(SM);
   double2* d_cw = ws.small<double2>(SM);
   double2* d_small = ws.small<double2>(SM);    // host-bound results
-  double2* d_coef = ws.small<double2>(128 * 128);
-  double2* d_Hinv = ws.small<double2>(128 * 128);
+  // basis rotations (m_max x m_max at most), extraction pairs (2 m_max), output
+  // vectors (kcap x nev)
+  double2* d_coef = ws.small<double2>((size_t)std::max({m_max * m_max, 2 * m_max, kcap * nev}));
+  double2* d_Hinv = ws.small<double2>((size_t)(kcap + 1) * (kcap + 1));
   double2* d_H = ws.small<double2>((size_t)(gm + 1) * gm);
   double* d_cs = ws.small<double>(gm);
   double2* d_sn = ws.small<double2>(gm);
@@ -914,13 +922,14 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     if ((s = op_apply(ctx, sigma, vnew, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
     cgs2(Zb, k, W, m, av, d_cw, d_small + 1, wnew);
     // small results gathered for one transfer: [0] |v|^2, [1] |w|^2, [3] GMRES steps,
-    // [4..] M_B column W^H v_new (m + 1), [132..] V^H w_new (m), [260..] Z,W coefficients
-    dot(W, m + 1, nullptr, 0, vnew, d_small + 4, 0);
-    if (m > 0) dot(V, m, nullptr, 0, wnew, d_small + 132, 0);
+    // [X_MB..] M_B column W^H v_new (m + 1), [X_VW..] V^H w_new (m), [X_CW..] Z,W
+    // coefficients (k + m)
+    dot(W, m + 1, nullptr, 0, vnew, d_small + X_MB, 0);
+    if (m > 0) dot(V, m, nullptr, 0, wnew, d_small + X_VW, 0);
     HIPCHK(hipMemcpyAsync(d_small + 3, d_steps, sizeof(int), hipMemcpyDeviceToDevice, st));
     if (k + m > 0)
-      HIPCHK(hipMemcpyAsync(d_small + 260, d_cw, sizeof(double2) * (k + m), hipMemcpyDeviceToDevice, st));
-    if ((s = fetch(260 + k + m)) != KLST_OK) return s;
+      HIPCHK(hipMemcpyAsync(d_small + X_CW, d_cw, sizeof(double2) * (k + m), hipMemcpyDeviceToDevice, st));
+    if ((s = fetch(X_CW + k + m)) != KLST_OK) return s;
     {
       const double v2 = hsmall[0].x, w2 = hsmall[1].x;
       if (!(v2 > 0) || !std::isfinite(v2) || !(w2 > 0) || !std::isfinite(w2))
@@ -932,11 +941,12 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       resize_sq(R, m, m + 1);
       resize_sq(MB, m, m + 1);
       // R column: Gram-Schmidt coefficients against W (after the k Z-coefficients)
-      for (int i = 0; i < m; ++i) R[(size_t)i * (m + 1) + m] = cd(hsmall[260 + k + i].x, hsmall[260 + k + i].y);
-      R[(size_t)m * (m + 1) + m] = std::sqrt(w2);
-      for (int i = 0; i <= m; ++i) MB[(size_t)i * (m + 1) + m] = cd(hsmall[4 + i].x, hsmall[4 + i].y);
       for (int i = 0; i < m; ++i)
-        MB[(size_t)m * (m + 1) + i] = std::conj(cd(hsmall[132 + i].x, hsmall[132 + i].y));
+        R[(size_t)i * (m + 1) + m] = cd(hsmall[X_CW + k + i].x, hsmall[X_CW + k + i].y);
+      R[(size_t)m * (m + 1) + m] = std::sqrt(w2);
+      for (int i = 0; i <= m; ++i) MB[(size_t)i * (m + 1) + m] = cd(hsmall[X_MB + i].x, hsmall[X_MB + i].y);
+      for (int i = 0; i < m; ++i)
+        MB[(size_t)m * (m + 1) + i] = std::conj(cd(hsmall[X_VW + i].x, hsmall[X_VW + i].y));
       ++m;
     }
     // ---- extraction, locking while pairs converge
@@ -978,34 +988,36 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       if ((s = pc_apply(ctx, zv, Yb + (size_t)k * n, nullptr)) != KLST_OK) return s;
       if ((s = op_apply(ctx, 0.0, uv, av, 1, o.op_mode, nullptr)) != KLST_OK) return s;
       launch_mask_bc(st, uv, bv, n, p.Ny, p.Nxi, ctx->d_xix);
-      dot(Zb, k + 1, nullptr, 0, av, d_small + 0, 0);            // S_A column
-      dot(Zb, k + 1, nullptr, 0, bv, d_small + 128, 0);          // S_B column
-      dot(Qb, k + 1, nullptr, 0, Yb + (size_t)k * n, d_small + 256, 0);   // Q^H y_new
-      dot(Yb, k, nullptr, 0, Qb + (size_t)k * n, d_small + 384, 0);       // Y^H q_new
+      dot(Zb, k + 1, nullptr, 0, av, d_small + L_SA, 0);                   // S_A column
+      dot(Zb, k + 1, nullptr, 0, bv, d_small + L_SB, 0);                   // S_B column
+      dot(Qb, k + 1, nullptr, 0, Yb + (size_t)k * n, d_small + L_QY, 0);   // Q^H y_new
+      dot(Yb, k, nullptr, 0, Qb + (size_t)k * n, d_small + L_YQ, 0);       // Y^H q_new
       if (mixed) {   // FP32 mirrors of the new locked pair for the inner solve
         launch_narrow(st, uv, Q32 + (size_t)k * n, n);
         launch_narrow(st, zv, a32, n);
         if ((s = pc_v(ctx, a32, Y32 + (size_t)k * n, nullptr)) != KLST_OK) return s;
-        dot32(Q32, k + 1, nullptr, 0, Y32 + (size_t)k * n, d_small + 400, 0);
+        dot32(Q32, k + 1, nullptr, 0, Y32 + (size_t)k * n, d_small + L_QY32, 0);
         if (k > 0)
-          dot32(Y32, k, nullptr, 0, Q32 + (size_t)k * n, d_small + 500, 0);
+          dot32(Y32, k, nullptr, 0, Q32 + (size_t)k * n, d_small + L_YQ32, 0);
       }
-      if ((s = fetch(mixed ? 500 + k : 384 + k)) != KLST_OK) return s;
+      if ((s = fetch(mixed ? L_YQ32 + k : L_YQ + k)) != KLST_OK) return s;
       if (mixed) {
         resize_sq(HQY32, k, k + 1);
-        for (int i = 0; i <= k; ++i) HQY32[(size_t)i * (k + 1) + k] = cd(hsmall[400 + i].x, hsmall[400 + i].y);
+        for (int i = 0; i <= k; ++i)
+          HQY32[(size_t)i * (k + 1) + k] = cd(hsmall[L_QY32 + i].x, hsmall[L_QY32 + i].y);
         for (int i = 0; i < k; ++i)
-          HQY32[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[500 + i].x, hsmall[500 + i].y));
+          HQY32[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[L_YQ32 + i].x, hsmall[L_YQ32 + i].y));
       }
       resize_sq(SA, k, k + 1);
       resize_sq(SB, k, k + 1);
       resize_sq(HQY, k, k + 1);
       for (int i = 0; i <= k; ++i) {
-        SA[(size_t)i * (k + 1) + k] = cd(hsmall[i].x, hsmall[i].y);
-        SB[(size_t)i * (k + 1) + k] = cd(hsmall[128 + i].x, hsmall[128 + i].y);
-        HQY[(size_t)i * (k + 1) + k] = cd(hsmall[256 + i].x, hsmall[256 + i].y);
+        SA[(size_t)i * (k + 1) + k] = cd(hsmall[L_SA + i].x, hsmall[L_SA + i].y);
+        SB[(size_t)i * (k + 1) + k] = cd(hsmall[L_SB + i].x, hsmall[L_SB + i].y);
+        HQY[(size_t)i * (k + 1) + k] = cd(hsmall[L_QY + i].x, hsmall[L_QY + i].y);
       }
-      for (int i = 0; i < k; ++i) HQY[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[384 + i].x, hsmall[384 + i].y));
+      for (int i = 0; i < k; ++i)
+        HQY[(size_t)k * (k + 1) + i] = std::conj(cd(hsmall[L_YQ + i].x, hsmall[L_YQ + i].y));
       ++k;
       // deflate the search and test spaces
       if (m > 1) {
@@ -1616,7 +1628,9 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
     b += 20 * nnz + 8 * (n + 1);
   }
   b += cvec * (2ull * (m_max + 1) + 3ull * (kcap + 1) + (gm + 1) + m_max + 6 + nev);    // JD workspace
-  b += 16ull * 512 * 256 + 16ull * (4 * 1024 + 2 * 128 * 128 + (gm + 1) * (gm + 3));    // reductions, small
+  const size_t ncoef = std::max({(size_t)m_max * m_max, (size_t)2 * m_max, (size_t)kcap * nev});
+  b += 16ull * 512 * 256 + 16ull * (4 * 1024 + ncoef + (size_t)(kcap + 1) * (kcap + 1) +
+                                    (gm + 1) * (gm + 3));                           // reductions, small
   return b;
 }
 

@@ -21,7 +21,9 @@ Workload recipe (the paper's BE-BGK base flows are not available):
   * "maxwellian" base: rho, u, T each blended with w (the paper's EQ case).
   * "bimodal" base: Mott-Smith mix g_c = (1-w) g_inf + w g_1 of the two
     Rankine-Hugoniot Maxwellians, same for h (the paper's NONEQ case, Sec. 5).
-  * Velocity table: tensor-product trapezoid rule Q_x x Q_y on [-a, a]^2.
+  * Velocity table: tensor-product trapezoid rule Q_x x Q_y on [-a, a]^2, or, for
+    the shapes of the paper's benchmark tables (Sec. 4.3), the Q x Q tensor
+    Gauss-Hermite rule of Sec. 3.2 converted to integrate plain functions.
 """
 from __future__ import annotations
 
@@ -113,6 +115,29 @@ def trapezoid_table(Qx: int, Qy: int, a: float, Dv: int = 2):
     return XX.ravel().copy(), YY.ravel().copy(), WW.ravel().copy()
 
 
+def gauss_hermite_table(Q: int, scale: float = 1.0, Dv: int = 2):
+    """Q x Q tensor Gauss-Hermite nodes/weights for integrating plain functions.
+
+    Sec. 3.2 gives the rule for integrals of f(x) exp(-x^2); a base VDF is
+    integrated as it stands, so each weight carries exp(x_i^2), and the nodes are
+    stretched by `scale` (the paper prints neither conversion).  Flattened
+    p = ix*Q + iy like the trapezoid table."""
+    z, wz = np.polynomial.hermite.hermgauss(Q)
+    z = scale * z
+    wz = scale * wz * np.exp((z / scale) ** 2)
+    if Dv == 1:
+        return z.copy(), np.zeros(Q), wz.copy()
+    XX, YY = np.meshgrid(z, z, indexing="ij")
+    return XX.ravel().copy(), YY.ravel().copy(), np.outer(wz, wz).ravel().copy()
+
+
+def gauss_hermite_scale(Q: int, mach: float) -> float:
+    """Node stretch so that the Q-point rule reaches the velocity box a(M) of the
+    trapezoid tables, and never shrinks below the free-stream thermal scale 1."""
+    zmax = float(np.max(np.polynomial.hermite.hermgauss(Q)[0]))
+    return max(1.0, velocity_range(mach) / zmax)
+
+
 def node_positions(Ny: int, L: float, s_inf: float) -> np.ndarray:
     """Physical positions of the mapped Chebyshev-Gauss-Lobatto nodes (base-flow side)."""
     N = Ny - 1
@@ -132,11 +157,19 @@ def make_workload(name: str, *, mach: float, Ny: int, Qx: int, Qy: int, beta: fl
                   sigma: complex, nev: int, base: str, delta: float,
                   s_visc: float = 0.5, nu_inf: float = NU_INF_HS, Dv: int = 2,
                   s_inf: Optional[float] = None, L: Optional[float] = None,
-                  vmax: Optional[float] = None) -> Workload:
+                  vmax: Optional[float] = None, velocity: str = "trapezoid") -> Workload:
     a = velocity_range(mach) if vmax is None else vmax
     s_inf = 5.0 * delta if s_inf is None else s_inf
     L = delta if L is None else L
-    xi_x, xi_y, w = trapezoid_table(Qx, Qy, a, Dv)
+    if velocity == "trapezoid":
+        xi_x, xi_y, w = trapezoid_table(Qx, Qy, a, Dv)
+    elif velocity == "gauss_hermite":
+        if Qx != Qy:
+            raise ValueError("the Gauss-Hermite table is Q x Q")
+        xi_x, xi_y, w = gauss_hermite_table(Qx, gauss_hermite_scale(Qx, mach), Dv)
+        a = float(np.max(xi_x))
+    else:
+        raise ValueError(velocity)
     x = node_positions(Ny, L, s_inf)
     wgt = 0.5 * (1.0 + np.tanh(2.0 * x / delta))      # 0 upstream (x<0), 1 downstream
     rho1, u1, T1, u_inf = rankine_hugoniot(mach)
@@ -185,6 +218,28 @@ def config3() -> Workload:
     delta = float(np.random.default_rng(3).uniform(2.0, 4.0))
     return make_workload("c3_m4_ny96_nxi1464", mach=4.0, Ny=96, Qx=61, Qy=24, beta=0.5,
                          sigma=0.0, nev=10, base="bimodal", delta=delta)
+
+
+def paper_benchmark(Q: int = 20, Ny: int = 81) -> Workload:
+    """Shape of the paper's benchmark cases (Sec. 4.3): M=1.2, N = 80 (Ny = 81),
+    Q x Q Gauss-Hermite velocities, beta = 16, 50 eigenvalues nearest 1e-2.
+
+    n = 2 Ny Q^2: 64,800 / 93,312 / 165,888 for Q = 20 / 24 / 32.  The BE-BGK base
+    flow is replaced by the Mott-Smith bimodal mix with Delta ~ U(2, 4), seed 20 + Q."""
+    delta = float(np.random.default_rng(20 + Q).uniform(2.0, 4.0))
+    return make_workload(f"pb_m1.2_ny{Ny}_gh{Q}", mach=1.2, Ny=Ny, Qx=Q, Qy=Q, beta=16.0,
+                         sigma=1e-2, nev=50, base="bimodal", delta=delta,
+                         velocity="gauss_hermite")
+
+
+def paper_mach4(Q: int = 48, Ny: int = 61, nev: int = 10) -> Workload:
+    """Shape of the paper's Mach 4 production run (Sec. 4.4): Ny = 61, Q = 48
+    Gauss-Hermite (n = 281,088), bimodal base with Delta ~ U(2, 4), seed 48,
+    beta = 0.5, the eigenvalues nearest 0 (the paper does not state nev)."""
+    delta = float(np.random.default_rng(48).uniform(2.0, 4.0))
+    return make_workload(f"m4_ny{Ny}_gh{Q}", mach=4.0, Ny=Ny, Qx=Q, Qy=Q, beta=0.5,
+                         sigma=0.0, nev=nev, base="bimodal", delta=delta,
+                         velocity="gauss_hermite")
 
 
 #: velocity counts of the batched sweep and their tensor factorisation Q_x x Q_y

@@ -1,0 +1,66 @@
+"""Write tests/golden/<workload>_reference.txt for the Gauss-Hermite paper-shape
+workloads: the eigenvalues nearest the target with their relative residuals and
+condition numbers, computed by the oracle only (exact structured shift-invert
+Arnoldi for right vectors, the adjoint structured inverse for left vectors).
+
+    python tests/golden/make_paper_shape_reference.py pb_q20   # n = 64,800, ~3 min
+    python tests/golden/make_paper_shape_reference.py m4_gh48  # n = 281,088, ~30 min
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import eig as E          # noqa: E402
+from oracle import operator as O     # noqa: E402
+from paper_2607_27440_amd import workloads as W   # noqa: E402
+
+#: workload, eigenvalues kept, Arnoldi basis size
+CASES = {
+    "pb_q20": (lambda: W.paper_benchmark(20), 60, 200),
+    "m4_gh48": (lambda: W.paper_mach4(), 24, 400),
+}
+
+
+def arnoldi(S, n, Bd, k, ncv):
+    op = spla.LinearOperator((n, n), matvec=lambda x: S.solve(Bd * x.ravel()), dtype=complex)
+    return spla.eigs(op, k=k, which="LM", ncv=ncv, tol=1e-12, maxiter=5000)
+
+
+def main(case):
+    make, K, ncv = CASES[case]
+    wl = make()
+    P = O.Pencil(wl)
+    t0 = time.time()
+    S = E.ShiftInvert(P, wl.sigma)
+    mu, X = arnoldi(S, P.n, P.bdiag, K + 16, ncv)
+    lam = wl.sigma + 1.0 / mu
+    idx = E.order_nearest(lam, wl.sigma)[:K]
+    lam, X = lam[idx], X[:, idx]
+    res = E.residuals(P, lam, X)
+    Sa = E.ShiftInvert(P, wl.sigma, adjoint=True)
+    mua, Y = arnoldi(Sa, P.n, P.bdiag, K + 16, ncv)
+    laml = np.conj(np.conj(wl.sigma) + 1.0 / mua)
+    kap = np.empty(K)
+    for i, l in enumerate(lam):
+        j = int(np.argmin(np.abs(laml - l)))
+        y = Y[:, j]
+        kap[i] = np.linalg.norm(y) * np.linalg.norm(X[:, i]) / abs(np.vdot(y, P.bdiag * X[:, i]))
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{case}_reference.txt")
+    with open(out, "w") as f:
+        f.write(f"# oracle eigenvalues of {wl.name} (n = {wl.n:,}) nearest {wl.sigma},\n")
+        f.write(f"# written by tests/golden/make_paper_shape_reference.py {case} in "
+                f"{time.time() - t0:.0f} s\n")
+        f.write("# columns: Re(lambda) Im(lambda) rel_residual kappa\n")
+        for l, r, k in zip(lam, res, kap):
+            f.write(f"{l.real:.17e} {l.imag:.17e} {r:.3e} {k:.3e}\n")
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1])

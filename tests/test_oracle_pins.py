@@ -221,6 +221,45 @@ def test_nnz_formula_reproduces_paper_table():
         assert O.nnz_formula(Ny, Nxi, n_bc) == nnz
 
 
+def test_paper_shape_workloads_match_benchmark_table():
+    """The Gauss-Hermite paper-shape workloads have the unknown counts and, through
+    the oracle's inflow mask, the nnz(A) of the paper's benchmark table."""
+    rows = np.loadtxt(os.path.join(HERE, "golden", "nnz_benchmark_cases.txt"), dtype=np.int64)
+    for Q, n, nnz in rows:
+        wl = W.paper_benchmark(int(Q))
+        assert wl.n == n and wl.Ny == 81 and wl.Nxi == Q * Q
+        n_bc = int(O.bc_mask(wl.Ny, wl.xi_x).sum())
+        assert n_bc == 2 * Q * Q
+        assert O.nnz_formula(wl.Ny, wl.Nxi, n_bc) == nnz
+    assert W.paper_mach4().n == 281088
+
+
+@pytest.mark.parametrize("Q", [8, 20, 48])
+def test_gauss_hermite_workload_table(Q):
+    """The input generator's Gauss-Hermite table (a library root finder) is exact
+    for sum W x^{2m} exp(-x^2) = Gamma(m + 1/2), m < Q (Sec. 3.2), matches the
+    oracle's Golub-Welsch nodes (and its weights where eigenvector components keep
+    their relative accuracy), and integrates the free-stream Maxwellian pair
+    exactly: rho = 1, u = 0, E = 3/4."""
+    xx, xy, w = W.gauss_hermite_table(Q, 1.0)
+    z1, w1 = xx[::Q], np.sqrt(np.diag(w.reshape(Q, Q)))   # one direction of the tensor rule
+    for m in range(min(Q, 40)):
+        ref = Gamma(m + 0.5)
+        assert abs(np.sum(w1 * z1 ** (2 * m) * np.exp(-z1 ** 2)) - ref) <= 1e-12 * ref
+    z, wz = Vq.gauss_hermite_plain(Q)
+    assert np.allclose(z1, z, rtol=0, atol=1e-12 * Q)
+    if Q <= 20:
+        assert np.allclose(w1, wz, rtol=1e-9)
+    one = np.ones(1)
+    g, h = O.equilibrium(one, 0 * one, one, xx, xy, 2)
+    rho, u, v, E_, T = O.moments(g, h, xx, xy, w)
+    assert abs(rho[0] - 1) <= 1e-13 and abs(u[0]) <= 1e-13 and abs(E_[0] - 0.75) <= 1e-13
+    # the stretch only ever widens the table, to the trapezoid box a(M)
+    assert W.gauss_hermite_scale(Q, 1.2) >= 1.0
+    z48, _ = Vq.gauss_hermite(48)
+    assert W.gauss_hermite_scale(48, 4.0) * np.max(z48) == pytest.approx(W.velocity_range(4.0))
+
+
 def test_structural_pattern_matches_formula_and_matrix():
     for wl in (W.config1(), _fine("bimodal", Ny=7, Qx=5, Qy=4)):
         P = O.Pencil(wl)
