@@ -455,28 +455,37 @@ def _golden(name):
     return a[:, 0] + 1j * a[:, 1], a[:, 3]
 
 
+#: case -> (workload, JD options, shift-invert options)
+PAPER_SHAPES = {
+    "pb_q20": (lambda: W.paper_benchmark(20), dict(pc_kernel=2, m_max=150, max_it=3000),
+               dict(m_max=150, max_it=100)),
+    "m4_gh48": (W.paper_mach4, dict(pc_kernel=2, m_max=80, fix=1e-3, max_it=3000),
+                dict(m_max=120, max_it=100)),
+}
+
+
 @pytest.mark.parametrize("method", ["jd", "shift_invert"])
-def test_solve_paper_q20_matches_oracle_reference(method):
-    """M = 1.2 shock at the paper's benchmark shape (Sec. 4.3: N = 80, Q = 20
-    Gauss-Hermite, beta = 16, n = 64,800), the 50 eigenpairs nearest 1e-2, against
-    the oracle's 60 nearest from structured shift-invert Arnoldi
-    (tests/golden/pb_q20_reference.txt).  FP64, exact structured inverse, search
-    space 150 as in the paper's solver settings (App. C)."""
-    wl = W.paper_benchmark(20)
+@pytest.mark.parametrize("case", ["pb_q20", "m4_gh48"])
+def test_solve_paper_shape_matches_oracle_reference(case, method):
+    """Gauss-Hermite workloads at the paper's shapes against the oracle's stored
+    structured shift-invert Arnoldi eigenvalues (tests/golden/<case>_reference.txt):
+    pb_q20 is the M = 1.2 benchmark case (Sec. 4.3: N = 80, Q = 20, beta = 16,
+    n = 64,800, the 50 eigenpairs nearest 1e-2, search space 150 as in App. C);
+    m4_gh48 the Mach 4 shape (Sec. 4.4: Ny = 61, Q = 48, n = 281,088, 10 nearest
+    0).  FP64; JD with the exact structured inverse, or shift-invert Krylov-Schur."""
+    make, jd_opts, si_opts = PAPER_SHAPES[case]
+    wl = make()
     P = O.Pencil(wl)
-    ref, kap = _golden("pb_q20")
+    ref, kap = _golden(case)
     normA = _norm1_bound(P)
-    if method == "jd":
-        ctx = _ctx(wl, pc_kernel=2, m_max=150, max_it=3000)
-    else:
-        ctx = _ctx(wl, m_max=150, max_it=100)
+    ctx = _ctx(wl, **(jd_opts if method == "jd" else si_opts))
     out = ctx.solve(wl.sigma, wl.nev, method=method)
     print(out["stats"], flush=True)
     assert out["nconv"] == wl.nev, out["stats"]
     assert np.all(out["resid"] <= 1e-10), out["resid"]
     assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
     res, skipped = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-10)
-    print("Q20 rel. errors (max):", max(r["err"] for r in res), flush=True)
+    print(case, "rel. errors (max):", max(r["err"] for r in res), flush=True)
     assert all(r["ok"] for r in res), [r for r in res if not r["ok"]]
     assert not skipped, skipped
     d = np.abs(out["lam"] - wl.sigma)
