@@ -20,4 +20,7 @@ Modules
                 deflation, block-Jacobi preconditioned GMRES correction) following
                 the steps of Sec. 4.2; the CPU baseline.
   parity     -- the eigenpair matching rule used by the parity tests.
+  post       -- macroscopic perturbations of eigenvectors and |U_hat| (Sec. 2.2,
+                Sec. 5 eq. Unormpert); the base flow's non-equilibrium level
+                (Sec. 5, eq. L2norm).
 """

@@ -18,6 +18,7 @@ from oracle import eig as E
 from oracle import grid as G
 from oracle import jd as J
 from oracle import operator as O
+from oracle import post as POST
 from oracle import velocity as Vq
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -370,3 +371,84 @@ def test_qz_shift_invert_jd_agree_c1():
     assert np.all(out["resid"] <= 1e-10)
     for l in out["lam"]:
         assert np.min(np.abs(lq - l)) <= 1e-9 * abs(l)
+
+
+# ------------------------------------------ post-processing (Sec. 2.2, Sec. 5) --
+def _fd_equilibrium_column(wl, j, a, h=1e-6):
+    """d (g^e, h^e) / d a at node j by central differences of the Maxwellian pair
+    of the macros (rho, u, v, E) -- independent of the analytic coefficients."""
+    st = O.base_state(wl)
+    m0 = np.array([st["rho"][j], st["u"][j], 0.0, st["E"][j]])
+
+    def pair(m):
+        rho, u, v, E = m
+        T = (4.0 / 3.0) * (E - 0.5 * (u * u + v * v))
+        c2 = (wl.xi_x - u) ** 2 + (wl.xi_y - v) ** 2
+        g = rho / (np.pi * T) ** (0.5 * wl.Dv) * np.exp(-c2 / T)
+        return g, 0.5 * (3 - wl.Dv) * T * g
+
+    e = np.zeros(4)
+    e[a] = h
+    gp, hp = pair(m0 + e)
+    gm, hm = pair(m0 - e)
+    x = np.zeros((wl.Ny, 2, wl.Nxi), complex)
+    x[j, 0] = (gp - gm) / (2 * h)
+    x[j, 1] = (hp - hm) / (2 * h)
+    return x.ravel()
+
+
+@pytest.mark.parametrize("base", ["maxwellian", "bimodal"])
+def test_macros_of_equilibrium_directions_are_unit(base):
+    """Chain rule: the perturbation macros of d(g^e, h^e)/d(rho, u, v, E) are the
+    unit vectors, and T_hat = dT/da = (0, -4u/3, 0, 4/3), up to the quadrature
+    error of the fine grid and the finite-difference error."""
+    wl = _fine(base, Ny=5)
+    st = O.base_state(wl)
+    j = 2
+    for a in range(4):
+        mac, _ = POST.perturbation_macros(wl, _fd_equilibrium_column(wl, j, a))
+        want = np.zeros(4)
+        want[a] = 1.0
+        dT = [0.0, -4.0 * st["u"][j] / 3.0, 0.0, 4.0 / 3.0][a]
+        got = mac[0, j, [0, 1, 2, 3]]
+        assert np.allclose(got, want, atol=2e-8), (a, got)
+        assert abs(mac[0, j, 4] - dT) <= 2e-8
+        others = np.delete(np.arange(wl.Ny), j)
+        assert np.all(mac[0, others] == 0)
+
+
+def test_u_amplitude_normalisation_invariants():
+    """|U_hat| / max is 1 at its maximum, lies in [0, 1], and does not change when
+    the eigenvector is multiplied by any non-zero complex number."""
+    wl = W.config1()
+    x = W.random_vector(wl.n, 3)
+    mac, um = POST.perturbation_macros(wl, x)
+    mac2, um2 = POST.perturbation_macros(wl, (0.3 - 2.0j) * x)
+    assert um.max() == pytest.approx(1.0) and um.min() >= 0
+    assert np.allclose(um, um2, rtol=1e-13, atol=1e-15)
+    assert np.allclose(mac2, (0.3 - 2.0j) * mac, rtol=1e-12, atol=1e-14)
+
+
+def test_noneq_level_closed_form():
+    """E_neq for the Mott-Smith mix g_c = (1-w) g_0 + w g_1 of two reduced 2-D
+    Maxwellians: with g^e the Maxwellian at the mix's macros, E_neq^2 is a sum of
+    Gaussian overlap integrals, int g_i g_j = rho_i rho_j exp(-|u_i - u_j|^2 /
+    (T_i + T_j)) / (pi (T_i + T_j)).  Fine trapezoid grid; zero for EQ bases."""
+    wl = _fine("bimodal", Ny=9, Qx=160, Qy=64, a=11.0, mach=3.0)
+    st = O.base_state(wl)
+    rho1, u1, T1, u0 = W.rankine_hugoniot(wl.mach)
+    wgt = 0.5 * (1.0 + np.tanh(2.0 * wl.x / wl.delta))
+    got = POST.noneq_level(wl)
+    for j in range(wl.Ny):
+        c = [1.0 - wgt[j], wgt[j], -1.0]
+        rr = [1.0, rho1, st["rho"][j]]
+        uu = [u0, u1, st["u"][j]]
+        TT = [1.0, T1, st["T"][j]]
+        s = 0.0
+        for i1 in range(3):
+            for i2 in range(3):
+                Ts = TT[i1] + TT[i2]
+                s += c[i1] * c[i2] * rr[i1] * rr[i2] * np.exp(-(uu[i1] - uu[i2]) ** 2 / Ts) / (np.pi * Ts)
+        # squares compared: the overlap sum cancels to O(1e-16) where w is 0 or 1
+        assert abs(got[j] ** 2 - s) <= 1e-7 * abs(s) + 1e-14, (j, got[j] ** 2, s)
+    assert np.all(POST.noneq_level(_fine("maxwellian", Ny=5)) == 0)
