@@ -217,6 +217,35 @@ klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);
 klst_status klst_get_history(const klst_ctx* ctx, double* rec, int cap, int* count);
 
 /* ---------------------------------------------------------------------------
+ * Post-processing of eigenvectors and of the base flow.
+ * ------------------------------------------------------------------------- */
+
+/* Macroscopic perturbations carried by nvec vectors of the assembled problem
+ * (eigenvectors returned by a solve, for instance), at every spatial node: the
+ * velocity integrals that define rho_hat, u_hat, v_hat and E_hat (Sec. 2.2, the
+ * perturbation-macro integrals), linearised about the base state like the
+ * operator's moment coupling, T_hat = (4/3)(E_hat - u u_hat), and the velocity
+ * amplitude |U_hat| = sqrt(|u_hat|^2 + |v_hat|^2) of Sec. 5 (eq. Unormpert).
+ *   X      device, nvec x n complex doubles (interleaved re, im), vector v at
+ *          X + 2 n v doubles, in the (2 j + f) Nxi + k ordering.
+ *   macros device, [nvec][Ny][5] complex doubles: rho_hat, u_hat, v_hat (0 when
+ *          Dv = 1), E_hat, T_hat.
+ *   umag   device, [nvec][Ny] doubles: |U_hat| divided by its maximum over the
+ *          nodes (all zero when that maximum is zero).
+ * Queued on the ctx stream (asynchronous like klst_apply); X must not overlap
+ * the outputs.  Errors: ESTATE (no problem), EINVAL (null pointer, nvec < 1 or
+ * nvec > 65535), ENOMEM. */
+klst_status klst_perturbation_macros(klst_ctx* ctx, const void* X, int nvec, void* macros, double* umag);
+
+/* Translational non-equilibrium level of the assembled base flow at every
+ * spatial node, E_neq(x_j) = sqrt(sum_k W_k (g_c - g^e)^2) (Sec. 5, eq. L2norm),
+ * with the reduced base g_c in place of f and g^e the reduced Maxwellian at the
+ * node's macros.  Zero for an EQ base (g_c = g^e).
+ *   eneq   device, [Ny] doubles.
+ * Queued on the ctx stream.  Errors: ESTATE (no problem), EINVAL (null pointer). */
+klst_status klst_noneq_level(klst_ctx* ctx, double* eneq);
+
+/* ---------------------------------------------------------------------------
  * Served / batched stability sweeps: many independent solves (different grids,
  * wavenumbers, Mach numbers, base flows) sharing one GPU.  A server owns `slots`
  * contexts, each on its own stream and worker thread.  Requests are admitted in

@@ -41,6 +41,8 @@ struct klst_ctx {
          *d_U = nullptr, *d_M = nullptr;
   double2* d_mom = nullptr;
   int mom_cap = 0;   // vectors
+  // post-processing: weights, base macros [Ny][rho, u, E, T], NONEQ base g
+  double *d_w = nullptr, *d_base = nullptr, *d_gc = nullptr;
   // explicit CSR
   int64_t* d_rowptr = nullptr;
   int32_t* d_col = nullptr;
@@ -121,6 +123,7 @@ void free_problem(klst_ctx* ctx) {
   dfree(ctx, ctx->d_M32); dfree(ctx, ctx->d_mom32); dfree(ctx, ctx->d_Kinv32);
   dfree(ctx, ctx->d_Pinv); dfree(ctx, ctx->d_Sinv); dfree(ctx, ctx->d_capd);
   dfree(ctx, ctx->d_Pinv32); dfree(ctx, ctx->d_Sinv32); dfree(ctx, ctx->d_capd32);
+  dfree(ctx, ctx->d_w); dfree(ctx, ctx->d_base); dfree(ctx, ctx->d_gc);
   ctx->mom_cap = 0;
   ctx->pc_ready = false;
   ctx->assembled = false;
@@ -529,6 +532,25 @@ klst_status klst_assemble(klst_ctx* ctx, const klst_grid* grid, const klst_vel* 
   HIPCHK(hipMemcpyAsync(ctx->d_nu, q.nu.data(), sizeof(double) * q.Ny, hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->d_U, q.U.data(), sizeof(double) * q.U.size(), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->d_M, q.M.data(), sizeof(double) * q.M.size(), hipMemcpyHostToDevice, ctx->stream));
+  {
+    std::vector<double> base((size_t)q.Ny * 4);
+    for (int j = 0; j < q.Ny; ++j) {
+      base[(size_t)j * 4 + 0] = q.rho[j]; base[(size_t)j * 4 + 1] = q.u[j];
+      base[(size_t)j * 4 + 2] = q.E[j]; base[(size_t)j * 4 + 3] = q.T[j];
+    }
+    ALLOC(ctx->d_w, sizeof(double) * q.Nxi);
+    ALLOC(ctx->d_base, sizeof(double) * base.size());
+    HIPCHK(hipMemcpyAsync(ctx->d_w, q.w.data(), sizeof(double) * q.Nxi, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->d_base, base.data(), sizeof(double) * base.size(), hipMemcpyHostToDevice,
+                          ctx->stream));
+    if (!q.gc.empty()) {
+      ALLOC(ctx->d_gc, sizeof(double) * q.gc.size());
+      HIPCHK(hipMemcpyAsync(ctx->d_gc, q.gc.data(), sizeof(double) * q.gc.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+    }
+    // the host base state is not read again while the tables above are alive
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+  }
   klst_status s = ensure_mom(ctx, 1);
   if (s != KLST_OK) return s;
   if (ctx->opt.precision == 1 && (s = upload_fp32_tables(ctx)) != KLST_OK) return s;
@@ -597,6 +619,30 @@ klst_status klst_get_history(const klst_ctx* ctx, double* rec, int cap, int* cou
   *count = total;
   const int nrec = std::min(cap, total);
   std::copy(ctx->history.begin(), ctx->history.begin() + (size_t)nrec * KLST_HISTORY_FIELDS, rec);
+  return KLST_OK;
+}
+
+klst_status klst_perturbation_macros(klst_ctx* ctx, const void* X, int nvec, void* macros, double* umag) {
+  if (!ctx || !X || !macros || !umag || nvec < 1 || nvec > 65535) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_perturbation_macros before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const klst::Problem& p = ctx->prob;
+  klst_status s = ensure_mom(ctx, nvec);
+  if (s != KLST_OK) return s;
+  klst::dev::launch_perturbation_macros(ctx->stream, (const double2*)X, p.n(), nvec, p.Ny, p.Nxi, p.r, ctx->d_M,
+                                        ctx->d_mom, ctx->d_base, (double2*)macros, umag);
+  HIPCHK(hipGetLastError());
+  return KLST_OK;
+}
+
+klst_status klst_noneq_level(klst_ctx* ctx, double* eneq) {
+  if (!ctx || !eneq) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_noneq_level before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_noneq_level(ctx->stream, ctx->d_gc, ctx->d_base, ctx->d_xix, ctx->d_xiy, ctx->d_w, p.Ny,
+                                p.Nxi, p.Dv, eneq);
+  HIPCHK(hipGetLastError());
   return KLST_OK;
 }
 

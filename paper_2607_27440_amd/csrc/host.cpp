@@ -124,6 +124,7 @@ std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base
       return "non-finite base VDF";
     gc.assign(b->g_c, b->g_c + (size_t)Ny * Nxi);
     hc.assign(b->h_c, b->h_c + (size_t)Ny * Nxi);
+    p.gc = gc;
     for (int j = 0; j < Ny; ++j) {
       double m0 = 0, m1 = 0, m2 = 0;
       for (int k = 0; k < Nxi; ++k) {

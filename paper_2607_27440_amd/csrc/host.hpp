@@ -20,6 +20,7 @@ struct Problem {
   std::vector<double> xi_x, xi_y, w;   // [Nxi]
   std::vector<double> Dx;              // [Ny*Ny] row-major, mapped derivative
   std::vector<double> rho, u, E, T, nu;
+  std::vector<double> gc;              // [Ny][Nxi] NONEQ base g (empty for EQ bases)
   std::vector<double> U;               // [Ny][2][r][Nxi] coupling columns G_a / H_a
   std::vector<double> M;               // [Ny][r][2][Nxi] moment functionals
   std::vector<uint8_t> bc;             // [Ny][2][Nxi] inflow rows

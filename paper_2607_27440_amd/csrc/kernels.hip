@@ -1158,6 +1158,74 @@ int moment_splits(int Ny, int nvec, int Nxi) {
   return std::max(1, std::min(8, (2 * Nxi) / 512));
 }
 
+// ------------------------------------------------------- post-processing ----
+
+// Macroscopic perturbations of vector v (blockIdx.x) at every node from the S
+// moment partials of k_moments: macros[(v Ny + j) 5 + (rho, u, v, E, T)], with
+// T_hat = (4/3)(E_hat - u u_hat), the linearisation of T = (4/3)(E - |u|^2/2)
+// about v = 0; umag[v Ny + j] = |U_hat| / max over j, |U_hat| = sqrt(|u_hat|^2 +
+// |v_hat|^2).  Each thread rescales the entries it wrote.  grid nvec, block 256.
+__global__ void __launch_bounds__(256) k_pert_macros(const double2* __restrict__ mom, int Ny, int r, int S,
+                                                     const double* __restrict__ base,
+                                                     double2* __restrict__ macros,
+                                                     double* __restrict__ umag) {
+  __shared__ double smax[256];
+  const int v = blockIdx.x;
+  double lmax = 0.0;
+  for (int j = threadIdx.x; j < Ny; j += 256) {
+    const double2 rh = mom_at<double>(mom, v, Ny, j, 0, r, S);
+    const double2 uh = mom_at<double>(mom, v, Ny, j, 1, r, S);
+    const double2 vh = (r == 4) ? mom_at<double>(mom, v, Ny, j, 2, r, S) : make_double2(0.0, 0.0);
+    const double2 eh = mom_at<double>(mom, v, Ny, j, r - 1, r, S);
+    const double u = base[(int64_t)j * 4 + 1];
+    const double2 th = make_double2((4.0 / 3.0) * (eh.x - u * uh.x), (4.0 / 3.0) * (eh.y - u * uh.y));
+    double2* o = macros + ((int64_t)v * Ny + j) * 5;
+    o[0] = rh;
+    o[1] = uh;
+    o[2] = vh;
+    o[3] = eh;
+    o[4] = th;
+    const double a = sqrt(uh.x * uh.x + uh.y * uh.y + vh.x * vh.x + vh.y * vh.y);
+    umag[(int64_t)v * Ny + j] = a;
+    lmax = fmax(lmax, a);
+  }
+  smax[threadIdx.x] = lmax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double mx = smax[0];
+  if (mx > 0.0)
+    for (int j = threadIdx.x; j < Ny; j += 256) umag[(int64_t)v * Ny + j] /= mx;
+}
+
+// Non-equilibrium level of the base flow at node j (blockIdx.x):
+// sqrt(sum_k w_k (g_c - g^e)^2), g^e the reduced Maxwellian rho / (pi T)^(Dv/2)
+// exp(-((xi_x - u)^2 + xi_y^2) / T) at the node's macros; gc == nullptr (an EQ
+// base, g_c = g^e) gives 0.  grid Ny, block 256.
+__global__ void __launch_bounds__(256) k_noneq_level(const double* __restrict__ gc,
+                                                     const double* __restrict__ base,
+                                                     const double* __restrict__ xix,
+                                                     const double* __restrict__ xiy,
+                                                     const double* __restrict__ w, int Nxi, int Dv,
+                                                     double* __restrict__ eneq) {
+  __shared__ double2 sh[4];
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  if (gc) {
+    const double rho = base[(int64_t)j * 4], u = base[(int64_t)j * 4 + 1], T = base[(int64_t)j * 4 + 3];
+    const double pre = rho / (Dv == 2 ? M_PI * T : sqrt(M_PI * T));
+    for (int k = threadIdx.x; k < Nxi; k += 256) {
+      const double cx = xix[k] - u, cy = xiy[k];
+      const double d = gc[(int64_t)j * Nxi + k] - pre * exp(-(cx * cx + cy * cy) / T);
+      acc += w[k] * d * d;
+    }
+  }
+  const double2 t = block_sum256(make_double2(acc, 0.0), sh);
+  if (threadIdx.x == 0) eneq[j] = sqrt(t.x);
+}
+
 template <class R>
 static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                       const R* M, cv<R>* mom, const int* skip) {
@@ -1468,6 +1536,20 @@ void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int
 
 void launch_set_int(hipStream_t st, int* p, int v) {
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, st, p, v);
+}
+
+void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                                const double* M, double2* mom, const double* base, double2* macros,
+                                double* umag) {
+  const int S = moment_splits(Ny, nvec, Nxi);
+  hipLaunchKernelGGL((k_moments<double>), dim3(Ny * S, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S,
+                     nullptr);
+  hipLaunchKernelGGL(k_pert_macros, dim3(nvec), dim3(256), 0, st, mom, Ny, r, S, base, macros, umag);
+}
+
+void launch_noneq_level(hipStream_t st, const double* gc, const double* base, const double* xix,
+                        const double* xiy, const double* w, int Ny, int Nxi, int Dv, double* eneq) {
+  hipLaunchKernelGGL(k_noneq_level, dim3(Ny), dim3(256), 0, st, gc, base, xix, xiy, w, Nxi, Dv, eneq);
 }
 
 }  // namespace dev

@@ -56,6 +56,15 @@ void launch_gmres_solve(hipStream_t st, const double2* H, int ldh, const double2
 void launch_mask_bc(hipStream_t st, const double2* x, double2* y, int64_t n, int Ny, int Nxi,
                     const double* xix);
 void launch_set_int(hipStream_t st, int* p, int v);
+// Macroscopic perturbations of nvec vectors x: macros [nvec][Ny][5] complex (rho,
+// u, v, E, T hats), umag [nvec][Ny] = |U_hat| / max_j |U_hat|; mom is scratch of
+// Ny * r * nvec * 8 entries, base [Ny][rho, u, E, T].  nvec <= 65535.
+void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
+                                const double* M, double2* mom, const double* base, double2* macros,
+                                double* umag);
+// Non-equilibrium level of the base g per node (gc == nullptr: an EQ base, zeros).
+void launch_noneq_level(hipStream_t st, const double* gc, const double* base, const double* xix,
+                        const double* xiy, const double* w, int Ny, int Nxi, int Dv, double* eneq);
 
 // ---- FP32 overloads (mixed-precision inner solve); coefficients stay FP64 ----
 void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny, int Nxi, int r,

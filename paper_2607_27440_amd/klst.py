@@ -91,6 +91,8 @@ _sig = {
     "klst_host_tables": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
                                    _D2, _D2, _D2, _D2, C.POINTER(C.c_uint8)]),
     "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
+    "klst_perturbation_macros": (C.c_int, [_P, _P, C.c_int, _P, _P]),
+    "klst_noneq_level": (C.c_int, [_P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -209,6 +211,7 @@ class Context:
         nbc = C.c_int()
         self._check(_lib.klst_dims(self._h, C.byref(n), C.byref(nnz), C.byref(nbc)), "klst_dims")
         self.n, self.nnz, self.n_bc = n.value, nnz.value, nbc.value
+        self._ny = int(wl.Ny)
         return self
 
     @staticmethod
@@ -235,6 +238,27 @@ class Context:
     def apply_csr(self, tau, x, y):
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_csr(self._h, p, self._ptr(x), self._ptr(y)), "klst_apply_csr")
+
+    def perturbation_macros(self, X):
+        """Macroscopic perturbations of the columns of X (device complex128, shape
+        [n] or [nvec, n]): (macros [nvec, Ny, 5] complex128 with rho, u, v, E, T
+        hats; |U_hat| / max [nvec, Ny] float64), both on the device."""
+        import torch
+        X = X.reshape(-1, self.n)
+        nvec = X.shape[0]
+        ny = self._ny
+        mac = torch.empty((nvec, ny, 5), dtype=torch.complex128, device=X.device)
+        um = torch.empty((nvec, ny), dtype=torch.float64, device=X.device)
+        self._check(_lib.klst_perturbation_macros(self._h, self._ptr(X), nvec, C.c_void_p(mac.data_ptr()),
+                                                  C.c_void_p(um.data_ptr())), "klst_perturbation_macros")
+        return mac, um
+
+    def noneq_level(self):
+        """E_neq of the assembled base flow at every spatial node (device float64 [Ny])."""
+        import torch
+        out = torch.empty(self._ny, dtype=torch.float64, device="cuda")
+        self._check(_lib.klst_noneq_level(self._h, C.c_void_p(out.data_ptr())), "klst_noneq_level")
+        return out
 
     def precond_setup(self, sigma):
         a, p = self._tau(sigma)
