@@ -48,11 +48,13 @@ WORKLOADS = {
     # of a cluster 1e-6 wide, which needs the larger search space.
     "c3": ("config3", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
     # Shapes of the paper's benchmark table (Sec. 4.3): M = 1.2, Ny = 81, Q x Q
-    # Gauss-Hermite velocities, beta = 16, 50 eigenvalues nearest 1e-2, search
-    # space 150 (the paper's ncv); exact structured inverse as preconditioner.
-    "pb_q20": ("paper_benchmark:20", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
-    "pb_q24": ("paper_benchmark:24", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
-    "pb_q32": ("paper_benchmark:32", dict(pc_kernel=2, m_max=150, m_min=6, gmres_m=20)),
+    # Gauss-Hermite velocities, beta = 16, 50 eigenvalues nearest 1e-2; exact
+    # structured inverse as preconditioner.  Search space 60 -> 20 and the
+    # correction shift switched to theta below rel. residual 0.1 (measured faster
+    # than the paper's ncv 150 here; the parity tests also run ncv 150).
+    "pb_q20": ("paper_benchmark:20", dict(pc_kernel=2, m_max=60, m_min=20, gmres_m=20, fix=0.1)),
+    "pb_q24": ("paper_benchmark:24", dict(pc_kernel=2, m_max=60, m_min=20, gmres_m=20, fix=0.1)),
+    "pb_q32": ("paper_benchmark:32", dict(pc_kernel=2, m_max=60, m_min=20, gmres_m=20, fix=0.1)),
     # Shape of the paper's Mach 4 run (Sec. 4.4): Ny = 61, 48 x 48 Gauss-Hermite
     # velocities (n = 281,088), 10 nearest 0.
     "m4_gh48": ("paper_mach4", dict(pc_kernel=2, m_max=80, m_min=6, gmres_m=20, fix=1e-3, max_it=3000)),
@@ -92,7 +94,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "profile"])
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--count", type=int, default=64, help="batched: number of sweep solves")
     ap.add_argument("--requests", type=int, default=80, help="served: number of requests")
     ap.add_argument("--rate", type=float, default=0.0,
