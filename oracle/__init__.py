@@ -20,6 +20,8 @@ Modules
                 deflation, block-Jacobi preconditioned GMRES correction) following
                 the steps of Sec. 4.2; the CPU baseline.
   parity     -- the eigenpair matching rule used by the parity tests.
+  bgk        -- BE-BGK base-flow relaxation: MUSCL-minmod finite volumes on the
+                mapped nodes, BGK collision, RK4 in time (Sec. 3.3).
   post       -- macroscopic perturbations of eigenvectors and |U_hat| (Sec. 2.2,
                 Sec. 5 eq. Unormpert); the base flow's non-equilibrium level
                 (Sec. 5, eq. L2norm).

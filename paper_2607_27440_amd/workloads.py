@@ -264,6 +264,29 @@ def sweep(seed: int = 4, count: int = 64, nev: int = 8):
     return out
 
 
+def bgk_start(wl: Workload):
+    """Initial state (g, h) [Ny, Nxi] of the base-flow relaxation: the Mott-Smith
+    mix of the two Rankine-Hugoniot Maxwellians, with the two end nodes set to
+    those Maxwellians exactly (node 0 downstream, node Ny-1 upstream)."""
+    one = np.ones(wl.Ny)
+    rho1, u1, T1, u_inf = rankine_hugoniot(wl.mach)
+    g0, h0 = _maxwell_vdf(one, one * u_inf, one, wl.xi_x, wl.xi_y, wl.Dv)
+    g1, h1 = _maxwell_vdf(one * rho1, one * u1, one * T1, wl.xi_x, wl.xi_y, wl.Dv)
+    wgt = 0.5 * (1.0 + np.tanh(2.0 * wl.x / wl.delta))[:, None]
+    g = (1.0 - wgt) * g0 + wgt * g1
+    h = (1.0 - wgt) * h0 + wgt * h1
+    g[0], h[0] = g1[0], h1[0]
+    g[-1], h[-1] = g0[-1], h0[-1]
+    return g, h
+
+
+def bgk_dt(wl: Workload, cfl: float = 0.4) -> float:
+    """Time step of the relaxation: cfl x the smallest interior cell width
+    (x_{i+1} - x_{i-1}) / 2 over the largest |xi_x|."""
+    x = np.sort(wl.x)
+    return float(cfl * np.min(0.5 * (x[2:] - x[:-2])) / np.max(np.abs(wl.xi_x)))
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded complex test vector, uniform in [-1,1] for real and imaginary parts."""
     rng = np.random.default_rng(seed)
