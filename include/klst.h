@@ -245,6 +245,30 @@ klst_status klst_perturbation_macros(klst_ctx* ctx, const void* X, int nvec, voi
  * Queued on the ctx stream.  Errors: ESTATE (no problem), EINVAL (null pointer). */
 klst_status klst_noneq_level(klst_ctx* ctx, double* eneq);
 
+/* BE-BGK base-flow relaxation (Sec. 3.3): march the reduced 1D2V BGK equations
+ * d(g, h)/dt = nu ((g^e, h^e) - (g, h)) - xi_x d(g, h)/dx to a steady shock with
+ * classical RK4 steps of size dt.  x-derivative: finite volumes on the mapped
+ * Chebyshev nodes of `grid` (cell widths (x_{j-1} - x_{j+1}) / 2), interface
+ * values by MUSCL reconstruction upwinded on xi_x with the minmod limiter;
+ * values beyond the two end nodes repeat the end node.  Collision: the reduced
+ * Maxwellians at each node's discrete macros (transverse velocity 0),
+ * nu = nu_inf rho T^(1 - s_visc).  The two end nodes keep their input states
+ * (the Rankine-Hugoniot boundary conditions).
+ *   g, h        host, [Ny][Nxi] row-major; in: the start state, out: the state
+ *               after the last step (the caller keeps ownership).
+ *   max_steps   step budget (0: only the residual is evaluated).
+ *   tol, check_every  with tol > 0, max |RHS| is checked before every
+ *               check_every-th step and the march stops once it is <= tol.
+ *   steps_done  (optional) steps taken; resid (optional) max |RHS| of the
+ *               returned state.
+ * Runs on ctx's device and stream (no assembled problem needed) and returns
+ * when the result is on the host.  Errors: EINVAL (Ny < 3, Nxi < 1, Dv not 1 or
+ * 2, w <= 0, dt <= 0, non-finite input), ENOMEM, ENOCONV (the state became
+ * non-finite: dt too large for the grid). */
+klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel* vel, double nu_inf,
+                           double s_visc, double* g, double* h, double dt, int max_steps, double tol,
+                           int check_every, int* steps_done, double* resid);
+
 /* ---------------------------------------------------------------------------
  * Served / batched stability sweeps: many independent solves (different grids,
  * wavenumbers, Mach numbers, base flows) sharing one GPU.  A server owns `slots`

@@ -635,6 +635,100 @@ klst_status klst_perturbation_macros(klst_ctx* ctx, const void* X, int nvec, voi
   return KLST_OK;
 }
 
+klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel* vel, double nu_inf,
+                           double s_visc, double* g, double* h, double dt, int max_steps, double tol,
+                           int check_every, int* steps_done, double* resid) {
+  if (!ctx || !grid || !vel || !g || !h || !vel->xi_x || !vel->xi_y || !vel->w) return KLST_EINVAL;
+  const int Ny = grid->Ny, Nxi = vel->Nxi, Dv = vel->Dv;
+  if (Ny < 3 || Nxi < 1 || (Dv != 1 && Dv != 2) || !(dt > 0) || !std::isfinite(dt) || max_steps < 0 ||
+      check_every < 1 || !(nu_inf >= 0) || !std::isfinite(nu_inf) || !std::isfinite(s_visc) ||
+      !(grid->L > 0) || !(grid->s_inf > 0) || !std::isfinite(grid->L) || !std::isfinite(grid->s_inf))
+    return fail(ctx, KLST_EINVAL, "klst_bgk_relax: bad sizes, time step or grid");
+  for (int k = 0; k < Nxi; ++k)
+    if (!(vel->w[k] > 0) || !std::isfinite(vel->xi_x[k]) || !std::isfinite(vel->xi_y[k]))
+      return fail(ctx, KLST_EINVAL, "klst_bgk_relax: bad velocity table");
+  const size_t cells = (size_t)Ny * Nxi;
+  for (size_t e = 0; e < cells; ++e)
+    if (!std::isfinite(g[e]) || !std::isfinite(h[e])) return fail(ctx, KLST_EINVAL, "klst_bgk_relax: non-finite state");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  hipStream_t st = ctx->stream;
+  // cell widths (x_{j-1} - x_{j+1}) / 2 of the mapped nodes; the end nodes are held
+  std::vector<double> x(Ny), inv_dx(Ny, 0.0);
+  klst::mapped_nodes(Ny, grid->L, grid->s_inf, x.data());
+  for (int j = 1; j < Ny - 1; ++j) inv_dx[j] = 2.0 / (x[j - 1] - x[j + 1]);
+  std::vector<double> hq(2 * cells);
+  for (int j = 0; j < Ny; ++j)
+    for (int k = 0; k < Nxi; ++k) {
+      hq[((size_t)2 * j) * Nxi + k] = g[(size_t)j * Nxi + k];
+      hq[((size_t)2 * j + 1) * Nxi + k] = h[(size_t)j * Nxi + k];
+    }
+  struct Buffers {
+    klst_ctx* c;
+    double *q0 = nullptr, *q1 = nullptr, *ka = nullptr, *kb = nullptr, *acc = nullptr, *tab = nullptr,
+           *res = nullptr;
+    ~Buffers() {
+      if (q0) (void)hipStreamSynchronize(c->stream);
+      dfree(c, q0); dfree(c, q1); dfree(c, ka); dfree(c, kb); dfree(c, acc); dfree(c, tab); dfree(c, res);
+    }
+  } b{ctx};
+  const size_t nb = sizeof(double) * 2 * cells;
+  if (dalloc(ctx, (void**)&b.q0, nb) != KLST_OK || dalloc(ctx, (void**)&b.q1, nb) != KLST_OK ||
+      dalloc(ctx, (void**)&b.ka, nb) != KLST_OK || dalloc(ctx, (void**)&b.kb, nb) != KLST_OK ||
+      dalloc(ctx, (void**)&b.acc, nb) != KLST_OK ||
+      dalloc(ctx, (void**)&b.tab, sizeof(double) * (3 * (size_t)Nxi + Ny)) != KLST_OK ||
+      dalloc(ctx, (void**)&b.res, sizeof(double) * Ny) != KLST_OK)
+    return KLST_ENOMEM;
+  double *d_xix = b.tab, *d_xiy = b.tab + Nxi, *d_w = b.tab + 2 * Nxi, *d_idx = b.tab + 3 * Nxi;
+  HIPCHK(hipMemcpyAsync(b.q0, hq.data(), nb, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_xix, vel->xi_x, sizeof(double) * Nxi, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_xiy, vel->xi_y, sizeof(double) * Nxi, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_w, vel->w, sizeof(double) * Nxi, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_idx, inv_dx.data(), sizeof(double) * Ny, hipMemcpyHostToDevice, st));
+  std::vector<double> hres(Ny);
+  auto max_resid = [&]() -> double {
+    HIPCHK(hipMemcpyAsync(hres.data(), b.res, sizeof(double) * Ny, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return *std::max_element(hres.begin(), hres.end());
+  };
+  using klst::dev::launch_bgk_stage;
+  double* q = b.q0;
+  double* qn = b.q1;
+  const double dt6 = dt / 6.0;
+  int step = 0;
+  for (; step < max_steps; ++step) {
+    const bool check = tol > 0 && step % check_every == 0;
+    launch_bgk_stage(st, q, nullptr, 0.0, b.ka, b.acc, nullptr, dt6, 1, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
+                     nu_inf, s_visc, check ? b.res : nullptr);
+    if (check) {
+      const double r = max_resid();
+      if (!std::isfinite(r)) return fail(ctx, KLST_ENOCONV, "klst_bgk_relax: non-finite state");
+      if (r <= tol) break;
+    }
+    launch_bgk_stage(st, q, b.ka, 0.5 * dt, b.kb, b.acc, nullptr, dt6, 2, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
+                     nu_inf, s_visc, nullptr);
+    launch_bgk_stage(st, q, b.kb, 0.5 * dt, b.ka, b.acc, nullptr, dt6, 3, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
+                     nu_inf, s_visc, nullptr);
+    launch_bgk_stage(st, q, b.ka, dt, b.kb, b.acc, qn, dt6, 4, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx, nu_inf,
+                     s_visc, nullptr);
+    std::swap(q, qn);
+  }
+  HIPCHK(hipGetLastError());
+  // residual of the final state
+  launch_bgk_stage(st, q, nullptr, 0.0, b.ka, b.acc, nullptr, dt6, 1, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
+                   nu_inf, s_visc, b.res);
+  const double rfin = max_resid();
+  HIPCHK(hipMemcpyAsync(hq.data(), q, nb, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int j = 0; j < Ny; ++j)
+    for (int k = 0; k < Nxi; ++k) {
+      g[(size_t)j * Nxi + k] = hq[((size_t)2 * j) * Nxi + k];
+      h[(size_t)j * Nxi + k] = hq[((size_t)2 * j + 1) * Nxi + k];
+    }
+  if (steps_done) *steps_done = step;
+  if (resid) *resid = rfin;
+  return std::isfinite(rfin) ? KLST_OK : fail(ctx, KLST_ENOCONV, "klst_bgk_relax: non-finite state");
+}
+
 klst_status klst_noneq_level(klst_ctx* ctx, double* eneq) {
   if (!ctx || !eneq) return KLST_EINVAL;
   if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_noneq_level before klst_assemble");

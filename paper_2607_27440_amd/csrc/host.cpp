@@ -34,6 +34,16 @@ bool finite_all(const double* a, size_t n) {
 // and the perturbation moments of the discrete rows (eq. comp_ghat1Dshock):
 //   m_rho = sum W g, m_u = sum W (xi_x - u) g / rho, m_v = sum W xi_y g / rho,
 //   m_E = sum W ((|xi|^2 - 2E) g + h) / (2 rho).
+void mapped_nodes(int Ny, double L, double s_inf, double* x) {
+  const int N = Ny - 1;
+  const double pi = 3.14159265358979323846;
+  const double s = (L / s_inf) * (L / s_inf);
+  for (int i = 0; i < Ny; ++i) {
+    const double y = std::cos(pi * i / N);
+    x[i] = L * y / std::sqrt(1.0 + s - y * y);
+  }
+}
+
 std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
                           double beta, Problem& p) {
   if (!g || !v || !b) return "null grid, velocity table or base flow";

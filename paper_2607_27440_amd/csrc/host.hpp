@@ -32,6 +32,10 @@ struct Problem {
   bool is_bc(int j, int k) const { return bc[((size_t)j * 2) * Nxi + k] != 0; }
 };
 
+// Mapped Chebyshev-Gauss-Lobatto node positions x_j = L y_j / sqrt(1 + s - y_j^2),
+// y_j = cos(j pi / (Ny - 1)), s = (L / s_inf)^2 (node 0 at x = +s_inf).
+void mapped_nodes(int Ny, double L, double s_inf, double* x);
+
 // Fills `p`; returns an empty string on success, else a description of the error.
 std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
                           double beta, Problem& p);

@@ -1226,6 +1226,107 @@ __global__ void __launch_bounds__(256) k_noneq_level(const double* __restrict__ 
   if (threadIdx.x == 0) eneq[j] = sqrt(t.x);
 }
 
+// --------------------------------------------- BE-BGK base-flow relaxation ----
+
+// Interface value between x-ascending nodes i and i+1 from the values at i-1, i,
+// i+1, i+2: MUSCL upwinded on the sign of xi_x, minmod limiter evaluated as
+// (sgn a + sgn b)/2 min(|a|, |b|) of the two one-sided differences.
+__device__ __forceinline__ double muscl_face(double pm, double p0, double pp, double ppp, double xi) {
+  auto mm = [](double a, double b) {
+    return 0.5 * ((a > 0) - (a < 0) + (b > 0) - (b < 0)) * fmin(fabs(a), fabs(b));
+  };
+  return xi >= 0.0 ? p0 + 0.5 * mm(p0 - pm, pp - p0) : pp - 0.5 * mm(ppp - pp, pp - p0);
+}
+
+// One Runge-Kutta stage of the reduced BGK equations at node j (blockIdx.x) of
+// the grid order (node 0 at x = +s_inf), state layout q[(2 j + f) Nxi + k]:
+//   stage state  Q = q + a kprev (kprev == nullptr: Q = q)
+//   kout         = nu (Q^e - Q) - xi_x (Q_{i+1/2} - Q_{i-1/2}) inv_dx_j at the
+//                  interior nodes (x-ascending index i = Ny - 1 - j, values beyond
+//                  the ends repeat the end node), 0 at the two held end nodes
+//   acc          = kout (stage 1) or acc + 2 kout (stages 2, 3)
+//   qout         = q + dt6 (acc + kout) (stage 4)
+// with Q^e the reduced Maxwellian pair at node j's macros of Q.  resid (optional)
+// receives max |kout| over the node.  grid Ny, block 256.
+__global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
+                                                   const double* __restrict__ kprev, double a,
+                                                   double* __restrict__ kout, double* __restrict__ acc,
+                                                   double* __restrict__ qout, double dt6, int stage, int Ny,
+                                                   int Nxi, int Dv, const double* __restrict__ xix,
+                                                   const double* __restrict__ xiy,
+                                                   const double* __restrict__ w,
+                                                   const double* __restrict__ inv_dx, double nu_inf,
+                                                   double s_visc, double* __restrict__ resid) {
+  __shared__ double red[3][256];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int nc = 2 * Nxi;
+  const bool held = (j == 0 || j == Ny - 1);
+  auto Q = [&](int jj, int c) {
+    const int64_t e = (int64_t)jj * nc + c;
+    return kprev ? q[e] + a * kprev[e] : q[e];
+  };
+  // macros of the stage state at node j
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  if (!held) {
+    for (int k = tid; k < Nxi; k += 256) {
+      const double gv = Q(j, k), hv = Q(j, Nxi + k), xx = xix[k], yy = xiy[k];
+      m0 += w[k] * gv;
+      m1 += w[k] * xx * gv;
+      m2 += w[k] * ((xx * xx + yy * yy) * gv + hv);
+    }
+  }
+  red[0][tid] = m0;
+  red[1][tid] = m1;
+  red[2][tid] = m2;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      red[0][tid] += red[0][tid + st];
+      red[1][tid] += red[1][tid + st];
+      red[2][tid] += red[2][tid + st];
+    }
+    __syncthreads();
+  }
+  const double rho = red[0][0], u = red[1][0] / rho, E = 0.5 * red[2][0] / rho;
+  const double T = (4.0 / 3.0) * (E - 0.5 * u * u);
+  const double nu = nu_inf * rho * pow(T, 1.0 - s_visc);
+  const double pre = rho / (Dv == 2 ? M_PI * T : sqrt(M_PI * T));
+  const double hfac = 0.5 * (3 - Dv) * T;
+  // neighbours in x-ascending order: i - 1 <-> j + 1, i + 1 <-> j - 1 (clamped)
+  const int jm2 = min(j + 2, Ny - 1), jm1 = min(j + 1, Ny - 1), jp1 = max(j - 1, 0), jp2 = max(j - 2, 0);
+  const double idx = inv_dx[j];
+  double rmax = 0.0;
+  for (int c = tid; c < nc; c += 256) {
+    const int64_t e = (int64_t)j * nc + c;
+    double r = 0.0;
+    if (!held) {
+      const int k = (c < Nxi) ? c : c - Nxi;
+      const double xx = xix[k], cx = xx - u, cy = xiy[k];
+      const double ge = pre * exp(-(cx * cx + cy * cy) / T);
+      const double eq = (c < Nxi) ? ge : hfac * ge;
+      const double v0 = Q(j, c), vm1 = Q(jm1, c), vm2 = Q(jm2, c), vp1 = Q(jp1, c), vp2 = Q(jp2, c);
+      const double fr = muscl_face(vm1, v0, vp1, vp2, xx);    // i + 1/2
+      const double fl = muscl_face(vm2, vm1, v0, vp1, xx);    // i - 1/2
+      r = nu * (eq - v0) - xx * (fr - fl) * idx;
+    }
+    kout[e] = r;
+    if (stage == 1) acc[e] = r;
+    else if (stage < 4) acc[e] += 2.0 * r;
+    else qout[e] = q[e] + dt6 * (acc[e] + r);
+    rmax = fmax(rmax, fabs(r));
+  }
+  if (resid) {
+    __syncthreads();
+    red[0][tid] = rmax;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (tid < st) red[0][tid] = fmax(red[0][tid], red[0][tid + st]);
+      __syncthreads();
+    }
+    if (tid == 0) resid[j] = red[0][0];
+  }
+}
+
 template <class R>
 static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                       const R* M, cv<R>* mom, const int* skip) {
@@ -1550,6 +1651,14 @@ void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int
 void launch_noneq_level(hipStream_t st, const double* gc, const double* base, const double* xix,
                         const double* xiy, const double* w, int Ny, int Nxi, int Dv, double* eneq) {
   hipLaunchKernelGGL(k_noneq_level, dim3(Ny), dim3(256), 0, st, gc, base, xix, xiy, w, Nxi, Dv, eneq);
+}
+
+void launch_bgk_stage(hipStream_t st, const double* q, const double* kprev, double a, double* kout, double* acc,
+                      double* qout, double dt6, int stage, int Ny, int Nxi, int Dv, const double* xix,
+                      const double* xiy, const double* w, const double* inv_dx, double nu_inf, double s_visc,
+                      double* resid) {
+  hipLaunchKernelGGL(k_bgk_stage, dim3(Ny), dim3(256), 0, st, q, kprev, a, kout, acc, qout, dt6, stage, Ny, Nxi,
+                     Dv, xix, xiy, w, inv_dx, nu_inf, s_visc, resid);
 }
 
 }  // namespace dev

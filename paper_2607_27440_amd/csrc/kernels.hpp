@@ -62,6 +62,13 @@ void launch_set_int(hipStream_t st, int* p, int v);
 void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                                 const double* M, double2* mom, const double* base, double2* macros,
                                 double* umag);
+// One RK4 stage (1..4) of the BE-BGK relaxation over all nodes; state q
+// [(2 j + f) Nxi + k]; kprev (nullptr at stage 1) and a form the stage state;
+// kout, acc and (stage 4) qout as documented at the kernel; resid optional [Ny].
+void launch_bgk_stage(hipStream_t st, const double* q, const double* kprev, double a, double* kout, double* acc,
+                      double* qout, double dt6, int stage, int Ny, int Nxi, int Dv, const double* xix,
+                      const double* xiy, const double* w, const double* inv_dx, double nu_inf, double s_visc,
+                      double* resid);
 // Non-equilibrium level of the base g per node (gc == nullptr: an EQ base, zeros).
 void launch_noneq_level(hipStream_t st, const double* gc, const double* base, const double* xix,
                         const double* xiy, const double* w, int Ny, int Nxi, int Dv, double* eneq);

@@ -93,6 +93,9 @@ _sig = {
     "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
     "klst_perturbation_macros": (C.c_int, [_P, _P, C.c_int, _P, _P]),
     "klst_noneq_level": (C.c_int, [_P, _P]),
+    "klst_bgk_relax": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Vel), C.c_double, C.c_double, _D2, _D2,
+                                 C.c_double, C.c_int, C.c_double, C.c_int, C.POINTER(C.c_int),
+                                 C.POINTER(C.c_double)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -259,6 +262,19 @@ class Context:
         out = torch.empty(self._ny, dtype=torch.float64, device="cuda")
         self._check(_lib.klst_noneq_level(self._h, C.c_void_p(out.data_ptr())), "klst_noneq_level")
         return out
+
+    def bgk_relax(self, wl, g0, h0, dt, steps, tol=0.0, check_every=100):
+        """BE-BGK relaxation on the workload's grid and velocity table from the
+        host start state (g0, h0) [Ny, Nxi]; returns (g, h, steps taken, max |RHS|)."""
+        g = np.ascontiguousarray(g0, dtype=np.float64).copy()
+        h = np.ascontiguousarray(h0, dtype=np.float64).copy()
+        gr, v, _b, keep = _structs(wl)
+        nst = C.c_int()
+        res = C.c_double()
+        self._check(_lib.klst_bgk_relax(self._h, C.byref(gr), C.byref(v), float(wl.nu_inf), float(wl.s_visc),
+                                        _dp(g), _dp(h), float(dt), int(steps), float(tol), int(check_every),
+                                        C.byref(nst), C.byref(res)), "klst_bgk_relax")
+        return g, h, nst.value, res.value
 
     def precond_setup(self, sigma):
         a, p = self._tau(sigma)

@@ -1,0 +1,95 @@
+"""GPU parity of the BE-BGK base-flow relaxation (klst_bgk_relax) against
+oracle/bgk.py, and the relaxed base flow carried through the stability solve.
+
+Bound for a march of K steps: every stage forms node macros from sums over Nxi
+velocity entries (relative error (Nxi + 16) u), which the Maxwellian's exponent
+amplifies by at most 64 on these tables (1 + c^2 / T with the conditioning of T)
+and each step carries at most a few such roundings into the state; the errors of
+successive steps add (the scheme is dissipative), so the state differs from the
+oracle's by at most K 64 (Nxi + 16) u max|q0|.  A discretisation mistake moves
+the state by O(dt) relative instead.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_2607_27440_amd import workloads as W
+from oracle import bgk as BGK
+from oracle import eig as E
+from oracle import operator as O
+from oracle import parity as PAR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+CASES = {"c1": (W.config1, 300), "c2": (W.config2, 200), "c3": (W.config3, 8),
+         "m4_gh48": (W.paper_mach4, 8), "pb_q20": (lambda: W.paper_benchmark(20), 40)}
+
+
+def _ctx():
+    from paper_2607_27440_amd import klst
+    return klst.Context()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_bgk_relax_matches_oracle(case):
+    make, K = CASES[case]
+    wl = make()
+    print(f"[case] bgk {wl.name} steps={K}", flush=True)
+    g0, h0 = W.bgk_start(wl)
+    dt = W.bgk_dt(wl)
+    g, h, steps, res = _ctx().bgk_relax(wl, g0, h0, dt, K)
+    rg, rh, rres = BGK.relax(wl.x, wl.xi_x, wl.xi_y, wl.w, wl.Dv, wl.nu_inf, wl.s_visc, g0, h0, dt, K)
+    assert steps == K
+    bound = K * 64 * (wl.Nxi + 16) * U * max(np.abs(g0).max(), np.abs(h0).max())
+    assert np.abs(g - rg).max() <= bound, np.abs(g - rg).max() / bound
+    assert np.abs(h - rh).max() <= bound, np.abs(h - rh).max() / bound
+    assert res == pytest.approx(rres, rel=1e-6, abs=1e3 * bound / dt)
+    # the march moved the state by far more than the bound
+    assert np.abs(rg - g0).max() > 1e3 * bound
+    assert np.array_equal(g[[0, -1]], g0[[0, -1]]) and np.array_equal(h[[0, -1]], h0[[0, -1]])
+
+
+def test_bgk_relax_tolerance_stop_is_deterministic():
+    """With tol > 0 the march stops at the first check whose residual is below
+    tol; the state equals a run of exactly that many steps, bit for bit."""
+    wl = W.config2()
+    g0, h0 = W.bgk_start(wl)
+    dt = W.bgk_dt(wl)
+    ctx = _ctx()
+    _, _, _, r0 = ctx.bgk_relax(wl, g0, h0, dt, 0)
+    tol = 1e-2 * r0
+    g, h, steps, res = ctx.bgk_relax(wl, g0, h0, dt, 100000, tol=tol, check_every=50)
+    assert 0 < steps < 100000 and steps % 50 == 0 and res <= tol
+    g2, h2, steps2, res2 = ctx.bgk_relax(wl, g0, h0, dt, steps)
+    assert steps2 == steps and np.array_equal(g, g2) and np.array_equal(h, h2) and res2 == res
+
+
+def test_relaxed_base_flow_through_the_stability_solve():
+    """Config 1 grid and velocities: the GPU-relaxed BGK shock (2000 steps) as a
+    NONEQ base flow, JD on the GPU, against the oracle's QZ eigenvalues of the
+    pencil built on the oracle's own relaxed base flow."""
+    from paper_2607_27440_amd import klst
+    wl = W.config1()
+    g0, h0 = W.bgk_start(wl)
+    dt = W.bgk_dt(wl)
+    g, h, _, _ = _ctx().bgk_relax(wl, g0, h0, dt, 2000)
+    rg, rh, _ = BGK.relax(wl.x, wl.xi_x, wl.xi_y, wl.w, wl.Dv, wl.nu_inf, wl.s_visc, g0, h0, dt, 2000)
+    base = dict(mode=1, rho=None, u=None, T=None)
+    wl_gpu = dataclasses.replace(wl, g_c=g, h_c=h, **base)
+    wl_ref = dataclasses.replace(wl, g_c=rg, h_c=rh, **base)
+    P = O.Pencil(wl_ref)
+    lam_all, X, Y, _ = E.qz_all(P)
+    idx = E.order_nearest(lam_all, wl.sigma)[:wl.nev + 10]
+    kap = E.condition_numbers(P, lam_all[idx], X[:, idx], Y[:, idx])
+    normA = abs(P.A).sum(axis=0).max()
+    with klst.Context(pc_kernel=2, m_max=40) as ctx:
+        ctx.assemble(wl_gpu)
+        out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    assert out["nconv"] == wl.nev and np.all(out["resid"] <= 1e-10)
+    res, skipped = PAR.match(out["lam"], lam_all[idx], kap, normA, sigma=wl.sigma, tol=1e-10)
+    assert all(r["ok"] for r in res), [r for r in res if not r["ok"]]
+    assert not skipped
