@@ -93,7 +93,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "profile"])
+    ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "profile", "bgk"])
+    ap.add_argument("--bgk-steps", type=int, default=2000, help="bgk: RK4 steps timed")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--count", type=int, default=64, help="batched: number of sweep solves")
     ap.add_argument("--requests", type=int, default=80, help="served: number of requests")
@@ -227,6 +228,51 @@ def _common(metric, unit, value, a, el, nsteps, dtype, config, extra):
             "data": "synthetic", "config": config}
     line.update(extra)
     return line
+
+
+#: flops counted per state entry and RK4 stage of the relaxation kernel: the
+#: macro sums (8), the Maxwellian (exponential counted as 20, plus 8), two MUSCL
+#: faces (2 x 8), the stage update and accumulator (8)
+BGK_FLOPS_PER_ENTRY = 60
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def run_bgk(a):
+    """BE-BGK base-flow relaxation on the workload's grid and velocity table from
+    the Mott-Smith start: `bgk_steps` RK4 steps (4 stage kernels each), timed
+    after a warm-up march, reported as state-entry updates per second (entries =
+    2 Ny Nxi, one update per step).  The per-stage kernel time is the difference
+    of a K-step and a 0-step march over 4K; its working set (a few state arrays)
+    stays in the caches, so its roofline is the FP64 vector rate."""
+    import numpy as np
+    import torch  # noqa: F401
+    from paper_2607_27440_amd import klst, workloads
+    gen, _ = WORKLOADS[a.workload]
+    wl = make_workload(workloads, gen)
+    g0, h0 = workloads.bgk_start(wl)
+    dt = workloads.bgk_dt(wl)
+    K = a.bgk_steps
+    with klst.Context() as ctx:
+        ctx.bgk_relax(wl, g0, h0, dt, max(1, K // 10))          # warm-up
+        t = time.perf_counter()
+        ctx.bgk_relax(wl, g0, h0, dt, 0)
+        t0 = time.perf_counter() - t
+        t = time.perf_counter()
+        g, h, steps, res = ctx.bgk_relax(wl, g0, h0, dt, K)
+        el = time.perf_counter() - t
+        _, _, _, res0 = ctx.bgk_relax(wl, g0, h0, dt, 0)
+    entries = 2 * wl.Ny * wl.Nxi
+    stage_s = max(el - t0, 1e-12) / (4 * K)
+    achieved = BGK_FLOPS_PER_ENTRY * entries / stage_s / 1e12
+    roof = {"kernel": "k_bgk_stage (one RK4 stage, one workgroup per node)", "bound": "alu",
+            "achieved": round(achieved, 4), "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_VECTOR_PEAK_TFLOPS, 5), "traffic": None,
+            "avg_us": round(stage_s * 1e6, 3), "flops_per_launch": BGK_FLOPS_PER_ENTRY * entries}
+    cfg = {"workload": f"bgk_relax_{wl.name}", "Ny": wl.Ny, "Nxi": wl.Nxi, "dt": dt, "mach": wl.mach}
+    return _common("BE-BGK state-entry updates/s (RK4 steps x 2 Ny Nxi)", "entry-updates/s",
+                   entries * K / el, a, el, K, "f64", cfg,
+                   {"roofline": roof, "residual_start": res0, "residual_end": res,
+                    "steps_per_s": round(K / el, 1), "host_roundtrip_s": round(t0, 4)})
 
 
 def run_batched(a):
@@ -390,6 +436,8 @@ def main():
         import torch  # noqa: F401  (device initialisation)
         if a.mode == "profile":
             line = run_profile(a)
+        elif a.mode == "bgk":
+            line = run_bgk(a)
         else:
             line = run_batched(a) if a.mode == "batched" else run_served(a)
         print(json.dumps(line), flush=True)

@@ -676,7 +676,7 @@ klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel*
       dalloc(ctx, (void**)&b.ka, nb) != KLST_OK || dalloc(ctx, (void**)&b.kb, nb) != KLST_OK ||
       dalloc(ctx, (void**)&b.acc, nb) != KLST_OK ||
       dalloc(ctx, (void**)&b.tab, sizeof(double) * (3 * (size_t)Nxi + Ny)) != KLST_OK ||
-      dalloc(ctx, (void**)&b.res, sizeof(double) * Ny) != KLST_OK)
+      dalloc(ctx, (void**)&b.res, sizeof(double) * Ny * klst::dev::bgk_parts(Nxi)) != KLST_OK)
     return KLST_ENOMEM;
   double *d_xix = b.tab, *d_xiy = b.tab + Nxi, *d_w = b.tab + 2 * Nxi, *d_idx = b.tab + 3 * Nxi;
   HIPCHK(hipMemcpyAsync(b.q0, hq.data(), nb, hipMemcpyHostToDevice, st));
@@ -684,11 +684,13 @@ klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel*
   HIPCHK(hipMemcpyAsync(d_xiy, vel->xi_y, sizeof(double) * Nxi, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_w, vel->w, sizeof(double) * Nxi, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_idx, inv_dx.data(), sizeof(double) * Ny, hipMemcpyHostToDevice, st));
-  std::vector<double> hres(Ny);
-  auto max_resid = [&]() -> double {
-    HIPCHK(hipMemcpyAsync(hres.data(), b.res, sizeof(double) * Ny, hipMemcpyDeviceToHost, st));
+  std::vector<double> hres((size_t)Ny * klst::dev::bgk_parts(Nxi));
+  auto max_resid = [&](double& r) -> klst_status {
+    HIPCHK(hipMemcpyAsync(hres.data(), b.res, sizeof(double) * hres.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    return *std::max_element(hres.begin(), hres.end());
+    r = 0.0;
+    for (double v : hres) r = (v > r || !std::isfinite(v)) ? v : r;   // keeps a NaN or inf
+    return KLST_OK;
   };
   using klst::dev::launch_bgk_stage;
   double* q = b.q0;
@@ -700,7 +702,9 @@ klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel*
     launch_bgk_stage(st, q, nullptr, 0.0, b.ka, b.acc, nullptr, dt6, 1, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
                      nu_inf, s_visc, check ? b.res : nullptr);
     if (check) {
-      const double r = max_resid();
+      double r = 0.0;
+      const klst_status sr = max_resid(r);
+      if (sr != KLST_OK) return sr;
       if (!std::isfinite(r)) return fail(ctx, KLST_ENOCONV, "klst_bgk_relax: non-finite state");
       if (r <= tol) break;
     }
@@ -716,7 +720,9 @@ klst_status klst_bgk_relax(klst_ctx* ctx, const klst_grid* grid, const klst_vel*
   // residual of the final state
   launch_bgk_stage(st, q, nullptr, 0.0, b.ka, b.acc, nullptr, dt6, 1, Ny, Nxi, Dv, d_xix, d_xiy, d_w, d_idx,
                    nu_inf, s_visc, b.res);
-  const double rfin = max_resid();
+  double rfin = 0.0;
+  const klst_status sr = max_resid(rfin);
+  if (sr != KLST_OK) return sr;
   HIPCHK(hipMemcpyAsync(hq.data(), q, nb, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   for (int j = 0; j < Ny; ++j)

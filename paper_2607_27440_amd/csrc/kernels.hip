@@ -1246,8 +1246,11 @@ __device__ __forceinline__ double muscl_face(double pm, double p0, double pp, do
 //                  the ends repeat the end node), 0 at the two held end nodes
 //   acc          = kout (stage 1) or acc + 2 kout (stages 2, 3)
 //   qout         = q + dt6 (acc + kout) (stage 4)
-// with Q^e the reduced Maxwellian pair at node j's macros of Q.  resid (optional)
-// receives max |kout| over the node.  grid Ny, block 256.
+// with Q^e the reduced Maxwellian pair at node j's macros of Q.  The node's 2 Nxi
+// columns are split over gridDim.y workgroups, each of which forms the node's
+// macros itself (same sums in the same order, so the copies agree bit for bit).
+// resid (optional) receives max |kout| over the workgroup's columns at
+// resid[j gridDim.y + blockIdx.y].  grid (Ny, parts), block 256.
 __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
                                                    const double* __restrict__ kprev, double a,
                                                    double* __restrict__ kout, double* __restrict__ acc,
@@ -1295,8 +1298,10 @@ __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
   // neighbours in x-ascending order: i - 1 <-> j + 1, i + 1 <-> j - 1 (clamped)
   const int jm2 = min(j + 2, Ny - 1), jm1 = min(j + 1, Ny - 1), jp1 = max(j - 1, 0), jp2 = max(j - 2, 0);
   const double idx = inv_dx[j];
+  const int per = (nc + gridDim.y - 1) / gridDim.y;
+  const int cbeg = blockIdx.y * per, cend = min(nc, cbeg + per);
   double rmax = 0.0;
-  for (int c = tid; c < nc; c += 256) {
+  for (int c = cbeg + tid; c < cend; c += 256) {
     const int64_t e = (int64_t)j * nc + c;
     double r = 0.0;
     if (!held) {
@@ -1313,17 +1318,21 @@ __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
     if (stage == 1) acc[e] = r;
     else if (stage < 4) acc[e] += 2.0 * r;
     else qout[e] = q[e] + dt6 * (acc[e] + r);
-    rmax = fmax(rmax, fabs(r));
+    const double ar = fabs(r);
+    rmax = (ar > rmax || ar != ar) ? ar : rmax;   // a NaN propagates (fmax would drop it)
   }
   if (resid) {
     __syncthreads();
     red[0][tid] = rmax;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
-      if (tid < st) red[0][tid] = fmax(red[0][tid], red[0][tid + st]);
+      if (tid < st) {
+        const double o = red[0][tid + st];
+        if (o > red[0][tid] || o != o) red[0][tid] = o;
+      }
       __syncthreads();
     }
-    if (tid == 0) resid[j] = red[0][0];
+    if (tid == 0) resid[(int64_t)j * gridDim.y + blockIdx.y] = red[0][0];
   }
 }
 
@@ -1653,12 +1662,14 @@ void launch_noneq_level(hipStream_t st, const double* gc, const double* base, co
   hipLaunchKernelGGL(k_noneq_level, dim3(Ny), dim3(256), 0, st, gc, base, xix, xiy, w, Nxi, Dv, eneq);
 }
 
+int bgk_parts(int Nxi) { return std::max(1, std::min(32, (2 * Nxi + 255) / 256)); }
+
 void launch_bgk_stage(hipStream_t st, const double* q, const double* kprev, double a, double* kout, double* acc,
                       double* qout, double dt6, int stage, int Ny, int Nxi, int Dv, const double* xix,
                       const double* xiy, const double* w, const double* inv_dx, double nu_inf, double s_visc,
                       double* resid) {
-  hipLaunchKernelGGL(k_bgk_stage, dim3(Ny), dim3(256), 0, st, q, kprev, a, kout, acc, qout, dt6, stage, Ny, Nxi,
-                     Dv, xix, xiy, w, inv_dx, nu_inf, s_visc, resid);
+  hipLaunchKernelGGL(k_bgk_stage, dim3(Ny, bgk_parts(Nxi)), dim3(256), 0, st, q, kprev, a, kout, acc, qout, dt6,
+                     stage, Ny, Nxi, Dv, xix, xiy, w, inv_dx, nu_inf, s_visc, resid);
 }
 
 }  // namespace dev

@@ -64,7 +64,9 @@ void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int
                                 double* umag);
 // One RK4 stage (1..4) of the BE-BGK relaxation over all nodes; state q
 // [(2 j + f) Nxi + k]; kprev (nullptr at stage 1) and a form the stage state;
-// kout, acc and (stage 4) qout as documented at the kernel; resid optional [Ny].
+// kout, acc and (stage 4) qout as documented at the kernel; resid optional
+// [Ny * bgk_parts(Nxi)] (per-workgroup max |kout|).
+int bgk_parts(int Nxi);
 void launch_bgk_stage(hipStream_t st, const double* q, const double* kprev, double a, double* kout, double* acc,
                       double* qout, double dt6, int stage, int Ny, int Nxi, int Dv, const double* xix,
                       const double* xiy, const double* w, const double* inv_dx, double nu_inf, double s_visc,
