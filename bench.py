@@ -108,6 +108,27 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _line_slots(wl, sigma):
+    """Line inverses the structured preconditioner stores: one per velocity node,
+    and one per mirrored pair (same xi_x, opposite non-zero xi_y) when the target
+    is real, since the mirror's block is the conjugate."""
+    if complex(sigma).imag != 0.0:
+        return wl.Nxi
+    pos = {(float(x), float(y)): k for k, (x, y) in enumerate(zip(wl.xi_x, wl.xi_y))}
+    taken = [False] * wl.Nxi
+    slots = 0
+    for k in range(wl.Nxi):
+        if taken[k]:
+            continue
+        taken[k] = True
+        slots += 1
+        if wl.xi_y[k] != 0.0:
+            m = pos.get((float(wl.xi_x[k]), float(-wl.xi_y[k])))
+            if m is not None and m != k and not taken[m]:
+                taken[m] = True
+    return slots
+
+
 def kernel_roofline(ctx, wl, torch, reps, workload=None):
     """Time the block-Jacobi ILU(0) apply (the dominant kernel of the solve) with
     HIP events on the library's stream.  Algorithmic bytes per launch: with the
@@ -134,11 +155,13 @@ def kernel_roofline(ctx, wl, torch, reps, workload=None):
     nlines = 2 * wl.Nxi
     nblocks = (nlines + nl - 1) // nl
     if ctx.options.pc_kernel == 2:
-        # two line-inverse passes (each reads the Nxi shared Ny x Ny inverses, x,
+        # two line-inverse passes (each reads the stored Ny x Ny inverses once, x,
         # writes y), the moment pass (reads y and M), the capacitance GEMV, and the
-        # rank update's U read in the second pass
+        # rank update's U read in the second pass; with a real target one stored
+        # inverse serves a velocity node and its xi_y mirror
         Rd = 4 * wl.Ny
-        nbytes = 2 * 16 * wl.Nxi * wl.Ny * wl.Ny + 16 * 5 * n + 2 * 8 * 4 * n + 16 * Rd * Rd
+        nslots = _line_slots(wl, wl.sigma)
+        nbytes = 2 * 16 * nslots * wl.Ny * wl.Ny + 16 * 5 * n + 2 * 8 * 4 * n + 16 * Rd * Rd
         kname = "structured exact inverse (2 x k_line_inverse + k_moments + k_capacitance)"
     elif ctx.options.pc_kernel == 1:
         sizes = [min(nl, nlines - b * nl) * wl.Ny for b in range(nblocks)]

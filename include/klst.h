@@ -51,7 +51,8 @@ typedef enum {
 
 /* Solver options (defaults from klst_default_options).  Paper defaults for the
  * JD solve are listed in its Appendix C; the values here follow the same
- * scheme: tol on ||A u - theta B u|| / (|theta| ||u||), restart from m_max to
+ * scheme: tol on ||A u - theta B u|| / (|theta| ||u||) (JD locks a Schur pair at
+ * tol / 2 so that the returned eigenvectors meet tol), restart from m_max to
  * m_min, correction equations solved by GMRES restarted every gmres_m steps,
  * up to inner_max_it steps or a residual reduction of inner_rtol. */
 typedef struct {
@@ -177,8 +178,9 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
 
 /* Jacobi-Davidson solve for the nev eigenvalues nearest sigma (Sec. 4.2).
  * Pairs are locked as they converge; once nev are locked the iteration goes on
- * until a newly locked eigenvalue is not nearer sigma than the nev-th nearest
- * locked one (at most min(2 nev, 100, 250 - m_max) pairs are locked), and the
+ * until max(1, nev / 10) consecutive newly locked eigenvalues were not nearer
+ * sigma than the nev-th nearest locked one (at most min(2 nev, 100, 250 - m_max)
+ * pairs are locked), and the
  * nev nearest are returned, ordered by |lambda - sigma| (ties: Im lambda > 0
  * first).
  * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at

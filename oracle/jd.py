@@ -163,15 +163,18 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
     outer = inner = 0
     restarts = 0
     # the result is the nev eigenvalues nearest sigma, and JD locks pairs in the
-    # order they converge: after nev are locked, go on until a newly locked
-    # eigenvalue is not nearer than the nev-th nearest locked one (beyond it, or
-    # tied as a conjugate partner is for a real target), then keep the nev nearest
+    # order they converge: after nev are locked, go on until max(1, nev // 10)
+    # consecutive newly locked eigenvalues were not nearer than the nev-th nearest
+    # locked one (beyond it, or tied as a conjugate partner is for a real target),
+    # then keep the nev nearest
     kcap = min(2 * nev, 100, 250 - m_max)
     complete = False
+    guard = {"run": max(1, nev // 10), "streak": 0}
 
     def passed_nearest():
         d = np.abs(np.diag(SA) / np.diag(SB) - sigma)
-        return d[-1] >= np.sort(d)[nev - 1] * (1 - 1e-12)
+        guard["streak"] = guard["streak"] + 1 if d[-1] >= np.sort(d)[nev - 1] * (1 - 1e-12) else 0
+        return guard["streak"] >= guard["run"]
 
     while not complete and outer < max_it:
         if time_limit is not None and time.perf_counter() - t_start > time_limit:

@@ -62,6 +62,8 @@ struct klst_ctx {
   float2* d_Kinv32 = nullptr;
   // structured exact inverse (pc_kernel 2): line inverses, capacitance inverse, d scratch
   double2 *d_Pinv = nullptr, *d_Sinv = nullptr, *d_capd = nullptr;
+  int* d_slots = nullptr;   // [2][nslots]: node, mirrored node (-1: none) per stored line inverse
+  int nslots = 0;
   float2 *d_Pinv32 = nullptr, *d_Sinv32 = nullptr, *d_capd32 = nullptr;
   // reductions
   double2* d_partial = nullptr;
@@ -121,7 +123,7 @@ void free_problem(klst_ctx* ctx) {
   dfree(ctx, ctx->d_F); dfree(ctx, ctx->d_C); dfree(ctx, ctx->d_Kinv); dfree(ctx, ctx->d_koff);
   dfree(ctx, ctx->d_Dx32); dfree(ctx, ctx->d_DxT32); dfree(ctx, ctx->d_xix32); dfree(ctx, ctx->d_xiy32); dfree(ctx, ctx->d_nu32); dfree(ctx, ctx->d_U32);
   dfree(ctx, ctx->d_M32); dfree(ctx, ctx->d_mom32); dfree(ctx, ctx->d_Kinv32);
-  dfree(ctx, ctx->d_Pinv); dfree(ctx, ctx->d_Sinv); dfree(ctx, ctx->d_capd);
+  dfree(ctx, ctx->d_Pinv); dfree(ctx, ctx->d_Sinv); dfree(ctx, ctx->d_capd); dfree(ctx, ctx->d_slots);
   dfree(ctx, ctx->d_Pinv32); dfree(ctx, ctx->d_Sinv32); dfree(ctx, ctx->d_capd32);
   dfree(ctx, ctx->d_w); dfree(ctx, ctx->d_base); dfree(ctx, ctx->d_gc);
   ctx->mom_cap = 0;
@@ -197,8 +199,8 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma, int pk_override = -1) {
   // GEMV stages nl Ny inputs plus up to 16 x 64 partial sums, the line inverse 2 Ny
   // inputs plus 2 x 16 x 64, the capacitance GEMV its r Ny right-hand side
   const size_t lds_max = 64 * 1024;
-  if (pk == 2 && (16 * (2 * (size_t)p.Ny + 2048) > lds_max || 16 * (size_t)p.r * p.Ny > lds_max))
-    return fail(ctx, KLST_EINVAL, "Ny too large for the structured inverse (Ny <= 1024)");
+  if (pk == 2 && (16 * (4 * (size_t)p.Ny + 2048) > lds_max || 16 * (size_t)p.r * p.Ny > lds_max))
+    return fail(ctx, KLST_EINVAL, "Ny too large for the structured inverse (Ny <= 512)");
   if (pk == 0 && 16 * (size_t)lines * p.Ny > lds_max)
     return fail(ctx, KLST_EINVAL, "lines_per_block * Ny too large for the level-set sweeps (<= 4096)");
   if (pk == 1 && 16 * ((size_t)lines * p.Ny + 1024) > lds_max)
@@ -224,6 +226,15 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma, int pk_override = -1) {
       return KLST_OK;
     };
     if ((s = put(ctx->d_Pinv, ctx->d_Pinv32, si.Pinv)) != KLST_OK) return s;
+    {
+      ctx->nslots = (int)si.slot_node.size();
+      std::vector<int> sl(si.slot_node);
+      sl.insert(sl.end(), si.slot_mate.begin(), si.slot_mate.end());
+      dfree(ctx, ctx->d_slots);
+      ALLOC(ctx->d_slots, sizeof(int) * sl.size());
+      HIPCHK(hipMemcpyAsync(ctx->d_slots, sl.data(), sizeof(int) * sl.size(), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     if ((s = put(ctx->d_Sinv, ctx->d_Sinv32, si.Sinv)) != KLST_OK) return s;
     dfree(ctx, ctx->d_capd);
     dfree(ctx, ctx->d_capd32);
@@ -293,7 +304,8 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma, int pk_override = -1) {
 klst_status pc_apply(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
   const klst::Problem& p = ctx->prob;
   if (ctx->pc_kernel_built == 2)
-    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv, ctx->d_Sinv, ctx->d_M,
+    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv, ctx->d_slots,
+                                         ctx->d_slots + ctx->nslots, ctx->nslots, ctx->d_Sinv, ctx->d_M,
                                          ctx->d_U, ctx->d_xix, ctx->d_mom, ctx->d_capd, skip);
   else if (ctx->pc_kernel_built == 1)
     klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
@@ -326,7 +338,8 @@ klst_status pc_v(klst_ctx* ctx, const double2* x, double2* y, const int* skip) {
 klst_status pc_v(klst_ctx* ctx, const float2* x, float2* y, const int* skip) {
   const klst::Problem& p = ctx->prob;
   if (ctx->pc_kernel_built == 2)
-    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv32, ctx->d_Sinv32,
+    klst::dev::launch_structured_inverse(ctx->stream, x, y, p.Ny, p.Nxi, p.r, ctx->d_Pinv32, ctx->d_slots,
+                                         ctx->d_slots + ctx->nslots, ctx->nslots, ctx->d_Sinv32,
                                          ctx->d_M32, ctx->d_U32, ctx->d_xix32, ctx->d_mom32, ctx->d_capd32, skip);
   else
     klst::dev::launch_blockinv_apply(ctx->stream, x, y, p.Ny, p.Nxi, ctx->ilu.nl, ctx->ilu.nblocks,
@@ -947,6 +960,11 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   launch_set_int(st, d_steps, 0);
 
   int outer = 0, inner = 0, restarts = 0;
+  // A pair locks once its deflated Schur-vector residual is below tol / 2: the
+  // returned eigenvectors are combinations of the Schur vectors, and their own
+  // residuals, checked against tol at the end, run a little above the Schur
+  // vectors' ones.
+  const double tol_lock = 0.5 * o.tol;
   std::vector<cd> U, T, UL, SR, G, coef;
   cd theta = 0.0;
   bool need_fresh = false;
@@ -1039,12 +1057,18 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
 
   // is the last locked eigenvalue not nearer than the nev-th nearest of those
   // locked (beyond it, or tied with it as a conjugate partner is for a real target)?
+  // After nev locks, each further lock is a guard: the set is complete once
+  // guard_run consecutive guards were not nearer than the nev-th nearest locked
+  // eigenvalue (beyond it, or tied as a conjugate partner is for a real target).
+  const int guard_run = std::max(1, nev / 10);
+  int guard_streak = 0;
   auto passed_nearest = [&]() {
     std::vector<double> d(k);
     for (int i = 0; i < k; ++i) d[i] = std::abs(SA[(size_t)i * k + i] / SB[(size_t)i * k + i] - sigma);
     const double last = d[k - 1];
     std::nth_element(d.begin(), d.begin() + (nev - 1), d.end());
-    return last >= d[nev - 1] * (1.0 - 1e-12);
+    guard_streak = (last >= d[nev - 1] * (1.0 - 1e-12)) ? guard_streak + 1 : 0;
+    return guard_streak >= guard_run;
   };
   klst_status status = KLST_OK;
   bool complete = false;
@@ -1123,11 +1147,11 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
         const double scale = std::abs(theta) >= 1e-6 ? std::abs(theta) : 1.0;
         rel = rn / scale;
         if (!std::isfinite(rel)) return fail(ctx, KLST_ENOCONV, "non-finite residual");
-        if (rel > o.tol || full) break;
+        if (rel > tol_lock || full) break;
         if (!extract()) return fail(ctx, KLST_ENOCONV, "projected Schur form did not converge");
         full = true;
       }
-      if (rel > o.tol) { have_pair = true; break; }
+      if (rel > tol_lock) { have_pair = true; break; }
       // ---- lock (u, z): Q, Z, Y = K^{-1} z, partial Schur columns, Q^H Y
       HIPCHK(hipMemcpyAsync(Qb + (size_t)k * n, uv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(Zb + (size_t)k * n, zv, sizeof(double2) * n, hipMemcpyDeviceToDevice, st));

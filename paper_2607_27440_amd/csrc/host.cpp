@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <thread>
 
 namespace klst {
@@ -758,8 +759,29 @@ std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInver
   si.Nxi = Nxi;
   si.r = r;
   const size_t blk = (size_t)Ny * Ny;
-  std::vector<cd> Prow((size_t)Nxi * blk);   // row-major line inverses
-  si.Pinv.assign((size_t)Nxi * blk, cd(0.0));
+  // slots: a node and its xi_y mirror share one inverse when sigma is real
+  si.slot_node.clear();
+  si.slot_mate.clear();
+  std::vector<int> slot_of(Nxi, -1), conj_of(Nxi, 0);
+  {
+    std::map<std::pair<double, double>, int> where;
+    for (int k = 0; k < Nxi; ++k) where[{p.xi_x[k], p.xi_y[k]}] = k;
+    for (int k = 0; k < Nxi; ++k) {
+      if (slot_of[k] >= 0) continue;
+      int mate = -1;
+      if (sigma.imag() == 0.0 && p.xi_y[k] != 0.0) {
+        auto it = where.find({p.xi_x[k], -p.xi_y[k]});
+        if (it != where.end() && it->second != k && slot_of[it->second] < 0) mate = it->second;
+      }
+      slot_of[k] = (int)si.slot_node.size();
+      if (mate >= 0) { slot_of[mate] = slot_of[k]; conj_of[mate] = 1; }
+      si.slot_node.push_back(k);
+      si.slot_mate.push_back(mate);
+    }
+  }
+  const int nslots = (int)si.slot_node.size();
+  std::vector<cd> Prow((size_t)nslots * blk);   // row-major line inverses
+  si.Pinv.assign((size_t)nslots * blk, cd(0.0));
   auto run = [&](int count, const std::function<void(int, int)>& work) {
     const int nt = std::max(1, std::min(nthreads, count));
     if (nt == 1) { work(0, 1); return; }
@@ -767,10 +789,11 @@ std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInver
     for (int t = 0; t < nt; ++t) th.emplace_back(work, t, nt);
     for (auto& x : th) x.join();
   };
-  std::vector<int> singular(Nxi, 0);
-  run(Nxi, [&](int t, int nt) {
+  std::vector<int> singular(nslots, 0);
+  run(nslots, [&](int t, int nt) {
     std::vector<cd> a(blk);
-    for (int k = t; k < Nxi; k += nt) {
+    for (int sl = t; sl < nslots; sl += nt) {
+      const int k = si.slot_node[sl];
       std::fill(a.begin(), a.end(), cd(0.0));
       for (int j = 0; j < Ny; ++j) {
         cd* aj = &a[(size_t)j * Ny];
@@ -778,15 +801,15 @@ std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInver
         for (int m = 0; m < Ny; ++m) aj[m] = p.xi_x[k] * p.Dx[(size_t)j * Ny + m];
         aj[j] += cd(p.nu[j], p.beta * p.xi_y[k]) - sigma;
       }
-      cd* inv = &Prow[(size_t)k * blk];
-      if (!invert(Ny, a.data(), inv)) { singular[k] = 1; continue; }
-      cd* col = &si.Pinv[(size_t)k * blk];
+      cd* inv = &Prow[(size_t)sl * blk];
+      if (!invert(Ny, a.data(), inv)) { singular[sl] = 1; continue; }
+      cd* col = &si.Pinv[(size_t)sl * blk];
       for (int j = 0; j < Ny; ++j)
         for (int m = 0; m < Ny; ++m) col[(size_t)m * Ny + j] = inv[(size_t)j * Ny + m];
     }
   });
-  for (int k = 0; k < Nxi; ++k)
-    if (singular[k]) return "singular velocity-line block at node " + std::to_string(k);
+  for (int sl = 0; sl < nslots; ++sl)
+    if (singular[sl]) return "singular velocity-line block at node " + std::to_string(si.slot_node[sl]);
   // G = M P^{-1} Ut:  G[(j,a),(j',b)] = sum_k P_k^{-1}[j][j'] sum_f M_a(j,f,k) Ut_b(j',f,k).
   // Node-major copies of M and U keep the inner loops contiguous.
   std::vector<double> Mt((size_t)Nxi * Ny * 2 * r), Ut((size_t)Nxi * Ny * 2 * r, 0.0);
@@ -803,13 +826,14 @@ std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInver
     std::vector<double> g((size_t)r * r);
     for (int j = t; j < Ny; j += nt) {
       for (int k = 0; k < Nxi; ++k) {
-        const cd* prow = &Prow[(size_t)k * blk + (size_t)j * Ny];
+        const cd* prow = &Prow[(size_t)slot_of[k] * blk + (size_t)j * Ny];
+        const bool cj = conj_of[k] != 0;
         const double* mj = &Mt[((size_t)k * Ny + j) * 2 * r];
         for (int jp = 0; jp < Ny; ++jp) {
           const double* uj = &Ut[((size_t)k * Ny + jp) * 2 * r];
           for (int a = 0; a < r; ++a)
             for (int b = 0; b < r; ++b) g[(size_t)a * r + b] = mj[a] * uj[b] + mj[r + a] * uj[r + b];
-          const cd w = prow[jp];
+          const cd w = cj ? std::conj(prow[jp]) : prow[jp];
           for (int a = 0; a < r; ++a) {
             cd* srow = &S[((size_t)j * r + a) * Rd + (size_t)jp * r];
             for (int b = 0; b < r; ++b) srow[b] += w * g[(size_t)a * r + b];

@@ -66,7 +66,12 @@ void build_block_inverse(const ILU0& f, std::vector<cd>& Kinv, std::vector<int64
 // (A - sigma B)^{-1} = P^{-1} + P^{-1} Ut S^{-1} M P^{-1}, S = I - M P^{-1} Ut.
 struct StructuredInverse {
   int Ny = 0, Nxi = 0, r = 0;
-  std::vector<cd> Pinv;   // [Nxi][Ny x Ny], column-major: entry (j, m) at m Ny + j
+  // Line inverses are stored per slot.  With sigma real, the block of the node
+  // mirrored in xi_y (same xi_x, opposite xi_y) is the complex conjugate of the
+  // node's block, so one slot serves both: slot s holds P_k^{-1} for k =
+  // slot_node[s] and stands for conj(P_k^{-1}) at slot_mate[s] (-1: no mate).
+  std::vector<int> slot_node, slot_mate;
+  std::vector<cd> Pinv;   // [slots][Ny x Ny], column-major: entry (j, m) at m Ny + j
   std::vector<cd> Sinv;   // [(r Ny) x (r Ny)], row-major, index q = j r + a
 };
 // Returns an empty string on success, else why (a singular line block or capacitance).

@@ -689,33 +689,42 @@ __global__ void __launch_bounds__(64 * NW) k_blockinv_apply(const cv<R>* __restr
 //   (A - sigma B)^{-1} x = P^{-1} (x + Ut d),  d = S^{-1} M P^{-1} x,
 // with the (r Ny) x (r Ny) capacitance S = I - M P^{-1} Ut (index q = j r + a).
 
-// y = P^{-1} (x + Ut d) for both fields of node k, reading P_k^{-1} once for the
-// two right-hand sides; d == nullptr skips the rank update.  Pinv: [Nxi][Ny x Ny]
-// column-major.  Lanes own rows, the NW wavefronts split the columns and their
-// partial sums are added in fixed order.  grid ((Ny + 63) / 64, Nxi), block 64 NW,
-// dynamic LDS (2 Ny + 128 NW) * sizeof(cv<R>).
-template <class R, int NW>
+// y = P^{-1} (x + Ut d) for both fields of the nodes of one slot, reading the
+// slot's inverse once: P_k^{-1} for node k = slot_node[s] and, with sigma real,
+// conj(P_k^{-1}) = P_k'^{-1} for its mirror k' = slot_mate[s] (same xi_x, xi_y
+// negated), so up to four right-hand sides per read.  d == nullptr skips the rank
+// update.  Pinv: [slots][Ny x Ny] column-major.  Lanes own rows, the NW
+// wavefronts split the columns and their partial sums are added in fixed order.
+// grid ((Ny + 63) / 64, slots), block 64 NW, dynamic LDS (cmax Ny + cmax 64 NW)
+// * sizeof(cv<R>), cmax = 4 when any slot has a mate, else 2.
+template <class R, int NW, bool PAIR>
 __global__ void __launch_bounds__(64 * NW) k_line_inverse(const cv<R>* __restrict__ x,
                                                           cv<R>* __restrict__ y, int Ny, int Nxi,
                                                           int r, const cv<R>* __restrict__ Pinv,
+                                                          const int* __restrict__ slot_node,
+                                                          const int* __restrict__ slot_mate, int cmax,
                                                           const R* __restrict__ U,
                                                           const R* __restrict__ xix,
                                                           const cv<R>* __restrict__ d,
                                                           const int* __restrict__ skip) {
   extern __shared__ unsigned char lds_raw[];
-  cv<R>* xs = reinterpret_cast<cv<R>*>(lds_raw);   // [2][Ny]
-  cv<R>* part = xs + 2 * Ny;                        // [2][NW][64]
+  cv<R>* xs = reinterpret_cast<cv<R>*>(lds_raw);   // [cmax][Ny]: node (g, h), mate (g, h)
+  cv<R>* part = xs + cmax * Ny;                     // [cmax][NW][64]
   if (skip && *skip) return;
   const int q = xcd_logical_id();
-  const int k = q / gridDim.x, tile = q - k * gridDim.x;
-  const R xk = xix[k];
-  for (int c = threadIdx.x; c < 2 * Ny; c += 64 * NW) {
-    const int f = c / Ny, m = c - f * Ny;
-    cv<R> v = x[((int64_t)2 * m + f) * Nxi + k];
+  const int sl = q / gridDim.x, tile = q - sl * gridDim.x;
+  const int k = slot_node[sl], km = PAIR ? slot_mate[sl] : -1;
+  const bool pair = PAIR && km >= 0;
+  const int ncol = pair ? 4 : 2;
+  const R xk = xix[k];                              // the mate has the same xi_x
+  for (int c = threadIdx.x; c < ncol * Ny; c += 64 * NW) {
+    const int col = c / Ny, m = c - col * Ny;
+    const int f = col & 1, kk = (col < 2) ? k : km;
+    cv<R> v = x[((int64_t)2 * m + f) * Nxi + kk];
     const bool inflow = (m == Ny - 1 && xk > 0) || (m == 0 && xk < 0);
     if (d && !inflow) {
       for (int b = 0; b < r; ++b) {
-        const R u = U[(((int64_t)m * 2 + f) * r + b) * Nxi + k];
+        const R u = U[(((int64_t)m * 2 + f) * r + b) * Nxi + kk];
         const cv<R> db = d[m * r + b];
         v.x += u * db.x;
         v.y += u * db.y;
@@ -726,8 +735,10 @@ __global__ void __launch_bounds__(64 * NW) k_line_inverse(const cv<R>* __restric
   __syncthreads();
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int row = tile * 64 + lane;
-  const cv<R>* K = Pinv + (int64_t)k * Ny * Ny;
-  cv<R> a0 = mk<R>(0, 0), a1 = mk<R>(0, 0);
+  const cv<R>* K = Pinv + (int64_t)sl * Ny * Ny;
+  // a: P x at the node; b: conj(P) x at the mate, conj(p) v = (p.x v.x + p.y v.y, p.x v.y - p.y v.x)
+  cv<R> a0 = mk<R>(0, 0), a1 = mk<R>(0, 0), b0 = mk<R>(0, 0), b1 = mk<R>(0, 0);
+  auto cjmul = [](cv<R> p, cv<R> v) { return mk<R>(p.x * v.x + p.y * v.y, p.x * v.y - p.y * v.x); };
   if (row < Ny) {
     const int cper = (Ny + NW - 1) / NW;
     const int cb = wv * cper, ce = min(Ny, cb + cper);
@@ -741,22 +752,37 @@ __global__ void __launch_bounds__(64 * NW) k_line_inverse(const cv<R>* __restric
         a0 = cadd(a0, cmul(kv[u], xs[c + u]));
         a1 = cadd(a1, cmul(kv[u], xs[Ny + c + u]));
       }
+      if (pair) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          b0 = cadd(b0, cjmul(kv[u], xs[2 * Ny + c + u]));
+          b1 = cadd(b1, cjmul(kv[u], xs[3 * Ny + c + u]));
+        }
+      }
     }
     for (; c < ce; ++c) {
       const cv<R> kv = K[(int64_t)c * Ny + row];
       a0 = cadd(a0, cmul(kv, xs[c]));
       a1 = cadd(a1, cmul(kv, xs[Ny + c]));
+      if (pair) {
+        b0 = cadd(b0, cjmul(kv, xs[2 * Ny + c]));
+        b1 = cadd(b1, cjmul(kv, xs[3 * Ny + c]));
+      }
     }
   }
-  part[wv * 64 + lane] = a0;
-  part[NW * 64 + wv * 64 + lane] = a1;
+  part[(0 * NW + wv) * 64 + lane] = a0;
+  part[(1 * NW + wv) * 64 + lane] = a1;
+  if (pair) {
+    part[(2 * NW + wv) * 64 + lane] = b0;
+    part[(3 * NW + wv) * 64 + lane] = b1;
+  }
   __syncthreads();
-  if (wv < 2 && row < Ny) {
+  if (wv < ncol && row < Ny) {
     const cv<R>* pf = part + wv * NW * 64;
     cv<R> rr = pf[lane];
 #pragma unroll
     for (int w = 1; w < NW; ++w) rr = cadd(rr, pf[w * 64 + lane]);
-    y[((int64_t)2 * row + wv) * Nxi + k] = rr;
+    y[((int64_t)2 * row + (wv & 1)) * Nxi + (wv < 2 ? k : km)] = rr;
   }
 }
 
@@ -1467,21 +1493,25 @@ void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, i
 
 template <class R>
 static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r,
-                         const cv<R>* Pinv, const cv<R>* Sinv, const R* M, const R* U, const R* xix,
-                         cv<R>* mom, cv<R>* d, const int* skip) {
-  const dim3 grid((Ny + 63) / 64, Nxi);
-  const int nw = gemv_waves((int64_t)grid.x * grid.y);
-  const size_t lds = (size_t)(2 * Ny + 128 * nw) * sizeof(cv<R>);
+                         const cv<R>* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                         const cv<R>* Sinv, const R* M, const R* U, const R* xix, cv<R>* mom, cv<R>* d,
+                         const int* skip) {
+  const dim3 grid((Ny + 63) / 64, nslots);
+  // slots that serve a mirrored node apply their inverse to 4 columns; the LDS
+  // then holds 4 Ny inputs and 4 x NW x 64 partial sums, which caps NW at 8
+  const int cmax = nslots < Nxi ? 4 : 2;
+  int nw = gemv_waves((int64_t)grid.x * grid.y);
+  if (cmax == 4 && nw > 8) nw = 8;
+  const size_t lds = (size_t)(cmax * Ny + cmax * 64 * nw) * sizeof(cv<R>);
   auto pass = [&](const cv<R>* dd) {
-    if (nw == 4)
-      hipLaunchKernelGGL((k_line_inverse<R, 4>), grid, dim3(256), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix, dd,
-                         skip);
-    else if (nw == 8)
-      hipLaunchKernelGGL((k_line_inverse<R, 8>), grid, dim3(512), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix, dd,
-                         skip);
-    else
-      hipLaunchKernelGGL((k_line_inverse<R, 16>), grid, dim3(1024), lds, st, x, y, Ny, Nxi, r, Pinv, U, xix,
-                         dd, skip);
+#define KLST_LI(NW_, P_) hipLaunchKernelGGL((k_line_inverse<R, NW_, P_>), grid, dim3(64 * NW_), lds, st, x, y, Ny, \
+                                            Nxi, r, Pinv, slot_node, slot_mate, cmax, U, xix, dd, skip)
+    if (cmax == 4) {
+      if (nw == 4) KLST_LI(4, true); else KLST_LI(8, true);
+    } else {
+      if (nw == 4) KLST_LI(4, false); else if (nw == 8) KLST_LI(8, false); else KLST_LI(16, false);
+    }
+#undef KLST_LI
   };
   pass(nullptr);
   const int64_t n = 2LL * Ny * Nxi;
@@ -1493,15 +1523,16 @@ static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int N
   pass(d);
 }
 void launch_structured_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
-                               const double2* Pinv, const double2* Sinv, const double* M,
-                               const double* U, const double* xix, double2* mom, double2* d,
-                               const int* skip) {
-  structured_t<double>(st, x, y, Ny, Nxi, r, Pinv, Sinv, M, U, xix, mom, d, skip);
+                               const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                               const double2* Sinv, const double* M, const double* U, const double* xix,
+                               double2* mom, double2* d, const int* skip) {
+  structured_t<double>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, Sinv, M, U, xix, mom, d, skip);
 }
 void launch_structured_inverse(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int r,
-                               const float2* Pinv, const float2* Sinv, const float* M, const float* U,
-                               const float* xix, float2* mom, float2* d, const int* skip) {
-  structured_t<float>(st, x, y, Ny, Nxi, r, Pinv, Sinv, M, U, xix, mom, d, skip);
+                               const float2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                               const float2* Sinv, const float* M, const float* U, const float* xix,
+                               float2* mom, float2* d, const int* skip) {
+  structured_t<float>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, Sinv, M, U, xix, mom, d, skip);
 }
 
 // Chunking for k_dot_partial: about 2048 wavefronts in total, at least 256

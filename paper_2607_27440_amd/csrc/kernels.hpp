@@ -22,17 +22,20 @@ void launch_csr_spmv(hipStream_t st, const int64_t* rowptr, const int32_t* col, 
                      double tre, double tim, const int* skip);
 void launch_ilu_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                       int nblocks, const double2* Fc, const double2* C, const int* skip);
-// y = (A - sigma B)^{-1} x in the structured form: line inverses Pinv [Nxi][Ny x Ny]
-// (column-major), capacitance inverse Sinv [(r Ny)^2] (row-major, q = j r + a),
-// moment functionals M, coupling columns U, xi_x for the inflow rows; mom (one
-// vector of moment partials) and d (r Ny) are scratch.  x and y must not overlap.
+// y = (A - sigma B)^{-1} x in the structured form: line inverses Pinv [nslots][Ny x Ny]
+// (column-major; slot s is P^{-1} of node slot_node[s] and, conjugated, of node
+// slot_mate[s] when >= 0), capacitance inverse Sinv [(r Ny)^2] (row-major,
+// q = j r + a), moment functionals M, coupling columns U, xi_x for the inflow
+// rows; mom (one vector of moment partials) and d (r Ny) are scratch.  x and y
+// must not overlap.
 void launch_structured_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
-                               const double2* Pinv, const double2* Sinv, const double* M,
-                               const double* U, const double* xix, double2* mom, double2* d,
-                               const int* skip);
+                               const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                               const double2* Sinv, const double* M, const double* U, const double* xix,
+                               double2* mom, double2* d, const int* skip);
 void launch_structured_inverse(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int r,
-                               const float2* Pinv, const float2* Sinv, const float* M, const float* U,
-                               const float* xix, float2* mom, float2* d, const int* skip);
+                               const float2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                               const float2* Sinv, const float* M, const float* U, const float* xix,
+                               float2* mom, float2* d, const int* skip);
 void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                            int nblocks, const double2* Kinv, const int64_t* koff, const int* skip);
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,

@@ -102,6 +102,7 @@ def trapezoid_table(Qx: int, Qy: int, a: float, Dv: int = 2):
         if Q == 1:
             return np.zeros(1), np.ones(1)
         z = np.linspace(-a, a, Q)
+        z = 0.5 * (z - z[::-1])          # exactly symmetric about 0 (linspace is not, by an ulp)
         h = 2.0 * a / (Q - 1)
         wt = np.full(Q, h)
         wt[0] = wt[-1] = 0.5 * h

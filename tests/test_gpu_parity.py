@@ -216,11 +216,11 @@ def test_solve_c1_matches_qz():
     assert np.all(r <= 1e-10), r
     # convergence history: one row per correction equation, locked count never
     # decreasing (past nev while guard pairs confirm the nearest set, below the
-    # 2 nev cap), every recorded residual above the acceptance tolerance
+    # 2 nev cap), every recorded residual above the locking threshold tol / 2
     h = ctx.history()
     assert h.shape[1] == 6 and 0 < len(h) <= out["stats"]["outer_iterations"]
     assert np.all(np.diff(h[:, 1]) >= 0) and h[-1, 1] < 2 * wl.nev
-    assert np.all(h[:, 2] > 1e-10)
+    assert np.all(h[:, 2] > 0.5e-10)
     assert np.all((h[:, 5] == 1) == (h[:, 2] <= 0.01))
 
 
