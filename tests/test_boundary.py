@@ -87,3 +87,33 @@ def test_create_without_device_fails_cleanly(klst):
     with pytest.raises(klst.KlstError) as ei:
         klst.Context()
     assert ei.value.status == klst.EDEVICE
+
+
+@pytest.mark.parametrize("kw", [dict(m_max=249), dict(m_min=0), dict(m_min=10, m_max=11), dict(gmres_m=0),
+                                dict(gmres_m=257), dict(tol=0.0), dict(inner_rtol=-1.0), dict(precision=2),
+                                dict(op_mode=2), dict(pc_kernel=3), dict(precision=1, pc_kernel=0),
+                                dict(inner_max_it=0), dict(reorth=2), dict(method=2), dict(lines_per_block=0),
+                                dict(lines_per_block=17), dict(max_it=0)])
+def test_invalid_options_are_rejected_before_any_device_use(klst, kw):
+    """Option validation precedes device selection: every out-of-range option
+    returns EINVAL (documented ranges in include/klst.h), with or without a GPU."""
+    with pytest.raises(klst.KlstError) as ei:
+        klst.Context(**kw)
+    assert ei.value.status == klst.EINVAL, kw
+
+
+def test_footprint_model(klst):
+    """The admission model grows with the problem and the search space, accounts
+    for the shift-invert basis and the mixed-precision mirrors, and is 0 for
+    invalid sizes."""
+    f = lambda *a, **kw: klst.footprint_bytes(*a, klst.default_options(**kw))
+    base = f(64, 96, 8)
+    assert base > 0
+    assert f(96, 96, 8) > base and f(64, 128, 8) > base and f(64, 96, 16) > base
+    assert f(64, 96, 8, m_max=60) > f(64, 96, 8, m_max=30)
+    assert f(64, 96, 8, precision=1) > base
+    assert f(64, 96, 8, method=1, m_max=60) > f(64, 96, 8, method=1, m_max=30) > 0
+    assert f(0, 96, 8) == 0 and f(64, 0, 8) == 0 and f(64, 96, 0) == 0
+    # the vectors alone: at least the JD search and test spaces at n = 2 Ny Nxi
+    n = 2 * 64 * 96
+    assert base >= 16 * n * 2 * 31
