@@ -381,6 +381,28 @@ def test_solve_c3_matches_oracle_reference():
     assert sorted(r["j"] for r in res)[:8] == list(range(8))
 
 
+def test_solve_c3_mixed_precision_matches_oracle_reference():
+    """The Mach 4 pencil with FP32 inner solves (FP32 structured inverse and
+    GMRES inside FP64 refinement of the correction equation): every eigenpair
+    within the mixed-precision bar of 1e-8 of the oracle's reference, residuals
+    gated in FP64."""
+    wl = W.config3()
+    P = O.Pencil(wl)
+    ref, kap = _c3_reference()
+    normA = _norm1_bound(P)
+    ctx = _ctx(wl, pc_kernel=2, m_max=80, fix=1e-3, max_it=3000, precision=1)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    assert out["nconv"] == wl.nev, out["stats"]
+    assert np.all(out["resid"] <= 1e-10), out["resid"]
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    res, skipped = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-8, tie=1e-5)
+    print("C3 mixed rel. errors:", [f"{r['err']:.2e}" for r in res], flush=True)
+    assert all(r["ok"] for r in res), res
+    assert not skipped, skipped
+    assert sorted(r["j"] for r in res)[:8] == list(range(8))
+
+
 # ---- shift-invert Krylov-Schur with the exact structured inverse --------------
 
 def test_shift_invert_c1_matches_qz():
