@@ -268,24 +268,64 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   dbl4 are[RT], aim[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
-  double2 xb = (lk < Ny && cb < nc) ? xv[(int64_t)lk * nc + cb] : make_double2(0.0, 0.0);
-  for (int m0 = 0; m0 < Ny; m0 += 4) {
-    const int m = m0 + lk;
-    const int mn = m + 4;
-    const double2 xn = (mn < Ny && cb < nc) ? xv[(int64_t)mn * nc + cb] : make_double2(0.0, 0.0);
+  if constexpr (NW == 1) {
+    // one-wavefront path (small launches): the K loop runs in blocks of XB steps
+    // of 4 rows, the next block's x strip loading while the current block's MFMAs
+    // run (XB loads in flight per lane)
+    constexpr int XB = 8;
+    auto load_block = [&](int mb, double2* dst) {
 #pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      double a;
-      if (NW > 1) {
-        a = As[m * W + t * 16 + li];
-      } else {
-        const int row = (rt0 + t) * 16 + li;
-        a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+      for (int p = 0; p < XB; ++p) {
+        const int m = mb + 4 * p + lk;
+        dst[p] = (m < Ny && cb < nc) ? xv[(int64_t)m * nc + cb] : make_double2(0.0, 0.0);
       }
-      are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.x, are[t], 0, 0, 0);
-      aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.y, aim[t], 0, 0, 0);
+    };
+    double2 xc[XB], xn[XB];
+    load_block(0, xc);
+    for (int mb = 0; mb < Ny; mb += 4 * XB) {
+      if (mb + 4 * XB < Ny) load_block(mb + 4 * XB, xn);
+#pragma unroll
+      for (int p = 0; p < XB; ++p) {
+        const int m = mb + 4 * p + lk;
+        if (mb + 4 * p >= Ny) break;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          double a;
+          if (NW > 1) {
+            a = As[m * W + t * 16 + li];
+          } else {
+            const int row = (rt0 + t) * 16 + li;
+            a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+          }
+          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].x, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].y, aim[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < XB; ++p) xc[p] = xn[p];
     }
-    xb = xn;
+  } else {
+    // wide path: one step of prefetch keeps the register count, and so the
+    // waves per SIMD, up (the blocked loop measured slower here)
+    double2 xb = (lk < Ny && cb < nc) ? xv[(int64_t)lk * nc + cb] : make_double2(0.0, 0.0);
+    for (int m0 = 0; m0 < Ny; m0 += 4) {
+      const int m = m0 + lk;
+      const int mn = m + 4;
+      const double2 xn = (mn < Ny && cb < nc) ? xv[(int64_t)mn * nc + cb] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        double a;
+        if (NW > 1) {
+          a = As[m * W + t * 16 + li];
+        } else {
+          const int row = (rt0 + t) * 16 + li;
+          a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+        }
+        are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.x, are[t], 0, 0, 0);
+        aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.y, aim[t], 0, 0, 0);
+      }
+      xb = xn;
+    }
   }
   // epilogue on the accumulator layout: column c, rows j = tile*16 + lk + 4q
   const int c = c0 + li;
