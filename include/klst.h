@@ -180,7 +180,10 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
  * Pairs are locked as they converge; once nev are locked the iteration goes on
  * until max(1, nev / 10) consecutive newly locked eigenvalues were not nearer
  * sigma than the nev-th nearest locked one (at most min(2 nev, 100, 250 - m_max)
- * pairs are locked), and the
+ * pairs are locked).  With sigma real and a problem symmetric under the xi_y
+ * reflection R (mirrored velocity table, even coupling tables), each locked
+ * complex eigenvalue also contributes its exact partner (conj(lambda),
+ * R conj(x)) when that partner was not locked itself.  The
  * nev nearest are returned, ordered by |lambda - sigma| (ties: Im lambda > 0
  * first).
  * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at

@@ -1392,32 +1392,78 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       Sv[(size_t)q * k + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
     }
   }
-  // the min(k, nev) nearest the target, by distance (ties within 1e-12 relative:
-  // Im lambda > 0 first, then locking order)
-  std::vector<int> order(k);
-  for (int i = 0; i < k; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const double da = std::abs(lam_all[a] - sigma), db = std::abs(lam_all[b] - sigma);
-    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
-    return (lam_all[a].imag() > 0) && !(lam_all[b].imag() > 0);
-  });
-  const int nconv = std::min(k, nev);
-  std::vector<cd> lam(nconv), Cs((size_t)std::max(1, k) * std::max(1, nconv), 0.0);
-  for (int o2 = 0; o2 < nconv; ++o2) {
-    lam[o2] = lam_all[order[o2]];
-    for (int q = 0; q < k; ++q) Cs[(size_t)q * nconv + o2] = Sv[(size_t)q * k + order[o2]];
+  // Candidates: every locked pair and, for a real target on a table closed under
+  // xi_y -> -xi_y, the conjugate partner (conj(lambda), R conj(x)) of each locked
+  // complex eigenvalue whose partner was not locked itself: the pencil commutes
+  // with R (the xi_y reflection) up to conjugation, so the partner is an exact
+  // eigenpair at the same distance from the target.  The min(#, nev) nearest are
+  // returned (ties within 1e-12 relative: Im lambda > 0 first, then locking order).
+  struct Cand { cd lam; int src; bool mirrored; };
+  std::vector<Cand> cand;
+  for (int i = 0; i < k; ++i) cand.push_back({lam_all[i], i, false});
+  std::vector<int> mk;
+  auto mirror_symmetric = [&]() {
+    // coupling columns and moment functionals even in xi_y, except the v moment's
+    // (a = 2 with r = 4), which is odd: then R A R = conj(A) entry by entry
+    for (int j = 0; j < p.Ny; ++j)
+      for (int f = 0; f < 2; ++f)
+        for (int a = 0; a < p.r; ++a) {
+          const double sg = (p.r == 4 && a == 2) ? -1.0 : 1.0;
+          const double* u = &p.U[(((size_t)j * 2 + f) * p.r + a) * p.Nxi];
+          const double* m = &p.M[(((size_t)j * p.r + a) * 2 + f) * p.Nxi];
+          for (int kk = 0; kk < p.Nxi; ++kk)
+            if (u[mk[kk]] != sg * u[kk] || m[mk[kk]] != sg * m[kk]) return false;
+        }
+    return true;
+  };
+  if (sigma.imag() == 0.0 && klst::mirror_nodes(p.xi_x, p.xi_y, mk) && mirror_symmetric()) {
+    for (int i = 0; i < k; ++i) {
+      const cd l = lam_all[i];
+      if (std::abs(l.imag()) <= 1e-12 * std::abs(l)) continue;
+      bool have = false;
+      for (int j = 0; j < k && !have; ++j) have = std::abs(lam_all[j] - std::conj(l)) <= 1e-9 * std::abs(l);
+      if (!have) cand.push_back({std::conj(l), i, true});
+    }
   }
+  std::vector<int> order(cand.size());
+  for (size_t i = 0; i < cand.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double da = std::abs(cand[a].lam - sigma), db = std::abs(cand[b].lam - sigma);
+    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
+    return (cand[a].lam.imag() > 0) && !(cand[b].lam.imag() > 0);
+  });
+  const int nconv = std::min((int)cand.size(), nev);
+  // eigenvectors x_i = Q s_i of the locked pairs the selection draws on
+  std::vector<int> srcs, slot_of(std::max(1, k), -1);
+  for (int o2 = 0; o2 < nconv; ++o2) {
+    const int sidx = cand[order[o2]].src;
+    if (slot_of[sidx] < 0) { slot_of[sidx] = (int)srcs.size(); srcs.push_back(sidx); }
+  }
+  const int nsrc = (int)srcs.size();
+  std::vector<cd> lam(nconv), Cs((size_t)std::max(1, k) * std::max(1, nsrc), 0.0);
+  for (int o2 = 0; o2 < nconv; ++o2) lam[o2] = cand[order[o2]].lam;
+  for (int c2 = 0; c2 < nsrc; ++c2)
+    for (int q = 0; q < k; ++q) Cs[(size_t)q * nsrc + c2] = Sv[(size_t)q * k + srcs[c2]];
   std::vector<double> res(nconv, 0.0);
   if (nconv > 0) {
-    double2* Xd = ws.vec(nconv);
+    double2* Xd = ws.vec(std::max(nconv, nsrc));
     if (!Xd) return KLST_ENOMEM;
     if ((s = upload(d_coef, Cs)) != KLST_OK) return s;
-    launch_combine(st, Qb, k, n, d_coef, nconv, nconv, Xd, nullptr);
-    std::vector<cd> hx((size_t)nconv * n);
-    HIPCHK(hipMemcpyAsync(hx.data(), Xd, sizeof(double2) * hx.size(), hipMemcpyDeviceToHost, st));
+    launch_combine(st, Qb, k, n, d_coef, nsrc, nsrc, Xd, nullptr);
+    std::vector<cd> hs((size_t)nsrc * n), hx((size_t)nconv * n);
+    HIPCHK(hipMemcpyAsync(hs.data(), Xd, sizeof(double2) * hs.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    for (int i = 0; i < nconv; ++i) {
-      cd* xi = &hx[(size_t)i * n];
+    const int64_t nx = p.Nxi;
+    for (int o2 = 0; o2 < nconv; ++o2) {
+      const Cand& cd_ = cand[order[o2]];
+      const cd* xs = &hs[(size_t)slot_of[cd_.src] * n];
+      cd* xi = &hx[(size_t)o2 * n];
+      if (!cd_.mirrored) {
+        std::copy(xs, xs + n, xi);
+      } else {
+        for (int64_t row = 0; row < n / nx; ++row)
+          for (int64_t kk = 0; kk < nx; ++kk) xi[row * nx + kk] = std::conj(xs[row * nx + mk[kk]]);
+      }
       double nrm = 0.0, big = -1.0;
       int64_t ib = 0;
       for (int64_t t = 0; t < n; ++t) {

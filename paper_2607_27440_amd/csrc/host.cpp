@@ -45,6 +45,19 @@ void mapped_nodes(int Ny, double L, double s_inf, double* x) {
   }
 }
 
+bool mirror_nodes(const std::vector<double>& xi_x, const std::vector<double>& xi_y, std::vector<int>& mk) {
+  const int Nxi = (int)xi_x.size();
+  std::map<std::pair<double, double>, int> where;
+  for (int k = 0; k < Nxi; ++k) where[{xi_x[k], xi_y[k]}] = k;
+  mk.assign(Nxi, -1);
+  for (int k = 0; k < Nxi; ++k) {
+    auto it = where.find({xi_x[k], -xi_y[k]});
+    if (it == where.end()) { mk.clear(); return false; }
+    mk[k] = it->second;
+  }
+  return true;
+}
+
 std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
                           double beta, Problem& p) {
   if (!g || !v || !b) return "null grid, velocity table or base flow";

@@ -36,6 +36,11 @@ struct Problem {
 // y_j = cos(j pi / (Ny - 1)), s = (L / s_inf)^2 (node 0 at x = +s_inf).
 void mapped_nodes(int Ny, double L, double s_inf, double* x);
 
+// Mirror of every velocity node in xi_y (same xi_x, xi_y negated; a node with
+// xi_y = 0 is its own), when the table has all of them exactly: mk[k] = mirror.
+// Returns false (mk cleared) when some node has none.
+bool mirror_nodes(const std::vector<double>& xi_x, const std::vector<double>& xi_y, std::vector<int>& mk);
+
 // Fills `p`; returns an empty string on success, else a description of the error.
 std::string build_problem(const klst_grid* g, const klst_vel* v, const klst_base* b,
                           double beta, Problem& p);

@@ -403,6 +403,37 @@ def test_solve_c3_mixed_precision_matches_oracle_reference():
     assert sorted(r["j"] for r in res)[:8] == list(range(8))
 
 
+@pytest.mark.parametrize("workload", ["c2", "c3", "m4_gh48", "pb_q20"])
+def test_bench_configurations_match_oracle(workload, c2_reference):
+    """The solve exactly as bench.py times it (its workload options) against the
+    oracle: config 2 against shift-invert Arnoldi, the other shapes against their
+    stored references; the nearest set complete, residuals gated in FP64."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+    from paper_2607_27440_amd import workloads as WL
+    gen, opts = bench.WORKLOADS[workload]
+    wl = bench.make_workload(WL, gen)
+    P = O.Pencil(wl)
+    if workload == "c2":
+        _, _, ref, kap, normA = c2_reference
+        tie = 1e-8
+    else:
+        ref, kap = (_c3_reference() if workload == "c3" else _golden(workload))
+        normA = _norm1_bound(P)
+        tie = 1e-5 if workload == "c3" else 1e-8
+    ctx = _ctx(wl, **opts)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    assert out["nconv"] == wl.nev and np.all(out["resid"] <= 1e-10), out["stats"]
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    res, skipped = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-10, tie=tie)
+    print(workload, "max rel. error:", max(r["err"] for r in res), flush=True)
+    assert all(r["ok"] for r in res), [r for r in res if not r["ok"]]
+    assert not skipped, skipped
+
+
 # ---- shift-invert Krylov-Schur with the exact structured inverse --------------
 
 def test_shift_invert_c1_matches_qz():
