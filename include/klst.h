@@ -178,7 +178,7 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
 
 /* Jacobi-Davidson solve for the nev eigenvalues nearest sigma (Sec. 4.2).
  * Pairs are locked as they converge; once nev are locked the iteration goes on
- * until max(1, nev / 10) consecutive newly locked eigenvalues were not nearer
+ * until max(1, nev / 25) consecutive newly locked eigenvalues were not nearer
  * sigma than the nev-th nearest locked one (at most min(2 nev, 100, 250 - m_max)
  * pairs are locked).  With sigma real and a problem symmetric under the xi_y
  * reflection R (mirrored velocity table, even coupling tables), each locked

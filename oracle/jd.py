@@ -163,13 +163,13 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
     outer = inner = 0
     restarts = 0
     # the result is the nev eigenvalues nearest sigma, and JD locks pairs in the
-    # order they converge: after nev are locked, go on until max(1, nev // 10)
+    # order they converge: after nev are locked, go on until max(1, nev // 25)
     # consecutive newly locked eigenvalues were not nearer than the nev-th nearest
     # locked one (beyond it, or tied as a conjugate partner is for a real target),
     # then keep the nev nearest
     kcap = min(2 * nev, 100, 250 - m_max)
     complete = False
-    guard = {"run": max(1, nev // 10), "streak": 0}
+    guard = {"run": max(1, nev // 25), "streak": 0}
 
     def passed_nearest():
         d = np.abs(np.diag(SA) / np.diag(SB) - sigma)

@@ -1060,7 +1060,7 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   // After nev locks, each further lock is a guard: the set is complete once
   // guard_run consecutive guards were not nearer than the nev-th nearest locked
   // eigenvalue (beyond it, or tied as a conjugate partner is for a real target).
-  const int guard_run = std::max(1, nev / 10);
+  const int guard_run = std::max(1, nev / 25);
   int guard_streak = 0;
   auto passed_nearest = [&]() {
     std::vector<double> d(k);
