@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
                                                  int Nxi, int r, const R* __restrict__ M,
                                                  cv<R>* __restrict__ mom, int S,
                                                  const int* __restrict__ skip) {
-  __shared__ double2 sh[4];
+  __shared__ double2 sh[4][4];
   if (skip && *skip) return;
   const int j = blockIdx.x / S, part = blockIdx.x - j * S, v = blockIdx.y;
   const int nc = 2 * Nxi;
@@ -105,11 +105,21 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
       }
     }
   }
+  // all r sums of the four wavefronts in one exchange: wave sums, one barrier,
+  // then thread a adds the four waves' values in wave order
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
   for (int a = 0; a < 4; ++a) {
     if (a < r) {
-      const double2 sres = block_sum256(make_double2((double)ar[a], (double)ai[a]), sh);
-      if (threadIdx.x == 0) mom[(((int64_t)v * Ny + j) * S + part) * r + a] = mk<R>((R)sres.x, (R)sres.y);
+      const double sr = wave_sum((double)ar[a]), si = wave_sum((double)ai[a]);
+      if (lane == 0) sh[wv][a] = make_double2(sr, si);
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < r) {
+    double2 sres = make_double2(0.0, 0.0);
+    for (int w = 0; w < 4; ++w) sres = cadd(sres, sh[w][threadIdx.x]);
+    mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = mk<R>((R)sres.x, (R)sres.y);
   }
 }
 
@@ -268,11 +278,14 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   dbl4 are[RT], aim[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
-  if constexpr (NW == 1) {
-    // one-wavefront path (small launches): the K loop runs in blocks of XB steps
-    // of 4 rows, the next block's x strip loading while the current block's MFMAs
-    // run (XB loads in flight per lane)
-    constexpr int XB = 8;
+  // The K loop runs in blocks of XB steps of 4 rows, the next block's x strip
+  // loading while the current block's MFMAs run (XB loads in flight per lane).
+  // One-wavefront workgroups (small launches) take 8 steps per block; the wide
+  // path, already at 2 waves per SIMD from its LDS slice and accumulators,
+  // takes 4 (measured at the M = 4 shape, 64 vectors: 374 us per launch against
+  // 446 us with one step of prefetch and 581 us with 8).
+  {
+    constexpr int XB = (NW == 1) ? 8 : 4;
     auto load_block = [&](int mb, double2* dst) {
 #pragma unroll
       for (int p = 0; p < XB; ++p) {
@@ -303,28 +316,6 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
       }
 #pragma unroll
       for (int p = 0; p < XB; ++p) xc[p] = xn[p];
-    }
-  } else {
-    // wide path: one step of prefetch keeps the register count, and so the
-    // waves per SIMD, up (the blocked loop measured slower here)
-    double2 xb = (lk < Ny && cb < nc) ? xv[(int64_t)lk * nc + cb] : make_double2(0.0, 0.0);
-    for (int m0 = 0; m0 < Ny; m0 += 4) {
-      const int m = m0 + lk;
-      const int mn = m + 4;
-      const double2 xn = (mn < Ny && cb < nc) ? xv[(int64_t)mn * nc + cb] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        double a;
-        if (NW > 1) {
-          a = As[m * W + t * 16 + li];
-        } else {
-          const int row = (rt0 + t) * 16 + li;
-          a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
-        }
-        are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.x, are[t], 0, 0, 0);
-        aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xb.y, aim[t], 0, 0, 0);
-      }
-      xb = xn;
     }
   }
   // epilogue on the accumulator layout: column c, rows j = tile*16 + lk + 4q
@@ -909,11 +900,21 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cv<R>* __restrict__ s
 
 // c[q] = sum over chunks of partial[q * nch + chunk], q < mtot, into LDS; one
 // wavefront per q, lanes over chunks, fixed tree: identical in every workgroup.
+// With stage (dynamic LDS of mtot * nch entries) the partials are first copied in
+// with all loads in flight, so the per-q rounds wait on LDS instead of on L2.
 __device__ __forceinline__ void reduce_partials(const double2* __restrict__ partial, int mtot, int nch,
-                                                double2* c) {
+                                                double2* c, double2* stage) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const double2* src = partial;
+  if (stage) {
+    const int tot = mtot * nch;
+#pragma unroll 8
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) stage[e] = partial[e];
+    __syncthreads();
+    src = stage;
+  }
   for (int q = wv; q < mtot; q += nw) {
-    const double2* pq = partial + (int64_t)q * nch;
+    const double2* pq = src + (int64_t)q * nch;
     double sr = 0.0, si = 0.0;
     for (int cc = lane; cc < nch; cc += 64) { const double2 pv = pq[cc]; sr += pv.x; si += pv.y; }
     sr = wave_sum(sr);
@@ -928,11 +929,13 @@ __device__ __forceinline__ void reduce_partials(const double2* __restrict__ part
 __global__ void __launch_bounds__(256) k_dot_reduce(const double2* __restrict__ partial, int m, int nch,
                                                     double2* __restrict__ out, int mode,
                                                     const double2* __restrict__ Hinv,
-                                                    double2* __restrict__ out2, const int* __restrict__ skip) {
+                                                    double2* __restrict__ out2, int staged,
+                                                    const int* __restrict__ skip) {
   __shared__ double2 c[256];
+  extern __shared__ double2 stage_dyn[];
   if (skip && *skip) return;
   const int mtot = (mode == 3) ? m + 1 : m;
-  reduce_partials(partial, mtot, nch, c);
+  reduce_partials(partial, mtot, nch, c, staged ? stage_dyn : nullptr);
   for (int q = threadIdx.x; q < mtot; q += 256) {
     double2 v = c[q];
     if (mode == 2) {
@@ -959,13 +962,14 @@ __global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0
                                                     const double2* __restrict__ Hinv,
                                                     double2* __restrict__ coef_set,
                                                     double2* __restrict__ coef_add, cv<R>* x, int64_t n,
-                                                    double2* __restrict__ norm_part,
+                                                    double2* __restrict__ norm_part, int staged,
                                                     const int* __restrict__ skip) {
   __shared__ double2 cr[256], cc[256];
   __shared__ double2 sh[4];
+  extern __shared__ double2 stage_dyn[];
   if (skip && *skip) return;
   const int m = m0 + m1;
-  reduce_partials(partial, m, nch, cr);
+  reduce_partials(partial, m, nch, cr, staged ? stage_dyn : nullptr);
   const double2* c = cr;
   if (Hinv) {
     for (int q = threadIdx.x; q < m; q += 256) {
@@ -985,9 +989,7 @@ __global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   R a2 = 0;
   if (t < n) {
-    cv<R> acc = mk<R>(0, 0);
-    for (int i = 0; i < m0; ++i) acc = cadd(acc, cmul(s0[(int64_t)i * n + t], narrow<R>(c[i])));
-    for (int i = 0; i < m1; ++i) acc = cadd(acc, cmul(s1[(int64_t)i * n + t], narrow<R>(c[m0 + i])));
+    const cv<R> acc = cadd(lincomb<R>(s0, m0, n, t, c, 1), lincomb<R>(s1, m1, n, t, c + m0, 1));
     const cv<R> xv = csub(x[t], acc);
     x[t] = xv;
     a2 = xv.x * xv.x + xv.y * xv.y;
@@ -1606,16 +1608,26 @@ int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s
                        const float2* x, int64_t n, double2* partial, int with_norm, const int* skip) {
   return dot_partial_t<float>(st, s0, m0, s1, m1, x, n, partial, with_norm, skip);
 }
+// Dynamic LDS for staging the dot partials in the consumer kernels: used when
+// they fit in 16 KB (mtot x nch <= 1024), which keeps 6 workgroups per CU for
+// the streaming part of k_subm_fused.
+static size_t partial_stage_bytes(int mtot, int nch) {
+  const int64_t tot = (int64_t)mtot * nch;
+  return (tot > 0 && tot <= 1024) ? (size_t)tot * sizeof(double2) : 0;
+}
 void launch_dot_reduce(hipStream_t st, const double2* partial, int m, int nch, double2* out, int mode,
                        const double2* Hinv, double2* out2, const int* skip) {
-  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), 0, st, partial, m, nch, out, mode, Hinv, out2, skip);
+  const size_t lds = partial_stage_bytes(mode == 3 ? m + 1 : m, nch);
+  hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), lds, st, partial, m, nch, out, mode, Hinv, out2,
+                     lds > 0 ? 1 : 0, skip);
 }
 template <class R>
 static void subm_fused_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1,
                          const double2* partial, int nch, const double2* Hinv, double2* coef_set,
                          double2* coef_add, cv<R>* x, int64_t n, double2* norm_part, const int* skip) {
-  hipLaunchKernelGGL((k_subm_fused<R>), dim3(nblk(n, 256)), dim3(256), 0, st, s0, m0, s1, m1, partial, nch,
-                     Hinv, coef_set, coef_add, x, n, norm_part, skip);
+  const size_t lds = partial_stage_bytes(m0 + m1, nch);
+  hipLaunchKernelGGL((k_subm_fused<R>), dim3(nblk(n, 256)), dim3(256), lds, st, s0, m0, s1, m1, partial, nch,
+                     Hinv, coef_set, coef_add, x, n, norm_part, lds > 0 ? 1 : 0, skip);
 }
 void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
                        const double2* partial, int nch, const double2* Hinv, double2* coef_set,
