@@ -180,7 +180,11 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
  * Pairs are locked as they converge; once nev are locked the iteration goes on
  * until max(1, nev / 25) consecutive newly locked eigenvalues were not nearer
  * sigma than the nev-th nearest locked one (at most min(2 nev, 100, 250 - m_max)
- * pairs are locked).  With sigma real and a problem symmetric under the xi_y
+ * pairs are locked), or until the current Petrov pair has stayed below relative
+ * residual 1e-6 and, by a margin of sqrt(residual) |theta|, not nearer than
+ * that eigenvalue for 50 consecutive outer iterations without a lock (a guard
+ * next to a nearly defective pair, whose attainable residual lies above the
+ * tolerance).  With sigma real and a problem symmetric under the xi_y
  * reflection R (mirrored velocity table, even coupling tables), each locked
  * complex eigenvalue also contributes its exact partner (conj(lambda),
  * R conj(x)) when that partner was not locked itself.  The

@@ -170,6 +170,11 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
     kcap = min(2 * nev, 100, 250 - m_max)
     complete = False
     guard = {"run": max(1, nev // 25), "streak": 0}
+    # a guard that never reaches tol (next to a nearly defective pair the attainable
+    # residual is about sqrt(u)) completes the set once it stays below 1e-6 and not
+    # nearer (by a margin of sqrt(residual)) than the nev-th nearest locked
+    # eigenvalue for 50 outer iterations in a row
+    settle = {"count": 0, "k": -1}
 
     def passed_nearest():
         d = np.abs(np.diag(SA) / np.diag(SB) - sigma)
@@ -252,6 +257,18 @@ def jd(P, sigma, nev, tol=1e-10, m_min=6, m_max=None, gmres_m=20, inner_rtol=1e-
         if rn is None:            # search space emptied by deflation: fresh start
             t = Bd * start_vector(n, seed, stream=outer)
             continue
+        k = Q.shape[1]
+        if k >= nev:
+            d = np.abs(np.diag(SA) / np.diag(SB) - sigma)
+            # theta may be off by about sqrt(residual) (relative) from its eigenvalue
+            beyond = abs(theta - sigma) - np.sqrt(rn / scale) * scale >= np.sort(d)[nev - 1] * (1 - 1e-12)
+            if rn <= 1e-6 * scale and beyond:
+                settle["count"] = settle["count"] + 1 if settle["k"] == k else 1
+                settle["k"] = k
+            else:
+                settle["count"] = 0
+            if settle["count"] >= 50:
+                break
         # --- correction equation, preconditioned with K, projected with [Q u], [Z z]
         Qt = np.hstack([Q, u[:, None]])
         Yt = np.hstack([Yk, K.solve(z)[:, None]])

@@ -1062,6 +1062,15 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   // eigenvalue (beyond it, or tied as a conjugate partner is for a real target).
   const int guard_run = std::max(1, nev / 25);
   int guard_streak = 0;
+  // A guard may never reach the locking tolerance: next to a nearly defective
+  // eigenvalue pair the residual a Petrov pair can attain is about sqrt(u) of
+  // the operator scale.  A guard that stays below kSettleRes and not nearer than
+  // the nev-th nearest locked eigenvalue for kSettleIts consecutive outer
+  // iterations (with no lock in between), with a margin of sqrt(residual) for
+  // the error of its Petrov value, also completes the set.
+  constexpr double kSettleRes = 1e-6;
+  constexpr int kSettleIts = 50;
+  int settle_count = 0, settle_k = -1;
   auto passed_nearest = [&]() {
     std::vector<double> d(k);
     for (int i = 0; i < k; ++i) d[i] = std::abs(SA[(size_t)i * k + i] / SB[(size_t)i * k + i] - sigma);
@@ -1207,6 +1216,21 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       need_fresh = true;
       launch_set_int(st, d_steps, 0);
       continue;
+    }
+    if (k >= nev) {
+      std::vector<double> d(k);
+      for (int i = 0; i < k; ++i) d[i] = std::abs(SA[(size_t)i * k + i] / SB[(size_t)i * k + i] - sigma);
+      std::nth_element(d.begin(), d.begin() + (nev - 1), d.end());
+      // theta itself may be off by about sqrt(rel) (relative) from its eigenvalue
+      const double scale = std::abs(theta) >= 1e-6 ? std::abs(theta) : 1.0;
+      const bool beyond = std::abs(theta - sigma) - std::sqrt(rel) * scale >= d[nev - 1] * (1.0 - 1e-12);
+      if (rel <= kSettleRes && beyond) {
+        settle_count = (settle_k == k) ? settle_count + 1 : 1;
+        settle_k = k;
+      } else {
+        settle_count = 0;
+      }
+      if (settle_count >= kSettleIts) { complete = true; break; }
     }
     // ---- correction equation
     // (I - Zt Zt^H)(A - shift B)(I - Qt Qt^H) t = -r, t _|_ Qt, Qt = [Q u], Zt = [Z z],
