@@ -430,6 +430,7 @@ def run_served(a):
                    {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
                     "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
                     "eigenpairs": good, "seconds": round(el, 3), "peak_running": st["peak_running"],
+                    "unconverged_requests": int(sum(1 for r in res if r["status"] != 0)),
                     "serial_plain_fp64": {"value": round(goodb / max(done, 1e-9), 4),
                                           "p50_latency_s": round(float(np.percentile(lat_b, 50)), 4),
                                           "p99_latency_s": round(float(np.percentile(lat_b, 99)), 4)}})
