@@ -858,36 +858,71 @@ std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInver
   for (auto& v : S) v = -v;
   for (int q = 0; q < Rd; ++q) S[(size_t)q * Rd + q] += 1.0;
   si.Sinv.assign((size_t)Rd * Rd, cd(0.0));
-  if (!invert(Rd, S.data(), si.Sinv.data())) return "singular moment capacitance matrix";
+  if (!invert(Rd, S.data(), si.Sinv.data(), nthreads)) return "singular moment capacitance matrix";
   return std::string();
 }
 
-bool invert(int m, const cd* A, cd* Ainv) {
-  std::vector<cd> a(A, A + (size_t)m * m), inv((size_t)m * m, cd(0.0));
-  for (int i = 0; i < m; ++i) inv[(size_t)i * m + i] = 1.0;
+bool invert(int m, const cd* A, cd* Ainv, int nthreads) {
+  // P A = L U in place (row-major; L unit lower below the diagonal)
+  std::vector<cd> a(A, A + (size_t)m * m);
+  std::vector<int> perm(m);
+  for (int i = 0; i < m; ++i) perm[i] = i;
   for (int k = 0; k < m; ++k) {
     int p = k;
-    for (int i = k + 1; i < m; ++i)
-      if (std::abs(a[(size_t)i * m + k]) > std::abs(a[(size_t)p * m + k])) p = i;
-    if (std::abs(a[(size_t)p * m + k]) == 0.0) return false;
-    if (p != k)
-      for (int j = 0; j < m; ++j) {
-        std::swap(a[(size_t)p * m + j], a[(size_t)k * m + j]);
-        std::swap(inv[(size_t)p * m + j], inv[(size_t)k * m + j]);
-      }
-    const cd piv = a[(size_t)k * m + k];
-    for (int j = 0; j < m; ++j) { a[(size_t)k * m + j] /= piv; inv[(size_t)k * m + j] /= piv; }
-    for (int i = 0; i < m; ++i) {
-      if (i == k) continue;
-      const cd f = a[(size_t)i * m + k];
+    double best = std::abs(a[(size_t)k * m + k]);
+    for (int i = k + 1; i < m; ++i) {
+      const double v = std::abs(a[(size_t)i * m + k]);
+      if (v > best) { best = v; p = i; }
+    }
+    if (best == 0.0) return false;
+    if (p != k) {
+      std::swap_ranges(a.begin() + (size_t)p * m, a.begin() + (size_t)(p + 1) * m, a.begin() + (size_t)k * m);
+      std::swap(perm[p], perm[k]);
+    }
+    const cd* ak = &a[(size_t)k * m];
+    const cd rpiv = 1.0 / ak[k];
+    for (int i = k + 1; i < m; ++i) {
+      cd* ai = &a[(size_t)i * m];
+      const cd f = ai[k] * rpiv;
+      ai[k] = f;
       if (f == 0.0) continue;
-      for (int j = 0; j < m; ++j) {
-        a[(size_t)i * m + j] -= f * a[(size_t)k * m + j];
-        inv[(size_t)i * m + j] -= f * inv[(size_t)k * m + j];
-      }
+      for (int j = k + 1; j < m; ++j) ai[j] -= f * ak[j];
     }
   }
-  std::copy(inv.begin(), inv.end(), Ainv);
+  // column c of A^{-1} solves L U x = P e_c, whose one nonzero sits at row i
+  // with perm[i] = c; the forward sweep starts there
+  std::vector<int> row_of(m);
+  for (int i = 0; i < m; ++i) row_of[perm[i]] = i;
+  auto solve_cols = [&](int c0, int c1) {
+    std::vector<cd> x(m);
+    for (int c = c0; c < c1; ++c) {
+      const int s0 = row_of[c];
+      std::fill(x.begin(), x.end(), cd(0.0));
+      x[s0] = 1.0;
+      for (int i = s0 + 1; i < m; ++i) {
+        const cd* ai = &a[(size_t)i * m];
+        cd acc = 0.0;
+        for (int q = s0; q < i; ++q) acc += ai[q] * x[q];
+        x[i] = -acc;
+      }
+      for (int i = m - 1; i >= 0; --i) {
+        const cd* ai = &a[(size_t)i * m];
+        cd acc = x[i];
+        for (int q = i + 1; q < m; ++q) acc -= ai[q] * x[q];
+        x[i] = acc / ai[i];
+      }
+      for (int i = 0; i < m; ++i) Ainv[(size_t)i * m + c] = x[i];
+    }
+  };
+  const int nt = std::max(1, std::min(nthreads, m / 32));
+  if (nt == 1) {
+    solve_cols(0, m);
+  } else {
+    std::vector<std::thread> th;
+    const int per = (m + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) th.emplace_back(solve_cols, t * per, std::min(m, (t + 1) * per));
+    for (auto& x : th) x.join();
+  }
   return true;
 }
 

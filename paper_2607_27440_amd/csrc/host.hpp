@@ -94,7 +94,9 @@ bool sorted_schur(int m, const cd* G, cd* U, cd* T, int nsort = 0);
 bool dominant_eig(int m, const cd* G, cd& mu, cd* x);
 // Householder QR of an m x m matrix A = Qm Rm.
 void qr_square(int m, const cd* A, cd* Qm, cd* Rm);
-// Inverse of an m x m matrix by LU with partial pivoting; false if singular.
-bool invert(int m, const cd* A, cd* Ainv);
+// Inverse of an m x m matrix by LU with partial pivoting, then one forward and
+// one backward sweep per column (columns split over up to nthreads threads);
+// false if singular.
+bool invert(int m, const cd* A, cd* Ainv, int nthreads = 1);
 
 }  // namespace klst
