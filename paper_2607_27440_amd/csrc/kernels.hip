@@ -123,13 +123,19 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
   }
 }
 
-// m_a(j) of vector v from the S partial sums (fixed order).
+// m_a(j) of vector v from the S <= 8 partial sums (fixed order); the parts are
+// loaded together, then added in part order.
 template <class R>
 __device__ __forceinline__ cv<R> mom_at(const cv<R>* __restrict__ mom, int64_t v, int Ny, int j, int a, int r,
                                         int S) {
   const cv<R>* p = mom + ((v * Ny + j) * S) * r + a;
-  cv<R> s = p[0];
-  for (int q = 1; q < S; ++q) s = cadd(s, p[(int64_t)q * r]);
+  cv<R> part[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) part[q] = (q < S) ? p[(int64_t)q * r] : mk<R>(0, 0);
+  cv<R> s = part[0];
+#pragma unroll
+  for (int q = 1; q < 8; ++q)
+    if (q < S) s = cadd(s, part[q]);
   return s;
 }
 
@@ -253,12 +259,7 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
     const int jl = idx / r, a = idx - jl * r;
     const int j = rt0 * 16 + jl;
-    double2 sm = make_double2(0.0, 0.0);
-    if (j < Ny) {
-      const double2* p = mom + (((int64_t)v * Ny + j) * S) * r + a;
-      for (int q = 0; q < S; ++q) sm = cadd(sm, p[(int64_t)q * r]);
-    }
-    ms[jl * 4 + a] = sm;
+    ms[jl * 4 + a] = (j < Ny) ? mom_at<double>(mom, v, Ny, j, a, r, S) : make_double2(0.0, 0.0);
   }
   if (NW > 1) {
     const int Ny4 = (Ny + 3) & ~3;
@@ -1220,10 +1221,16 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 // Column parts of the moment reduction: enough workgroups per vector to fill
 // the chip.  A function of the grid only (not of the batch size), so a vector
 // gets bit-identical results alone and in a batch.
+// Column parts per node for k_moments: one per 512 columns and, from 512
+// columns on, enough for about 256 workgroups, with no part under 128 columns;
+// at most 8.  (Below 512 columns, splitting measured slower: the consumers then
+// add more parts.)
 int moment_splits(int Ny, int nvec, int Nxi) {
   (void)nvec;
-  (void)Ny;
-  return std::max(1, std::min(8, (2 * Nxi) / 512));
+  const int nc = 2 * Nxi;
+  if (nc < 512) return 1;
+  const int fill = (256 + Ny - 1) / Ny;
+  return std::max(1, std::min({8, std::max(nc / 512, fill), nc / 128}));
 }
 
 // ------------------------------------------------------- post-processing ----
