@@ -276,6 +276,26 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   double2* yv = y + (int64_t)v * n;
   const int li = lane & 15, lk = lane >> 4;
   const int cb = c0 + li;
+  // With one row tile (the single-vector launches) the epilogue's operands (x
+  // at the tile's rows, nu, the U columns) are loaded before the K loop, so they
+  // arrive while the MFMAs run.
+  constexpr bool kPre = (RT == 1);
+  double2 pre_x[4];
+  double pre_nu[4], pre_u[4][4];
+  if constexpr (kPre) {
+    const bool cok = cb < nc;
+    const int fp = cok ? cb / Nxi : 0, kp = cok ? cb - fp * Nxi : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = rt0 * 16 + lk + 4 * q;
+      const bool ok = cok && j < Ny;
+      pre_x[q] = ok ? xv[(int64_t)j * nc + cb] : make_double2(0.0, 0.0);
+      pre_nu[q] = ok ? nu[j] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        pre_u[q][a] = (ok && a < r) ? U[((int64_t)(j * 2 + fp) * r + a) * Nxi + kp] : 0.0;
+    }
+  }
   dbl4 are[RT], aim[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
@@ -332,21 +352,24 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
       const int jl = t * 16 + lk + 4 * q;
       const int j = rt0 * 16 + jl;
       if (j >= Ny) continue;
-      const double2 xjc = xv[(int64_t)j * nc + c];
+      const double2 xjc = kPre ? pre_x[q] : xv[(int64_t)j * nc + c];
       const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
       double2 out;
       if (bc) {
         out = xjc;
       } else {
-        const double dre = nu[j] - tau_re, dim = bxy - tau_im;
+        const double dre = (kPre ? pre_nu[q] : nu[j]) - tau_re, dim = bxy - tau_im;
         out.x = xik * are[t][q] + dre * xjc.x - dim * xjc.y;
         out.y = xik * aim[t][q] + dre * xjc.y + dim * xjc.x;
         const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
-        for (int a = 0; a < r; ++a) {
-          const double ua = Uj[(int64_t)a * Nxi];
-          const double2 ma = ms[jl * 4 + a];
-          out.x -= ua * ma.x;
-          out.y -= ua * ma.y;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a < r) {
+            const double ua = kPre ? pre_u[q][a] : Uj[(int64_t)a * Nxi];
+            const double2 ma = ms[jl * 4 + a];
+            out.x -= ua * ma.x;
+            out.y -= ua * ma.y;
+          }
         }
       }
       yv[(int64_t)j * nc + c] = out;
