@@ -361,11 +361,20 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
         const double dre = (kPre ? pre_nu[q] : nu[j]) - tau_re, dim = bxy - tau_im;
         out.x = xik * are[t][q] + dre * xjc.x - dim * xjc.y;
         out.y = xik * aim[t][q] + dre * xjc.y + dim * xjc.x;
-        const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+        if constexpr (kPre) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (a < r) {
-            const double ua = kPre ? pre_u[q][a] : Uj[(int64_t)a * Nxi];
+          for (int a = 0; a < 4; ++a) {
+            if (a < r) {
+              const double2 ma = ms[jl * 4 + a];
+              out.x -= pre_u[q][a] * ma.x;
+              out.y -= pre_u[q][a] * ma.y;
+            }
+          }
+        } else {
+          // (a rolled loop keeps the wide path at 2 waves per SIMD)
+          const double* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+          for (int a = 0; a < r; ++a) {
+            const double ua = Uj[(int64_t)a * Nxi];
             const double2 ma = ms[jl * 4 + a];
             out.x -= ua * ma.x;
             out.y -= ua * ma.y;
