@@ -119,3 +119,25 @@ def test_served_eigenpairs_match_oracle():
         m, skipped = PAR.match(r["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-8)
         assert all(x["ok"] for x in m), (wl.name, m)
         assert not skipped
+
+
+def test_served_trace_converges_within_budget():
+    """The served-sweep request mix (seed 5: 80 requests, 95% sweep draws and 5% at
+    the config-2 shape, 8 eigenpairs each) with the served options: every request
+    converges all its pairs well inside the 2,000-iteration cap (draw 69's guard
+    used to stall above the locking tolerance until the cap)."""
+    klst = _klst()
+    rng = np.random.default_rng(5)
+    pool = W.sweep(seed=5, count=80, nev=8)
+    c2 = W.config2()
+    c2.nev = 8
+    reqs = [c2 if rng.uniform() < 0.05 else pool[i] for i in range(80)]
+    print("[case] served mix, 80 requests", flush=True)
+    with klst.Server(slots=8, max_it=2000, pc_kernel=2, m_max=30, m_min=6, gmres_m=20) as sv:
+        res = sv.solve_all(reqs)
+    worst = max(r["stats"]["outer_iterations"] for r in res)
+    print("max outer iterations", worst, flush=True)
+    for wl, r in zip(reqs, res):
+        assert r["status"] == 0 and r["nconv"] == wl.nev, (wl.name, r["status"], r["stats"])
+        assert np.all(r["resid"] <= 1e-10), wl.name
+    assert worst < 1000, worst
