@@ -1,7 +1,7 @@
 // C ABI of the kLST library (include/klst.h): context, assembly, operator and
 // preconditioner entry points, and the Jacobi-Davidson driver.
 //
-// The driver keeps every n-vector in HBM.  The host sees only small projected
+// The Jacobi-Davidson driver keeps every n-vector in HBM.  The host sees only small projected
 // matrices (R, M_B, the partial Schur form), scalars and flags: one host
 // synchronisation per expansion and one per residual check.  The GMRES solve of
 // the correction equation runs entirely on the device (Hessenberg, Givens
