@@ -4,6 +4,8 @@ condition numbers, computed by the oracle only (exact structured shift-invert
 Arnoldi for right vectors, the adjoint structured inverse for left vectors).
 
     python tests/golden/make_paper_shape_reference.py pb_q20   # n = 64,800, ~3 min
+    python tests/golden/make_paper_shape_reference.py pb_q24   # n = 93,312
+    python tests/golden/make_paper_shape_reference.py pb_q32   # n = 165,888
     python tests/golden/make_paper_shape_reference.py m4_gh48  # n = 281,088, ~30 min
 """
 import os
@@ -23,6 +25,8 @@ from paper_2607_27440_amd import workloads as W   # noqa: E402
 #: workload, eigenvalues kept, Arnoldi basis size
 CASES = {
     "pb_q20": (lambda: W.paper_benchmark(20), 60, 200),
+    "pb_q24": (lambda: W.paper_benchmark(24), 60, 200),
+    "pb_q32": (lambda: W.paper_benchmark(32), 60, 200),
     "m4_gh48": (lambda: W.paper_mach4(), 24, 400),
 }
 

@@ -425,7 +425,7 @@ def test_solve_c3_mixed_precision_matches_oracle_reference():
     assert sorted(r["j"] for r in res)[:8] == list(range(8))
 
 
-@pytest.mark.parametrize("workload", ["c2", "c3", "m4_gh48", "pb_q20"])
+@pytest.mark.parametrize("workload", ["c2", "c3", "m4_gh48", "pb_q20", "pb_q24", "pb_q32"])
 def test_bench_configurations_match_oracle(workload, c2_reference):
     """The solve exactly as bench.py times it (its workload options) against the
     oracle: config 2 against shift-invert Arnoldi, the other shapes against their
