@@ -534,13 +534,17 @@ def _golden(name):
 PAPER_SHAPES = {
     "pb_q20": (lambda: W.paper_benchmark(20), dict(pc_kernel=2, m_max=150, max_it=3000),
                dict(m_max=150, max_it=100)),
+    "pb_q24": (lambda: W.paper_benchmark(24), dict(pc_kernel=2, m_max=150, max_it=3000),
+               dict(m_max=150, max_it=100)),
+    "pb_q32": (lambda: W.paper_benchmark(32), dict(pc_kernel=2, m_max=150, max_it=3000),
+               dict(m_max=150, max_it=100)),
     "m4_gh48": (W.paper_mach4, dict(pc_kernel=2, m_max=80, fix=1e-3, max_it=3000),
                 dict(m_max=120, max_it=100)),
 }
 
 
 @pytest.mark.parametrize("method", ["jd", "shift_invert"])
-@pytest.mark.parametrize("case", ["pb_q20", "m4_gh48"])
+@pytest.mark.parametrize("case", ["pb_q20", "pb_q24", "pb_q32", "m4_gh48"])
 def test_solve_paper_shape_matches_oracle_reference(case, method):
     """Gauss-Hermite workloads at the paper's shapes against the oracle's stored
     structured shift-invert Arnoldi eigenvalues (tests/golden/<case>_reference.txt):
