@@ -187,7 +187,9 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
  * tolerance).  With sigma real and a problem symmetric under the xi_y
  * reflection R (mirrored velocity table, even coupling tables), each locked
  * complex eigenvalue also contributes its exact partner (conj(lambda),
- * R conj(x)) when that partner was not locked itself.  The
+ * R conj(x)) when that partner was not locked itself (a locked eigenvalue
+ * within 1e-6 relative of conj(lambda), matched one to one, counts as the
+ * partner).  The
  * nev nearest are returned, ordered by |lambda - sigma| (ties: Im lambda > 0
  * first).
  * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at

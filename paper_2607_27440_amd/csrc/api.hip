@@ -1441,12 +1441,32 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     return true;
   };
   if (sigma.imag() == 0.0 && klst::mirror_nodes(p.xi_x, p.xi_y, mk) && mirror_symmetric()) {
+    // A locked eigenvalue's partner counts as locked when the nearest other,
+    // still unmatched locked eigenvalue lies within kPartnerTol (relative) of
+    // conj(lambda); matches are one to one.  Locking at tol / 2 leaves an
+    // eigenvalue error of up to kappa * tol / 2, and the sweep has pairs with
+    // kappa ~ 1e4 whose two locked members differ from exact conjugates by more
+    // than 1e-9: a tighter test added both mirrors again as duplicates.  An
+    // eigenvalue within kPartnerTol of the real axis with no such match is
+    // taken as real.
+    constexpr double kPartnerTol = 1e-6;
+    std::vector<int> partner(k, -1);
     for (int i = 0; i < k; ++i) {
       const cd l = lam_all[i];
-      if (std::abs(l.imag()) <= 1e-12 * std::abs(l)) continue;
-      bool have = false;
-      for (int j = 0; j < k && !have; ++j) have = std::abs(lam_all[j] - std::conj(l)) <= 1e-9 * std::abs(l);
-      if (!have) cand.push_back({std::conj(l), i, true});
+      if (std::abs(l.imag()) <= 1e-12 * std::abs(l) || partner[i] >= 0) continue;
+      int best = -1;
+      double bd = 0.0;
+      for (int j = 0; j < k; ++j) {
+        if (j == i || partner[j] >= 0) continue;
+        const double d = std::abs(lam_all[j] - std::conj(l));
+        if (best < 0 || d < bd) { best = j; bd = d; }
+      }
+      if (best >= 0 && bd <= kPartnerTol * std::abs(l)) {
+        partner[i] = best;
+        partner[best] = i;
+      } else if (std::abs(l.imag()) > kPartnerTol * std::abs(l)) {
+        cand.push_back({std::conj(l), i, true});
+      }
     }
   }
   std::vector<int> order(cand.size());
