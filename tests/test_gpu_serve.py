@@ -143,17 +143,20 @@ def test_served_trace_converges_within_budget():
     assert worst < 1000, worst
 
 
-def test_sweep_draws_return_the_nearest_sets():
+@pytest.mark.parametrize("precision,method", [(0, 0), (1, 0), (0, 1)])
+def test_sweep_draws_return_the_nearest_sets(precision, method):
     """Every draw of the batched sweep (seed 4, 64 draws) and of the served mix
     (seed 5, 80 draws), served with 8 slots, returns exactly the oracle's 8
     nearest eigenvalues (shift-invert Arnoldi): no duplicates and no skipped
-    eigenvalue.  Ill-conditioned conjugate pairs whose locked members differ from
-    exact conjugates by more than 1e-9 used to come back twice, in place of a
-    nearer eigenvalue."""
+    eigenvalue; FP64 JD, FP32-inner JD and shift-invert Krylov-Schur.  With JD,
+    ill-conditioned conjugate pairs whose locked members differ from exact
+    conjugates by more than 1e-9 used to come back twice, in place of a nearer
+    eigenvalue."""
     klst = _klst()
     draws = W.sweep(seed=4, count=64, nev=8) + W.sweep(seed=5, count=80, nev=8)
-    print("[case] 144 sweep draws", flush=True)
-    with klst.Server(slots=8, max_it=2000, pc_kernel=2, m_max=30, m_min=6, gmres_m=20) as sv:
+    print("[case] 144 sweep draws, precision", precision, "method", method, flush=True)
+    with klst.Server(slots=8, max_it=2000, pc_kernel=2, m_max=30, m_min=6, gmres_m=20, precision=precision,
+                     method=method) as sv:
         res = sv.solve_all(draws)
     bad = []
     for wl, r in zip(draws, res):
