@@ -32,7 +32,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # each scaled by the same counter's reading for a 256 MiB copy (profiles/
 # jd_solve_c2_m3_ny64_nxi96_bjilu_fp64.md, jd_solve_c3_m4_ny96_nxi1464_exact_pc_fp64.md);
 # keyed by (workload, pc_kernel), valid for the kernels as they were counted
-TRAFFIC_BYTES = {("c2", 1): 38185716, ("c3", 2): 263705722}
+TRAFFIC_BYTES = {("c2", 1): 38185716, ("c3", 2): 263705722, ("pb_q20", 2): 55018833,
+                 ("m4_gh48", 2): 179294232}
 RES_GATE = 1e-10
 
 # workload -> (generator, library options)
