@@ -1,7 +1,7 @@
 """Benchmark: Jacobi-Davidson eigenpairs/s for the kLST shock-stability pencil.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3]
-                    [--precision fp64|mixed] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2|...]
+                    [--precision fp64|mixed] [--no-cpu-baseline] [--no-variants]
 
 One step = the whole hot path on one synthetic input: assemble the operator
 (grids, coefficient tables, device upload) and solve for the nev eigenpairs
@@ -10,13 +10,17 @@ solves, CGS2, projected problems, locking, eigenvectors).  The value counts only
 eigenpairs whose relative residual is <= 1e-10.  Inputs are seeded synthetic
 shock base flows (paper_2607_27440_amd.workloads).
 
-Workload c2 (the default) is the configured method: block-Jacobi ILU(0) with 64
-blocks and GMRES(20); its line also reports, as "variants", the same solve with
-FP32 inner solves in FP64 refinement and with the exact structured inverse as
-preconditioner.  After the timed steps, the dominant kernel is re-timed with HIP
-events on the library's stream to report its roofline fraction, and the CPU
-oracle's Jacobi-Davidson is timed on a bounded sample for the cpu_baseline field.
-Prints ONE JSON line.
+Workload c3 (the default) is the paper's Mach 4 size: Ny = 96 Chebyshev nodes
+times 61 x 24 velocities, n = 281,088 complex unknowns, the 10 eigenvalues
+nearest 0, FP64, with the exact structured inverse as preconditioner.  Its line
+also reports, as "variants", the same solve with FP32 inner solves in FP64
+refinement and shift-invert Krylov-Schur, each eigenvalue's relative distance
+to the oracle's reference eigenvalues (a file written by the oracle alone),
+the roofline of the solve's dominant kernel (one pass of the velocity-line
+inverses, timed with HIP events on the library's stream), an HBM entry on
+working sets above 512 MB (the explicit CSR product at 0.84 B stored entries,
+and the matrix-free operator on 64 vectors), and the CPU oracle on a bounded
+sample for the cpu_baseline field.  Prints ONE JSON line.
 """
 import argparse
 import json
@@ -28,12 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix cores)
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
-# each scaled by the same counter's reading for a 256 MiB copy (profiles/
-# jd_solve_c2_m3_ny64_nxi96_bjilu_fp64.md, jd_solve_c3_m4_ny96_nxi1464_exact_pc_fp64.md);
-# keyed by (workload, pc_kernel), valid for the kernels as they were counted
-TRAFFIC_BYTES = {("c2", 1): 38185716, ("c3", 2): 263705722, ("pb_q20", 2): 55018833,
-                 ("m4_gh48", 2): 179294232}
+# each scaled by the same counter's reading for a 256 MiB copy; keyed by workload,
+# valid for the kernel as counted (the profile named beside each figure)
+TRAFFIC = {
+    "c3": (123620000, "profiles/line_inverse_c3_m4_ny96_nxi1464_counters.md"),
+}
 RES_GATE = 1e-10
 
 # workload -> (generator, library options)
@@ -66,6 +71,40 @@ WORKLOADS = {
 }
 
 
+REFERENCES = {"c3": "c3_m4_reference.txt", "m4_gh48": "m4_gh48_reference.txt",
+              "pb_q20": "pb_q20_reference.txt", "pb_q24": "pb_q24_reference.txt",
+              "pb_q32": "pb_q32_reference.txt"}
+
+
+def reference_eigs(workload):
+    """Eigenvalues nearest the target written by tests/golden/make_*.py from the
+    oracle alone (first two columns: Re, Im), or None."""
+    name = REFERENCES.get(workload)
+    if name is None:
+        return None
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array([complex(float(r[0]), float(r[1])) for r in rows])
+
+
+def error_vs_reference(lam, ref):
+    """Relative distance of each eigenvalue to its nearest reference eigenvalue,
+    matched one to one, nearest first."""
+    import numpy as np
+    used = np.zeros(len(ref), bool)
+    out = []
+    for lv in lam:
+        d = np.abs(ref - lv)
+        d[used] = np.inf
+        j = int(np.argmin(d))
+        used[j] = True
+        out.append(float("%.3g" % (abs(lv - ref[j]) / abs(ref[j]))))
+    return out
+
+
 def make_workload(workloads, gen):
     """Generator spec "name" or "name:int_arg" -> workload."""
     name, _, arg = gen.partition(":")
@@ -95,11 +134,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--variant-steps", type=int, default=2, help="timed steps per variant")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--mode", default="single", choices=["single", "batched", "served", "profile", "bgk"])
     ap.add_argument("--bgk-steps", type=int, default=2000, help="bgk: RK4 steps timed")
@@ -137,84 +177,109 @@ def _line_slots(wl, sigma):
     return slots
 
 
-def kernel_roofline(ctx, wl, torch, reps, workload=None):
-    """Time the block-Jacobi ILU(0) apply (the dominant kernel of the solve) with
-    HIP events on the library's stream.  Algorithmic bytes per launch: with the
-    stored block inverse (pc_kernel 1), every block's dense (nl Ny)^2 inverse read
-    once plus the input and output vectors (32 n); with the level-set sweeps
-    (pc_kernel 0), the factor tables (2 Nxi lines x Ny^2 + coupling entries)
-    plus 32 n.  Complex FP64 = 16 B per entry."""
+def _event_times(fn, reps, torch, st):
+    """Launch fn() reps times on stream st with a HIP event between launches;
+    returns (average s, median s, min s) per launch.  The average is the span
+    from the first event to the last over reps; the events themselves add no
+    work on the stream."""
+    import numpy as np
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    ev[0].record(st)
+    for i in range(reps):
+        fn()
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]) / 1e3
+    return ev[0].elapsed_time(ev[reps]) / 1e3 / reps, float(np.median(per)), float(np.min(per))
+
+
+def line_inverse_roofline(ctx, wl, torch, reps, workload=None):
+    """Roofline of the dominant kernel of the structured-inverse JD solve: one
+    pass of the velocity-line inverses, y = P^{-1} x (k_line_inverse through
+    klst_precond_apply_lines), timed with HIP events on the library's stream.
+    Algorithmic bytes per launch: every stored Ny x Ny inverse read once
+    (16 Ny^2 B per slot; one slot per velocity node, or per mirrored pair for a
+    real target, whose mirror takes the conjugate) plus x read and y written
+    once (32 n)."""
     n = wl.n
+    st = torch.cuda.current_stream()
     x = torch.randn(n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
     ctx.precond_setup(wl.sigma)
+    for _ in range(5):
+        ctx.precond_apply_lines(x, y)
+    avg, med, mn = _event_times(lambda: ctx.precond_apply_lines(x, y), reps, torch, st)
+    nslots = _line_slots(wl, wl.sigma)
+    nbytes = 16 * nslots * wl.Ny * wl.Ny + 32 * n
+    achieved = nbytes / avg / 1e9
+    tr = TRAFFIC.get(workload)
+    return {"kernel": "k_line_inverse (one pass of the structured inverse's velocity-line inverses)",
+            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": tr[0] if tr else None,
+            "traffic_source": (tr[1] + " (rocprofv3 FETCH_SIZE + WRITE_SIZE per launch, stored figure)")
+            if tr else None,
+            "avg_us": round(avg * 1e6, 3), "median_us": round(med * 1e6, 3), "min_us": round(mn * 1e6, 3),
+            "bytes_per_launch": nbytes, "stored_inverses": nslots,
+            "working_set_MB": round(nbytes / 1e6, 1)}
+
+
+def blockjacobi_roofline(ctx, wl, torch, reps):
+    """Roofline of the block-Jacobi ILU(0) apply (pc_kernel 0 or 1), timed with
+    HIP events on the library's stream.  Algorithmic bytes are the method's own:
+    the ILU(0) factors of every block (one dense Ny x Ny L\\U factor per velocity
+    line, since D_x is dense, plus the nl x nl x Ny coupling entries per block of
+    nl lines) read once, plus x read and y written once.  The stored-inverse
+    kernel (pc_kernel 1) reads its dense (nl Ny)^2 block inverses instead, more
+    bytes than the factors: that excess counts against it."""
+    n = wl.n
     st = torch.cuda.current_stream()
+    x = torch.randn(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    ctx.precond_setup(wl.sigma)
     for _ in range(5):
         ctx.precond_apply(x, y)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        ctx.precond_apply(x, y)
-    e1.record(st)
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / reps
+    avg, med, mn = _event_times(lambda: ctx.precond_apply(x, y), reps, torch, st)
     nl = ctx.options.lines_per_block
     nlines = 2 * wl.Nxi
     nblocks = (nlines + nl - 1) // nl
-    if ctx.options.pc_kernel == 2:
-        # two line-inverse passes (each reads the stored Ny x Ny inverses once, x,
-        # writes y), the moment pass (reads y and M), the capacitance GEMV, and the
-        # rank update's U read in the second pass; with a real target one stored
-        # inverse serves a velocity node and its xi_y mirror
-        Rd = 4 * wl.Ny
-        nslots = _line_slots(wl, wl.sigma)
-        nbytes = 2 * 16 * nslots * wl.Ny * wl.Ny + 16 * 5 * n + 2 * 8 * 4 * n + 16 * Rd * Rd
-        kname = "structured exact inverse (2 x k_line_inverse + k_moments + k_capacitance)"
-    elif ctx.options.pc_kernel == 1:
-        sizes = [min(nl, nlines - b * nl) * wl.Ny for b in range(nblocks)]
-        nbytes = 16 * sum(s * s for s in sizes) + 32 * n
-        kname = "k_blockinv_apply (block-Jacobi ILU(0), stored block inverse)"
-    else:
-        nbytes = 16 * (nlines * wl.Ny * wl.Ny + nblocks * nl * nl * wl.Ny) + 32 * n
-        kname = "k_ilu_apply (block-Jacobi ILU(0) level-set sweeps)"
-    achieved = nbytes / sec / 1e9
-    return {"kernel": kname,
-            "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": TRAFFIC_BYTES.get((workload, ctx.options.pc_kernel)),
-            "avg_us": round(sec * 1e6, 3), "bytes_per_launch": nbytes}
+    nbytes = 16 * (nlines * wl.Ny * wl.Ny + nblocks * nl * nl * wl.Ny) + 32 * n
+    achieved = nbytes / avg / 1e9
+    kname = ("k_blockinv_apply (block-Jacobi ILU(0) as stored block inverses)" if ctx.options.pc_kernel == 1
+             else "k_ilu_apply (block-Jacobi ILU(0) level-set sweeps)")
+    return {"kernel": kname, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_us": round(avg * 1e6, 3), "median_us": round(med * 1e6, 3), "min_us": round(mn * 1e6, 3),
+            "bytes_per_launch": nbytes}
 
 
-def op_apply_rate(ctx, wl, torch, reps, nvec=64):
-    """Matrix-free (A - tau B) x (one vector, and nvec vectors in one launch so the
-    working set exceeds the 256 MB Infinity Cache) and CSR SpMV rates on this
-    workload (events).  Bytes: vectors in and out, U and M tables once per launch
-    (CSR: 20 B per stored entry)."""
+def hbm_entries(ctx, wl, torch, reps, nvec=64):
+    """HBM rates on working sets above 512 MB (twice the 256 MB Infinity Cache):
+    the explicit CSR product (A - tau B) x, 20 B per stored entry plus the row
+    pointers and the vectors, and the matrix-free operator on nvec vectors in
+    one call (vectors in and out, 32 n B each, plus the U and M tables once).
+    Both timed with HIP events on the library's stream: average, median, min."""
     n = wl.n
+    st = torch.cuda.current_stream()
+    out = {}
     x = torch.randn(n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
     xm = torch.randn(nvec * n, dtype=torch.complex128, device="cuda")
     ym = torch.empty_like(xm)
-    st = torch.cuda.current_stream()
-    out = {}
     tables = 8 * 2 * 2 * 4 * wl.Nxi * wl.Ny
-    for name, fn, nbytes in (
-            ("matrix_free", ctx.apply, 32 * n + tables),
-            (f"matrix_free_x{nvec}", lambda t, a, b: ctx.apply_many(t, nvec, xm, ym), 32 * n * nvec + tables),
-            ("csr", ctx.apply_csr, 20 * ctx.nnz + 8 * (n + 1) + 32 * n)):
+    flops_mf = nvec * n * (4 * wl.Ny + 8 * 4 + 8)
+    for name, fn, nbytes, flops in (
+            ("csr_spmv", lambda: ctx.apply_csr(0.0, x, y), 20 * ctx.nnz + 8 * (n + 1) + 32 * n, 8 * ctx.nnz),
+            (f"matrix_free_x{nvec}", lambda: ctx.apply_many(0.0, nvec, xm, ym), 32 * n * nvec + tables, flops_mf),
+            ("matrix_free_x1_latency", lambda: ctx.apply(0.0, x, y), 32 * n + tables, n * (4 * wl.Ny + 40))):
         for _ in range(3):
-            fn(0.0, x, y)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            fn(0.0, x, y)
-        e1.record(st)
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / reps
-        out[name] = {"avg_us": round(sec * 1e6, 3), "GB/s": round(nbytes / sec / 1e9, 2),
-                     "bytes": nbytes}
+            fn()
+        avg, med, mn = _event_times(fn, reps, torch, st)
+        out[name] = {"avg_us": round(avg * 1e6, 3), "median_us": round(med * 1e6, 3), "min_us": round(mn * 1e6, 3),
+                     "bytes": nbytes, "GB/s": round(nbytes / avg / 1e9, 2),
+                     "frac_hbm": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4),
+                     "TFLOP/s": round(flops / avg / 1e12, 3),
+                     "frac_fp64": round(flops / avg / 1e12 / FP64_PEAK_TFLOPS, 4)}
     return out
 
 
@@ -227,11 +292,15 @@ def _cpu_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(wl, seconds, opts):
+def cpu_baseline(wl, seconds, opts, gpu_outer=None):
     """The oracle's plain CPU Jacobi-Davidson on the same workload with the same
-    preconditioner (block-Jacobi ILU(0) over the same line blocks, or the exact
-    structured inverse), stopped after `seconds` of work (a bounded sample);
-    rate = converged eigenpairs / time."""
+    options and preconditioner (block-Jacobi ILU(0) over the same line blocks, or
+    the exact structured inverse), run for a bounded sample of `seconds`.  When
+    the sample converges pairs, rate = converged eigenpairs / time.  When it
+    converges none (the Mach 4 shape: one outer iteration, 20 GMRES steps of
+    structured solves, takes seconds on the host), the sample's time per outer
+    iteration is scaled to the outer-iteration count of the GPU solve with the
+    same options, and rate = nev / that estimated solve time (stated as such)."""
     import numpy as np
     from oracle import jd as OJ
     from oracle import operator as O
@@ -243,15 +312,26 @@ def cpu_baseline(wl, seconds, opts):
         K = OE.ShiftInvert(P, wl.sigma)
     else:
         K = OJ.LineBlockILU0(P, wl.sigma, opts["lines_per_block"])
-    remaining = max(1.0, seconds - (time.perf_counter() - t0))
-    out = OJ.jd(P, wl.sigma, wl.nev, tol=RES_GATE, m_max=opts["m_max"], gmres_m=opts["gmres_m"],
-                fix=opts.get("fix", 0.01), precond=K, time_limit=remaining)
+    t_setup = time.perf_counter() - t0
+    remaining = max(1.0, seconds - t_setup)
+    t1 = time.perf_counter()
+    out = OJ.jd(P, wl.sigma, wl.nev, tol=RES_GATE, m_min=opts.get("m_min", 6), m_max=opts["m_max"],
+                gmres_m=opts["gmres_m"], fix=opts.get("fix", 0.01), precond=K, time_limit=remaining)
+    t_jd = time.perf_counter() - t1
     el = time.perf_counter() - t0
     good = int(np.sum(out["resid"] <= RES_GATE))
-    return {"value": round(good / el, 6), "unit": "eigenpairs/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"{wl.name}: CPU JD (same parameters) for {el:.1f} s incl. ILU(0) set-up; "
-                      f"{good} eigenpairs converged, {out['outer']} outer iterations"}
+    base = {"unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle"}
+    if good > 0 or not gpu_outer:
+        return dict(base, value=round(good / el, 6),
+                    sample=f"{wl.name}: CPU JD (same options) for {el:.1f} s incl. preconditioner set-up; "
+                           f"{good} eigenpairs converged, {out['outer']} outer iterations")
+    per_outer = t_jd / max(1, out["outer"])
+    est = t_setup + per_outer * gpu_outer
+    return dict(base, value=round(wl.nev / est, 8),
+                sample=f"{wl.name}: CPU JD (same options) for {el:.1f} s: preconditioner set-up {t_setup:.1f} s, "
+                       f"{out['outer']} outer iterations at {per_outer:.2f} s each, no pair converged; scaled to "
+                       f"the {gpu_outer} outer iterations of the GPU solve: est. {est:.0f} s for {wl.nev} "
+                       f"eigenpairs", estimated=True)
 
 
 SWEEP_OPTS = dict(pc_kernel=2, m_max=30, m_min=6, gmres_m=20)
@@ -452,7 +532,13 @@ def run_profile(a):
     out = {"mode": "profile", "workload": wl.name, "options": opts}
     with klst.Context(stream=st.cuda_stream, **opts) as ctx:
         ctx.assemble(wl)
-        out["precond"] = kernel_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
+        ctx.precond_setup(wl.sigma)
+        if ctx.options.pc_kernel == 2:
+            out["line_inverse"] = line_inverse_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
+        xp = torch.randn(wl.n, dtype=torch.complex128, device="cuda")
+        yp = torch.empty_like(xp)
+        avg, med, mn = _event_times(lambda: ctx.precond_apply(xp, yp), a.kernel_reps, torch, st)
+        out["precond_apply_us"] = {"avg": round(avg * 1e6, 3), "median": round(med * 1e6, 3), "min": round(mn * 1e6, 3)}
         x = torch.randn(wl.n, dtype=torch.complex128, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
@@ -502,6 +588,7 @@ def main():
     st = torch.cuda.current_stream()
     ctx = klst.Context(stream=st.cuda_stream, precision=prec, **opts)
     log(f"[bench] workload {wl.name} n={wl.n} nev={wl.nev} sigma={wl.sigma} opts={opts}")
+    ref = reference_eigs(a.workload)
     good_total = 0
     stats = None
     for i in range(a.warmup):
@@ -517,7 +604,8 @@ def main():
         good_total += int(np.sum(out["resid"] <= RES_GATE))
         stats = out["stats"]
         log(f"[bench] step {i}: nconv {out['nconv']} outer {stats['outer_iterations']} "
-            f"inner {stats['inner_iterations']} {stats['seconds_total']:.3f}s")
+            f"inner {stats['inner_iterations']} {stats['seconds_total']:.3f}s "
+            f"(set-up {stats['seconds_setup'] * 1e3:.1f} ms)")
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     value = good_total / el
@@ -531,7 +619,8 @@ def main():
                 torch.cuda.synchronize()
                 tv = time.perf_counter()
                 gv = 0
-                for _ in range(a.steps):
+                nv = max(1, a.variant_steps)
+                for _ in range(nv):
                     vctx.assemble(wl)
                     vo = vctx.solve(wl.sigma, wl.nev, want_vectors=False)
                     gv += int(np.sum(vo["resid"] <= RES_GATE))
@@ -542,19 +631,26 @@ def main():
             if vo["nconv"] == out["nconv"] and out["nconv"] > 0:
                 # the spectrum is closed under conjugation and a pair split at
                 # position nev may come back as either member: compare with both
-                ref = np.concatenate([out["lam"], np.conj(out["lam"])])
-                d = [np.min(np.abs(ref - lv)) / abs(lv) for lv in vo["lam"]]
+                refl = np.concatenate([out["lam"], np.conj(out["lam"])])
+                d = [np.min(np.abs(refl - lv)) / abs(lv) for lv in vo["lam"]]
                 diff = float(max(d))
                 per_pair = [float("%.3g" % v) for v in d]
-            variants[vname] = {"value": round(gv / ev, 4), "ms_per_step": round(1e3 * ev / a.steps, 3),
+            variants[vname] = {"value": round(gv / ev, 4), "ms_per_step": round(1e3 * ev / nv, 3), "steps": nv,
                                "max_rel_eig_diff_vs_line": diff,
                                "rel_eig_diff_vs_line_per_pair": per_pair if diff is not None else None,
+                               "rel_err_vs_oracle_reference_per_pair":
+                                   error_vs_reference(vo["lam"], ref) if ref is not None else None,
                                "speedup_vs_line": round((gv / ev) / value, 3),
                                "outer": vo["stats"]["outer_iterations"], "inner": vo["stats"]["inner_iterations"],
                                "options": vopt}
             log(f"[bench] variant {vname}: {variants[vname]}")
-    roof = kernel_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
-    ops = op_apply_rate(ctx, wl, torch, max(20, a.kernel_reps // 4))
+    if ctx.options.pc_kernel == 2:
+        roof = line_inverse_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
+    else:
+        roof = blockjacobi_roofline(ctx, wl, torch, a.kernel_reps)
+    log(f"[bench] roofline {roof}")
+    hbm = hbm_entries(ctx, wl, torch, max(10, a.kernel_reps // 10))
+    log(f"[bench] hbm {hbm}")
     line = {
         "metric": "eigenpairs/s at rel. residual <= 1e-10",
         "value": round(value, 4),
@@ -571,14 +667,15 @@ def main():
         "config": {"workload": wl.name, "n": wl.n, "nev": wl.nev, "sigma": str(wl.sigma),
                    "Ny": wl.Ny, "Nxi": wl.Nxi, "precision": a.precision, **opts},
         "roofline": roof,
-        "op_apply": ops,
+        "hbm": hbm,
         "solve_stats": stats,
+        "rel_err_vs_oracle_reference_per_pair": error_vs_reference(out["lam"], ref) if ref is not None else None,
     }
     if variants:
         line["variants"] = variants
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds, opts)
+        line["cpu_baseline"] = cpu_baseline(wl, a.cpu_seconds, opts, stats["outer_iterations"])
     print(json.dumps(line), flush=True)
 
 

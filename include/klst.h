@@ -176,6 +176,42 @@ klst_status klst_precond_setup(klst_ctx* ctx, const double sigma[2]);
 /* y = K^{-1} x with the current preconditioner, device vectors. */
 klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
 
+/* y = P^{-1} x for device vectors: one pass of the velocity-line inverses of
+ * the structured preconditioner alone (the block-diagonal streaming +
+ * relaxation part P of A - sigma B with unit inflow rows, one Ny x Ny inverse
+ * per velocity node, Sec. 2.2 rows with the moment coupling left out), the
+ * first half of what klst_precond_apply applies.  Needs klst_precond_setup
+ * with pc_kernel 2.  x and y must not overlap.  Errors: ESTATE, EINVAL. */
+klst_status klst_precond_apply_lines(klst_ctx* ctx, const void* x, void* y);
+
+/* Copy out the structured inverse that klst_precond_setup built on the device
+ * (pc_kernel 2; the exact (A - sigma B)^{-1} in the Woodbury form of the
+ * velocity-line blocks of Sec. 2.2's streaming + relaxation rows and the
+ * moment capacitance): Pinv [nslots][Ny x Ny] column-major line inverses
+ * (slot s holds node slot_node[s]; with sigma real a node's xi_y mirror is
+ * served by the conjugate and has no slot of its own), Sinv [(r Ny)^2]
+ * row-major capacitance inverse (index q = j r + a), both complex doubles on
+ * the host.  *nslots receives the slot count; any array may be NULL (query
+ * nslots first to size Pinv).  Errors: ESTATE, EINVAL. */
+klst_status klst_precond_export(klst_ctx* ctx, double* Pinv, double* Sinv, int* slot_node, int* nslots);
+
+/* Host-only (no device needed): the same structured inverse built by the host
+ * (LU with partial pivoting per line block and for the capacitance), in the
+ * layout of klst_precond_export, for testing the device set-up.  Errors:
+ * EINVAL (bad input, as klst_assemble), ENOCONV (a singular block). */
+klst_status klst_host_structured_inverse(const klst_grid* grid, const klst_vel* vel, const klst_base* base,
+                                         double beta, const double sigma[2], double* Pinv, double* Sinv,
+                                         int* slot_node, int* nslots);
+
+/* Copy out the explicit CSR matrix of A (Sec. 4.3's stored form; B is the
+ * diagonal 0/1 mask of non-inflow rows): rowptr [n + 1] int64, col [nnz] int32
+ * (ascending within a row), val [nnz] complex doubles (interleaved re, im),
+ * nnz as klst_dims reports.  on_device = 1: the three buffers are device
+ * memory, else host memory; all are caller-allocated.  Generates the matrix on
+ * the device first if op_mode 0 had not.  Errors: ESTATE (no problem), EINVAL,
+ * ENOMEM (the matrix does not fit). */
+klst_status klst_export_csr(klst_ctx* ctx, void* rowptr, void* col, void* val, int on_device);
+
 /* Jacobi-Davidson solve for the nev eigenvalues nearest sigma (Sec. 4.2).
  * Pairs are locked as they converge; once nev are locked the iteration goes on
  * until max(1, nev / 25) consecutive newly locked eigenvalues were not nearer
@@ -187,9 +223,8 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y);
  * tolerance).  With sigma real and a problem symmetric under the xi_y
  * reflection R (mirrored velocity table, even coupling tables), each locked
  * complex eigenvalue also contributes its exact partner (conj(lambda),
- * R conj(x)) when that partner was not locked itself (a locked eigenvalue
- * within 1e-6 relative of conj(lambda), matched one to one, counts as the
- * partner).  The
+ * R conj(x)) when that partner was not locked itself; partnership is read from
+ * the eigenvectors as klst_host_select_output describes.  The
  * nev nearest are returned, ordered by |lambda - sigma| (ties: Im lambda > 0
  * first).
  * lambda: [2*nev] host doubles.  X: [nev * n] complex doubles (eigenvector i at
@@ -338,6 +373,23 @@ klst_status klst_server_stats(klst_server* sv, int* peak_running, size_t* peak_b
 klst_status klst_host_tables(const klst_grid* grid, const klst_vel* vel, const klst_base* base,
                              double beta, double* Dx, double* nu, double* U, double* M,
                              uint8_t* bc);
+
+/* Host-only: the selection of returned eigenpairs that klst_solve makes from
+ * its k locked pairs, exposed for testing.  lam [2k] locked eigenvalues; G
+ * [2 k^2] (or NULL) the overlaps <R conj(x_i), x_j> of the locked eigenvectors
+ * (row-major, interleaved), R the xi_y reflection, and nrm2 [k] = ||x_i||^2.
+ * With G, lambda_i counts as real when |G_ii| >= (1 - 1e-10) ||x_i||^2, locked
+ * x_j as the conjugate partner of x_i when |G_ij| >= (1 - 1e-6) ||x_i|| ||x_j||
+ * and |lambda_j - conj(lambda_i)| <= 1e-6 |lambda_i| (one to one, best
+ * alignment first), and every other locked complex eigenvalue adds its partner
+ * (conj(lambda_i), R conj(x_i)) as a candidate.  The min(nev, #) candidates
+ * nearest sigma are returned (ties within 1e-12 relative: Im lambda > 0 first,
+ * then locking order): out_lam [2 nev], out_src [nev] (the locked pair used),
+ * out_mirrored [nev] (1: the partner of out_src), *nout the count.  Any output
+ * array may be NULL.  Errors: EINVAL. */
+klst_status klst_host_select_output(int k, const double* lam, const double* G, const double* nrm2,
+                                    const double sigma[2], int nev, double* out_lam, int* out_src,
+                                    int* out_mirrored, int* nout);
 
 /* Host-only: sorted complex Schur form of a small m x m complex matrix G
  * (row-major interleaved), G U = U T with |T_00| >= |T_11| >= ...; used by the

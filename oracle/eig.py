@@ -73,6 +73,7 @@ class ShiftInvert:
                     Pk[j, :] = 0.0
                     Pk[j, j] = 1.0
             lines[k] = Pk.conj().T if adjoint else Pk
+        self.lines = lines                                         # [k, j, m]
         self.lines_inv = np.linalg.inv(lines)                      # [k, j, m]
         U = P.U * (~P.bc)[:, :, None, :]                           # zero on inflow rows
         M = P.M
@@ -141,10 +142,15 @@ def left_vectors_si(P, lam, sigma, tol=1e-14):
     return out
 
 
+#: largest n for which residuals() uses the assembled matrices; above it the
+#: structured product of the row definition
+EXPLICIT_MAX_N = 60000
+
+
 def residuals(P, lam, X):
     """Relative residual ||A x - lambda B x|| / (|lambda| ||x||) (the acceptance
     test of Sec. 4.2; absolute residual over ||x|| when |lambda| < 1e-6)."""
-    if P.n <= 60000:
+    if P.n <= EXPLICIT_MAX_N:
         R = P.A @ X - (P.B @ X) * lam[None, :]
     else:
         R = np.stack([P.apply_structured(X[:, i], lam[i]) for i in range(len(lam))], axis=1)

@@ -206,40 +206,75 @@ klst_status pc_setup(klst_ctx* ctx, cd sigma, int pk_override = -1) {
   if (pk == 1 && 16 * ((size_t)lines * p.Ny + 1024) > lds_max)
     return fail(ctx, KLST_EINVAL, "lines_per_block * Ny too large for the stored block inverse (<= 3072)");
   if (pk == 2) {
-    klst::StructuredInverse si;
-    const std::string e = klst::build_structured_inverse(p, sigma, si, nth);
-    if (!e.empty()) return fail(ctx, KLST_ENOCONV, e);
     klst_status s;
     if ((s = ensure_mom(ctx, 1)) != KLST_OK) return s;
-    auto put = [&](double2*& d64, float2*& d32, const std::vector<cd>& h) -> klst_status {
-      dfree(ctx, d64);
-      dfree(ctx, d32);
-      ALLOC(d64, sizeof(double2) * h.size());
-      HIPCHK(hipMemcpyAsync(d64, h.data(), sizeof(double2) * h.size(), hipMemcpyHostToDevice, ctx->stream));
-      if (ctx->opt.precision == 1) {
-        std::vector<float2> h32(h.size());
-        for (size_t i = 0; i < h.size(); ++i) h32[i] = make_float2((float)h[i].real(), (float)h[i].imag());
-        ALLOC(d32, sizeof(float2) * h32.size());
-        HIPCHK(hipMemcpyAsync(d32, h32.data(), sizeof(float2) * h32.size(), hipMemcpyHostToDevice, ctx->stream));
-      }
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      return KLST_OK;
-    };
-    if ((s = put(ctx->d_Pinv, ctx->d_Pinv32, si.Pinv)) != KLST_OK) return s;
+    const int Rd = p.r * p.Ny;
+    std::vector<int> slot_node, slot_mate, slot_of, conj_of;
+    klst::structured_slots(p, sigma, slot_node, slot_mate, slot_of, conj_of);
+    const int nslots = (int)slot_node.size();
+    dfree(ctx, ctx->d_Pinv); dfree(ctx, ctx->d_Pinv32);
+    dfree(ctx, ctx->d_Sinv); dfree(ctx, ctx->d_Sinv32);
+    dfree(ctx, ctx->d_slots);
+    ctx->nslots = nslots;
+    ALLOC(ctx->d_Pinv, sizeof(double2) * (size_t)nslots * p.Ny * p.Ny);
+    ALLOC(ctx->d_Sinv, sizeof(double2) * (size_t)Rd * Rd);
     {
-      ctx->nslots = (int)si.slot_node.size();
-      std::vector<int> sl(si.slot_node);
-      sl.insert(sl.end(), si.slot_mate.begin(), si.slot_mate.end());
-      dfree(ctx, ctx->d_slots);
+      std::vector<int> sl(slot_node);
+      sl.insert(sl.end(), slot_mate.begin(), slot_mate.end());
       ALLOC(ctx->d_slots, sizeof(int) * sl.size());
       HIPCHK(hipMemcpyAsync(ctx->d_slots, sl.data(), sizeof(int) * sl.size(), hipMemcpyHostToDevice, ctx->stream));
       HIPCHK(hipStreamSynchronize(ctx->stream));
     }
-    if ((s = put(ctx->d_Sinv, ctx->d_Sinv32, si.Sinv)) != KLST_OK) return s;
+    if ((size_t)Rd * (2 * sizeof(double2) + sizeof(int)) <= 64 * 1024) {
+      // set-up on the device: line blocks inverted in place, capacitance assembled
+      // and inverted there; the host reads back only the singularity flags
+      int *d_aux = nullptr;
+      double2* d_part = nullptr;
+      ALLOC(d_aux, sizeof(int) * (2 * (size_t)p.Nxi + 1 + nslots));
+      const klst_status sp = dalloc(ctx, (void**)&d_part, sizeof(double2) * klst::dev::kCapParts * (size_t)Rd * Rd);
+      if (sp != KLST_OK) { dfree(ctx, d_aux); return sp; }
+      std::vector<int> aux(slot_of);
+      aux.insert(aux.end(), conj_of.begin(), conj_of.end());
+      int* d_status = d_aux + 2 * p.Nxi;
+      HIPCHK(hipMemcpyAsync(d_aux, aux.data(), sizeof(int) * aux.size(), hipMemcpyHostToDevice, ctx->stream));
+      klst::dev::launch_structured_setup(ctx->stream, ctx->d_Pinv, ctx->d_Sinv, d_part, p.Ny, p.Nxi, p.r,
+                                         ctx->d_slots, nslots, d_aux, d_aux + p.Nxi, ctx->d_Dx, ctx->d_xix,
+                                         ctx->d_xiy, ctx->d_nu, ctx->d_U, ctx->d_M, p.beta, sigma.real(),
+                                         sigma.imag(), d_status);
+      HIPCHK(hipGetLastError());
+      std::vector<int> status(1 + nslots);
+      HIPCHK(hipMemcpyAsync(status.data(), d_status, sizeof(int) * status.size(), hipMemcpyDeviceToHost,
+                            ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      dfree(ctx, d_part);
+      dfree(ctx, d_aux);
+      for (int sl = 0; sl < nslots; ++sl)
+        if (status[1 + sl]) return fail(ctx, KLST_ENOCONV, "singular velocity-line block at node " +
+                                                             std::to_string(slot_node[sl]));
+      if (status[0]) return fail(ctx, KLST_ENOCONV, "singular moment capacitance matrix");
+    } else {
+      // (r Ny)^2 too large for the one-workgroup capacitance inversion: host set-up
+      klst::StructuredInverse si;
+      const std::string e = klst::build_structured_inverse(p, sigma, si, nth);
+      if (!e.empty()) return fail(ctx, KLST_ENOCONV, e);
+      HIPCHK(hipMemcpyAsync(ctx->d_Pinv, si.Pinv.data(), sizeof(double2) * si.Pinv.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->d_Sinv, si.Sinv.data(), sizeof(double2) * si.Sinv.size(), hipMemcpyHostToDevice,
+                            ctx->stream));
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    if (ctx->opt.precision == 1) {
+      const size_t np = (size_t)nslots * p.Ny * p.Ny;
+      ALLOC(ctx->d_Pinv32, sizeof(float2) * np);
+      ALLOC(ctx->d_Sinv32, sizeof(float2) * (size_t)Rd * Rd);
+      klst::dev::launch_narrow(ctx->stream, ctx->d_Pinv, ctx->d_Pinv32, (int64_t)np);
+      klst::dev::launch_narrow(ctx->stream, ctx->d_Sinv, ctx->d_Sinv32, (int64_t)Rd * Rd);
+      HIPCHK(hipGetLastError());
+    }
     dfree(ctx, ctx->d_capd);
     dfree(ctx, ctx->d_capd32);
-    ALLOC(ctx->d_capd, sizeof(double2) * (size_t)p.r * p.Ny);
-    if (ctx->opt.precision == 1) ALLOC(ctx->d_capd32, sizeof(float2) * (size_t)p.r * p.Ny);
+    ALLOC(ctx->d_capd, sizeof(double2) * (size_t)Rd);
+    if (ctx->opt.precision == 1) ALLOC(ctx->d_capd32, sizeof(float2) * (size_t)Rd);
     ctx->ilu = klst::ILU0{};
     ctx->pc_ready = true;
     ctx->pc_sigma = sigma;
@@ -505,6 +540,23 @@ klst_status klst_host_tables(const klst_grid* grid, const klst_vel* vel, const k
   return KLST_OK;
 }
 
+klst_status klst_host_select_output(int k, const double* lam, const double* G, const double* nrm2,
+                                    const double sigma[2], int nev, double* out_lam, int* out_src,
+                                    int* out_mirrored, int* nout) {
+  if (k < 0 || nev < 0 || !sigma || !nout || (k > 0 && !lam) || (G && !nrm2)) return KLST_EINVAL;
+  std::vector<cd> l(k), g(G ? (size_t)k * k : 0);
+  for (int i = 0; i < k; ++i) l[i] = cd(lam[2 * i], lam[2 * i + 1]);
+  for (size_t i = 0; i < g.size(); ++i) g[i] = cd(G[2 * i], G[2 * i + 1]);
+  const auto sel = klst::select_output(l, G ? g.data() : nullptr, nrm2, cd(sigma[0], sigma[1]), nev);
+  *nout = (int)sel.size();
+  for (size_t o = 0; o < sel.size(); ++o) {
+    if (out_lam) { out_lam[2 * o] = sel[o].lam.real(); out_lam[2 * o + 1] = sel[o].lam.imag(); }
+    if (out_src) out_src[o] = sel[o].src;
+    if (out_mirrored) out_mirrored[o] = sel[o].mirrored ? 1 : 0;
+  }
+  return KLST_OK;
+}
+
 klst_status klst_host_sorted_schur(int m, const double* G, double* U, double* T) {
   if (m < 1 || !G || !U || !T) return KLST_EINVAL;
   std::vector<cd> g(m * m), u(m * m), t(m * m);
@@ -618,6 +670,68 @@ klst_status klst_precond_apply(klst_ctx* ctx, const void* x, void* y) {
   if (!ctx->pc_ready) return fail(ctx, KLST_ESTATE, "klst_precond_apply before klst_precond_setup");
   HIPCHK(hipSetDevice(ctx->opt.device));
   return pc_apply(ctx, (const double2*)x, (double2*)y, nullptr);
+}
+
+klst_status klst_precond_apply_lines(klst_ctx* ctx, const void* x, void* y) {
+  if (!ctx || !x || !y || x == y) return KLST_EINVAL;
+  if (!ctx->pc_ready || ctx->pc_kernel_built != 2)
+    return fail(ctx, KLST_ESTATE, "klst_precond_apply_lines needs the structured inverse (pc_kernel 2) set up");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_line_inverse(ctx->stream, (const double2*)x, (double2*)y, p.Ny, p.Nxi, p.r, ctx->d_Pinv,
+                                 ctx->d_slots, ctx->d_slots + ctx->nslots, ctx->nslots, ctx->d_U, ctx->d_xix);
+  HIPCHK(hipGetLastError());
+  return KLST_OK;
+}
+
+klst_status klst_precond_export(klst_ctx* ctx, double* Pinv, double* Sinv, int* slot_node, int* nslots) {
+  if (!ctx || !nslots) return KLST_EINVAL;
+  if (!ctx->pc_ready || ctx->pc_kernel_built != 2)
+    return fail(ctx, KLST_ESTATE, "klst_precond_export needs the structured inverse (pc_kernel 2) set up");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const klst::Problem& p = ctx->prob;
+  const size_t Rd = (size_t)p.r * p.Ny;
+  *nslots = ctx->nslots;
+  if (Pinv)
+    HIPCHK(hipMemcpyAsync(Pinv, ctx->d_Pinv, sizeof(double2) * (size_t)ctx->nslots * p.Ny * p.Ny,
+                          hipMemcpyDeviceToHost, ctx->stream));
+  if (Sinv) HIPCHK(hipMemcpyAsync(Sinv, ctx->d_Sinv, sizeof(double2) * Rd * Rd, hipMemcpyDeviceToHost, ctx->stream));
+  if (slot_node)
+    HIPCHK(hipMemcpyAsync(slot_node, ctx->d_slots, sizeof(int) * ctx->nslots, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KLST_OK;
+}
+
+klst_status klst_host_structured_inverse(const klst_grid* grid, const klst_vel* vel, const klst_base* base,
+                                         double beta, const double sigma[2], double* Pinv, double* Sinv,
+                                         int* slot_node, int* nslots) {
+  if (!sigma || !nslots) return KLST_EINVAL;
+  klst::Problem p;
+  if (!klst::build_problem(grid, vel, base, beta, p).empty()) return KLST_EINVAL;
+  klst::StructuredInverse si;
+  const unsigned hw = std::thread::hardware_concurrency();
+  if (!klst::build_structured_inverse(p, cd(sigma[0], sigma[1]), si, (int)std::max(1u, std::min(hw, 16u))).empty())
+    return KLST_ENOCONV;
+  *nslots = (int)si.slot_node.size();
+  if (Pinv) std::memcpy(Pinv, si.Pinv.data(), sizeof(cd) * si.Pinv.size());
+  if (Sinv) std::memcpy(Sinv, si.Sinv.data(), sizeof(cd) * si.Sinv.size());
+  if (slot_node) std::memcpy(slot_node, si.slot_node.data(), sizeof(int) * si.slot_node.size());
+  return KLST_OK;
+}
+
+klst_status klst_export_csr(klst_ctx* ctx, void* rowptr, void* col, void* val, int on_device) {
+  if (!ctx || !rowptr || !col || !val) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_export_csr before klst_assemble");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  klst_status s = ensure_csr(ctx);
+  if (s != KLST_OK) return s;
+  const int64_t n = ctx->prob.n(), nnz = ctx->prob.nnz();
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(hipMemcpyAsync(rowptr, ctx->d_rowptr, sizeof(int64_t) * (n + 1), kind, ctx->stream));
+  HIPCHK(hipMemcpyAsync(col, ctx->d_col, sizeof(int32_t) * nnz, kind, ctx->stream));
+  HIPCHK(hipMemcpyAsync(val, ctx->d_val, sizeof(double2) * nnz, kind, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return KLST_OK;
 }
 
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out) {
@@ -1416,19 +1530,15 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       Sv[(size_t)q * k + i] = (std::abs(d) > 0) ? -acc / d : cd(0.0);
     }
   }
-  // Candidates: every locked pair and, for a real target on a table closed under
-  // xi_y -> -xi_y, the conjugate partner (conj(lambda), R conj(x)) of each locked
-  // complex eigenvalue whose partner was not locked itself: the pencil commutes
-  // with R (the xi_y reflection) up to conjugation, so the partner is an exact
-  // eigenpair at the same distance from the target.  The min(#, nev) nearest are
-  // returned (ties within 1e-12 relative: Im lambda > 0 first, then locking order).
-  struct Cand { cd lam; int src; bool mirrored; };
-  std::vector<Cand> cand;
-  for (int i = 0; i < k; ++i) cand.push_back({lam_all[i], i, false});
+  // Every locked eigenvector x_i = Q s_i on the device.  For a real target on a
+  // problem symmetric under the xi_y reflection R (velocity table closed under
+  // xi_y -> -xi_y; coupling columns and moment functionals even in xi_y except
+  // the v moment's, which is odd: then R A R = conj(A) entry by entry), the
+  // partner (conj(lambda), R conj(x)) of a locked complex eigenvalue is an exact
+  // eigenpair at the same distance from the target; which locked pairs are each
+  // other's partners is read from the overlaps <R conj(x_i), x_j>.
   std::vector<int> mk;
   auto mirror_symmetric = [&]() {
-    // coupling columns and moment functionals even in xi_y, except the v moment's
-    // (a = 2 with r = 4), which is odd: then R A R = conj(A) entry by entry
     for (int j = 0; j < p.Ny; ++j)
       for (int f = 0; f < 2; ++f)
         for (int a = 0; a < p.r; ++a) {
@@ -1440,74 +1550,53 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
         }
     return true;
   };
-  if (sigma.imag() == 0.0 && klst::mirror_nodes(p.xi_x, p.xi_y, mk) && mirror_symmetric()) {
-    // A locked eigenvalue's partner counts as locked when the nearest other,
-    // still unmatched locked eigenvalue lies within kPartnerTol (relative) of
-    // conj(lambda); matches are one to one.  Locking at tol / 2 leaves an
-    // eigenvalue error of up to kappa * tol / 2, and the sweep has pairs with
-    // kappa ~ 1e4 whose two locked members differ from exact conjugates by more
-    // than 1e-9: a tighter test added both mirrors again as duplicates.  An
-    // eigenvalue within kPartnerTol of the real axis with no such match is
-    // taken as real.
-    constexpr double kPartnerTol = 1e-6;
-    std::vector<int> partner(k, -1);
-    for (int i = 0; i < k; ++i) {
-      const cd l = lam_all[i];
-      if (std::abs(l.imag()) <= 1e-12 * std::abs(l) || partner[i] >= 0) continue;
-      int best = -1;
-      double bd = 0.0;
-      for (int j = 0; j < k; ++j) {
-        if (j == i || partner[j] >= 0) continue;
-        const double d = std::abs(lam_all[j] - std::conj(l));
-        if (best < 0 || d < bd) { best = j; bd = d; }
-      }
-      if (best >= 0 && bd <= kPartnerTol * std::abs(l)) {
-        partner[i] = best;
-        partner[best] = i;
-      } else if (std::abs(l.imag()) > kPartnerTol * std::abs(l)) {
-        cand.push_back({std::conj(l), i, true});
-      }
+  const bool mirror = k > 0 && sigma.imag() == 0.0 && klst::mirror_nodes(p.xi_x, p.xi_y, mk) && mirror_symmetric();
+  double2* Xall = ws.vec(std::max(1, k));
+  double2* Mall = mirror ? ws.vec(k) : nullptr;
+  double2* d_sv = ws.small<double2>((size_t)std::max(1, k) * std::max(1, k));
+  double2* d_gram = mirror ? ws.small<double2>((size_t)k * (k + 1)) : nullptr;
+  int* d_mk = mirror ? ws.small<int>(p.Nxi) : nullptr;
+  if (!Xall || !d_sv || (mirror && (!Mall || !d_gram || !d_mk))) return KLST_ENOMEM;
+  if (k > 0) {
+    if ((s = upload(d_sv, Sv)) != KLST_OK) return s;
+    launch_combine(st, Qb, k, n, d_sv, k, k, Xall, nullptr);
+  }
+  std::vector<cd> gram;
+  std::vector<double> nrm2;
+  if (mirror) {
+    HIPCHK(hipMemcpyAsync(d_mk, mk.data(), sizeof(int) * p.Nxi, hipMemcpyHostToDevice, st));
+    launch_mirror_conj(st, Xall, Mall, n, k, p.Nxi, d_mk);
+    for (int j = 0; j < k; ++j) dot(Mall, k, nullptr, 0, Xall + (size_t)j * n, d_gram + (size_t)j * (k + 1), 3);
+    std::vector<double2> hg((size_t)k * (k + 1));
+    const auto tw = std::chrono::steady_clock::now();
+    HIPCHK(hipMemcpyAsync(hg.data(), d_gram, sizeof(double2) * hg.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    t_wait += since(tw);
+    gram.assign((size_t)k * k, 0.0);
+    nrm2.assign(k, 0.0);
+    for (int j = 0; j < k; ++j) {
+      for (int i = 0; i < k; ++i) gram[(size_t)i * k + j] = cd(hg[(size_t)j * (k + 1) + i].x, hg[(size_t)j * (k + 1) + i].y);
+      nrm2[j] = hg[(size_t)j * (k + 1) + k].x;
     }
   }
-  std::vector<int> order(cand.size());
-  for (size_t i = 0; i < cand.size(); ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const double da = std::abs(cand[a].lam - sigma), db = std::abs(cand[b].lam - sigma);
-    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
-    return (cand[a].lam.imag() > 0) && !(cand[b].lam.imag() > 0);
-  });
-  const int nconv = std::min((int)cand.size(), nev);
-  // eigenvectors x_i = Q s_i of the locked pairs the selection draws on
-  std::vector<int> srcs, slot_of(std::max(1, k), -1);
-  for (int o2 = 0; o2 < nconv; ++o2) {
-    const int sidx = cand[order[o2]].src;
-    if (slot_of[sidx] < 0) { slot_of[sidx] = (int)srcs.size(); srcs.push_back(sidx); }
-  }
-  const int nsrc = (int)srcs.size();
-  std::vector<cd> lam(nconv), Cs((size_t)std::max(1, k) * std::max(1, nsrc), 0.0);
-  for (int o2 = 0; o2 < nconv; ++o2) lam[o2] = cand[order[o2]].lam;
-  for (int c2 = 0; c2 < nsrc; ++c2)
-    for (int q = 0; q < k; ++q) Cs[(size_t)q * nsrc + c2] = Sv[(size_t)q * k + srcs[c2]];
+  const std::vector<klst::OutputCandidate> sel =
+      klst::select_output(lam_all, mirror ? gram.data() : nullptr, mirror ? nrm2.data() : nullptr, sigma, nev);
+  const int nconv = (int)sel.size();
+  std::vector<cd> lam(nconv);
+  for (int o2 = 0; o2 < nconv; ++o2) lam[o2] = sel[o2].lam;
   std::vector<double> res(nconv, 0.0);
   if (nconv > 0) {
-    double2* Xd = ws.vec(std::max(nconv, nsrc));
+    double2* Xd = ws.vec(nconv);
     if (!Xd) return KLST_ENOMEM;
-    if ((s = upload(d_coef, Cs)) != KLST_OK) return s;
-    launch_combine(st, Qb, k, n, d_coef, nsrc, nsrc, Xd, nullptr);
-    std::vector<cd> hs((size_t)nsrc * n), hx((size_t)nconv * n);
-    HIPCHK(hipMemcpyAsync(hs.data(), Xd, sizeof(double2) * hs.size(), hipMemcpyDeviceToHost, st));
+    for (int o2 = 0; o2 < nconv; ++o2)
+      HIPCHK(hipMemcpyAsync(Xd + (size_t)o2 * n, (sel[o2].mirrored ? Mall : Xall) + (size_t)sel[o2].src * n,
+                            sizeof(double2) * n, hipMemcpyDeviceToDevice, st));
+    std::vector<cd> hx((size_t)nconv * n);
+    HIPCHK(hipMemcpyAsync(hx.data(), Xd, sizeof(double2) * hx.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    const int64_t nx = p.Nxi;
+    // unit 2-norm, largest entry real positive
     for (int o2 = 0; o2 < nconv; ++o2) {
-      const Cand& cd_ = cand[order[o2]];
-      const cd* xs = &hs[(size_t)slot_of[cd_.src] * n];
       cd* xi = &hx[(size_t)o2 * n];
-      if (!cd_.mirrored) {
-        std::copy(xs, xs + n, xi);
-      } else {
-        for (int64_t row = 0; row < n / nx; ++row)
-          for (int64_t kk = 0; kk < nx; ++kk) xi[row * nx + kk] = std::conj(xs[row * nx + mk[kk]]);
-      }
       double nrm = 0.0, big = -1.0;
       int64_t ib = 0;
       for (int64_t t = 0; t < n; ++t) {

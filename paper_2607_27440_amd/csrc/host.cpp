@@ -766,32 +766,38 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
   return true;
 }
 
+void structured_slots(const Problem& p, cd sigma, std::vector<int>& slot_node, std::vector<int>& slot_mate,
+                      std::vector<int>& slot_of, std::vector<int>& conj_of) {
+  const int Nxi = p.Nxi;
+  slot_node.clear();
+  slot_mate.clear();
+  slot_of.assign(Nxi, -1);
+  conj_of.assign(Nxi, 0);
+  // a node and its xi_y mirror share one inverse when sigma is real
+  std::map<std::pair<double, double>, int> where;
+  for (int k = 0; k < Nxi; ++k) where[{p.xi_x[k], p.xi_y[k]}] = k;
+  for (int k = 0; k < Nxi; ++k) {
+    if (slot_of[k] >= 0) continue;
+    int mate = -1;
+    if (sigma.imag() == 0.0 && p.xi_y[k] != 0.0) {
+      auto it = where.find({p.xi_x[k], -p.xi_y[k]});
+      if (it != where.end() && it->second != k && slot_of[it->second] < 0) mate = it->second;
+    }
+    slot_of[k] = (int)slot_node.size();
+    if (mate >= 0) { slot_of[mate] = slot_of[k]; conj_of[mate] = 1; }
+    slot_node.push_back(k);
+    slot_mate.push_back(mate);
+  }
+}
+
 std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads) {
   const int Ny = p.Ny, Nxi = p.Nxi, r = p.r, Rd = r * Ny;
   si.Ny = Ny;
   si.Nxi = Nxi;
   si.r = r;
   const size_t blk = (size_t)Ny * Ny;
-  // slots: a node and its xi_y mirror share one inverse when sigma is real
-  si.slot_node.clear();
-  si.slot_mate.clear();
-  std::vector<int> slot_of(Nxi, -1), conj_of(Nxi, 0);
-  {
-    std::map<std::pair<double, double>, int> where;
-    for (int k = 0; k < Nxi; ++k) where[{p.xi_x[k], p.xi_y[k]}] = k;
-    for (int k = 0; k < Nxi; ++k) {
-      if (slot_of[k] >= 0) continue;
-      int mate = -1;
-      if (sigma.imag() == 0.0 && p.xi_y[k] != 0.0) {
-        auto it = where.find({p.xi_x[k], -p.xi_y[k]});
-        if (it != where.end() && it->second != k && slot_of[it->second] < 0) mate = it->second;
-      }
-      slot_of[k] = (int)si.slot_node.size();
-      if (mate >= 0) { slot_of[mate] = slot_of[k]; conj_of[mate] = 1; }
-      si.slot_node.push_back(k);
-      si.slot_mate.push_back(mate);
-    }
-  }
+  std::vector<int> slot_of, conj_of;
+  structured_slots(p, sigma, si.slot_node, si.slot_mate, slot_of, conj_of);
   const int nslots = (int)si.slot_node.size();
   std::vector<cd> Prow((size_t)nslots * blk);   // row-major line inverses
   si.Pinv.assign((size_t)nslots * blk, cd(0.0));
@@ -924,6 +930,50 @@ bool invert(int m, const cd* A, cd* Ainv, int nthreads) {
     for (auto& x : th) x.join();
   }
   return true;
+}
+
+
+std::vector<OutputCandidate> select_output(const std::vector<cd>& lam, const cd* G, const double* nrm2, cd sigma,
+                                           int nev) {
+  const int k = (int)lam.size();
+  std::vector<OutputCandidate> cand;
+  for (int i = 0; i < k; ++i) cand.push_back({lam[i], i, false});
+  if (G && k > 0) {
+    auto align = [&](int i, int j) {
+      const double d = std::sqrt(nrm2[i] * nrm2[j]);
+      return d > 0 ? std::abs(G[(size_t)i * k + j]) / d : 0.0;
+    };
+    std::vector<int> partner(k, -1);
+    for (int i = 0; i < k; ++i)
+      if (align(i, i) >= 1.0 - kSelfAlign) partner[i] = i;
+    for (int i = 0; i < k; ++i) {
+      if (partner[i] >= 0) continue;
+      int best = -1;
+      double ba = 0.0;
+      for (int j = 0; j < k; ++j) {
+        if (j == i || partner[j] >= 0) continue;
+        const double a = align(i, j);
+        if (a > ba) { ba = a; best = j; }
+      }
+      if (best >= 0 && ba >= 1.0 - kPairAlign &&
+          std::abs(lam[best] - std::conj(lam[i])) <= kPairTol * std::abs(lam[i])) {
+        partner[i] = best;
+        partner[best] = i;
+      } else {
+        cand.push_back({std::conj(lam[i]), i, true});
+      }
+    }
+  }
+  std::vector<int> order(cand.size());
+  for (size_t i = 0; i < cand.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const double da = std::abs(cand[a].lam - sigma), db = std::abs(cand[b].lam - sigma);
+    if (std::abs(da - db) > 1e-12 * std::max(da, db)) return da < db;
+    return (cand[a].lam.imag() > 0) && !(cand[b].lam.imag() > 0);
+  });
+  std::vector<OutputCandidate> out;
+  for (int o = 0; o < (int)order.size() && o < nev; ++o) out.push_back(cand[order[o]]);
+  return out;
 }
 
 }  // namespace klst

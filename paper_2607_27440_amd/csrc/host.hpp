@@ -79,8 +79,35 @@ struct StructuredInverse {
   std::vector<cd> Pinv;   // [slots][Ny x Ny], column-major: entry (j, m) at m Ny + j
   std::vector<cd> Sinv;   // [(r Ny) x (r Ny)], row-major, index q = j r + a
 };
+// Slot assignment of the structured inverse: slot s stores node slot_node[s]
+// and, with sigma real, serves its xi_y mirror slot_mate[s] (-1: none) by
+// conjugation; slot_of[k] / conj_of[k] per node.
+void structured_slots(const Problem& p, cd sigma, std::vector<int>& slot_node, std::vector<int>& slot_mate,
+                      std::vector<int>& slot_of, std::vector<int>& conj_of);
 // Returns an empty string on success, else why (a singular line block or capacitance).
 std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads);
+
+// ---- returned eigenpairs of a Jacobi-Davidson solve ----
+struct OutputCandidate {
+  cd lam;
+  int src;         // locked pair whose eigenvector the candidate uses
+  bool mirrored;   // (conj(lambda_src), R conj(x_src)) rather than the pair itself
+};
+// Candidates for the returned set: every locked pair and, when G != nullptr (a
+// real target on a problem symmetric under the xi_y reflection R), the partner
+// (conj(lambda_i), R conj(x_i)) of each locked complex eigenvalue whose partner
+// was not locked.  G [k x k] row-major, G[i k + j] = <R conj(x_i), x_j>, and
+// nrm2[i] = ||x_i||^2.  Partnership is read from the eigenvectors: lambda_i is
+// real (its own partner) when |G_ii| >= (1 - kSelfAlign) ||x_i||^2, and locked
+// x_j is the partner of x_i when |G_ij| >= (1 - kPairAlign) ||x_i|| ||x_j|| and
+// |lambda_j - conj(lambda_i)| <= kPairTol |lambda_i| (one to one, best
+// alignment first).  Returns at most nev candidates ordered by |lambda - sigma|
+// (ties within 1e-12 relative: Im lambda > 0 first, then locking order).
+constexpr double kSelfAlign = 1e-10;
+constexpr double kPairAlign = 1e-6;
+constexpr double kPairTol = 1e-6;
+std::vector<OutputCandidate> select_output(const std::vector<cd>& lam, const cd* G, const double* nrm2, cd sigma,
+                                           int nev);
 
 // ---- small dense complex matrices, row-major m x m ----
 // Schur form G U = U T, T upper triangular, with the diagonal ordered by

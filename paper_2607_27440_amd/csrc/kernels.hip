@@ -882,6 +882,217 @@ __global__ void __launch_bounds__(256) k_capacitance(const cv<R>* __restrict__ m
   if (lane == 0) d[q] = mk<R>((R)dr, (R)di);
 }
 
+// ------------------------------------ structured inverse set-up (device) ----
+//
+// In-place inversion of one N x N complex matrix in global memory by one
+// workgroup: Gauss-Jordan elimination with partial (row) pivoting, the pivot
+// the entry of largest modulus in the column (the first on ties), the row
+// interchanges undone as column interchanges in reverse order at the end.
+// Column-major storage, (i, j) at j N + i; on a row-major matrix the same steps
+// invert the transpose, which is the row-major inverse.  The matrix stays in
+// the workgroup's caches; each step stages the scaled pivot row and the old
+// pivot column in LDS.  Returns false (uniformly) for an exactly singular matrix.
+// lds: [N] scaled pivot row, [N] pivot column, [N] pivot rows (int).
+__device__ bool gj_invert(double2* __restrict__ a, int N, double2* srow, double2* fcol, int* piv) {
+  __shared__ int s_p, s_sing;
+  const int NN = N * N;
+  for (int c = 0; c < N; ++c) {
+    if (threadIdx.x < 64) {
+      double best = -1.0;
+      int bi = N;
+      for (int i = c + (int)threadIdx.x; i < N; i += 64) {
+        const double2 v = a[(int64_t)c * N + i];
+        const double m = v.x * v.x + v.y * v.y;
+        if (m > best) { best = m; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (threadIdx.x == 0) {
+        s_p = bi;
+        piv[c] = bi;
+        s_sing = (best > 0.0) ? 0 : 1;
+      }
+    }
+    __syncthreads();
+    if (s_sing) return false;
+    const int p = s_p;
+    if (p != c) {
+      for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const double2 t = a[(int64_t)j * N + c];
+        a[(int64_t)j * N + c] = a[(int64_t)j * N + p];
+        a[(int64_t)j * N + p] = t;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < N; t += blockDim.x) {
+      srow[t] = a[(int64_t)t * N + c];
+      fcol[t] = a[(int64_t)c * N + t];
+    }
+    __syncthreads();
+    const double2 pv = srow[c];
+    const double pm = 1.0 / (pv.x * pv.x + pv.y * pv.y);
+    const double2 inv = make_double2(pv.x * pm, -pv.y * pm);
+    __syncthreads();
+    for (int t = threadIdx.x; t < N; t += blockDim.x) srow[t] = (t == c) ? inv : cmul(srow[t], inv);
+    __syncthreads();
+    for (int e = threadIdx.x; e < NN; e += blockDim.x) {
+      const int j = e / N, i = e - j * N;
+      double2 v;
+      if (i == c) {
+        v = srow[j];
+      } else {
+        const double2 f = fcol[i];
+        if (j == c) {
+          v = cmul(f, inv);
+          v.x = -v.x;
+          v.y = -v.y;
+        } else {
+          v = csub(a[e], cmul(f, srow[j]));
+        }
+      }
+      a[e] = v;
+    }
+    __syncthreads();
+  }
+  for (int c = N - 1; c >= 0; --c) {
+    const int p = piv[c];
+    if (p != c) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const double2 t = a[(int64_t)c * N + i];
+        a[(int64_t)c * N + i] = a[(int64_t)p * N + i];
+        a[(int64_t)p * N + i] = t;
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// The velocity-line block of slot sl, P_k = xi_x,k D_x + diag(nu_j + i beta
+// xi_y,k - sigma) with unit inflow rows (k = slot_node[sl]), written
+// column-major into the slot and inverted in place.  One workgroup per slot;
+// status[sl] = 1 for an exactly singular block, else 0.  Dx row-major.
+// Dynamic LDS: 2 Ny double2 + Ny int.
+__global__ void __launch_bounds__(256) k_line_blocks_invert(double2* __restrict__ Pinv, int Ny,
+                                                            const int* __restrict__ slot_node,
+                                                            const double* __restrict__ Dx,
+                                                            const double* __restrict__ xix,
+                                                            const double* __restrict__ xiy,
+                                                            const double* __restrict__ nu, double beta,
+                                                            double sre, double sim, int* __restrict__ status) {
+  extern __shared__ unsigned char lds_raw[];
+  double2* srow = reinterpret_cast<double2*>(lds_raw);
+  double2* fcol = srow + Ny;
+  int* piv = reinterpret_cast<int*>(fcol + Ny);
+  const int sl = blockIdx.x;
+  const int k = slot_node[sl];
+  double2* a = Pinv + (int64_t)sl * Ny * Ny;
+  const double xk = xix[k], by = beta * xiy[k];
+  for (int e = threadIdx.x; e < Ny * Ny; e += blockDim.x) {
+    const int j = e / Ny, i = e - j * Ny;
+    const bool bc = (i == Ny - 1 && xk > 0.0) || (i == 0 && xk < 0.0);
+    double2 v;
+    if (bc) {
+      v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    } else {
+      v = make_double2(xk * Dx[(int64_t)i * Ny + j], 0.0);
+      if (i == j) {
+        v.x += nu[i] - sre;
+        v.y += by - sim;
+      }
+    }
+    a[e] = v;
+  }
+  __syncthreads();
+  const bool ok = gj_invert(a, Ny, srow, fcol, piv);
+  if (threadIdx.x == 0) status[sl] = ok ? 0 : 1;
+}
+
+// Partial sums of the moment capacitance's coupling part
+//   G[(j, a), (j', b)] = sum_k P_k^{-1}(j, j') sum_f M_a(j, f, k) Ut_b(j', f, k)
+// (Ut = U with inflow rows zeroed) over the node range of part ks: grid (Ny [j'],
+// KS), one thread per row j; slot_of[k] / conj_of[k] give node k's stored
+// inverse (conjugated for a mirrored node).  part [KS][Rd][Rd], Rd = r Ny,
+// row-major over q = j r + a.
+__global__ void __launch_bounds__(128) k_cap_partial(const double2* __restrict__ Pinv, int Ny, int Nxi,
+                                                     int r, const int* __restrict__ slot_of,
+                                                     const int* __restrict__ conj_of,
+                                                     const double* __restrict__ M,
+                                                     const double* __restrict__ U,
+                                                     const double* __restrict__ xix,
+                                                     double2* __restrict__ part) {
+  const int jp = blockIdx.x, ks = blockIdx.y, KS = gridDim.y;
+  const int per = (Nxi + KS - 1) / KS;
+  const int k0 = ks * per, k1 = min(Nxi, k0 + per);
+  const int Rd = r * Ny;
+  for (int j = threadIdx.x; j < Ny; j += blockDim.x) {
+    double2 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int k = k0; k < k1; ++k) {
+      const double xk = xix[k];
+      if ((jp == Ny - 1 && xk > 0.0) || (jp == 0 && xk < 0.0)) continue;
+      double2 w = Pinv[((int64_t)slot_of[k] * Ny + jp) * Ny + j];
+      if (conj_of[k]) w.y = -w.y;
+      double g[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) g[a][b] = 0.0;
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        double ma[4], ub[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ma[a] = (a < r) ? M[(((int64_t)j * r + a) * 2 + f) * Nxi + k] : 0.0;
+          ub[a] = (a < r) ? U[(((int64_t)jp * 2 + f) * r + a) * Nxi + k] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) g[a][b] = fma(ma[a], ub[b], g[a][b]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x = fma(w.x, g[a][b], acc[a][b].x);
+          acc[a][b].y = fma(w.y, g[a][b], acc[a][b].y);
+        }
+    }
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b)
+        part[((int64_t)ks * Rd + j * r + a) * Rd + jp * r + b] = acc[a][b];
+  }
+}
+
+// S = I - sum over the KS parts (added in part order), row-major Rd x Rd.
+__global__ void __launch_bounds__(256) k_cap_finish(const double2* __restrict__ part, int KS, int Rd,
+                                                    double2* __restrict__ S) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t RR = (int64_t)Rd * Rd;
+  if (e >= RR) return;
+  double2 v = part[e];
+  for (int ks = 1; ks < KS; ++ks) v = cadd(v, part[(int64_t)ks * RR + e]);
+  const int q = (int)(e / Rd), qc = (int)(e - (int64_t)q * Rd);
+  S[e] = make_double2((q == qc ? 1.0 : 0.0) - v.x, -v.y);
+}
+
+// In-place inverse of the capacitance (one workgroup).  status[0] = 1 if singular.
+__global__ void __launch_bounds__(1024) k_invert_one(double2* __restrict__ S, int N, int* __restrict__ status) {
+  extern __shared__ unsigned char lds_raw[];
+  double2* srow = reinterpret_cast<double2*>(lds_raw);
+  double2* fcol = srow + N;
+  int* piv = reinterpret_cast<int*>(fcol + N);
+  const bool ok = gj_invert(S, N, srow, fcol, piv);
+  if (threadIdx.x == 0) status[0] = ok ? 0 : 1;
+}
+
 // ------------------------------------------------------- vector kernels ----
 
 // ---- two-phase deterministic reductions (no cross-workgroup synchronisation) ----
@@ -1144,6 +1355,20 @@ __global__ void k_axpby(const cv<R>* __restrict__ x, cv<R>* y, int64_t n, R are,
   cv<R> r = mk<R>(are * xv.x - aim * xv.y, are * xv.y + aim * xv.x);
   if (accum) r = cadd(r, y[t]);
   y[t] = r;
+}
+
+// out_v = R conj(x_v) for nvec vectors: entry (j, f, k) takes conj of entry
+// (j, f, mk[k]), mk the xi_y reflection of the velocity nodes.  grid (ceil(n /
+// 256), nvec).
+__global__ void k_mirror_conj(const double2* __restrict__ x, double2* __restrict__ out, int64_t n, int Nxi,
+                              const int* __restrict__ mk) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t v = blockIdx.y;
+  const int64_t row = t / Nxi;
+  const int k = (int)(t - row * Nxi);
+  const double2 a = x[v * n + row * Nxi + mk[k]];
+  out[v * n + t] = make_double2(a.x, -a.y);
 }
 
 // Precision conversion: y32 = (float) x64, or y64 (+)= (double) x32.
@@ -1572,11 +1797,12 @@ void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, i
   blockinv_t<float>(st, x, y, Ny, Nxi, nl, nblocks, Kinv, koff, skip);
 }
 
+// One pass y = P^{-1} (x + Ut d) over all stored line inverses (d == nullptr:
+// y = P^{-1} x).
 template <class R>
-static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r,
-                         const cv<R>* Pinv, const int* slot_node, const int* slot_mate, int nslots,
-                         const cv<R>* Sinv, const R* M, const R* U, const R* xix, cv<R>* mom, cv<R>* d,
-                         const int* skip) {
+static void line_pass_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r, const cv<R>* Pinv,
+                        const int* slot_node, const int* slot_mate, int nslots, const R* U, const R* xix,
+                        const cv<R>* dd, const int* skip) {
   const dim3 grid((Ny + 63) / 64, nslots);
   // slots that serve a mirrored node apply their inverse to 4 columns; the LDS
   // then holds 4 Ny inputs and 4 x NW x 64 partial sums, which caps NW at 8
@@ -1584,24 +1810,50 @@ static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int N
   int nw = gemv_waves((int64_t)grid.x * grid.y);
   if (cmax == 4 && nw > 8) nw = 8;
   const size_t lds = (size_t)(cmax * Ny + cmax * 64 * nw) * sizeof(cv<R>);
-  auto pass = [&](const cv<R>* dd) {
 #define KLST_LI(NW_, P_) hipLaunchKernelGGL((k_line_inverse<R, NW_, P_>), grid, dim3(64 * NW_), lds, st, x, y, Ny, \
                                             Nxi, r, Pinv, slot_node, slot_mate, cmax, U, xix, dd, skip)
-    if (cmax == 4) {
-      if (nw == 4) KLST_LI(4, true); else KLST_LI(8, true);
-    } else {
-      if (nw == 4) KLST_LI(4, false); else if (nw == 8) KLST_LI(8, false); else KLST_LI(16, false);
-    }
+  if (cmax == 4) {
+    if (nw == 4) KLST_LI(4, true); else KLST_LI(8, true);
+  } else {
+    if (nw == 4) KLST_LI(4, false); else if (nw == 8) KLST_LI(8, false); else KLST_LI(16, false);
+  }
 #undef KLST_LI
-  };
-  pass(nullptr);
+}
+
+template <class R>
+static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi, int r,
+                         const cv<R>* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                         const cv<R>* Sinv, const R* M, const R* U, const R* xix, cv<R>* mom, cv<R>* d,
+                         const int* skip) {
+  line_pass_t<R>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, U, xix, nullptr, skip);
   const int64_t n = 2LL * Ny * Nxi;
   moments_t<R>(st, y, n, 1, Ny, Nxi, r, M, mom, skip);
   const int Rd = r * Ny;
   const int S = moment_splits(Ny, 1, Nxi);
   hipLaunchKernelGGL((k_capacitance<R>), dim3((Rd + 3) / 4), dim3(256), (size_t)Rd * sizeof(cv<R>), st, mom,
                      Ny, r, S, Sinv, d, skip);
-  pass(d);
+  line_pass_t<R>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, U, xix, d, skip);
+}
+void launch_structured_setup(hipStream_t st, double2* Pinv, double2* Sinv, double2* part, int Ny, int Nxi, int r,
+                             const int* slot_node, int nslots, const int* slot_of, const int* conj_of,
+                             const double* Dx, const double* xix, const double* xiy, const double* nu,
+                             const double* U, const double* M, double beta, double sre, double sim,
+                             int* status) {
+  const size_t lds_line = (size_t)Ny * (2 * sizeof(double2) + sizeof(int));
+  hipLaunchKernelGGL(k_line_blocks_invert, dim3(nslots), dim3(256), lds_line, st, Pinv, Ny, slot_node, Dx, xix,
+                     xiy, nu, beta, sre, sim, status + 1);
+  const int Rd = r * Ny;
+  hipLaunchKernelGGL(k_cap_partial, dim3(Ny, kCapParts), dim3(128), 0, st, Pinv, Ny, Nxi, r, slot_of, conj_of, M,
+                     U, xix, part);
+  hipLaunchKernelGGL(k_cap_finish, dim3(nblk((int64_t)Rd * Rd, 256)), dim3(256), 0, st, part, kCapParts, Rd,
+                     Sinv);
+  const size_t lds_cap = (size_t)Rd * (2 * sizeof(double2) + sizeof(int));
+  hipLaunchKernelGGL(k_invert_one, dim3(1), dim3(1024), lds_cap, st, Sinv, Rd, status);
+}
+void launch_line_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
+                         const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                         const double* U, const double* xix) {
+  line_pass_t<double>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, U, xix, nullptr, nullptr);
 }
 void launch_structured_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
                                const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
@@ -1738,6 +1990,10 @@ void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double 
                      (float)aim, accum);
 }
 
+void launch_mirror_conj(hipStream_t st, const double2* x, double2* out, int64_t n, int nvec, int Nxi,
+                        const int* mk) {
+  hipLaunchKernelGGL(k_mirror_conj, dim3(nblk(n, 256), nvec), dim3(256), 0, st, x, out, n, Nxi, mk);
+}
 void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n) {
   hipLaunchKernelGGL(k_narrow, dim3(nblk(n, 256)), dim3(256), 0, st, x, y, n);
 }

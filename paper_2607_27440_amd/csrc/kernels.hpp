@@ -36,6 +36,26 @@ void launch_structured_inverse(hipStream_t st, const float2* x, float2* y, int N
                                const float2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
                                const float2* Sinv, const float* M, const float* U, const float* xix,
                                float2* mom, float2* d, const int* skip);
+// Device set-up of the structured inverse at shift sigma = (sre, sim): the line
+// blocks of the nslots stored slots built and inverted into Pinv [nslots][Ny x
+// Ny] (column-major), the capacitance S = I - M P^{-1} Ut assembled from
+// kCapParts partial sums (part: kCapParts (r Ny)^2 entries of scratch) and
+// inverted into Sinv [(r Ny)^2] (row-major).  slot_of / conj_of [Nxi]: node k's
+// slot and whether it is the slot's mirrored node.  Dx row-major.
+// status [1 + nslots]: status[0] = 1 for a singular capacitance, status[1 + s]
+// = 1 for a singular line block of slot s.  Needs 2 (r Ny) x 16 + (r Ny) x 4
+// bytes of LDS (r Ny <= 2048).
+constexpr int kCapParts = 4;
+void launch_structured_setup(hipStream_t st, double2* Pinv, double2* Sinv, double2* part, int Ny, int Nxi, int r,
+                             const int* slot_node, int nslots, const int* slot_of, const int* conj_of,
+                             const double* Dx, const double* xix, const double* xiy, const double* nu,
+                             const double* U, const double* M, double beta, double sre, double sim,
+                             int* status);
+// y = P^{-1} x: one pass of the structured inverse's line inverses alone (no
+// moment coupling), as above.
+void launch_line_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
+                         const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
+                         const double* U, const double* xix);
 void launch_blockinv_apply(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int nl,
                            int nblocks, const double2* Kinv, const int64_t* koff, const int* skip);
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -95,6 +115,10 @@ void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const
                         const int* skip);
 void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double are, double aim,
                   int accum);
+// out_v = R conj(x_v) for nvec vectors of length n: entry (j, f, k) is the
+// conjugate of entry (j, f, mk[k]) (mk: the xi_y reflection of the nodes).
+void launch_mirror_conj(hipStream_t st, const double2* x, double2* out, int64_t n, int nvec, int Nxi,
+                        const int* mk);
 // precision conversion of n complex entries: y32 = x64; y64 = x32 (+ y64 if accum)
 void launch_narrow(hipStream_t st, const double2* x, float2* y, int64_t n);
 void launch_widen(hipStream_t st, const float2* x, double2* y, int64_t n, int accum);

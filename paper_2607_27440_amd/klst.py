@@ -72,6 +72,11 @@ _sig = {
     "klst_apply": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_many": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_apply_csr": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_precond_apply_lines": (C.c_int, [_P, _P, _P]),
+    "klst_precond_export": (C.c_int, [_P, _D2, _D2, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "klst_host_structured_inverse": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
+                                               _D2, _D2, _D2, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "klst_export_csr": (C.c_int, [_P, _P, _P, _P, C.c_int]),
     "klst_precond_setup": (C.c_int, [_P, _D2]),
     "klst_precond_apply": (C.c_int, [_P, _P, _P]),
     "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
@@ -91,6 +96,8 @@ _sig = {
     "klst_host_tables": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
                                    _D2, _D2, _D2, _D2, C.POINTER(C.c_uint8)]),
     "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
+    "klst_host_select_output": (C.c_int, [C.c_int, _D2, _D2, _D2, _D2, C.c_int, _D2, C.POINTER(C.c_int),
+                                          C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "klst_perturbation_macros": (C.c_int, [_P, _P, C.c_int, _P, _P]),
     "klst_noneq_level": (C.c_int, [_P, _P]),
     "klst_bgk_relax": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Vel), C.c_double, C.c_double, _D2, _D2,
@@ -162,6 +169,55 @@ def host_tables(wl):
                 bc=bc.reshape(Ny, 2, Nxi).astype(bool))
 
 
+def host_structured_inverse(wl, sigma):
+    """The structured inverse built by the library's host code (no device
+    needed), in the layout of Context.precond_export."""
+    g, v, b, keep = _structs(wl)
+    ny = int(wl.Ny)
+    r = 4 if wl.Dv == 2 else 3
+    sg = np.array([complex(sigma).real, complex(sigma).imag])
+    ns = C.c_int()
+    st = _lib.klst_host_structured_inverse(C.byref(g), C.byref(v), C.byref(b), float(wl.beta), _dp(sg), None,
+                                           None, None, C.byref(ns))
+    if st != OK:
+        raise KlstError(st, "host structured inverse")
+    P = np.zeros(2 * ns.value * ny * ny)
+    S = np.zeros(2 * (r * ny) ** 2)
+    sn = np.zeros(ns.value, np.int32)
+    st = _lib.klst_host_structured_inverse(C.byref(g), C.byref(v), C.byref(b), float(wl.beta), _dp(sg), _dp(P),
+                                           _dp(S), sn.ctypes.data_as(C.POINTER(C.c_int)), C.byref(ns))
+    if st != OK:
+        raise KlstError(st, "host structured inverse")
+    Pc = P.view(np.complex128).reshape(ns.value, ny, ny).transpose(0, 2, 1)
+    return Pc, S.view(np.complex128).reshape(r * ny, r * ny), sn
+
+
+def host_select_output(lam, sigma, nev, G=None, nrm2=None):
+    """The library's choice of returned eigenpairs from locked pairs lam (with
+    overlaps G[i, j] = <R conj(x_i), x_j> and ||x_i||^2 = nrm2[i], or none):
+    (lam_out, src, mirrored)."""
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    k = len(lam)
+    la = lam.view(np.float64)
+    sg = np.array([complex(sigma).real, complex(sigma).imag])
+    gp = np2 = None
+    if G is not None:
+        gp = np.ascontiguousarray(G, dtype=np.complex128).view(np.float64).ravel()
+        np2 = np.ascontiguousarray(nrm2, dtype=np.float64)
+    out = np.zeros(2 * max(nev, 1))
+    src = np.zeros(max(nev, 1), np.int32)
+    mir = np.zeros(max(nev, 1), np.int32)
+    cnt = C.c_int()
+    st = _lib.klst_host_select_output(int(k), _dp(la), _dp(gp) if gp is not None else None,
+                                      _dp(np2) if np2 is not None else None, _dp(sg), int(nev), _dp(out),
+                                      src.ctypes.data_as(C.POINTER(C.c_int)),
+                                      mir.ctypes.data_as(C.POINTER(C.c_int)), C.byref(cnt))
+    if st != OK:
+        raise KlstError(st, "host select output")
+    c = cnt.value
+    return out.view(np.complex128)[:c].copy(), src[:c].copy(), mir[:c].astype(bool)
+
+
 def host_sorted_schur(G: np.ndarray):
     """(U, T) with G U = U T, |T_00| >= |T_11| >= ...  (library host routine)."""
     m = G.shape[0]
@@ -215,6 +271,7 @@ class Context:
         self._check(_lib.klst_dims(self._h, C.byref(n), C.byref(nnz), C.byref(nbc)), "klst_dims")
         self.n, self.nnz, self.n_bc = n.value, nnz.value, nbc.value
         self._ny = int(wl.Ny)
+        self._r = 4 if wl.Dv == 2 else 3
         return self
 
     @staticmethod
@@ -237,6 +294,35 @@ class Context:
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_many(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
                     "klst_apply_many")
+
+    def precond_apply_lines(self, x, y):
+        """y = P^{-1} x: one pass of the structured preconditioner's line inverses."""
+        self._check(_lib.klst_precond_apply_lines(self._h, self._ptr(x), self._ptr(y)),
+                    "klst_precond_apply_lines")
+
+    def precond_export(self):
+        """(Pinv [nslots, Ny, Ny] (row j, column m), Sinv [(r Ny), (r Ny)], slot_node [nslots])
+        of the structured inverse built on the device."""
+        ns = C.c_int()
+        self._check(_lib.klst_precond_export(self._h, None, None, None, C.byref(ns)), "klst_precond_export")
+        ny = self._ny
+        rd = self._r * ny
+        P = np.zeros(2 * ns.value * ny * ny)
+        S = np.zeros(2 * rd * rd)
+        sn = np.zeros(ns.value, np.int32)
+        self._check(_lib.klst_precond_export(self._h, _dp(P), _dp(S), sn.ctypes.data_as(C.POINTER(C.c_int)),
+                                             C.byref(ns)), "klst_precond_export")
+        Pc = P.view(np.complex128).reshape(ns.value, ny, ny).transpose(0, 2, 1)
+        return Pc, S.view(np.complex128).reshape(rd, rd), sn
+
+    def export_csr(self):
+        """(rowptr int64 [n+1], col int32 [nnz], val complex128 [nnz]) on the host."""
+        rp = np.zeros(self.n + 1, np.int64)
+        col = np.zeros(self.nnz, np.int32)
+        val = np.zeros(self.nnz, np.complex128)
+        self._check(_lib.klst_export_csr(self._h, C.c_void_p(rp.ctypes.data), C.c_void_p(col.ctypes.data),
+                                         C.c_void_p(val.ctypes.data), 0), "klst_export_csr")
+        return rp, col, val
 
     def apply_csr(self, tau, x, y):
         a, p = self._tau(tau)

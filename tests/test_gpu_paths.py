@@ -1,0 +1,186 @@
+"""GPU paths that earlier parity tests did not reach, through the C ABI against
+the oracle:
+
+  * block-Jacobi ILU(0), both application kernels, at Ny = 81, 96 and 144 (the
+    level-set sweeps with two and four rows per lane) and with enough blocks to
+    select the 8- and 4-wavefront block GEMVs, against the oracle's row-built
+    line-block ILU(0);
+  * the explicit CSR product at the full Mach 4 shape (0.84 B stored entries),
+    entry by entry against the oracle's structured product, and the exported
+    CSR matrix at config 2 against the oracle's assembled A;
+  * Jacobi-Davidson with the explicit CSR operator (op_mode 1) at config 2;
+  * eigenvectors against the oracle's (SURVEY rule c4): at config 1 within a
+    bound derived from the residuals and the second-smallest singular value of
+    A - lambda B, at config 2 within 10 e_i kappa_i.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2607_27440_amd import workloads as W
+from oracle import eig as E
+from oracle import jd as OJ
+from oracle import operator as O
+from oracle import parity as PAR
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+DEV = "cuda:0"
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _ctx(wl, **kw):
+    from paper_2607_27440_amd import klst
+    print(f"[case] {wl.name} n={wl.n} opts={kw}", flush=True)
+    return klst.Context(**kw).assemble(wl)
+
+
+def _shape(Ny, Qx, Qy, name):
+    return W.make_workload(name, mach=3.0, Ny=Ny, Qx=Qx, Qy=Qy, beta=0.5, sigma=0.05j, nev=4,
+                           base="bimodal", delta=3.0)
+
+
+# (Ny, Qx, Qy, lines per block): rows per lane in the level-set sweeps are
+# ceil(Ny / 64) (1, 2 or 4); block-GEMV wavefronts per workgroup are 16 below
+# 512 workgroups, 8 below 1024 and 4 above ((lines Ny / 64) tiles x blocks)
+BJ_CASES = [
+    (81, 4, 4, 1), (81, 4, 4, 2), (96, 4, 4, 3), (144, 4, 2, 1), (144, 2, 2, 2),
+    (96, 16, 8, 1),      # 2 tiles x 256 blocks = 512 workgroups: 8-wavefront GEMV
+    (96, 16, 16, 1),     # 2 tiles x 512 blocks = 1,024 workgroups: 4-wavefront GEMV
+]
+
+
+@pytest.mark.parametrize("pc_kernel", [0, 1])
+@pytest.mark.parametrize("Ny,Qx,Qy,lines", BJ_CASES)
+def test_block_jacobi_ilu0_at_larger_grids(Ny, Qx, Qy, lines, pc_kernel):
+    wl = _shape(Ny, Qx, Qy, f"bj_ny{Ny}_{Qx}x{Qy}")
+    P = O.Pencil(wl)
+    K = OJ.LineBlockILU0Rows(P, wl.sigma, lines)
+    b = W.random_vector(wl.n, 33) * P.bdiag
+    ctx = _ctx(wl, pc_kernel=pc_kernel, lines_per_block=lines)
+    ctx.precond_setup(wl.sigma)
+    bd = _dev(b)
+    yd = torch.empty_like(bd)
+    ctx.precond_apply(bd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = K.solve(b)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(f"relative difference {err:.2e}", flush=True)
+    assert err <= 1e-11, err
+
+
+def _abs_bound(P, x, tau):
+    wl = P.wl
+    ax = np.abs(x).reshape(P.Ny, 2, P.Nxi)
+    y = np.einsum("jm,mfk->jfk", np.abs(P.Dx), ax) * np.abs(wl.xi_x)[None, None, :]
+    y += np.abs(1j * wl.beta * wl.xi_y[None, None, :] + P.state["nu"][:, None, None] - tau) * ax
+    m = np.einsum("jafk,jfk->ja", np.abs(P.M), ax)
+    y += np.einsum("jfak,ja->jfk", np.abs(P.U), m)
+    y[P.bc] = ax[P.bc]
+    return y.ravel()
+
+
+def test_csr_product_at_the_mach4_shape():
+    """Every entry of the explicit CSR product at n = 281,088 (0.84 B stored
+    entries, rows of 3,023) within the dot-product bound of its row."""
+    wl = W.config3()
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 14)
+    tau = 0.2 - 0.1j
+    ctx = _ctx(wl)
+    assert ctx.nnz == O.nnz_formula(P.Ny, P.Nxi, int(P.bc.sum()))
+    xd = _dev(x)
+    yd = torch.empty_like(xd)
+    ctx.apply_csr(tau, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy()
+    ref = P.apply_structured(x, tau)
+    L = wl.Ny - 1 + 2 * wl.Nxi + 8
+    bound = 2 * L * U * _abs_bound(P, x, tau) + 1e-300
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+
+
+def test_exported_csr_equals_the_assembled_matrix():
+    wl = W.config2()
+    P = O.Pencil(wl)
+    ctx = _ctx(wl)
+    rp, col, val = ctx.export_csr()
+    A = P.A.tocsr()
+    A.sort_indices()
+    assert len(val) == ctx.nnz == A.nnz
+    assert np.array_equal(rp, A.indptr) and np.array_equal(col, A.indices)
+    # values: the coupling entries are r-term sums, the diagonal adds three terms
+    scale = np.abs(A.data) + np.max(np.abs(A.data)) * 1e-3
+    assert np.all(np.abs(val - A.data) <= 16 * U * scale)
+
+
+@pytest.fixture(scope="module")
+def c2_reference():
+    wl = W.config2()
+    P = O.Pencil(wl)
+    ref, X = E.si_nearest(P, wl.sigma, wl.nev + 10)
+    Y = E.left_vectors_si(P, ref, wl.sigma)
+    kap = E.condition_numbers(P, ref, X, Y)
+    normA = abs(P.A).sum(axis=0).max()
+    return wl, P, ref, X, kap, normA
+
+
+def test_jd_with_the_explicit_csr_operator(c2_reference):
+    wl, P, ref, X, kap, normA = c2_reference
+    ctx = _ctx(wl, op_mode=1, pc_kernel=1, lines_per_block=3, m_max=60, m_min=20, fix=0.1)
+    out = ctx.solve(wl.sigma, wl.nev)
+    print(out["stats"], flush=True)
+    assert out["nconv"] == wl.nev
+    assert np.all(E.residuals(P, out["lam"], out["X"]) <= 1e-10)
+    res, skipped = PAR.match(out["lam"], ref, kap, normA, sigma=wl.sigma, tol=1e-10)
+    assert not [r for r in res if not r["ok"]] and not skipped
+
+
+def test_eigenvectors_c1_within_the_residual_bound():
+    """x_gpu = a x + e with e orthogonal to the null vector x of A - lambda B, so
+    (A - lambda B) e = (A - lambda B) x_gpu and sin angle(x_gpu, x) <=
+    ||(A - lambda B) x_gpu|| / sigma_{n-1}(A - lambda B); with r the GPU residual,
+    ||(A - lambda B) x_gpu|| <= r |lambda_gpu| + |lambda_gpu - lambda| ||B||."""
+    wl = W.config1()
+    P = O.Pencil(wl)
+    lam_all, Xq, Yq, _ = E.qz_all(P)
+    ctx = _ctx(wl, pc_kernel=2, m_max=40)
+    out = ctx.solve(wl.sigma, wl.nev)
+    A, B = P.dense()
+    for i, lv in enumerate(out["lam"]):
+        j = int(np.argmin(np.abs(lam_all - lv)))
+        lr = lam_all[j]
+        x_ref = Xq[:, j] / np.linalg.norm(Xq[:, j])
+        x = out["X"][:, i]
+        s = sla.svdvals(A - lr * B)
+        gap = s[-2]
+        rnorm = out["resid"][i] * max(abs(lv), 1e-300) + abs(lv - lr)
+        cosang = abs(np.vdot(x_ref, x))
+        sinang = np.sqrt(max(0.0, 1.0 - cosang ** 2))
+        bound = 2.0 * rnorm / gap + 1e-12
+        print(f"pair {i}: sin angle {sinang:.2e}, bound {bound:.2e}", flush=True)
+        assert sinang <= bound, (i, sinang, bound)
+
+
+def test_eigenvectors_c2_rule_c4(c2_reference):
+    """1 - |x_gpu^H x_ref| <= 10 e_i kappa_i (both unit vectors) for the simple
+    eigenvalues of config 2, with e_i the relative eigenvalue error, floored at
+    the reference vectors' own accuracy."""
+    wl, P, ref, X, kap, normA = c2_reference
+    ctx = _ctx(wl, pc_kernel=2, m_max=60)
+    out = ctx.solve(wl.sigma, wl.nev)
+    res_ref = E.residuals(P, ref, X)
+    for i, lv in enumerate(out["lam"]):
+        j = int(np.argmin(np.abs(ref - lv)))
+        e = abs(lv - ref[j]) / abs(ref[j])
+        xr = X[:, j] / np.linalg.norm(X[:, j])
+        one_minus = 1.0 - abs(np.vdot(xr, out["X"][:, i]))
+        bound = 10 * kap[j] * max(e, res_ref[j], out["resid"][i])
+        print(f"pair {i}: 1 - |cos| {one_minus:.2e}, bound {bound:.2e}", flush=True)
+        assert one_minus <= bound, (i, one_minus, bound)
