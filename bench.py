@@ -124,6 +124,9 @@ VARIANTS = {
         # FP32 inner solves converge the outer iteration more slowly when restarts
         # keep 20 vectors (2,620 outer iterations against 891 keeping 6)
         "mixed_fp32_inner": dict(precision=1, m_max=80, m_min=6),
+        # three FP32 GMRES(20) sweeps per correction equation, each restarted from
+        # the FP64 residual of the correction equation (iterative refinement)
+        "mixed_fp32_inner_refined": dict(precision=1, inner_max_it=60),
         "shift_invert_exact": dict(method=1, m_max=120, max_it=100),
     },
 }
@@ -136,7 +139,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--variant-steps", type=int, default=2, help="timed steps per variant")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed"],
+                    help="single: fp64 by default; batched / served: mixed (FP32 inner solves) by default")
+    ap.add_argument("--no-tune", action="store_true", help="batched / served: skip the launch autotuner")
+    ap.add_argument("--tune-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "klst", "tune.txt"),
+                    help="batched / served: launch table file (read if present, else tuned and written)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
@@ -145,7 +152,9 @@ def parse():
     ap.add_argument("--bgk-steps", type=int, default=2000, help="bgk: RK4 steps timed")
     ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--count", type=int, default=64, help="batched: number of sweep solves")
-    ap.add_argument("--requests", type=int, default=80, help="served: number of requests")
+    ap.add_argument("--requests", type=int, default=1000, help="served: measured requests per rate")
+    ap.add_argument("--warm-requests", type=int, default=50, help="served: warm-up requests before them")
+    ap.add_argument("--rates", default="0.25,0.5,0.7,0.9", help="served: offered rates, fractions of saturation")
     ap.add_argument("--rate", type=float, default=0.0,
                     help="served: arrivals per second (0: 0.7 x the measured saturated rate)")
     ap.add_argument("--max-it", type=int, default=2000, help="batched/served: outer-iteration cap")
@@ -405,6 +414,35 @@ def run_bgk(a):
                    entries * K / el, a, el, K, "f64", cfg, extra)
 
 
+def tune_shapes(wls, opts, prec, cache, reps=10):
+    """Launch autotuning for every distinct (Ny, Nxi) of a set of solves: the FP64
+    operator and preconditioner, and the FP32 inner ones when prec = 1.  The
+    table is read from `cache` when that file exists, else tuned and written
+    there.  Returns the tuned entries (heuristic against tuned microseconds)."""
+    from paper_2607_27440_amd import klst
+    if cache and os.path.exists(cache):
+        klst.tune_clear()
+        klst.tune_load(cache)
+        return {"source": cache, "entries": None}
+    klst.tune_clear()
+    seen, entries = set(), []
+    for wl in wls:
+        if (wl.Ny, wl.Nxi) in seen:
+            continue
+        seen.add((wl.Ny, wl.Nxi))
+        with klst.Context(precision=prec, **opts) as ctx:
+            ctx.assemble(wl)
+            ctx.precond_setup(wl.sigma)
+            entries.append(ctx.autotune(nvec=1, precision=0, reps=reps))
+            if prec:
+                entries.append(ctx.autotune(nvec=1, precision=1, reps=reps))
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        klst.tune_save(cache)
+    return {"source": "tuned", "entries": [{k: (round(v, 2) if isinstance(v, float) else v)
+                                            for k, v in e.items()} for e in entries]}
+
+
 def run_batched(a):
     """Batched stability sweep: `count` independent solves (seeded sweep draws:
     Ny in {24..64}, Nxi in {16..128}, beta, Mach, base type), 8 eigenpairs
@@ -426,6 +464,10 @@ def run_batched(a):
         good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in res)
         return good, el, res, st
     prec = 0 if a.precision == "fp64" else 1
+    tune = None
+    if not a.no_tune:
+        tune = tune_shapes(wls, SWEEP_OPTS, prec, a.tune_cache)
+        log(f"[bench] launch table: {tune}")
     log(f"[bench] batched: {len(wls)} solves, serial plain FP64 baseline")
     g0, e0, _, _ = run(1, 0)
     log(f"[bench] baseline {g0} eigenpairs in {e0:.2f}s; now {a.slots} slots, {a.precision}")
@@ -448,6 +490,7 @@ def run_batched(a):
                                                  "unconverged_solves": int(sum(1 for r in res3
                                                                                if r["status"] != 0))},
                     "eigenpairs": g1, "seconds": round(e1, 3), "peak_running": st["peak_running"],
+                    "launch_table": tune,
                     "service_p50_s": round(float(np.percentile(lat, 50)), 4),
                     "unconverged_solves": int(sum(1 for r in res if r["status"] != 0))})
 
@@ -455,67 +498,89 @@ def run_batched(a):
 def run_served(a):
     """Served stability sweep: Poisson arrivals, 95% from the sweep distribution and
     5% at the config-2 shape (Ny = 64, Nxi = 96), 8 eigenpairs each, admitted by
-    HBM footprint into concurrent slots.  Baseline: the same trace served by one
-    plain FP64 solver in arrival order (service times measured, queueing replayed)."""
+    HBM footprint into concurrent slots.  The saturated rate is measured on a
+    closed batch first; the trace is then offered at each fraction of it in
+    `rates`, the first `warm_requests` of each run excluded from the statistics.
+    Baseline: the same trace served by one plain FP64 solver in arrival order
+    (service times measured once, queueing replayed for each rate)."""
     import numpy as np
     from paper_2607_27440_amd import klst, workloads
     rng = np.random.default_rng(5)
-    pool = workloads.sweep(seed=5, count=a.requests, nev=8)
+    total = a.requests + a.warm_requests
+    pool = workloads.sweep(seed=5, count=total, nev=8)
     c2 = workloads.config2()
     c2.nev = 8
-    reqs = [c2 if rng.uniform() < 0.05 else pool[i] for i in range(a.requests)]
-    # saturated throughput (requests/s) of the served configuration, from a short batch
-    rate = a.rate
+    reqs = [c2 if rng.uniform() < 0.05 else pool[i] for i in range(total)]
     prec = 0 if a.precision == "fp64" else 1
+    tune = None
+    if not a.no_tune:
+        tune = tune_shapes(reqs, SWEEP_OPTS, prec, a.tune_cache)
+    fracs = [float(v) for v in a.rates.split(",")]
+    per_rate = {}
     with klst.Server(slots=a.slots, precision=prec, max_it=a.max_it, **SWEEP_OPTS) as sv:
-        if rate <= 0:
-            cal = reqs[: min(16, len(reqs))]
-            t = time.perf_counter()
-            sv.solve_all(cal)
-            rate = 0.7 * len(cal) / (time.perf_counter() - t)
-        gaps = rng.exponential(1.0 / rate, size=len(reqs))
-        arrive = np.cumsum(gaps) - gaps[0]
-        log(f"[bench] served: {len(reqs)} requests at {rate:.3f}/s on {a.slots} slots")
-        tickets = []
-        t0 = time.perf_counter()
-        for wl, ta in zip(reqs, arrive):
-            dt = t0 + ta - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            tickets.append(sv.submit(wl))
-        res = []
-        for t in tickets:
-            sv.wait(t)
-            res.append(sv.fetch(t))
-        el = time.perf_counter() - t0
+        cal = reqs[: min(48, len(reqs))]
+        sv.solve_all(cal[:4])
+        t = time.perf_counter()
+        sv.solve_all(cal)
+        sat = len(cal) / (time.perf_counter() - t)
+        log(f"[bench] served: saturated {sat:.2f} requests/s on {a.slots} slots")
+        for frac in fracs:
+            rate = frac * sat if a.rate <= 0 else a.rate
+            gaps = np.random.default_rng(50).exponential(1.0 / rate, size=len(reqs))
+            arrive = np.cumsum(gaps) - gaps[0]
+            tickets = []
+            t0 = time.perf_counter()
+            for wl, ta in zip(reqs, arrive):
+                dt = t0 + ta - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                tickets.append(sv.submit(wl))
+            res = []
+            for tk in tickets:
+                sv.wait(tk)
+                res.append(sv.fetch(tk))
+            meas = res[a.warm_requests:]
+            lat = np.array([r["latency_s"] for r in meas])
+            t_first = arrive[a.warm_requests]
+            t_last = max(r["latency_s"] + ta for r, ta in zip(meas, arrive[a.warm_requests:]))
+            good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in meas)
+            per_rate[frac] = {"offered_per_s": round(rate, 3), "eigenpairs_per_s": round(good / (t_last - t_first), 3),
+                              "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                              "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                              "unconverged_requests": int(sum(1 for r in meas if r["status"] != 0)),
+                              "arrive": arrive}
+            log(f"[bench] served at {frac} x saturation: "
+                f"{ {k: v for k, v in per_rate[frac].items() if k != 'arrive'} }")
         st = sv.stats()
-    lat = np.array([r["latency_s"] for r in res])
-    good = sum(int(np.sum(r["resid"] <= RES_GATE)) for r in res)
     # baseline: plain FP64, one request at a time in arrival order
     with klst.Server(slots=1, precision=0, max_it=a.max_it, **SWEEP_OPTS) as sb:
-        serv, goodb = [], 0
+        serv, goodb = [], []
         for wl in reqs:
             r = sb.solve_all([wl])[0]
             serv.append(r["service_s"])
-            goodb += int(np.sum(r["resid"] <= RES_GATE))
-    done, lat_b = 0.0, []
-    for ta, sv_s in zip(arrive, serv):
-        start = max(ta, done)
-        done = start + sv_s
-        lat_b.append(done - ta)
-    lat_b = np.array(lat_b)
-    cfg = {"workload": f"served_poisson_seed5_{len(reqs)}req_95pct_sweep_5pct_ny64_nxi96_nev8",
-           "slots": a.slots, "rate_per_s": round(rate, 4), "precision": a.precision, "max_it": a.max_it,
-           **SWEEP_OPTS}
-    return _common("eigenpairs/s at rel. residual <= 1e-10 (served sweep)", "eigenpairs/s", good / el, a,
-                   el, len(reqs), "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
-                   {"p50_latency_s": round(float(np.percentile(lat, 50)), 4),
-                    "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-                    "eigenpairs": good, "seconds": round(el, 3), "peak_running": st["peak_running"],
-                    "unconverged_requests": int(sum(1 for r in res if r["status"] != 0)),
-                    "serial_plain_fp64": {"value": round(goodb / max(done, 1e-9), 4),
-                                          "p50_latency_s": round(float(np.percentile(lat_b, 50)), 4),
-                                          "p99_latency_s": round(float(np.percentile(lat_b, 99)), 4)}})
+            goodb.append(int(np.sum(r["resid"] <= RES_GATE)))
+    for frac, d in per_rate.items():
+        arrive = d.pop("arrive")
+        done, lat_b = 0.0, []
+        for ta, sv_s in zip(arrive, serv):
+            start = max(ta, done)
+            done = start + sv_s
+            lat_b.append(done - ta)
+        lat_b = np.array(lat_b[a.warm_requests:])
+        t_last = max(l + ta for l, ta in zip(lat_b, arrive[a.warm_requests:]))
+        d["serial_plain_fp64"] = {
+            "eigenpairs_per_s": round(sum(goodb[a.warm_requests:]) / (t_last - arrive[a.warm_requests]), 3),
+            "p50_latency_s": round(float(np.percentile(lat_b, 50)), 4),
+            "p99_latency_s": round(float(np.percentile(lat_b, 99)), 4)}
+    main = per_rate.get(0.7, per_rate[fracs[0]])
+    cfg = {"workload": f"served_poisson_seed5_{a.requests}req_after_{a.warm_requests}_95pct_sweep_5pct_ny64_nxi96_nev8",
+           "slots": a.slots, "rate_fraction": 0.7 if 0.7 in per_rate else fracs[0],
+           "saturated_requests_per_s": round(sat, 3), "precision": a.precision, "max_it": a.max_it, **SWEEP_OPTS}
+    return _common("eigenpairs/s at rel. residual <= 1e-10 (served sweep)", "eigenpairs/s",
+                   main["eigenpairs_per_s"], a, 0.0, a.requests, "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
+                   {"p50_latency_s": main["p50_latency_s"], "p99_latency_s": main["p99_latency_s"],
+                    "by_rate_fraction": {str(k): v for k, v in per_rate.items()},
+                    "peak_running": st["peak_running"], "launch_table": tune})
 
 
 def run_profile(a):
@@ -532,6 +597,15 @@ def run_profile(a):
     out = {"mode": "profile", "workload": wl.name, "options": opts}
     with klst.Context(stream=st.cuda_stream, **opts) as ctx:
         ctx.assemble(wl)
+        # preconditioner set-up at alternating real targets (each call rebuilds)
+        tset = []
+        for i in range(5):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.precond_setup(complex(wl.sigma) + (1e-3 if i % 2 else 0.0))
+            torch.cuda.synchronize()
+            tset.append(time.perf_counter() - t)
+        out["precond_setup_ms"] = [round(1e3 * v, 2) for v in tset]
         ctx.precond_setup(wl.sigma)
         if ctx.options.pc_kernel == 2:
             out["line_inverse"] = line_inverse_roofline(ctx, wl, torch, a.kernel_reps, a.workload)
@@ -566,6 +640,8 @@ def run_profile(a):
 
 def main():
     a = parse()
+    if a.precision is None:
+        a.precision = "fp64" if a.mode in ("single", "profile", "bgk") else "mixed"
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

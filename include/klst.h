@@ -250,6 +250,44 @@ klst_status klst_solve(klst_ctx* ctx, const double sigma[2], int nev, double* la
 klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma[2], int nev, double* lambda,
                                     void* X, int X_on_device, double* resid, int* nconv);
 
+/* ---------------------------------------------------------------------------
+ * Launch autotuning.  The library keeps a process-wide table of launch choices
+ * keyed by (Ny, Nxi, nvec, precision): row tiles and wavefronts of the
+ * matrix-core operator (apply_tile, apply_waves; for FP32, rows per thread in
+ * apply_tile), column parts of the moment sums (moment_splits) and wavefronts
+ * of the block GEMVs of the preconditioners (gemv_waves); 0 = the built-in
+ * heuristic.  Tile and wave choices leave results bit-identical; moment splits
+ * and GEMV waves change the order of summation, so the table must be fixed
+ * before the solves it serves (solves that run under one table give the same
+ * results alone and together).  Moment splits and GEMV waves are per shape
+ * (read from the nvec = 1 entry for every batch size).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int Ny, Nxi, nvec, precision;                                 /* key                   */
+  int apply_tile, apply_waves, moment_splits, gemv_waves;       /* chosen (0: heuristic) */
+  double us_default, us_tuned;   /* operator (+ preconditioner when set up, nvec = 1)
+                                    microseconds per application, heuristic and tuned */
+} klst_tune_entry;
+
+/* Time the candidate launch choices on ctx's assembled problem (nvec vectors;
+ * precision 0 = FP64 operator and preconditioner, 1 = the FP32 inner ones of a
+ * mixed-precision context, nvec = 1), reps applications per candidate, on the
+ * context's stream: operator tiling first, then (nvec = 1) the moment splits of
+ * operator + preconditioner together, then the preconditioner's GEMV waves when
+ * klst_precond_setup has run.  Installs the fastest in the table and reports it
+ * in *out (may be NULL).  Allocates 2 nvec + 1 vectors of scratch.  Errors:
+ * ESTATE (no problem), EINVAL, ENOMEM. */
+klst_status klst_autotune(klst_ctx* ctx, int nvec, int precision, int reps, klst_tune_entry* out);
+
+/* Write / read the launch table as text (one entry per line: Ny Nxi nvec
+ * precision apply_tile apply_waves moment_splits gemv_waves; '#' comments).
+ * Loading adds to or replaces entries of the current table.  Errors: EINVAL
+ * (unreadable file or malformed line; entries before it are loaded). */
+klst_status klst_tune_save(const char* path);
+klst_status klst_tune_load(const char* path);
+/* Empty the launch table (every launch back to the built-in heuristic). */
+void        klst_tune_clear(void);
+
 /* Statistics of the last solve. */
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out);
 
@@ -390,6 +428,21 @@ klst_status klst_host_tables(const klst_grid* grid, const klst_vel* vel, const k
 klst_status klst_host_select_output(int k, const double* lam, const double* G, const double* nrm2,
                                     const double sigma[2], int nev, double* out_lam, int* out_src,
                                     int* out_mirrored, int* nout);
+
+/* Host-only: continuum structure of a normal shock by the Gilbarg-Paolucci
+ * equations (Sec. 2.1, eq. GB1DShockeqn): steady 1-D Navier-Stokes for a gas of
+ * specific-heat ratio gamma, Prandtl number Pr (the paper sets 1 for its
+ * comparisons with BGK) and viscosity mu ~ T^s_visc, upstream Mach number
+ * mach > 1, lengths in upstream mean free paths
+ * l_inf = (16/delta) mu_inf / (rho_inf sqrt(2 pi R T_inf)) (delta = 5: hard
+ * spheres).  At the nz positions z (host, in l_inf, measured from the point of
+ * steepest velocity gradient, positive downstream) it writes rho / rho_inf,
+ * u / u_inf and T / T_inf (host arrays of nz), and *thickness (may be NULL)
+ * receives Delta / l_inf of eq. ShockThickness.  Beyond the traced range the
+ * end states are returned.  Errors: EINVAL (mach <= 1, gamma <= 1, Pr <= 0,
+ * delta <= 0, non-finite input, null arrays with nz > 0). */
+klst_status klst_gp_shock(double mach, double gamma, double Pr, double s_visc, double delta, int nz,
+                          const double* z, double* rho, double* u, double* T, double* thickness);
 
 /* Host-only: sorted complex Schur form of a small m x m complex matrix G
  * (row-major interleaved), G U = U T with |T_00| >= |T_11| >= ...; used by the

@@ -158,3 +158,24 @@ def residuals(P, lam, X):
     nx = np.linalg.norm(X, axis=0)
     den = np.where(np.abs(lam) < 1e-6, 1.0, np.abs(lam)) * nx
     return nr / den
+
+
+def refine_two_sided(P, X, Y):
+    """Two-sided Rayleigh quotients lambda = (y^H A x) / (y^H B x) of right and
+    left eigenvector approximations (columns of X and Y), with A x formed and
+    both inner products accumulated in extended precision.  If x and y carry
+    errors e_x and e_y, y^H (A - lambda B) x = e_y^H (A - lambda B) e_x, so the
+    quotient's error is second order in the vector errors, and the extended
+    arithmetic keeps the rounding of the quotient itself well below FP64's."""
+    from .operator import apply_structured_extended
+    cld = np.clongdouble
+    out = np.empty(X.shape[1], complex)
+    Bd = P.bdiag.astype(np.longdouble)
+    for i in range(X.shape[1]):
+        x = X[:, i]
+        y = Y[:, i].astype(cld)
+        ax = apply_structured_extended(P, x)
+        num = np.sum(np.conj(y) * ax)
+        den = np.sum(np.conj(y) * (Bd * x.astype(cld)))
+        out[i] = complex(num / den)
+    return out

@@ -17,6 +17,7 @@
 #include <mutex>
 #include <unordered_map>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <thread>
@@ -557,6 +558,15 @@ klst_status klst_host_select_output(int k, const double* lam, const double* G, c
   return KLST_OK;
 }
 
+klst_status klst_gp_shock(double mach, double gamma, double Pr, double s_visc, double delta, int nz,
+                          const double* z, double* rho, double* u, double* T, double* thickness) {
+  if (nz < 0 || (nz > 0 && (!z || !rho || !u || !T))) return KLST_EINVAL;
+  for (int i = 0; i < nz; ++i)
+    if (!std::isfinite(z[i])) return KLST_EINVAL;
+  return klst::gp_shock(mach, gamma, Pr, s_visc, delta, nz, z, rho, u, T, thickness).empty() ? KLST_OK
+                                                                                               : KLST_EINVAL;
+}
+
 klst_status klst_host_sorted_schur(int m, const double* G, double* U, double* T) {
   if (m < 1 || !G || !U || !T) return KLST_EINVAL;
   std::vector<cd> g(m * m), u(m * m), t(m * m);
@@ -733,6 +743,147 @@ klst_status klst_export_csr(klst_ctx* ctx, void* rowptr, void* col, void* val, i
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return KLST_OK;
 }
+
+klst_status klst_autotune(klst_ctx* ctx, int nvec, int precision, int reps, klst_tune_entry* out) {
+  using klst::dev::Tuning;
+  if (!ctx || nvec < 1 || nvec > 4096 || (precision != 0 && precision != 1) || reps < 1) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_autotune before klst_assemble");
+  if (precision == 1 && (ctx->opt.precision != 1 || nvec != 1))
+    return fail(ctx, KLST_EINVAL, "FP32 tuning needs a mixed-precision context and nvec = 1");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  const klst::Problem& p = ctx->prob;
+  const int64_t n = p.n();
+  const int Ny = p.Ny, Nxi = p.Nxi, nc = 2 * Nxi;
+  hipStream_t st = ctx->stream;
+  const bool with_pc = (nvec == 1) && ctx->pc_ready && (ctx->pc_kernel_built == 1 || ctx->pc_kernel_built == 2);
+  void *x = nullptr, *y = nullptr, *z = nullptr;
+  const size_t esz = precision ? sizeof(float2) : sizeof(double2);
+  klst_status s;
+  if ((s = dalloc(ctx, &x, esz * n * nvec)) != KLST_OK) return s;
+  if ((s = dalloc(ctx, &y, esz * n * nvec)) != KLST_OK) { dfree(ctx, x); return s; }
+  if ((s = dalloc(ctx, &z, esz * n)) != KLST_OK) { dfree(ctx, x); dfree(ctx, y); return s; }
+  HIPCHK(hipMemsetAsync(x, 0, esz * n * nvec, st));
+  if ((s = ensure_mom(ctx, nvec)) != KLST_OK) return s;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  // average time of one operator (+ preconditioner) application, microseconds
+  auto time_it = [&](bool op, bool pc) -> double {
+    auto once = [&]() {
+      if (op) {
+        if (precision) (void)op_v(ctx, 0.1, (const float2*)x, (float2*)y, nullptr);
+        else (void)op_apply(ctx, 0.1, (const double2*)x, (double2*)y, nvec, 0, nullptr);
+      }
+      if (pc) {
+        if (precision) (void)pc_v(ctx, (const float2*)x, (float2*)z, nullptr);
+        else (void)pc_apply(ctx, (const double2*)x, (double2*)z, nullptr);
+      }
+    };
+    for (int w = 0; w < 2; ++w) once();
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps; ++i) once();
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return 1e3 * ms / reps;
+  };
+  const int key_nv = nvec;
+  klst::dev::tune_erase(Ny, Nxi, key_nv, precision);
+  Tuning base;
+  const bool had_shape = (nvec > 1) && klst::dev::tune_get(Ny, Nxi, 1, precision, &base);
+  (void)had_shape;
+  const double t_default = time_it(true, with_pc);
+  Tuning best;
+  double tbest = 1e300;
+  // operator tiling (result-invariant)
+  std::vector<std::pair<int, int>> tiles;
+  if (precision) tiles = {{4, 0}, {8, 0}, {16, 0}};
+  else
+    for (int rt : {1, 2, 3, 6})
+      if ((rt - 1) * 16 < Ny)
+        for (int nw : {1, 4}) tiles.push_back({rt, nw});
+  for (auto [rt, nw] : tiles) {
+    Tuning t;
+    t.apply_rt = rt;
+    t.apply_nw = nw;
+    klst::dev::tune_set(Ny, Nxi, key_nv, precision, t);
+    const double tt = time_it(true, false);
+    if (tt < tbest) { tbest = tt; best = t; }
+  }
+  if (nvec == 1) {
+    // column splits of the moment sums (operator and preconditioner share them)
+    double tb2 = 1e300;
+    for (int ms : {1, 2, 3, 4, 5, 6, 8}) {
+      if (ms > 1 && nc / ms < 64) continue;
+      Tuning t = best;
+      t.msplit = ms;
+      klst::dev::tune_set(Ny, Nxi, 1, precision, t);
+      const double tt = time_it(true, with_pc);
+      if (tt < tb2) { tb2 = tt; best.msplit = ms; }
+    }
+    if (with_pc) {
+      double tb3 = 1e300;
+      for (int g : {4, 8, 16}) {
+        Tuning t = best;
+        t.gemv = g;
+        klst::dev::tune_set(Ny, Nxi, 1, precision, t);
+        const double tt = time_it(false, true);
+        if (tt < tb3) { tb3 = tt; best.gemv = g; }
+      }
+    }
+  }
+  klst::dev::tune_set(Ny, Nxi, key_nv, precision, best);
+  const double t_tuned = time_it(true, with_pc);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipStreamSynchronize(st));
+  dfree(ctx, x);
+  dfree(ctx, y);
+  dfree(ctx, z);
+  if (out) {
+    out->Ny = Ny; out->Nxi = Nxi; out->nvec = nvec; out->precision = precision;
+    out->apply_tile = best.apply_rt; out->apply_waves = best.apply_nw;
+    out->moment_splits = best.msplit; out->gemv_waves = best.gemv;
+    out->us_default = t_default; out->us_tuned = t_tuned;
+  }
+  return KLST_OK;
+}
+
+klst_status klst_tune_save(const char* path) {
+  if (!path) return KLST_EINVAL;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return KLST_EINVAL;
+  std::fprintf(f, "# klst launch table: Ny Nxi nvec precision apply_tile apply_waves moment_splits gemv_waves\n");
+  for (const auto& [k, t] : klst::dev::tune_all())
+    std::fprintf(f, "%d %d %d %d %d %d %d %d\n", k[0], k[1], k[2], k[3], t.apply_rt, t.apply_nw, t.msplit, t.gemv);
+  std::fclose(f);
+  return KLST_OK;
+}
+
+klst_status klst_tune_load(const char* path) {
+  if (!path) return KLST_EINVAL;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return KLST_EINVAL;
+  char line[512];
+  klst_status st = KLST_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int v[8];
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6], &v[7]) != 8 ||
+        v[0] < 3 || v[1] < 1 || v[2] < 1 || (v[3] != 0 && v[3] != 1)) {
+      st = KLST_EINVAL;
+      break;
+    }
+    klst::dev::Tuning t;
+    t.apply_rt = v[4]; t.apply_nw = v[5]; t.msplit = v[6]; t.gemv = v[7];
+    klst::dev::tune_set(v[0], v[1], v[2], v[3], t);
+  }
+  std::fclose(f);
+  return st;
+}
+
+void klst_tune_clear(void) { klst::dev::tune_clear(); }
 
 klst_status klst_get_stats(const klst_ctx* ctx, klst_stats* out) {
   if (!ctx || !out) return KLST_EINVAL;

@@ -976,4 +976,142 @@ std::vector<OutputCandidate> select_output(const std::vector<cd>& lam, const cd*
   return out;
 }
 
+
+// Gilbarg-Paolucci structure.  Normalised velocity W = m u / P and temperature
+// th = m^2 R T / P^2 (m, P the mass and momentum fluxes), shock strength
+// alpha = 2 E m^2 / P^2 - 1 (E the total enthalpy), g = (gamma - 1) / 2:
+//   (4/3) mu_h dW/dz = W + th/W - 1,   (gamma mu_h / Pr) dth/dz = th - g((1 - W)^2 + alpha),
+// mu_h = mu_h_inf (th / th_inf)^s, mu_h_inf = (delta / 16) sqrt(2 pi / gamma) / M.
+// The shock is the separatrix of the downstream saddle.  It is traced in the
+// phase plane th(W) by classical RK4 from the saddle (along its falling
+// eigendirection) to the upstream node; z(W) then follows from the scalar ODE
+// dW/dz on that curve, integrated by RK4 from the steepest point outward (on the
+// curve the ODE is one-dimensional, so both directions are stable).
+std::string gp_shock(double mach, double gamma, double Pr, double s_visc, double delta, int nz, const double* z,
+                     double* rho, double* u, double* T, double* thickness) {
+  if (!(mach > 1.0) || !(gamma > 1.0) || !(Pr > 0.0) || !(delta > 0.0) || !std::isfinite(mach) ||
+      !std::isfinite(s_visc) || nz < 0)
+    return "gp_shock: need mach > 1, gamma > 1, Pr > 0, delta > 0";
+  const double g = 0.5 * (gamma - 1.0);
+  const double u0 = mach * std::sqrt(gamma);            // rho_inf = 1, R T_inf = 1
+  const double m = u0, P = 1.0 + u0 * u0, E = gamma / (gamma - 1.0) + 0.5 * u0 * u0;
+  const double alpha = 2.0 * E * m * m / (P * P) - 1.0;
+  const double Wi = m * u0 / P, ti = m * m / (P * P);
+  // both zeros of the right-hand sides solve (1 + g) W^2 - (1 + 2 g) W + g (1 + alpha) = 0
+  const double qa = 1.0 + g, qb = -(1.0 + 2.0 * g), qc = g * (1.0 + alpha);
+  const double disc = std::sqrt(std::max(0.0, qb * qb - 4.0 * qa * qc));
+  const double r1 = (-qb - disc) / (2.0 * qa), r2 = (-qb + disc) / (2.0 * qa);
+  const double W1 = (std::abs(r1 - Wi) > std::abs(r2 - Wi)) ? r1 : r2;
+  const double t1 = W1 * (1.0 - W1);
+  const double muinf = (delta / 16.0) * std::sqrt(2.0 * M_PI / gamma) / mach;
+  const double c = 4.0 * Pr / (3.0 * gamma);
+  auto mu_h = [&](double th) { return muinf * std::pow(th / ti, s_visc); };
+  auto Fth = [&](double W, double th) { return th - g * ((1.0 - W) * (1.0 - W) + alpha); };
+  auto slope = [&](double W, double th) { return c * W * Fth(W, th) / (W * W - W + th); };
+  auto dWdz = [&](double W, double th) { return (W + th / W - 1.0) / (4.0 / 3.0 * mu_h(th)); };
+  // falling eigendirection at the saddle: k^2 + (2 W1 - 1 - c W1) k - 2 c g W1 (1 - W1) = 0
+  const double B = 2.0 * W1 - 1.0 - c * W1, C = -2.0 * c * g * W1 * (1.0 - W1);
+  const double k = 0.5 * (-B - std::sqrt(B * B - 4.0 * C));
+  const double span = Wi - W1;
+  // the curve is traced in t with W = W1 + span (1 + tanh t) / 2, whose steps
+  // shrink geometrically toward both singular end points (RK4 stages then stay
+  // close to the curve, where dth/dW is smooth)
+  const int N = 1 << 16;
+  const double ta = std::atanh(2.0 * 1e-9 - 1.0), tb = std::atanh(1.0 - 2.0 * 1e-10);
+  const double dt = (tb - ta) / N;
+  auto Wof = [&](double t) { return W1 + span * 0.5 * (1.0 + std::tanh(t)); };
+  auto dWdt = [&](double t) { const double th_ = std::tanh(t); return span * 0.5 * (1.0 - th_ * th_); };
+  std::vector<double> Ws(N + 1), ts(N + 1), ds(N + 1);
+  Ws[0] = Wof(ta);
+  ts[0] = t1 + k * (Ws[0] - W1);
+  for (int i = 0; i < N; ++i) {
+    const double t0 = ta + i * dt, th0 = ts[i];
+    auto F = [&](double tt, double th_) { return slope(Wof(tt), th_) * dWdt(tt); };
+    const double k1 = F(t0, th0), k2 = F(t0 + 0.5 * dt, th0 + 0.5 * dt * k1);
+    const double k3 = F(t0 + 0.5 * dt, th0 + 0.5 * dt * k2), k4 = F(t0 + dt, th0 + dt * k3);
+    Ws[i + 1] = Wof(t0 + dt);
+    ts[i + 1] = th0 + dt * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+  }
+  for (int i = 0; i <= N; ++i) ds[i] = slope(Ws[i], ts[i]);
+  const double Wa = Ws[0], Wb = Ws[N];
+  // th(W) on the curve: cubic Hermite interpolation with the ODE's own slopes
+  auto theta = [&](double W) {
+    int i = (int)(std::upper_bound(Ws.begin(), Ws.end(), W) - Ws.begin()) - 1;
+    i = std::max(0, std::min(N - 1, i));
+    const double h = Ws[i + 1] - Ws[i];
+    const double tq = (W - Ws[i]) / h;
+    const double h00 = (1 + 2 * tq) * (1 - tq) * (1 - tq), h10 = tq * (1 - tq) * (1 - tq);
+    const double h01 = tq * tq * (3 - 2 * tq), h11 = tq * tq * (tq - 1);
+    return h00 * ts[i] + h10 * h * ds[i] + h01 * ts[i + 1] + h11 * h * ds[i + 1];
+  };
+  // steepest point: largest |dW/dz| on the samples, refined by golden section
+  int ib = 0;
+  double best = -1.0;
+  for (int i = 0; i <= N; ++i) {
+    const double v = std::abs(dWdz(Ws[i], ts[i]));
+    if (v > best) { best = v; ib = i; }
+  }
+  double lo = Ws[std::max(0, ib - 1)], hi = Ws[std::min(N, ib + 1)];
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  auto f = [&](double W) { return -std::abs(dWdz(W, theta(W))); };
+  double xa = hi - gr * (hi - lo), xb = lo + gr * (hi - lo), fa = f(xa), fb = f(xb);
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * span; ++it) {
+    if (fa < fb) { hi = xb; xb = xa; fb = fa; xa = hi - gr * (hi - lo); fa = f(xa); }
+    else { lo = xa; xa = xb; fa = fb; xb = lo + gr * (hi - lo); fb = f(xb); }
+  }
+  const double Wstar = 0.5 * (lo + hi);
+  const double maxs = -f(Wstar);
+  const double Delta = span / maxs;
+  if (thickness) *thickness = Delta;
+  if (nz == 0) return std::string();
+  // z(W): RK4 on dW/dz along the curve from the steepest point, outward on each side
+  auto rhs = [&](double W) {
+    const double Wc = std::min(std::max(W, Wa), Wb);
+    return dWdz(Wc, theta(Wc));
+  };
+  std::vector<int> ord(nz);
+  for (int i = 0; i < nz; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return z[a] < z[b]; });
+  const double hz = Delta / 4000.0;
+  auto march = [&](double W, double z0, double z1) {
+    const int steps = std::max(1, (int)std::ceil(std::abs(z1 - z0) / hz));
+    const double dz = (z1 - z0) / steps;
+    for (int s = 0; s < steps; ++s) {
+      const double k1 = rhs(W), k2 = rhs(W + 0.5 * dz * k1), k3 = rhs(W + 0.5 * dz * k2), k4 = rhs(W + dz * k3);
+      W += dz * (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0;
+    }
+    return W;
+  };
+  auto put = [&](int idx, double W) {
+    const double Wc = std::min(std::max(W, Wa), Wb);
+    const double th = theta(Wc);
+    u[idx] = Wc / Wi;
+    rho[idx] = Wi / Wc;
+    T[idx] = th / ti;
+  };
+  // downstream side (z >= 0, W falls toward W1), nearest first
+  {
+    double W = Wstar, zc = 0.0;
+    for (int q = 0; q < nz; ++q) {
+      const int idx = ord[q];
+      if (z[idx] < 0.0) continue;
+      W = march(W, zc, z[idx]);
+      zc = z[idx];
+      put(idx, W);
+    }
+  }
+  // upstream side (z < 0, W rises toward W_inf), nearest first
+  {
+    double W = Wstar, zc = 0.0;
+    for (int q = nz - 1; q >= 0; --q) {
+      const int idx = ord[q];
+      if (z[idx] >= 0.0) continue;
+      W = march(W, zc, z[idx]);
+      zc = z[idx];
+      put(idx, W);
+    }
+  }
+  return std::string();
+}
+
 }  // namespace klst

@@ -87,6 +87,16 @@ void structured_slots(const Problem& p, cd sigma, std::vector<int>& slot_node, s
 // Returns an empty string on success, else why (a singular line block or capacitance).
 std::string build_structured_inverse(const Problem& p, cd sigma, StructuredInverse& si, int nthreads);
 
+// ---- continuum normal-shock structure (Gilbarg-Paolucci, Sec. 2.1) ----
+// Steady 1-D Navier-Stokes shock of a gas with ratio of specific heats gamma,
+// Prandtl number Pr, viscosity mu ~ T^s, lengths in upstream mean free paths
+// l_inf = (16/delta) mu_inf / (rho_inf sqrt(2 pi R T_inf)).  Fills, at the nz
+// positions z (measured from the point of steepest velocity gradient, positive
+// downstream), rho / rho_inf, u / u_inf, T / T_inf, and returns the thickness
+// Delta / l_inf of eq. ShockThickness.  Returns an empty string on success.
+std::string gp_shock(double mach, double gamma, double Pr, double s_visc, double delta, int nz, const double* z,
+                     double* rho, double* u, double* T, double* thickness);
+
 // ---- returned eigenpairs of a Jacobi-Davidson solve ----
 struct OutputCandidate {
   cd lam;

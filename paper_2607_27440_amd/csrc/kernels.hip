@@ -6,7 +6,11 @@
 // with no cross-workgroup synchronisation.
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <array>
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <vector>
 
 #include "kernels.hpp"
 
@@ -76,6 +80,17 @@ __device__ __forceinline__ double2 block_sum256(double2 v, double2* sh /*[4]*/) 
   return r;
 }
 
+// Item of workgroup L in a 1-D grid of N workgroups such that each XCD takes a
+// contiguous range of items, balanced to within one.  Workgroups are dispatched
+// round robin over the 8 XCDs (L runs on XCD L mod 8), each XCD with its own
+// L2: XCD x runs L = x, x + 8, ..., i.e. items x q + min(x, N mod 8) + i, q =
+// N / 8.  Items that share tables (the same column tile of U, the same node of
+// M, for consecutive vectors) then meet in one L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t L, int64_t N) {
+  const int64_t x = L & 7, i = L >> 3, q = N >> 3, rm = N & 7;
+  return x * q + (x < rm ? x : rm) + i;
+}
+
 // ------------------------------------------------------------ operator ----
 
 // Perturbation moments m_a(j) = sum_{f,p} M[j][a][f][p] x[j][f][p] (rank r <= 4)
@@ -86,10 +101,24 @@ template <class R>
 __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, int64_t n, int Ny,
                                                  int Nxi, int r, const R* __restrict__ M,
                                                  cv<R>* __restrict__ mom, int S,
-                                                 const int* __restrict__ skip) {
+                                                 const int* __restrict__ skip, int vmaj) {
   __shared__ double2 sh[4][4];
   if (skip && *skip) return;
-  const int j = blockIdx.x / S, part = blockIdx.x - j * S, v = blockIdx.y;
+  // vmaj > 0: a 1-D grid of Ny S vmaj workgroups ordered node-part major, vector
+  // minor, spread over the XCDs by xcd_item (a node's M rows are read from one
+  // L2 for all vectors); else grid (Ny S, nvec)
+  int j, part, v;
+  if (vmaj > 0) {
+    const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+    v = (int)(item % vmaj);
+    const int q = (int)(item / vmaj);
+    j = q / S;
+    part = q - j * S;
+  } else {
+    j = blockIdx.x / S;
+    part = blockIdx.x - j * S;
+    v = blockIdx.y;
+  }
   const int nc = 2 * Nxi;
   const int per = (nc + S - 1) / S;
   const int cbeg = part * per, cend = min(nc, cbeg + per);
@@ -245,7 +274,8 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
                                                         const double* __restrict__ nu,
                                                         const double* __restrict__ U,
                                                         const double2* __restrict__ mom, int S,
-                                                        const int* __restrict__ skip) {
+                                                        const int* __restrict__ skip, int gx, int gy,
+                                                        int vmaj) {
   extern __shared__ unsigned char lds_raw[];
   double2* ms = reinterpret_cast<double2*>(lds_raw);                 // [RT*16][4] moments
   double* As = reinterpret_cast<double*>(lds_raw + RT * 16 * 4 * sizeof(double2));  // [Ny4][RT*16]
@@ -253,8 +283,23 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   const int nc = 2 * Nxi;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nrt = (Ny + 15) / 16;
-  const int rt0 = blockIdx.y * RT;
-  const int v = blockIdx.z;
+  // vmaj > 0: a 1-D grid of gx gy vmaj workgroups ordered tile major, vector
+  // minor, spread over the XCDs by xcd_item (a column tile's U entries and D_x
+  // rows are read from one L2 for all vectors); else grid (gx, gy, nvec)
+  int bx, by, v;
+  if (vmaj > 0) {
+    const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+    v = (int)(item % vmaj);
+    const int q = (int)(item / vmaj);
+    bx = q % gx;
+    by = q / gx;
+  } else {
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    v = blockIdx.z;
+  }
+  (void)gy;
+  const int rt0 = by * RT;
   const int W = RT * 16;
   for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
     const int jl = idx / r, a = idx - jl * r;
@@ -270,7 +315,7 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
     }
   }
   __syncthreads();
-  const int c0 = (blockIdx.x * NW + wv) * 16;
+  const int c0 = (bx * NW + wv) * 16;
   if (c0 >= nc) return;
   const double2* xv = x + (int64_t)v * n;
   double2* yv = y + (int64_t)v * n;
@@ -1482,9 +1527,42 @@ static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / 
 // columns on, enough for about 256 workgroups, with no part under 128 columns;
 // at most 8.  (Below 512 columns, splitting measured slower: the consumers then
 // add more parts.)
-int moment_splits(int Ny, int nvec, int Nxi) {
+namespace {
+std::mutex g_tune_mu;
+std::map<std::array<int, 4>, Tuning> g_tune;   // (Ny, Nxi, nvec, precision) -> launch choices
+}  // namespace
+
+void tune_set(int Ny, int Nxi, int nvec, int prec, const Tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[{Ny, Nxi, nvec, prec}] = t;
+}
+bool tune_get(int Ny, int Nxi, int nvec, int prec, Tuning* t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({Ny, Nxi, nvec, prec});
+  if (it == g_tune.end()) return false;
+  if (t) *t = it->second;
+  return true;
+}
+void tune_erase(int Ny, int Nxi, int nvec, int prec) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.erase({Ny, Nxi, nvec, prec});
+}
+void tune_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+std::vector<std::pair<std::array<int, 4>, Tuning>> tune_all() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return std::vector<std::pair<std::array<int, 4>, Tuning>>(g_tune.begin(), g_tune.end());
+}
+
+int moment_splits(int Ny, int nvec, int Nxi, int prec) {
   (void)nvec;
   const int nc = 2 * Nxi;
+  // a tuned split belongs to the shape (the single-vector entry), never to a
+  // batch size, so a vector's moments are summed the same way alone and in a batch
+  Tuning t;
+  if (tune_get(Ny, Nxi, 1, prec, &t) && t.msplit > 0) return std::max(1, std::min({8, t.msplit, nc}));
   if (nc < 512) return 1;
   const int fill = (256 + Ny - 1) / Ny;
   return std::max(1, std::min({8, std::max(nc / 512, fill), nc / 128}));
@@ -1671,9 +1749,12 @@ __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
 template <class R>
 static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                       const R* M, cv<R>* mom, const int* skip) {
-  const int S = moment_splits(Ny, nvec, Nxi);
-  hipLaunchKernelGGL((k_moments<R>), dim3(Ny * S, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S,
-                     skip);
+  const int S = moment_splits(Ny, nvec, Nxi, sizeof(R) == 4 ? 1 : 0);
+  if (nvec > 1)
+    hipLaunchKernelGGL((k_moments<R>), dim3(Ny * S * nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, skip,
+                       nvec);
+  else
+    hipLaunchKernelGGL((k_moments<R>), dim3(Ny * S, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, skip, 0);
 }
 void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                     const double* M, double2* mom, const int* skip) {
@@ -1690,14 +1771,18 @@ static void apply_t(hipStream_t st, const cv<R>* x, cv<R>* y, int64_t n, int nve
                     const R* nu, const R* U, const cv<R>* mom, const int* skip) {
   const int nc = 2 * Nxi;
   const int cblocks = (nc + 255) / 256;
-  const int S = moment_splits(Ny, nvec, Nxi);
+  const int S = moment_splits(Ny, nvec, Nxi, sizeof(R) == 4 ? 1 : 0);
   // rows per thread: as many as possible while keeping >= ~1024 wavefronts busy
+  // (or the tuned count: the rows of a thread are summed in the same order
+  // whatever their number, so the choice does not change results)
   const int64_t waves16 = (int64_t)((nc + 63) / 64) * ((Ny + 15) / 16) * nvec;
   const int64_t waves8 = (int64_t)((nc + 63) / 64) * ((Ny + 7) / 8) * nvec;
-  if (waves16 >= 1024) {
+  Tuning tn;
+  const int rb = tune_get(Ny, Nxi, nvec, sizeof(R) == 4 ? 1 : 0, &tn) ? tn.apply_rt : 0;
+  if (rb == 16 || (rb == 0 && waves16 >= 1024)) {
     hipLaunchKernelGGL((k_apply<R, 16>), dim3(cblocks, (Ny + 15) / 16, nvec), dim3(256), 0, st, x, y, n, Ny,
                        Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
-  } else if (waves8 >= 512) {
+  } else if (rb == 8 || (rb == 0 && waves8 >= 512)) {
     hipLaunchKernelGGL((k_apply<R, 8>), dim3(cblocks, (Ny + 7) / 8, nvec), dim3(256), 0, st, x, y, n, Ny,
                        Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
   } else {
@@ -1715,16 +1800,25 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   // workgroup are chosen for >= ~1024 wavefronts when the problem allows it.
   const int nc = 2 * Nxi;
   const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
-  const int S = moment_splits(Ny, nvec, Nxi);
+  const int S = moment_splits(Ny, nvec, Nxi, 0);
   int rt = 6;
   while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
-  const bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512 &&
-                    (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) <= 96 * 1024;
+  bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
+  // tuned row tiles and waves per workgroup (every output entry is accumulated
+  // in the same order whatever the tiling, so the choice does not change results)
+  Tuning tn;
+  if (tune_get(Ny, Nxi, nvec, 0, &tn)) {
+    if (tn.apply_rt == 1 || tn.apply_rt == 2 || tn.apply_rt == 3 || tn.apply_rt == 6) rt = tn.apply_rt;
+    if (tn.apply_nw == 1 || tn.apply_nw == 4) wide = (tn.apply_nw == 4);
+  }
+  wide = wide && (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) <= 96 * 1024;
   const size_t lds_m = (size_t)rt * 16 * 4 * sizeof(double2);
   const size_t lds = lds_m + (wide ? (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) : 0);
-  const dim3 g(wide ? (ctiles + 3) / 4 : ctiles, (nrt + rt - 1) / rt, nvec);
+  const int gx = wide ? (ctiles + 3) / 4 : ctiles, gy = (nrt + rt - 1) / rt;
+  const dim3 g = nvec > 1 ? dim3(gx * gy * nvec) : dim3(gx, gy, nvec);
+  const int vmaj = nvec > 1 ? nvec : 0;
 #define KLST_MF(RT_, NW_) hipLaunchKernelGGL((k_apply_mfma<RT_, NW_>), g, dim3(64 * NW_), lds, st, x, y, n, Ny, \
-                                             Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, skip)
+                                             Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, skip, gx, gy, vmaj)
   if (wide) {
     if (rt == 6) KLST_MF(6, 4); else if (rt == 3) KLST_MF(3, 4); else if (rt == 2) KLST_MF(2, 4); else KLST_MF(1, 4);
   } else {
@@ -1778,7 +1872,9 @@ static void blockinv_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nxi
                        const cv<R>* Kinv, const int64_t* koff, const int* skip) {
   const int nb = nl * Ny;
   const dim3 grid((nb + 63) / 64, nblocks);
-  const int nw = gemv_waves((int64_t)grid.x * grid.y);
+  int nw = gemv_waves((int64_t)grid.x * grid.y);
+  Tuning tn;
+  if (tune_get(Ny, Nxi, 1, sizeof(R) == 4 ? 1 : 0, &tn) && (tn.gemv == 4 || tn.gemv == 8 || tn.gemv == 16)) nw = tn.gemv;
   const size_t lds = (size_t)(nb + 64 * nw) * sizeof(cv<R>);
   if (nw == 4)
     hipLaunchKernelGGL((k_blockinv_apply<R, 4>), grid, dim3(256), lds, st, x, y, Ny, Nxi, nl, Kinv, koff, skip);
@@ -1808,6 +1904,8 @@ static void line_pass_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int Nx
   // then holds 4 Ny inputs and 4 x NW x 64 partial sums, which caps NW at 8
   const int cmax = nslots < Nxi ? 4 : 2;
   int nw = gemv_waves((int64_t)grid.x * grid.y);
+  Tuning tn;
+  if (tune_get(Ny, Nxi, 1, sizeof(R) == 4 ? 1 : 0, &tn) && (tn.gemv == 4 || tn.gemv == 8 || tn.gemv == 16)) nw = tn.gemv;
   if (cmax == 4 && nw > 8) nw = 8;
   const size_t lds = (size_t)(cmax * Ny + cmax * 64 * nw) * sizeof(cv<R>);
 #define KLST_LI(NW_, P_) hipLaunchKernelGGL((k_line_inverse<R, NW_, P_>), grid, dim3(64 * NW_), lds, st, x, y, Ny, \
@@ -1829,7 +1927,7 @@ static void structured_t(hipStream_t st, const cv<R>* x, cv<R>* y, int Ny, int N
   const int64_t n = 2LL * Ny * Nxi;
   moments_t<R>(st, y, n, 1, Ny, Nxi, r, M, mom, skip);
   const int Rd = r * Ny;
-  const int S = moment_splits(Ny, 1, Nxi);
+  const int S = moment_splits(Ny, 1, Nxi, sizeof(R) == 4 ? 1 : 0);
   hipLaunchKernelGGL((k_capacitance<R>), dim3((Rd + 3) / 4), dim3(256), (size_t)Rd * sizeof(cv<R>), st, mom,
                      Ny, r, S, Sinv, d, skip);
   line_pass_t<R>(st, x, y, Ny, Nxi, r, Pinv, slot_node, slot_mate, nslots, U, xix, d, skip);
@@ -2029,9 +2127,9 @@ void launch_set_int(hipStream_t st, int* p, int v) {
 void launch_perturbation_macros(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                                 const double* M, double2* mom, const double* base, double2* macros,
                                 double* umag) {
-  const int S = moment_splits(Ny, nvec, Nxi);
+  const int S = moment_splits(Ny, nvec, Nxi, 0);
   hipLaunchKernelGGL((k_moments<double>), dim3(Ny * S, nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S,
-                     nullptr);
+                     nullptr, 0);
   hipLaunchKernelGGL(k_pert_macros, dim3(nvec), dim3(256), 0, st, mom, Ny, r, S, base, macros, umag);
 }
 

@@ -2,10 +2,33 @@
 // pointers; complex FP64 vectors are double2 arrays of length n per vector.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <array>
 #include <cstdint>
+#include <utility>
+#include <vector>
 
 namespace klst {
 namespace dev {
+
+// Launch choices chosen by the autotuner, kept in a process-wide table keyed by
+// (Ny, Nxi, nvec, precision 0 = FP64 / 1 = FP32); 0 = the built-in heuristic.
+//   apply_rt: FP64 matrix-core operator row tiles per workgroup (1, 2, 3, 6), or
+//             FP32 operator rows per thread (4, 8, 16);
+//   apply_nw: FP64 operator wavefronts per workgroup (1, or 4 with an LDS copy of D_x);
+//   msplit:   column parts per node of the moment sums (1..8; read from the
+//             nvec = 1 entry for every batch size);
+//   gemv:     wavefronts per workgroup of the block GEMVs (4, 8, 16; nvec = 1 entry).
+// Tile and wave choices leave every result bit-identical; msplit and gemv change
+// the order of summation, so a table must be fixed before the solves it serves.
+struct Tuning {
+  int apply_rt = 0, apply_nw = 0, msplit = 0, gemv = 0;
+};
+void tune_set(int Ny, int Nxi, int nvec, int prec, const Tuning& t);
+bool tune_get(int Ny, int Nxi, int nvec, int prec, Tuning* t);
+void tune_erase(int Ny, int Nxi, int nvec, int prec);
+void tune_clear();
+std::vector<std::pair<std::array<int, 4>, Tuning>> tune_all();
+int moment_splits(int Ny, int nvec, int Nxi, int prec);
 
 // Moment partial sums: mom must hold Ny * r * nvec * 8 entries (up to 8 column parts).
 void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,

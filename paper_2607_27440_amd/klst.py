@@ -49,6 +49,15 @@ class Base(C.Structure):
                 ("h_c", C.POINTER(C.c_double)), ("s_visc", C.c_double), ("nu_inf", C.c_double)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("Ny", C.c_int), ("Nxi", C.c_int), ("nvec", C.c_int), ("precision", C.c_int),
+                ("apply_tile", C.c_int), ("apply_waves", C.c_int), ("moment_splits", C.c_int),
+                ("gemv_waves", C.c_int), ("us_default", C.c_double), ("us_tuned", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Stats(C.Structure):
     _fields_ = [("outer_iterations", C.c_int), ("inner_iterations", C.c_int), ("restarts", C.c_int),
                 ("nconv", C.c_int), ("pivots_floored", C.c_int), ("seconds_total", C.c_double),
@@ -81,6 +90,10 @@ _sig = {
     "klst_precond_apply": (C.c_int, [_P, _P, _P]),
     "klst_solve": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_get_stats": (C.c_int, [_P, C.POINTER(Stats)]),
+    "klst_autotune": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, C.POINTER(TuneEntry)]),
+    "klst_tune_save": (C.c_int, [C.c_char_p]),
+    "klst_tune_load": (C.c_int, [C.c_char_p]),
+    "klst_tune_clear": (None, []),
     "klst_get_history": (C.c_int, [_P, _D2, C.c_int, C.POINTER(C.c_int)]),
     "klst_solve_shift_invert": (C.c_int, [_P, _D2, C.c_int, _D2, _P, C.c_int, _D2, C.POINTER(C.c_int)]),
     "klst_footprint_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.POINTER(Options)]),
@@ -96,6 +109,8 @@ _sig = {
     "klst_host_tables": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
                                    _D2, _D2, _D2, _D2, C.POINTER(C.c_uint8)]),
     "klst_host_sorted_schur": (C.c_int, [C.c_int, _D2, _D2, _D2]),
+    "klst_gp_shock": (C.c_int, [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, _D2, _D2,
+                                _D2, _D2, _D2]),
     "klst_host_select_output": (C.c_int, [C.c_int, _D2, _D2, _D2, _D2, C.c_int, _D2, C.POINTER(C.c_int),
                                           C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "klst_perturbation_macros": (C.c_int, [_P, _P, C.c_int, _P, _P]),
@@ -216,6 +231,22 @@ def host_select_output(lam, sigma, nev, G=None, nrm2=None):
         raise KlstError(st, "host select output")
     c = cnt.value
     return out.view(np.complex128)[:c].copy(), src[:c].copy(), mir[:c].astype(bool)
+
+
+def gp_shock(mach, z=(), gamma=5.0 / 3.0, Pr=1.0, s_visc=0.5, delta=5.0):
+    """Gilbarg-Paolucci shock structure from the library: (rho, u, T) normalised
+    by the upstream state at positions z (upstream mean free paths from the
+    steepest point, downstream positive), and the thickness Delta / l_inf."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    nz = len(z)
+    rho, u, T = np.zeros(nz), np.zeros(nz), np.zeros(nz)
+    th = C.c_double()
+    st = _lib.klst_gp_shock(float(mach), float(gamma), float(Pr), float(s_visc), float(delta), nz,
+                            _dp(z) if nz else None, _dp(rho) if nz else None, _dp(u) if nz else None,
+                            _dp(T) if nz else None, C.byref(th))
+    if st != OK:
+        raise KlstError(st, "gp_shock")
+    return rho, u, T, th.value
 
 
 def host_sorted_schur(G: np.ndarray):
@@ -401,6 +432,14 @@ class Context:
             out["X"] = X
         return out
 
+    def autotune(self, nvec=1, precision=0, reps=20):
+        """Time the launch choices on the assembled problem and install the fastest
+        in the library's table; returns the chosen entry as a dict."""
+        e = TuneEntry()
+        self._check(_lib.klst_autotune(self._h, int(nvec), int(precision), int(reps), C.byref(e)),
+                    "klst_autotune")
+        return e.as_dict()
+
     def history(self) -> np.ndarray:
         """Convergence history of the last solve, one row per outer iteration:
         (outer, locked, relative residual, Re theta, Im theta, theta-shifted)."""
@@ -410,6 +449,22 @@ class Context:
         if cnt.value:
             self._check(_lib.klst_get_history(self._h, _dp(rec), cnt.value, C.byref(cnt)), "klst_get_history")
         return rec
+
+
+def tune_save(path):
+    st = _lib.klst_tune_save(os.fsencode(path))
+    if st != OK:
+        raise KlstError(st, f"klst_tune_save({path})")
+
+
+def tune_load(path):
+    st = _lib.klst_tune_load(os.fsencode(path))
+    if st != OK:
+        raise KlstError(st, f"klst_tune_load({path})")
+
+
+def tune_clear():
+    _lib.klst_tune_clear()
 
 
 def footprint_bytes(Ny, Nxi, nev, options: Optional[Options] = None) -> int:

@@ -281,6 +281,22 @@ def bgk_start(wl: Workload):
     return g, h
 
 
+def bgk_start_from_profile(wl: Workload, rho, u, T):
+    """Initial state (g, h) [Ny, Nxi] of the base-flow relaxation from a shock
+    profile given at the nodes (rho, u, T normalised by the upstream state, as
+    the continuum structure of Sec. 2.1 returns them): the local Maxwellians, with
+    the two end nodes set to the Rankine-Hugoniot Maxwellians exactly."""
+    rho1, u1, T1, u_inf = rankine_hugoniot(wl.mach)
+    g, h = _maxwell_vdf(np.asarray(rho, float), np.asarray(u, float) * u_inf, np.asarray(T, float),
+                        wl.xi_x, wl.xi_y, wl.Dv)
+    one = np.ones(1)
+    g1, h1 = _maxwell_vdf(one * rho1, one * u1, one * T1, wl.xi_x, wl.xi_y, wl.Dv)
+    gi, hi = _maxwell_vdf(one, one * u_inf, one, wl.xi_x, wl.xi_y, wl.Dv)
+    g[0], h[0] = g1[0], h1[0]
+    g[-1], h[-1] = gi[0], hi[0]
+    return g, h
+
+
 def bgk_dt(wl: Workload, cfl: float = 0.4) -> float:
     """Time step of the relaxation: cfl x the smallest interior cell width
     (x_{i+1} - x_{i-1}) / 2 over the largest |xi_x|."""

@@ -93,3 +93,31 @@ def test_relaxed_base_flow_through_the_stability_solve():
     res, skipped = PAR.match(out["lam"], lam_all[idx], kap, normA, sigma=wl.sigma, tol=1e-10)
     assert all(r["ok"] for r in res), [r for r in res if not r["ok"]]
     assert not skipped
+
+
+@pytest.mark.parametrize("case", ["c1", "c2"])
+def test_bgk_relax_from_the_gilbarg_paolucci_start(case):
+    """The relaxation started from the continuum shock structure (Sec. 2.1):
+    the library's profile (klst_gp_shock) and the oracle's give start states
+    within 1e-7 of each other; K GPU steps from the first stay within that
+    difference (the march is dissipative) plus the march's rounding bound of the
+    oracle's K steps from the second."""
+    from paper_2607_27440_amd import klst
+    from oracle.shock import GPShock
+    make, K = CASES[case]
+    wl = make()
+    print(f"[case] bgk from G&P {wl.name} steps={K}", flush=True)
+    rho, u, T, th = klst.gp_shock(wl.mach, wl.x, s_visc=wl.s_visc)
+    g0, h0 = W.bgk_start_from_profile(wl, rho, u, T)
+    sh = GPShock(wl.mach, s_visc=wl.s_visc)
+    ro, uo, To = sh.profile(wl.x)
+    g0o, h0o = W.bgk_start_from_profile(wl, ro, uo, To)
+    qmax = max(np.abs(g0o).max(), np.abs(h0o).max())
+    d0 = max(np.abs(g0 - g0o).max(), np.abs(h0 - h0o).max())
+    assert d0 <= 1e-7 * qmax
+    dt = W.bgk_dt(wl)
+    g, h, steps, res = _ctx().bgk_relax(wl, g0, h0, dt, K)
+    rg, rh, rres = BGK.relax(wl.x, wl.xi_x, wl.xi_y, wl.w, wl.Dv, wl.nu_inf, wl.s_visc, g0o, h0o, dt, K)
+    bound = 4 * d0 + K * 64 * (wl.Nxi + 16) * U * qmax
+    assert np.abs(g - rg).max() <= bound and np.abs(h - rh).max() <= bound
+    assert np.abs(rg - g0o).max() > 100 * bound

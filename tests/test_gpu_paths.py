@@ -115,9 +115,12 @@ def test_exported_csr_equals_the_assembled_matrix():
     A.sort_indices()
     assert len(val) == ctx.nnz == A.nnz
     assert np.array_equal(rp, A.indptr) and np.array_equal(col, A.indices)
-    # values: the coupling entries are r-term sums, the diagonal adds three terms
-    scale = np.abs(A.data) + np.max(np.abs(A.data)) * 1e-3
-    assert np.all(np.abs(val - A.data) <= 16 * U * scale)
+    # values: the library's host tables agree with the oracle's to 1e-13 of their
+    # largest entries (test_boundary), and each stored entry is a product or an
+    # r-term sum of them
+    err = np.max(np.abs(val - A.data)) / np.max(np.abs(A.data))
+    print(f"max entry difference {err:.2e} of max |A|", flush=True)
+    assert err <= 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -143,27 +146,28 @@ def test_jd_with_the_explicit_csr_operator(c2_reference):
 
 
 def test_eigenvectors_c1_within_the_residual_bound():
-    """x_gpu = a x + e with e orthogonal to the null vector x of A - lambda B, so
-    (A - lambda B) e = (A - lambda B) x_gpu and sin angle(x_gpu, x) <=
-    ||(A - lambda B) x_gpu|| / sigma_{n-1}(A - lambda B); with r the GPU residual,
-    ||(A - lambda B) x_gpu|| <= r |lambda_gpu| + |lambda_gpu - lambda| ||B||."""
+    """For a simple eigenvalue lambda with unit null vector x of C = A - lambda B,
+    any unit vector v splits as v = a x + e with e orthogonal to x, so C e = C v
+    and sin angle(v, x) = ||e|| <= ||C v|| / sigma_{n-1}(C).  Applied to the GPU
+    eigenvector and to the QZ one (both against the exact x) this bounds the
+    angle between them by (||C x_gpu|| + ||C x_qz||) / sigma_{n-1}, plus the
+    rounding of forming C v (n u ||A|| / sigma_{n-1})."""
     wl = W.config1()
     P = O.Pencil(wl)
     lam_all, Xq, Yq, _ = E.qz_all(P)
     ctx = _ctx(wl, pc_kernel=2, m_max=40)
     out = ctx.solve(wl.sigma, wl.nev)
     A, B = P.dense()
+    normA = np.linalg.norm(A, 2)
     for i, lv in enumerate(out["lam"]):
         j = int(np.argmin(np.abs(lam_all - lv)))
         lr = lam_all[j]
+        C = A - lr * B
         x_ref = Xq[:, j] / np.linalg.norm(Xq[:, j])
-        x = out["X"][:, i]
-        s = sla.svdvals(A - lr * B)
-        gap = s[-2]
-        rnorm = out["resid"][i] * max(abs(lv), 1e-300) + abs(lv - lr)
-        cosang = abs(np.vdot(x_ref, x))
-        sinang = np.sqrt(max(0.0, 1.0 - cosang ** 2))
-        bound = 2.0 * rnorm / gap + 1e-12
+        x = out["X"][:, i] / np.linalg.norm(out["X"][:, i])
+        gap = sla.svdvals(C)[-2]
+        sinang = np.linalg.norm(x - np.vdot(x_ref, x) * x_ref)
+        bound = (np.linalg.norm(C @ x) + np.linalg.norm(C @ x_ref) + 2 * wl.n * U * normA) / gap
         print(f"pair {i}: sin angle {sinang:.2e}, bound {bound:.2e}", flush=True)
         assert sinang <= bound, (i, sinang, bound)
 
@@ -180,7 +184,10 @@ def test_eigenvectors_c2_rule_c4(c2_reference):
         j = int(np.argmin(np.abs(ref - lv)))
         e = abs(lv - ref[j]) / abs(ref[j])
         xr = X[:, j] / np.linalg.norm(X[:, j])
-        one_minus = 1.0 - abs(np.vdot(xr, out["X"][:, i]))
+        xg = out["X"][:, i] / np.linalg.norm(out["X"][:, i])
+        # 1 - |cos| from the orthogonal part (sin^2 / (1 + |cos|)), free of cancellation
+        perp = xg - np.vdot(xr, xg) * xr
+        one_minus = np.linalg.norm(perp) ** 2 / (1.0 + abs(np.vdot(xr, xg)))
         bound = 10 * kap[j] * max(e, res_ref[j], out["resid"][i])
         print(f"pair {i}: 1 - |cos| {one_minus:.2e}, bound {bound:.2e}", flush=True)
         assert one_minus <= bound, (i, one_minus, bound)
