@@ -163,6 +163,19 @@ klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* 
  * x + i n).  Matrix-free only. */
 klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);
 
+/* klst_apply_many without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same product, same kernels and bit-identical results as
+ * klst_apply_many; the moment partial sums go to a library-owned device array
+ * of 2^19 complex doubles (8 MiB per GPU, held until the process ends) instead
+ * of context memory, so nvec * Ny * r * 8 must not exceed 2^19 (r = 4 for
+ * Dv = 2, 3 for Dv = 1).  The array is shared by every call on the GPU: calls
+ * that overlap on one GPU (two streams, two threads) race and give undefined
+ * results; calls ordered on one stream are safe.  Nothing in it needs to start
+ * at zero.  Errors: ESTATE (no problem), EINVAL (null pointer, nvec < 1, or the
+ * size limit above), EDEVICE. */
+klst_status klst_apply_many_noalloc(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);
+
 /* y = (A - tau B) x with the explicit CSR matrix regardless of op_mode
  * (generated on first use).  Errors: ENOMEM if the matrix does not fit. */
 klst_status klst_apply_csr(klst_ctx* ctx, const double tau[2], const void* x, void* y);

@@ -74,6 +74,12 @@ struct klst_ctx {
   const volatile int* cancel = nullptr;   // set by the server: stop the current solve
 };
 
+// Moment partial sums of klst_apply_many_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code reaches it only through
+// the per-device address that klst_create resolves with hipGetSymbolAddress.
+constexpr size_t kScratchEntries = (size_t)1 << 19;   // double2 entries (8 MiB)
+static __device__ __align__(256) double2 scratch[kScratchEntries];
+
 namespace {
 
 #define HIPCHK(expr)                                                            \
@@ -84,6 +90,29 @@ namespace {
       return KLST_EDEVICE;                                                      \
     }                                                                           \
   } while (0)
+
+std::mutex g_scratch_mu;
+std::vector<double2*> g_scratch_ptr;   // device address of `scratch`, per device ordinal
+
+// Resolve `scratch` on the current device (ordinal dev) once; called by
+// klst_create with that device current.
+bool resolve_scratch(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (g_scratch_ptr[dev]) return true;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return false;
+  }
+  g_scratch_ptr[dev] = (double2*)ptr;
+  return true;
+}
+
+double2* scratch_on(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (dev >= 0 && dev < (int)g_scratch_ptr.size()) ? g_scratch_ptr[dev] : nullptr;
+}
 
 klst_status fail(klst_ctx* ctx, klst_status s, const std::string& msg) {
   if (ctx) ctx->err = msg;
@@ -499,6 +528,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
   klst_ctx* ctx = new klst_ctx();
   ctx->opt = o;
   if (hipSetDevice(o.device) != hipSuccess) { delete ctx; return KLST_EDEVICE; }
+  if (!resolve_scratch(o.device)) { delete ctx; return KLST_EDEVICE; }
   // NULL selects the device's default (null) stream, so work is ordered with
   // anything else the caller issues there (torch's default stream included).
   ctx->stream = (hipStream_t)o.stream;
@@ -659,6 +689,27 @@ klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const 
   if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many before klst_assemble");
   HIPCHK(hipSetDevice(ctx->opt.device));
   return op_apply(ctx, cd(tau[0], tau[1]), (const double2*)x, (double2*)y, nvec, 0, nullptr);
+}
+
+klst_status klst_apply_many_noalloc(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y) {
+  if (!ctx || !tau || !x || !y || nvec < 1 || nvec > 65535) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many_noalloc before klst_assemble");
+  const klst::Problem& p = ctx->prob;
+  // moment partials: nvec x Ny x r x (up to 8 column parts) entries
+  if ((size_t)nvec * p.Ny * p.r * 8 > kScratchEntries)
+    return fail(ctx, KLST_EINVAL, "klst_apply_many_noalloc: nvec * Ny * r * 8 = " +
+                                      std::to_string((size_t)nvec * p.Ny * p.r * 8) + " exceeds the " +
+                                      std::to_string(kScratchEntries) + "-entry scratch");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  double2* mom = scratch_on(ctx->opt.device);
+  if (!mom) return fail(ctx, KLST_EDEVICE, "scratch address not resolved for this device");
+  const cd t(tau[0], tau[1]);
+  klst::dev::launch_moments(ctx->stream, (const double2*)x, p.n(), nvec, p.Ny, p.Nxi, p.r, ctx->d_M, mom, nullptr);
+  klst::dev::launch_apply(ctx->stream, (const double2*)x, (double2*)y, p.n(), nvec, p.Ny, p.Nxi, p.r, t.real(),
+                          t.imag(), p.beta, ctx->d_DxT, ctx->d_xix, ctx->d_xiy, ctx->d_nu, ctx->d_U, mom, nullptr);
+  HIPCHK(hipGetLastError());
+  ctx->stats.op_applies += nvec;
+  return KLST_OK;
 }
 
 klst_status klst_apply_csr(klst_ctx* ctx, const double tau[2], const void* x, void* y) {

@@ -81,6 +81,7 @@ _sig = {
     "klst_apply": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_many": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_apply_csr": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_apply_many_noalloc": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_precond_apply_lines": (C.c_int, [_P, _P, _P]),
     "klst_precond_export": (C.c_int, [_P, _D2, _D2, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "klst_host_structured_inverse": (C.c_int, [C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double,
@@ -325,6 +326,11 @@ class Context:
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_many(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
                     "klst_apply_many")
+
+    def apply_many_noalloc(self, tau, nvec, x, y):
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply_many_noalloc(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
+                    "klst_apply_many_noalloc")
 
     def precond_apply_lines(self, x, y):
         """y = P^{-1} x: one pass of the structured preconditioner's line inverses."""
