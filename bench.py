@@ -37,7 +37,7 @@ FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix cores)
 # each scaled by the same counter's reading for a 256 MiB copy; keyed by workload,
 # valid for the kernel as counted (the profile named beside each figure)
 TRAFFIC = {
-    "c3": (123620000, "profiles/line_inverse_c3_m4_ny96_nxi1464_counters.md"),
+    "c3": (117771690, "profiles/line_inverse_c3_m4_ny96_nxi1464_counters.md"),
 }
 RES_GATE = 1e-10
 
@@ -187,11 +187,18 @@ def _line_slots(wl, sigma):
 
 
 def _event_times(fn, reps, torch, st):
-    """Launch fn() reps times on stream st with a HIP event between launches;
-    returns (average s, median s, min s) per launch.  The average is the span
-    from the first event to the last over reps; the events themselves add no
-    work on the stream."""
+    """Launch fn() reps times back to back on stream st between two HIP events
+    (the average per launch), then reps more times with an event after every
+    launch (median and min per launch; those events add a few microseconds of
+    their own to each interval).  Returns (average s, median s, min s)."""
     import numpy as np
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        fn()
+    e1.record(st)
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) / 1e3 / reps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     ev[0].record(st)
     for i in range(reps):
@@ -199,7 +206,7 @@ def _event_times(fn, reps, torch, st):
         ev[i + 1].record(st)
     torch.cuda.synchronize()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]) / 1e3
-    return ev[0].elapsed_time(ev[reps]) / 1e3 / reps, float(np.median(per)), float(np.min(per))
+    return avg, float(np.median(per)), float(np.min(per))
 
 
 def line_inverse_roofline(ctx, wl, torch, reps, workload=None):

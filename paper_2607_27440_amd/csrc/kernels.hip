@@ -431,6 +431,200 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   }
 }
 
+// Many-vector operator, y_v = (A - tau B) x_v for a group of vectors: one
+// workgroup per (16-column tile, vector group), one wavefront per 16-row tile
+// (NRT wavefronts).  Each wavefront keeps its row tile's D_x fragments (the A
+// operands of v_mfma_f64_16x16x4f64) and its epilogue operands (U, nu, xi) in
+// registers for the whole group; the column strip of x (Ny x 16) and the
+// moments of each vector are staged in LDS, double-buffered so that the next
+// vector's strip loads while the current one's MFMAs run.  Every output entry
+// is accumulated in the order of k_apply_mfma (K in steps of 4 from 0, then the
+// epilogue terms in the same order), so the results are bit-identical to it.
+// grid (ceil(2 Nxi / 16), vector groups), block 64 NRT; dynamic LDS
+// 2 (Ny4 x 16 + NRT x 16 x 4) double2, Ny4 = Ny rounded up to 4.
+template <int NRT>
+__global__ void __launch_bounds__(64 * NRT) k_apply_mfma_batch(const double2* __restrict__ x,
+                                                               double2* __restrict__ y, int64_t n, int Ny,
+                                                               int Nxi, int r, double tau_re, double tau_im,
+                                                               double beta, const double* __restrict__ DxT,
+                                                               const double* __restrict__ xi_x,
+                                                               const double* __restrict__ xi_y,
+                                                               const double* __restrict__ nu,
+                                                               const double* __restrict__ U,
+                                                               const double2* __restrict__ mom, int S, int nvec,
+                                                               int VG) {
+  constexpr int K4 = 4 * NRT;                       // K steps of 4 rows, Ny <= 16 NRT
+  extern __shared__ unsigned char lds_raw[];
+  const int Ny4 = (Ny + 3) & ~3;
+  double2* xs = reinterpret_cast<double2*>(lds_raw);           // [2][Ny4][16]
+  double2* ms = xs + 2 * Ny4 * 16;                              // [2][NRT * 16][4]
+  const int nc = 2 * Nxi;
+  const int c0 = blockIdx.x * 16;
+  const int v0 = blockIdx.y * VG, v1 = min(nvec, v0 + VG);
+  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int nthr = 64 * NRT;
+  // A fragments: row t*16 + li, K index 4 s + lk
+  double afr[K4];
+#pragma unroll
+  for (int s2 = 0; s2 < K4; ++s2) {
+    const int m = 4 * s2 + lk, row = t * 16 + li;
+    afr[s2] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+  }
+  // epilogue operands of this lane: column c, rows j = t*16 + lk + 4q
+  const int c = c0 + li;
+  const bool cok = c < nc;
+  const int f = cok ? c / Nxi : 0, k = cok ? c - f * Nxi : 0;
+  const double xik = cok ? xi_x[k] : 0.0, bxy = cok ? beta * xi_y[k] : 0.0;
+  double nuq[4], uq[4][4];
+  bool bcq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = t * 16 + lk + 4 * q;
+    const bool ok = cok && j < Ny;
+    nuq[q] = ok ? nu[j] : 0.0;
+    bcq[q] = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) uq[q][a] = (ok && a < r) ? U[((int64_t)(j * 2 + f) * r + a) * Nxi + k] : 0.0;
+  }
+  // staging of one vector: x strip (rows >= Ny zero) and its moments (S parts summed)
+  constexpr int XPT = 4;          // strip entries per thread: Ny4 x 16 <= 256 NRT
+  const int xcount = Ny4 * 16, mcount = NRT * 16 * 4;
+  auto load_strip = [&](int v, double2* xr, double2* mr) {
+    const double2* xv = x + (int64_t)v * n;
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int idx = threadIdx.x + e * nthr;
+      const int m = idx >> 4, cc = c0 + (idx & 15);
+      xr[e] = (idx < xcount && m < Ny && cc < nc) ? xv[(int64_t)m * nc + cc] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int e = 0; e < 1; ++e) {
+      const int idx = threadIdx.x + e * nthr;
+      const int jl = idx >> 2, a = idx & 3;
+      mr[e] = (idx < mcount && jl < Ny && a < r) ? mom_at<double>(mom, v, Ny, jl, a, r, S) : make_double2(0.0, 0.0);
+    }
+  };
+  auto store_strip = [&](int buf, const double2* xr, const double2* mr) {
+#pragma unroll
+    for (int e = 0; e < XPT; ++e) {
+      const int idx = threadIdx.x + e * nthr;
+      if (idx < xcount) xs[buf * xcount + idx] = xr[e];
+    }
+#pragma unroll
+    for (int e = 0; e < 1; ++e) {
+      const int idx = threadIdx.x + e * nthr;
+      if (idx < mcount) ms[buf * mcount + idx] = mr[e];
+    }
+  };
+  double2 xr[XPT], mr[1];         // moments: NRT x 16 x 4 = 64 NRT entries, one per thread
+  if (v0 < v1) {
+    load_strip(v0, xr, mr);
+    store_strip(0, xr, mr);
+  }
+  __syncthreads();
+  for (int v = v0; v < v1; ++v) {
+    const int buf = (v - v0) & 1;
+    if (v + 1 < v1) load_strip(v + 1, xr, mr);
+    const double2* xb = xs + buf * xcount;
+    dbl4 are = dbl4{0, 0, 0, 0}, aim = dbl4{0, 0, 0, 0};
+#pragma unroll
+    for (int s2 = 0; s2 < K4; ++s2) {
+      if (4 * s2 < Ny) {
+        const double2 b = xb[(4 * s2 + lk) * 16 + li];
+        are = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s2], b.x, are, 0, 0, 0);
+        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s2], b.y, aim, 0, 0, 0);
+      }
+    }
+    if (cok) {
+      const double2* mb = ms + buf * mcount;
+      double2* yv = y + (int64_t)v * n;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int jl = t * 16 + lk + 4 * q;
+        if (jl >= Ny) continue;
+        const double2 xjc = xb[jl * 16 + li];
+        double2 out;
+        if (bcq[q]) {
+          out = xjc;
+        } else {
+          const double dre = nuq[q] - tau_re, dim = bxy - tau_im;
+          out.x = xik * are[q] + dre * xjc.x - dim * xjc.y;
+          out.y = xik * aim[q] + dre * xjc.y + dim * xjc.x;
+#pragma unroll
+          for (int a = 0; a < 4; ++a) {
+            if (a < r) {
+              const double2 ma = mb[jl * 4 + a];
+              out.x -= uq[q][a] * ma.x;
+              out.y -= uq[q][a] * ma.y;
+            }
+          }
+        }
+        yv[(int64_t)jl * nc + c] = out;
+      }
+    }
+    if (v + 1 < v1) store_strip(buf ^ 1, xr, mr);
+    __syncthreads();
+  }
+}
+
+// Moment partials of a group of vectors per workgroup (node j, column part):
+// each thread holds the M entries of its columns (the columns k_moments gives
+// it) in registers and sums every vector of the group in the order of
+// k_moments, so the partials are bit-identical to it.  grid (Ny S, vector
+// groups), block 256; CPT = columns per thread (the part has <= 256 CPT).
+template <int CPT>
+__global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict__ x, int64_t n, int Ny, int Nxi,
+                                                       int r, const double* __restrict__ M,
+                                                       double2* __restrict__ mom, int S, int nvec, int VG) {
+  __shared__ double2 sh[4][4];
+  const int j = blockIdx.x / S, part = blockIdx.x - j * S;
+  const int v0 = blockIdx.y * VG, v1 = min(nvec, v0 + VG);
+  const int nc = 2 * Nxi;
+  const int per = (nc + S - 1) / S;
+  const int cbeg = part * per, cend = min(nc, cbeg + per);
+  double mw[CPT][4];
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    const int cc = cbeg + threadIdx.x + 256 * i;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) mw[i][a] = (cc < cend && a < r) ? M[((int64_t)j * r + a) * nc + cc] : 0.0;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int v = v0; v < v1; ++v) {
+    const double2* xj = x + (int64_t)v * n + (int64_t)j * nc;
+    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int cc = cbeg + threadIdx.x + 256 * i;
+      if (cc < cend) {
+        const double2 xv = xj[cc];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a < r) {
+            ar[a] += mw[i][a] * xv.x;
+            ai[a] += mw[i][a] * xv.y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if (a < r) {
+        const double sr = wave_sum(ar[a]), si = wave_sum(ai[a]);
+        if (lane == 0) sh[wv][a] = make_double2(sr, si);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < r) {
+      double2 sres = make_double2(0.0, 0.0);
+      for (int w = 0; w < 4; ++w) sres = cadd(sres, sh[w][threadIdx.x]);
+      mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = sres;
+    }
+    __syncthreads();
+  }
+}
+
 // ----------------------------------------------------------------- CSR -----
 
 // Row pointer of the explicit matrix: uniform length Ny - 1 + 2 Nxi for
@@ -1056,6 +1250,46 @@ __global__ void __launch_bounds__(256) k_line_blocks_invert(double2* __restrict_
   if (threadIdx.x == 0) status[sl] = ok ? 0 : 1;
 }
 
+// The same for Ny <= 96 with the block held in LDS (147 KB at Ny = 96, one
+// workgroup per CU): built there, inverted by the same Gauss-Jordan steps, and
+// written out once; the global-memory version rewrites the whole block at every
+// step.  Results are bit-identical to it (same operations in the same order).
+constexpr int kLdsLineMax = 96;
+__global__ void __launch_bounds__(256) k_line_blocks_invert_lds(double2* __restrict__ Pinv, int Ny,
+                                                                const int* __restrict__ slot_node,
+                                                                const double* __restrict__ Dx,
+                                                                const double* __restrict__ xix,
+                                                                const double* __restrict__ xiy,
+                                                                const double* __restrict__ nu, double beta,
+                                                                double sre, double sim, int* __restrict__ status) {
+  __shared__ double2 mat[kLdsLineMax * kLdsLineMax];
+  __shared__ double2 srow[kLdsLineMax], fcol[kLdsLineMax];
+  __shared__ int piv[kLdsLineMax];
+  const int sl = blockIdx.x;
+  const int k = slot_node[sl];
+  const double xk = xix[k], by = beta * xiy[k];
+  for (int e = threadIdx.x; e < Ny * Ny; e += blockDim.x) {
+    const int j = e / Ny, i = e - j * Ny;
+    const bool bc = (i == Ny - 1 && xk > 0.0) || (i == 0 && xk < 0.0);
+    double2 v;
+    if (bc) {
+      v = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    } else {
+      v = make_double2(xk * Dx[(int64_t)i * Ny + j], 0.0);
+      if (i == j) {
+        v.x += nu[i] - sre;
+        v.y += by - sim;
+      }
+    }
+    mat[e] = v;
+  }
+  __syncthreads();
+  const bool ok = gj_invert(mat, Ny, srow, fcol, piv);
+  double2* a = Pinv + (int64_t)sl * Ny * Ny;
+  for (int e = threadIdx.x; e < Ny * Ny; e += blockDim.x) a[e] = mat[e];
+  if (threadIdx.x == 0) status[sl] = ok ? 0 : 1;
+}
+
 // Partial sums of the moment capacitance's coupling part
 //   G[(j, a), (j', b)] = sum_k P_k^{-1}(j, j') sum_f M_a(j, f, k) Ut_b(j', f, k)
 // (Ut = U with inflow rows zeroed) over the node range of part ks: grid (Ny [j'],
@@ -1110,9 +1344,11 @@ __global__ void __launch_bounds__(128) k_cap_partial(const double2* __restrict__
           acc[a][b].y = fma(w.y, g[a][b], acc[a][b].y);
         }
     }
-    for (int a = 0; a < r; ++a)
-      for (int b = 0; b < r; ++b)
-        part[((int64_t)ks * Rd + j * r + a) * Rd + jp * r + b] = acc[a][b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (a < r && b < r) part[((int64_t)ks * Rd + j * r + a) * Rd + jp * r + b] = acc[a][b];
   }
 }
 
@@ -1128,15 +1364,92 @@ __global__ void __launch_bounds__(256) k_cap_finish(const double2* __restrict__ 
   S[e] = make_double2((q == qc ? 1.0 : 0.0) - v.x, -v.y);
 }
 
-// In-place inverse of the capacitance (one workgroup).  status[0] = 1 if singular.
-__global__ void __launch_bounds__(1024) k_invert_one(double2* __restrict__ S, int N, int* __restrict__ status) {
-  extern __shared__ unsigned char lds_raw[];
-  double2* srow = reinterpret_cast<double2*>(lds_raw);
-  double2* fcol = srow + N;
-  int* piv = reinterpret_cast<int*>(fcol + N);
-  const bool ok = gj_invert(S, N, srow, fcol, piv);
-  if (threadIdx.x == 0) status[0] = ok ? 0 : 1;
+// Gauss-Jordan inversion of an N x N row-major matrix across many workgroups,
+// one pivot step per launch: step c reads A and writes the next iterate to B
+// (separate buffers, so no workgroup reads what another writes in the launch).
+// Every workgroup finds the pivot of column c itself (largest modulus among rows
+// >= c, the first on ties; the same result everywhere), and writes its rows of
+// the row-interchanged, eliminated matrix: row c = pivot row / pivot (entry c:
+// 1 / pivot), row p = old row c, and every row i != c gets row_i - a_ic row_c'
+// (entry c: -a_ic / pivot), exactly the in-place Gauss-Jordan update.  The
+// pivot row index is recorded in piv[c]; status[0] = 1 for a zero pivot.
+// grid ceil(N / 4), block 256 (4 rows per workgroup, lanes over columns).
+__global__ void __launch_bounds__(256) k_gj_step(const double2* __restrict__ A, double2* __restrict__ B, int N,
+                                                 int c, int* __restrict__ piv, int* __restrict__ status) {
+  __shared__ int s_p;
+  __shared__ double2 s_inv;
+  if (threadIdx.x < 64) {
+    double best = -1.0;
+    int bi = N;
+    for (int i = c + (int)threadIdx.x; i < N; i += 64) {
+      const double2 v = A[(int64_t)i * N + c];
+      const double mm = v.x * v.x + v.y * v.y;
+      if (mm > best) { best = mm; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (threadIdx.x == 0) {
+      s_p = (best > 0.0) ? bi : c;
+      const double2 pv = A[(int64_t)s_p * N + c];
+      const double pm = (best > 0.0) ? 1.0 / best : 0.0;
+      s_inv = make_double2(pv.x * pm, -pv.y * pm);
+      if (blockIdx.x == 0) {
+        piv[c] = s_p;
+        if (!(best > 0.0)) status[0] = 1;
+        else if (c == 0) status[0] = 0;
+      }
+    }
+  }
+  __syncthreads();
+  const int p = s_p;
+  const double2 inv = s_inv;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  if (i >= N) return;
+  const int src = (i == c) ? p : (i == p ? c : i);
+  const double2* arow = A + (int64_t)src * N;
+  const double2* prow = A + (int64_t)p * N;
+  double2* brow = B + (int64_t)i * N;
+  if (i == c) {
+    for (int j = lane; j < N; j += 64) brow[j] = (j == c) ? inv : cmul(prow[j], inv);
+  } else {
+    const double2 f = arow[c];
+    const double2 fi = cmul(f, inv);
+    for (int j = lane; j < N; j += 64) {
+      if (j == c) {
+        brow[j] = make_double2(-fi.x, -fi.y);
+      } else {
+        brow[j] = csub(arow[j], cmul(f, cmul(prow[j], inv)));
+      }
+    }
+  }
 }
+
+// out[i][j] = X[i][pi(j)] with pi the composition of the interchanges of rows c
+// and piv[c], c = 0 .. N-1 (the inverse of the interchanged matrix times the
+// permutation).  grid ceil(N / 4), block 256.
+__global__ void __launch_bounds__(256) k_gj_unpermute(const double2* __restrict__ X, double2* __restrict__ out,
+                                                      int N, const int* __restrict__ piv) {
+  extern __shared__ int s_pi[];
+  for (int j = threadIdx.x; j < N; j += blockDim.x) {
+    int pos = j;
+    for (int c = 0; c < N; ++c) {
+      const int q = piv[c];
+      if (pos == c) pos = q;
+      else if (pos == q) pos = c;
+    }
+    s_pi[j] = pos;
+  }
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + wv;
+  if (i >= N) return;
+  for (int j = lane; j < N; j += 64) out[(int64_t)i * N + j] = X[(int64_t)i * N + s_pi[j]];
+}
+
 
 // ------------------------------------------------------- vector kernels ----
 
@@ -1377,6 +1690,46 @@ __global__ void __launch_bounds__(256) k_combine(const cv<R>* __restrict__ S, in
   if (t >= n) return;
   const int mm = count ? min(m, *count) : m;
   out[(int64_t)j * n + t] = lincomb<R>(S, mm, n, t, coef + j, ldc);
+}
+
+// The same rotation for CB outputs per pass: every input entry S_i[t] is read
+// once per group of CB outputs instead of once per output; each output is
+// accumulated in the order of k_combine (i = 0, 1, ...), so the results are
+// bit-identical to it.  grid (ceil(n / 256), ceil(k / CB)).
+template <class R, int CB>
+__global__ void __launch_bounds__(256) k_combine_multi(const cv<R>* __restrict__ S, int m, int64_t n,
+                                                       const double2* __restrict__ coef, int ldc, int k,
+                                                       cv<R>* __restrict__ out, const int* __restrict__ count) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j0 = blockIdx.y * CB;
+  if (t >= n) return;
+  const int mm = count ? min(m, *count) : m;
+  cv<R> acc[CB];
+#pragma unroll
+  for (int q = 0; q < CB; ++q) acc[q] = mk<R>(0, 0);
+  int i = 0;
+  for (; i + 4 <= mm; i += 4) {
+    cv<R> sv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sv[u] = S[(int64_t)(i + u) * n + t];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2* cr = coef + (int64_t)(i + u) * ldc + j0;
+#pragma unroll
+      for (int q = 0; q < CB; ++q)
+        if (j0 + q < k) acc[q] = cadd(acc[q], cmul(sv[u], narrow<R>(cr[q])));
+    }
+  }
+  for (; i < mm; ++i) {
+    const cv<R> sv = S[(int64_t)i * n + t];
+    const double2* cr = coef + (int64_t)i * ldc + j0;
+#pragma unroll
+    for (int q = 0; q < CB; ++q)
+      if (j0 + q < k) acc[q] = cadd(acc[q], cmul(sv, narrow<R>(cr[q])));
+  }
+#pragma unroll
+  for (int q = 0; q < CB; ++q)
+    if (j0 + q < k) out[(int64_t)(j0 + q) * n + t] = acc[q];
 }
 
 // x *= 1 / sqrt(*nrm2) (nrm2 on device), optionally into dst.
@@ -1746,10 +2099,35 @@ __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
   }
 }
 
+// Vector groups for the many-vector kernels: enough workgroups to fill the chip
+// (about `want` of them over `per_group` workgroups per group).
+static void vector_groups(int nvec, int64_t per_group, int64_t want, int* VG, int* nvg) {
+  int g = (int)std::max<int64_t>(1, std::min<int64_t>(nvec, (want + per_group - 1) / per_group));
+  *VG = (nvec + g - 1) / g;
+  *nvg = (nvec + *VG - 1) / *VG;
+}
+//: batch sizes from which the many-vector operator and moment kernels take over
+constexpr int kBatchMin = 8;
+
 template <class R>
 static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                       const R* M, cv<R>* mom, const int* skip) {
   const int S = moment_splits(Ny, nvec, Nxi, sizeof(R) == 4 ? 1 : 0);
+  if constexpr (sizeof(R) == 8) {
+    const int per = (2 * Nxi + S - 1) / S;
+    if (nvec >= kBatchMin && !skip && per <= 3 * 256) {
+      int VG, nvg;
+      vector_groups(nvec, (int64_t)Ny * S, 2048, &VG, &nvg);
+      const dim3 g(Ny * S, nvg);
+      if (per <= 256)
+        hipLaunchKernelGGL((k_moments_batch<1>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+      else if (per <= 512)
+        hipLaunchKernelGGL((k_moments_batch<2>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+      else
+        hipLaunchKernelGGL((k_moments_batch<3>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+      return;
+    }
+  }
   if (nvec > 1)
     hipLaunchKernelGGL((k_moments<R>), dim3(Ny * S * nvec), dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, skip,
                        nvec);
@@ -1801,6 +2179,26 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   const int nc = 2 * Nxi;
   const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
   const int S = moment_splits(Ny, nvec, Nxi, 0);
+  const size_t lds_batch = 2 * ((size_t)((Ny + 3) & ~3) * 16 + (size_t)nrt * 16 * 4) * sizeof(double2);
+  if (nvec >= kBatchMin && !skip && nrt <= 8 && lds_batch <= 64 * 1024) {
+    int VG, nvg;
+    vector_groups(nvec, ctiles, 1024, &VG, &nvg);
+    const dim3 g(ctiles, nvg);
+#define KLST_MB(NRT_) hipLaunchKernelGGL((k_apply_mfma_batch<NRT_>), g, dim3(64 * NRT_), lds_batch, st, x, y, n, Ny, \
+                                         Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, nvec, VG)
+    switch (nrt) {
+      case 1: KLST_MB(1); break;
+      case 2: KLST_MB(2); break;
+      case 3: KLST_MB(3); break;
+      case 4: KLST_MB(4); break;
+      case 5: KLST_MB(5); break;
+      case 6: KLST_MB(6); break;
+      case 7: KLST_MB(7); break;
+      default: KLST_MB(8); break;
+    }
+#undef KLST_MB
+    return;
+  }
   int rt = 6;
   while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
   bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
@@ -1938,15 +2336,36 @@ void launch_structured_setup(hipStream_t st, double2* Pinv, double2* Sinv, doubl
                              const double* U, const double* M, double beta, double sre, double sim,
                              int* status) {
   const size_t lds_line = (size_t)Ny * (2 * sizeof(double2) + sizeof(int));
-  hipLaunchKernelGGL(k_line_blocks_invert, dim3(nslots), dim3(256), lds_line, st, Pinv, Ny, slot_node, Dx, xix,
-                     xiy, nu, beta, sre, sim, status + 1);
+  if (Ny <= kLdsLineMax)
+    hipLaunchKernelGGL(k_line_blocks_invert_lds, dim3(nslots), dim3(256), 0, st, Pinv, Ny, slot_node, Dx, xix, xiy,
+                       nu, beta, sre, sim, status + 1);
+  else
+    hipLaunchKernelGGL(k_line_blocks_invert, dim3(nslots), dim3(256), lds_line, st, Pinv, Ny, slot_node, Dx, xix,
+                       xiy, nu, beta, sre, sim, status + 1);
   const int Rd = r * Ny;
   hipLaunchKernelGGL(k_cap_partial, dim3(Ny, kCapParts), dim3(128), 0, st, Pinv, Ny, Nxi, r, slot_of, conj_of, M,
                      U, xix, part);
   hipLaunchKernelGGL(k_cap_finish, dim3(nblk((int64_t)Rd * Rd, 256)), dim3(256), 0, st, part, kCapParts, Rd,
                      Sinv);
-  const size_t lds_cap = (size_t)Rd * (2 * sizeof(double2) + sizeof(int));
-  hipLaunchKernelGGL(k_invert_one, dim3(1), dim3(1024), lds_cap, st, Sinv, Rd, status);
+  // the capacitance is assembled into part (free again after k_cap_finish has
+  // read it) and inverted by one Gauss-Jordan step per launch, ping-ponging
+  // between part and Sinv; piv sits after the two matrices in part
+  const int64_t RR = (int64_t)Rd * Rd;
+  double2* bufA = Sinv;
+  double2* bufB = part;
+  int* piv = reinterpret_cast<int*>(part + RR);
+  const unsigned rows = (unsigned)((Rd + 3) / 4);
+  for (int c = 0; c < Rd; ++c) {
+    hipLaunchKernelGGL(k_gj_step, dim3(rows), dim3(256), 0, st, bufA, bufB, Rd, c, piv, status);
+    std::swap(bufA, bufB);
+  }
+  // the final iterate is in bufA; undo the interchanges into Sinv
+  if (bufA == Sinv) {
+    hipLaunchKernelGGL(k_gj_unpermute, dim3(rows), dim3(256), (size_t)Rd * sizeof(int), st, Sinv, part, Rd, piv);
+    hipMemcpyAsync(Sinv, part, sizeof(double2) * RR, hipMemcpyDeviceToDevice, st);
+  } else {
+    hipLaunchKernelGGL(k_gj_unpermute, dim3(rows), dim3(256), (size_t)Rd * sizeof(int), st, part, Sinv, Rd, piv);
+  }
 }
 void launch_line_inverse(hipStream_t st, const double2* x, double2* y, int Ny, int Nxi, int r,
                          const double2* Pinv, const int* slot_node, const int* slot_mate, int nslots,
@@ -2060,8 +2479,12 @@ void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int
 
 void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, double2* out, const int* count) {
-  hipLaunchKernelGGL((k_combine<double>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
-                     count);
+  if (k >= 2)
+    hipLaunchKernelGGL((k_combine_multi<double, 8>), dim3(nblk(n, 256), (k + 7) / 8), dim3(256), 0, st, S, m, n,
+                       coef, ldc, k, out, count);
+  else
+    hipLaunchKernelGGL((k_combine<double>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
+                       count);
 }
 void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, float2* out, const int* count) {

@@ -62,8 +62,9 @@ void launch_structured_inverse(hipStream_t st, const float2* x, float2* y, int N
 // Device set-up of the structured inverse at shift sigma = (sre, sim): the line
 // blocks of the nslots stored slots built and inverted into Pinv [nslots][Ny x
 // Ny] (column-major), the capacitance S = I - M P^{-1} Ut assembled from
-// kCapParts partial sums (part: kCapParts (r Ny)^2 entries of scratch) and
-// inverted into Sinv [(r Ny)^2] (row-major).  slot_of / conj_of [Nxi]: node k's
+// kCapParts partial sums (part: kCapParts (r Ny)^2 entries of scratch, reused
+// for the inversion's second buffer and pivot list) and inverted into Sinv
+// [(r Ny)^2] (row-major) by one Gauss-Jordan pivot step per launch.  slot_of / conj_of [Nxi]: node k's
 // slot and whether it is the slot's mirrored node.  Dx row-major.
 // status [1 + nslots]: status[0] = 1 for a singular capacitance, status[1 + s]
 // = 1 for a singular line block of slot s.  Needs 2 (r Ny) x 16 + (r Ny) x 4
