@@ -78,7 +78,11 @@ typedef struct {
                            lines_per_block unused (the default).  Mixed precision
                            needs 1 or 2.                                             */
   int inner_max_it;     /* GMRES steps per correction equation, over all restarts;
-                           values <= gmres_m give one unrestarted cycle              */
+                           values <= gmres_m give one unrestarted cycle; 0 (the
+                           default) = gmres_m in FP64 and 3 gmres_m in mixed
+                           precision (three FP64-refined FP32 cycles: one FP32
+                           cycle alone can stall the outer iteration near
+                           relative residual 1e-7 at ill-conditioned pairs)     */
   int reorth;           /* GMRES Arnoldi orthogonalisation: 0 = classical Gram-Schmidt
                            twice (CGS2, the default); 1 = second pass only when the
                            first keeps less than 1/sqrt(2) of the norm (DGKS test,
@@ -166,9 +170,10 @@ klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const 
 /* klst_apply_many without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same product, same kernels and bit-identical results as
- * klst_apply_many; the moment partial sums go to a library-owned device array
- * of 2^19 complex doubles (8 MiB per GPU, held until the process ends) instead
- * of context memory, so nvec * Ny * r * 8 must not exceed 2^19 (r = 4 for
+ * klst_apply_many; the moment partial sums and their totals go to a
+ * library-owned device array of 2^19 complex doubles (8 MiB per GPU, held until
+ * the process ends) instead of context memory, so nvec * Ny * r * 9 must not
+ * exceed 2^19 (r = 4 for
  * Dv = 2, 3 for Dv = 1).  The array is shared by every call on the GPU: calls
  * that overlap on one GPU (two streams, two threads) race and give undefined
  * results; calls ordered on one stream are safe.  Nothing in it needs to start
@@ -266,8 +271,10 @@ klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma[2], int ne
 /* ---------------------------------------------------------------------------
  * Launch autotuning.  The library keeps a process-wide table of launch choices
  * keyed by (Ny, Nxi, nvec, precision): row tiles and wavefronts of the
- * matrix-core operator (apply_tile, apply_waves; for FP32, rows per thread in
- * apply_tile), column parts of the moment sums (moment_splits) and wavefronts
+ * matrix-core operator (apply_tile, apply_waves; apply_waves = 8 selects the
+ * streaming many-vector kernel, the default from 8 vectors on; for FP32, rows
+ * per thread in apply_tile), column parts of the moment sums (moment_splits)
+ * and wavefronts
  * of the block GEMVs of the preconditioners (gemv_waves); 0 = the built-in
  * heuristic.  Tile and wave choices leave results bit-identical; moment splits
  * and GEMV waves change the order of summation, so the table must be fixed

@@ -164,7 +164,7 @@ void free_problem(klst_ctx* ctx) {
 klst_status ensure_mom(klst_ctx* ctx, int nvec) {
   if (ctx->mom_cap >= nvec) return KLST_OK;
   dfree(ctx, ctx->d_mom);
-  ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 8);
+  ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 9);
   ctx->mom_cap = nvec;
   return KLST_OK;
 }
@@ -487,7 +487,7 @@ void klst_default_options(klst_options* o) {
   o->fix = 0.01;
   o->seed = 0;
   o->pc_kernel = 2;
-  o->inner_max_it = 20;
+  o->inner_max_it = 0;
   o->reorth = 0;
   o->method = 0;
 }
@@ -517,7 +517,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
       !(o.tol > 0) || !(o.inner_rtol > 0) || o.lines_per_block < 1 || o.lines_per_block > 16 ||
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 248 ||
       o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
-      o.inner_max_it < 1 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1) ||
+      o.inner_max_it < 0 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1) ||
       (o.method != 0 && o.method != 1))
     return KLST_EINVAL;
   int ndev = 0;
@@ -695,10 +695,10 @@ klst_status klst_apply_many_noalloc(klst_ctx* ctx, const double tau[2], int nvec
   if (!ctx || !tau || !x || !y || nvec < 1 || nvec > 65535) return KLST_EINVAL;
   if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many_noalloc before klst_assemble");
   const klst::Problem& p = ctx->prob;
-  // moment partials: nvec x Ny x r x (up to 8 column parts) entries
-  if ((size_t)nvec * p.Ny * p.r * 8 > kScratchEntries)
-    return fail(ctx, KLST_EINVAL, "klst_apply_many_noalloc: nvec * Ny * r * 8 = " +
-                                      std::to_string((size_t)nvec * p.Ny * p.r * 8) + " exceeds the " +
+  // moment partials (up to 8 column parts) and their totals: nvec x Ny x r x 9 entries
+  if ((size_t)nvec * p.Ny * p.r * 9 > kScratchEntries)
+    return fail(ctx, KLST_EINVAL, "klst_apply_many_noalloc: nvec * Ny * r * 9 = " +
+                                      std::to_string((size_t)nvec * p.Ny * p.r * 9) + " exceeds the " +
                                       std::to_string(kScratchEntries) + "-entry scratch");
   HIPCHK(hipSetDevice(ctx->opt.device));
   double2* mom = scratch_on(ctx->opt.device);
@@ -850,10 +850,12 @@ klst_status klst_autotune(klst_ctx* ctx, int nvec, int precision, int reps, klst
   // operator tiling (result-invariant)
   std::vector<std::pair<int, int>> tiles;
   if (precision) tiles = {{4, 0}, {8, 0}, {16, 0}};
-  else
+  else {
     for (int rt : {1, 2, 3, 6})
       if ((rt - 1) * 16 < Ny)
         for (int nw : {1, 4}) tiles.push_back({rt, nw});
+    if (nvec >= 8) tiles.push_back({0, 8});   // the streaming many-vector kernel
+  }
   for (auto [rt, nw] : tiles) {
     Tuning t;
     t.apply_rt = rt;
@@ -1142,7 +1144,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   const int m_max = std::max(o.m_max, o.m_min + 2);
   const int m_min = o.m_min;
   const int gm = o.gmres_m;
-  const int imax = std::max(o.inner_max_it, 1);
+  // correction-equation budget: 0 selects one GMRES cycle in FP64 and three
+  // FP64-refined FP32 cycles in mixed precision
+  const int imax = o.inner_max_it > 0 ? o.inner_max_it : (o.precision == 1 ? 3 * o.gmres_m : o.gmres_m);
   const cd sigma(sigma_in[0], sigma_in[1]);
   hipStream_t st = ctx->stream;
   ctx->stats = klst_stats{};

@@ -5,6 +5,7 @@
 // partial sums are combined in a fixed order by the kernel that consumes them,
 // with no cross-workgroup synchronisation.
 #include <hip/hip_runtime.h>
+#include <atomic>
 #include <algorithm>
 #include <array>
 #include <cstdint>
@@ -60,9 +61,38 @@ __device__ __forceinline__ cv<R> lincomb(const cv<R>* __restrict__ S, int m, int
   return acc;
 }
 
+// 64-bit value of lane l' for each lane l, l' given by a DPP lane pattern
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value in
+// every lane.  A fixed butterfly: lane pairs l ^ 1 and l ^ 2 (quad
+// permutations), then the two quads of each 8 (half-row mirror), the two halves
+// of each 16 (row mirror), the two rows of each 32 (swizzle swap 16), each
+// stage adding two equal-shaped partial sums, and finally the two 32-lane
+// halves read from lanes 0 and 32.  Addition is commutative in IEEE
+// arithmetic, so every lane of a group holds the same bits after each stage and
+// the result is deterministic.  The lane moves run on the VALU (DPP) and the
+// LDS crossbar without memory traffic, unlike 64-lane permutes.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f64<0x141>(v);   // row_half_mirror
+  v += dpp_f64<0x140>(v);   // row_mirror
+  {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);   // lane ^ 16 within 32
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    v += __hiloint2double(hi, lo);
+  }
+  const double h0 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                     __builtin_amdgcn_readlane(__double2loint(v), 0));
+  const double h1 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                     __builtin_amdgcn_readlane(__double2loint(v), 32));
+  return h0 + h1;
 }
 
 // Sum of a double2 over a 256-thread block, result valid in thread 0.
@@ -92,6 +122,23 @@ __device__ __forceinline__ int64_t xcd_item(int64_t L, int64_t N) {
 }
 
 // ------------------------------------------------------------ operator ----
+
+// One output entry of y = (A - tau B) x from its streaming sum (sr, si) =
+// (D_x x)(j, c): xi_x times the sum plus the diagonal (dre + i dim) times x(j,
+// c); then op_moment subtracts each rank-r moment term.  Written as explicit
+// fused multiply-adds so that every operator kernel rounds an entry the same
+// way, whatever contractions the compiler would pick in each.
+__device__ __forceinline__ double2 op_out(double xik, double sr, double si, double dre, double dim,
+                                          double2 xjc) {
+  double2 o;
+  o.x = fma(xik, sr, fma(dre, xjc.x, -(dim * xjc.y)));
+  o.y = fma(xik, si, fma(dre, xjc.y, dim * xjc.x));
+  return o;
+}
+__device__ __forceinline__ void op_moment(double2& o, double ua, double2 ma) {
+  o.x = fma(-ua, ma.x, o.x);
+  o.y = fma(-ua, ma.y, o.y);
+}
 
 // Perturbation moments m_a(j) = sum_{f,p} M[j][a][f][p] x[j][f][p] (rank r <= 4)
 // for each node j and vector v, split over S column parts: workgroup
@@ -404,15 +451,13 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
         out = xjc;
       } else {
         const double dre = (kPre ? pre_nu[q] : nu[j]) - tau_re, dim = bxy - tau_im;
-        out.x = xik * are[t][q] + dre * xjc.x - dim * xjc.y;
-        out.y = xik * aim[t][q] + dre * xjc.y + dim * xjc.x;
+        out = op_out(xik, are[t][q], aim[t][q], dre, dim, xjc);
         if constexpr (kPre) {
 #pragma unroll
           for (int a = 0; a < 4; ++a) {
             if (a < r) {
               const double2 ma = ms[jl * 4 + a];
-              out.x -= pre_u[q][a] * ma.x;
-              out.y -= pre_u[q][a] * ma.y;
+              op_moment(out, pre_u[q][a], ma);
             }
           }
         } else {
@@ -421,8 +466,7 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
           for (int a = 0; a < r; ++a) {
             const double ua = Uj[(int64_t)a * Nxi];
             const double2 ma = ms[jl * 4 + a];
-            out.x -= ua * ma.x;
-            out.y -= ua * ma.y;
+            op_moment(out, ua, ma);
           }
         }
       }
@@ -431,153 +475,214 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   }
 }
 
-// Many-vector operator, y_v = (A - tau B) x_v for a group of vectors: one
-// workgroup per (16-column tile, vector group), one wavefront per 16-row tile
-// (NRT wavefronts).  Each wavefront keeps its row tile's D_x fragments (the A
-// operands of v_mfma_f64_16x16x4f64) and its epilogue operands (U, nu, xi) in
-// registers for the whole group; the column strip of x (Ny x 16) and the
-// moments of each vector are staged in LDS, double-buffered so that the next
-// vector's strip loads while the current one's MFMAs run.  Every output entry
-// is accumulated in the order of k_apply_mfma (K in steps of 4 from 0, then the
-// epilogue terms in the same order), so the results are bit-identical to it.
-// grid (ceil(2 Nxi / 16), vector groups), block 64 NRT; dynamic LDS
-// 2 (Ny4 x 16 + NRT x 16 x 4) double2, Ny4 = Ny rounded up to 4.
-template <int NRT>
-__global__ void __launch_bounds__(64 * NRT) k_apply_mfma_batch(const double2* __restrict__ x,
-                                                               double2* __restrict__ y, int64_t n, int Ny,
-                                                               int Nxi, int r, double tau_re, double tau_im,
-                                                               double beta, const double* __restrict__ DxT,
-                                                               const double* __restrict__ xi_x,
-                                                               const double* __restrict__ xi_y,
-                                                               const double* __restrict__ nu,
-                                                               const double* __restrict__ U,
-                                                               const double2* __restrict__ mom, int S, int nvec,
-                                                               int VG) {
-  constexpr int K4 = 4 * NRT;                       // K steps of 4 rows, Ny <= 16 NRT
-  extern __shared__ unsigned char lds_raw[];
-  const int Ny4 = (Ny + 3) & ~3;
-  double2* xs = reinterpret_cast<double2*>(lds_raw);           // [2][Ny4][16]
-  double2* ms = xs + 2 * Ny4 * 16;                              // [2][NRT * 16][4]
+// Load / store at a uniform base plus a 32-bit byte offset (the global_load
+// form with a scalar base and a 32-bit vector offset).
+template <class T>
+__device__ __forceinline__ T ld_off(const T* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const unsigned char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<unsigned char*>(base) + byte_off) = v;
+}
+
+// Totals of the S moment parts of nvec vectors, in the order of mom_at:
+// tot[(v Ny + j) r + a].  One thread per entry.
+__global__ void __launch_bounds__(256) k_mom_total(const double2* __restrict__ mom, double2* __restrict__ tot,
+                                                   int64_t count, int r, int S) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  const int64_t vj = e / r, a = e - vj * r;
+  const double2* p = mom + vj * S * r + a;
+  double2 part[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) part[q] = (q < S) ? p[(int64_t)q * r] : make_double2(0.0, 0.0);
+  double2 s = part[0];
+#pragma unroll
+  for (int q = 1; q < 8; ++q)
+    if (q < S) s = cadd(s, part[q]);
+  tot[e] = s;
+}
+
+// Many-vector operator as a stream of work items, y_v = (A - tau B) x_v.  An
+// item is (group of WPG 16-column tiles, vector v); wavefront w computes the
+// whole output strip (all N_y rows) of column tile WPG g + w for vector v.
+// * The D_x fragments of every row tile (the A operands of
+//   v_mfma_f64_16x16x4f64) sit in LDS in lane order, so each K step reads them
+//   conflict-free with one 8-byte load per lane and row tile.
+// * The x strip streams from memory into registers in chunks of XB K steps;
+//   the next chunk, of this item or of the next, loads while the current
+//   chunk's MFMAs run.  The one barrier per item orders only LDS (an LDS-only
+//   fence), so these loads stay in flight across it.
+// * The item's moments (totals over the column parts, summed in fixed order by
+//   k_mom_total) are staged in LDS, double buffered; the next item's load
+//   during the current epilogue.
+// * Loads and stores within one vector or table address it as a uniform base
+//   plus a 32-bit byte offset (each vector and table is under 4 GiB, checked by
+//   the launcher), which keeps the address arithmetic in few registers.
+// Every output entry is accumulated as in k_apply_mfma (K in steps of 4 from 0,
+// then op_out and op_moment), so the results are bit-identical to it.
+// Workgroup b takes a contiguous range of items, ordered column group major and
+// vector minor, at its XCD-ordered index, so the U entries and tables of a
+// column group are reused from one L2.  A wavefront whose tile lies past the
+// last column (in the last group) only relays the next item's first chunk.
+// grid ceil(items / per), block 64 WPG; items = ceil(ceil(2 Nxi / 16) / WPG) nvec.
+template <int NRT, int WPG, int RR>
+__global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __restrict__ x,
+                                                          double2* __restrict__ y, int64_t n, int Ny,
+                                                          int Nxi, double tau_re, double tau_im,
+                                                          double beta, const double* __restrict__ DxT,
+                                                          const double* __restrict__ xi_x,
+                                                          const double* __restrict__ xi_y,
+                                                          const double* __restrict__ nu,
+                                                          const double* __restrict__ U,
+                                                          const double2* __restrict__ mtot, int nvec,
+                                                          int64_t nitems, int per) {
+  constexpr int K4 = 4 * NRT;             // K steps of 4 rows, N_y <= 16 NRT
+  constexpr int XB = 4;                   // K steps per chunk
+  constexpr int NMOM = NRT * 16 * 4;      // moments of one vector: rows x 4
+  __shared__ double afs[K4 * NRT * 64];   // [step][row tile][lane]
+  __shared__ double2 ms[2][NMOM];         // [buffer][row * 4 + a]
   const int nc = 2 * Nxi;
-  const int c0 = blockIdx.x * 16;
-  const int v0 = blockIdx.y * VG, v1 = min(nvec, v0 + VG);
-  const int t = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int nthr = 64 * NRT;
-  // A fragments: row t*16 + li, K index 4 s + lk
-  double afr[K4];
-#pragma unroll
-  for (int s2 = 0; s2 < K4; ++s2) {
-    const int m = 4 * s2 + lk, row = t * 16 + li;
-    afr[s2] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+  const int64_t i0 = xcd_item(blockIdx.x, gridDim.x) * per;
+  const int64_t i1 = min(nitems, i0 + per);
+  if (i0 >= i1) return;                   // uniform over the workgroup
+  // fragment (s, t, l) = D_x[t 16 + l % 16][4 s + l / 16] = DxT[(4 s + l / 16) Ny + t 16 + l % 16]
+  for (int idx = threadIdx.x; idx < K4 * NRT * 64; idx += 64 * WPG) {
+    const int l = idx & 63, st = idx >> 6;
+    const int t = st % NRT, s = st / NRT;
+    const int m = 4 * s + (l >> 4), row = t * 16 + (l & 15);
+    afs[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
   }
-  // epilogue operands of this lane: column c, rows j = t*16 + lk + 4q
-  const int c = c0 + li;
-  const bool cok = c < nc;
-  const int f = cok ? c / Nxi : 0, k = cok ? c - f * Nxi : 0;
-  const double xik = cok ? xi_x[k] : 0.0, bxy = cok ? beta * xi_y[k] : 0.0;
-  double nuq[4], uq[4][4];
-  bool bcq[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int j = t * 16 + lk + 4 * q;
-    const bool ok = cok && j < Ny;
-    nuq[q] = ok ? nu[j] : 0.0;
-    bcq[q] = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
-#pragma unroll
-    for (int a = 0; a < 4; ++a) uq[q][a] = (ok && a < r) ? U[((int64_t)(j * 2 + f) * r + a) * Nxi + k] : 0.0;
-  }
-  // staging of one vector: x strip (rows >= Ny zero) and its moments (S parts summed)
-  constexpr int XPT = 4;          // strip entries per thread: Ny4 x 16 <= 256 NRT
-  const int xcount = Ny4 * 16, mcount = NRT * 16 * 4;
-  auto load_strip = [&](int v, double2* xr, double2* mr) {
+  const int nsteps = (Ny + 3) >> 2;
+  const int nch = (nsteps + XB - 1) / XB;
+  const bool mthr = threadIdx.x < NMOM;
+  const int mj = threadIdx.x >> 2, ma = threadIdx.x & 3;
+  // moment entry (mj, ma) of vector v
+  auto mom_load = [&](int v) {
+    return (mthr && mj < Ny && ma < RR) ? mtot[((int64_t)v * Ny + mj) * RR + ma] : make_double2(0.0, 0.0);
+  };
+  auto load_chunk = [&](int v, int c, int ch, double2* dst) {
     const double2* xv = x + (int64_t)v * n;
 #pragma unroll
-    for (int e = 0; e < XPT; ++e) {
-      const int idx = threadIdx.x + e * nthr;
-      const int m = idx >> 4, cc = c0 + (idx & 15);
-      xr[e] = (idx < xcount && m < Ny && cc < nc) ? xv[(int64_t)m * nc + cc] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int e = 0; e < 1; ++e) {
-      const int idx = threadIdx.x + e * nthr;
-      const int jl = idx >> 2, a = idx & 3;
-      mr[e] = (idx < mcount && jl < Ny && a < r) ? mom_at<double>(mom, v, Ny, jl, a, r, S) : make_double2(0.0, 0.0);
+    for (int p = 0; p < XB; ++p) {
+      const int m = 4 * (ch * XB + p) + lk;
+      dst[p] = (m < Ny && c < nc) ? ld_off(xv, (uint32_t)(m * nc + c) * 16u) : make_double2(0.0, 0.0);
     }
   };
-  auto store_strip = [&](int buf, const double2* xr, const double2* mr) {
-#pragma unroll
-    for (int e = 0; e < XPT; ++e) {
-      const int idx = threadIdx.x + e * nthr;
-      if (idx < xcount) xs[buf * xcount + idx] = xr[e];
-    }
-#pragma unroll
-    for (int e = 0; e < 1; ++e) {
-      const int idx = threadIdx.x + e * nthr;
-      if (idx < mcount) ms[buf * mcount + idx] = mr[e];
-    }
-  };
-  double2 xr[XPT], mr[1];         // moments: NRT x 16 x 4 = 64 NRT entries, one per thread
-  if (v0 < v1) {
-    load_strip(v0, xr, mr);
-    store_strip(0, xr, mr);
-  }
+  int v = (int)(i0 % nvec), g = (int)(i0 / nvec);
+  if (mthr) ms[0][threadIdx.x] = mom_load(v);
+  double2 xa[XB], xb[XB];
+  load_chunk(v, (g * WPG + w) * 16 + li, 0, xa);
   __syncthreads();
-  for (int v = v0; v < v1; ++v) {
-    const int buf = (v - v0) & 1;
-    if (v + 1 < v1) load_strip(v + 1, xr, mr);
-    const double2* xb = xs + buf * xcount;
-    dbl4 are = dbl4{0, 0, 0, 0}, aim = dbl4{0, 0, 0, 0};
+  int buf = 0;
+  for (int64_t it = i0; it < i1; ++it, buf ^= 1) {
+    const int c = (g * WPG + w) * 16 + li;
+    const bool more = it + 1 < i1;
+    const int vn = (v + 1 == nvec) ? 0 : v + 1, gn = (v + 1 == nvec) ? g + 1 : g;
+    const int cn = (gn * WPG + w) * 16 + li;
+    dbl4 are[NRT], aim[NRT];
 #pragma unroll
-    for (int s2 = 0; s2 < K4; ++s2) {
-      if (4 * s2 < Ny) {
-        const double2 b = xb[(4 * s2 + lk) * 16 + li];
-        are = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s2], b.x, are, 0, 0, 0);
-        aim = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s2], b.y, aim, 0, 0, 0);
-      }
-    }
-    if (cok) {
-      const double2* mb = ms + buf * mcount;
-      double2* yv = y + (int64_t)v * n;
+    for (int t = 0; t < NRT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
+    if ((g * WPG + w) * 16 < nc) {
+      for (int ch = 0; ch < nch; ++ch) {
+        if (ch + 1 < nch) load_chunk(v, c, ch + 1, xb);
+        else if (more) load_chunk(vn, cn, 0, xb);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int jl = t * 16 + lk + 4 * q;
-        if (jl >= Ny) continue;
-        const double2 xjc = xb[jl * 16 + li];
-        double2 out;
-        if (bcq[q]) {
-          out = xjc;
-        } else {
-          const double dre = nuq[q] - tau_re, dim = bxy - tau_im;
-          out.x = xik * are[q] + dre * xjc.x - dim * xjc.y;
-          out.y = xik * aim[q] + dre * xjc.y + dim * xjc.x;
+        for (int p = 0; p < XB; ++p) {
+          const int s = ch * XB + p;
+          if (s < nsteps) {
 #pragma unroll
-          for (int a = 0; a < 4; ++a) {
-            if (a < r) {
-              const double2 ma = mb[jl * 4 + a];
-              out.x -= uq[q][a] * ma.x;
-              out.y -= uq[q][a] * ma.y;
+            for (int t = 0; t < NRT; ++t) {
+              const double a = afs[(s * NRT + t) * 64 + lane];
+              are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xa[p].x, are[t], 0, 0, 0);
+              aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xa[p].y, aim[t], 0, 0, 0);
             }
           }
         }
-        yv[(int64_t)jl * nc + c] = out;
+#pragma unroll
+        for (int p = 0; p < XB; ++p) xa[p] = xb[p];
+      }
+    } else if (more) {
+      load_chunk(vn, cn, 0, xa);
+    }
+    // the next item's moments load during the epilogue
+    const double2 mnext = more ? mom_load(vn) : make_double2(0.0, 0.0);
+    // epilogue on the accumulator layout: column c, rows j = t 16 + lk + 4 q.
+    // The row index is made opaque per item so the compiler keeps no
+    // per-row masks or offsets live across items; loads take clamped rows and
+    // only the stores are guarded.
+    int lko = lk;
+    asm volatile("" : "+v"(lko));
+    if (c < nc) {
+      const int f = c / Nxi, k = c - f * Nxi;
+      const double xik = xi_x[k], bxy = beta * xi_y[k];
+      const double2* xv = x + (int64_t)v * n;
+      double2* yv = y + (int64_t)v * n;
+      const double2* mb = ms[buf];
+#pragma unroll
+      for (int t = 0; t < NRT; ++t) {
+        if (t * 16 < Ny) {
+          double2 xq[4];
+          double nq[4], uq[4][RR];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int jc = min(t * 16 + lko + 4 * q, Ny - 1);
+            xq[q] = ld_off(xv, (uint32_t)(jc * nc + c) * 16u);
+            nq[q] = nu[jc];
+#pragma unroll
+            for (int a = 0; a < RR; ++a)
+              uq[q][a] = ld_off(U + (int64_t)a * Nxi, (uint32_t)((jc * 2 + f) * RR * Nxi + k) * 8u);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = t * 16 + lko + 4 * q;
+            if (j < Ny) {
+              const double2 xjc = xq[q];
+              const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
+              double2 out;
+              if (bc) {
+                out = xjc;
+              } else {
+                const double dre = nq[q] - tau_re, dim = bxy - tau_im;
+                out = op_out(xik, are[t][q], aim[t][q], dre, dim, xjc);
+#pragma unroll
+                for (int a = 0; a < RR; ++a) op_moment(out, uq[q][a], mb[j * 4 + a]);
+              }
+              st_off(yv, (uint32_t)(j * nc + c) * 16u, out);
+            }
+          }
+        }
+        // one row tile's epilogue loads in flight at a time (keeps the
+        // accumulators, the prefetched chunk and these loads in registers)
+        asm volatile("" ::: "memory");
       }
     }
-    if (v + 1 < v1) store_strip(buf ^ 1, xr, mr);
-    __syncthreads();
+    if (more && mthr) ms[buf ^ 1][threadIdx.x] = mnext;
+    // LDS-only barrier: the next item's first x chunk stays in flight
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    v = vn;
+    g = gn;
   }
 }
 
 // Moment partials of a group of vectors per workgroup (node j, column part):
 // each thread holds the M entries of its columns (the columns k_moments gives
 // it) in registers and sums every vector of the group in the order of
-// k_moments, so the partials are bit-identical to it.  grid (Ny S, vector
-// groups), block 256; CPT = columns per thread (the part has <= 256 CPT).
+// k_moments, so the partials are bit-identical to it.  The next vector's x
+// entries load while the current one is reduced; the per-vector exchange of
+// wavefront sums is double buffered with one LDS-only barrier, so those loads
+// stay in flight across it.  grid (Ny S, vector groups), block 256; CPT =
+// columns per thread (the part has <= 256 CPT).
 template <int CPT>
 __global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict__ x, int64_t n, int Ny, int Nxi,
                                                        int r, const double* __restrict__ M,
                                                        double2* __restrict__ mom, int S, int nvec, int VG) {
-  __shared__ double2 sh[4][4];
+  __shared__ double2 sh[2][4][4];
   const int j = blockIdx.x / S, part = blockIdx.x - j * S;
   const int v0 = blockIdx.y * VG, v1 = min(nvec, v0 + VG);
   const int nc = 2 * Nxi;
@@ -591,19 +696,29 @@ __global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict
     for (int a = 0; a < 4; ++a) mw[i][a] = (cc < cend && a < r) ? M[((int64_t)j * r + a) * nc + cc] : 0.0;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int v = v0; v < v1; ++v) {
+  auto load = [&](int v, double2* xr) {
     const double2* xj = x + (int64_t)v * n + (int64_t)j * nc;
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int cc = cbeg + threadIdx.x + 256 * i;
+      xr[i] = (cc < cend) ? xj[cc] : make_double2(0.0, 0.0);
+    }
+  };
+  double2 xc[CPT], xn[CPT];
+  if (v0 < v1) load(v0, xc);
+  for (int v = v0; v < v1; ++v) {
+    const int buf = (v - v0) & 1;
+    if (v + 1 < v1) load(v + 1, xn);
     double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int cc = cbeg + threadIdx.x + 256 * i;
       if (cc < cend) {
-        const double2 xv = xj[cc];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
           if (a < r) {
-            ar[a] += mw[i][a] * xv.x;
-            ai[a] += mw[i][a] * xv.y;
+            ar[a] += mw[i][a] * xc[i].x;
+            ai[a] += mw[i][a] * xc[i].y;
           }
         }
       }
@@ -612,16 +727,19 @@ __global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict
     for (int a = 0; a < 4; ++a) {
       if (a < r) {
         const double sr = wave_sum(ar[a]), si = wave_sum(ai[a]);
-        if (lane == 0) sh[wv][a] = make_double2(sr, si);
+        if (lane == 0) sh[buf][wv][a] = make_double2(sr, si);
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
     if (threadIdx.x < r) {
       double2 sres = make_double2(0.0, 0.0);
-      for (int w = 0; w < 4; ++w) sres = cadd(sres, sh[w][threadIdx.x]);
+      for (int w = 0; w < 4; ++w) sres = cadd(sres, sh[buf][w][threadIdx.x]);
       mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = sres;
     }
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) xc[i] = xn[i];
   }
 }
 
@@ -2099,6 +2217,19 @@ __global__ void __launch_bounds__(256) k_bgk_stage(const double* __restrict__ q,
   }
 }
 
+// Compute units of the current device (cached per device).
+static int64_t device_cus() {
+  static std::atomic<int> cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int c = cache[dev].load(std::memory_order_relaxed);
+  if (c <= 0) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cache[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
 // Vector groups for the many-vector kernels: enough workgroups to fill the chip
 // (about `want` of them over `per_group` workgroups per group).
 static void vector_groups(int nvec, int64_t per_group, int64_t want, int* VG, int* nvg) {
@@ -2170,7 +2301,7 @@ static void apply_t(hipStream_t st, const cv<R>* x, cv<R>* y, int64_t n, int nve
 }
 void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const double* Dx, const double* xix,
-                  const double* xiy, const double* nu, const double* U, const double2* mom,
+                  const double* xiy, const double* nu, const double* U, double2* mom,
                   const int* skip) {
   // FP64: streaming GEMM on the matrix cores.  Large launches use workgroups of
   // 4 wavefronts sharing an LDS copy of their D_x row slice; small ones use one
@@ -2179,24 +2310,41 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   const int nc = 2 * Nxi;
   const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
   const int S = moment_splits(Ny, nvec, Nxi, 0);
-  const size_t lds_batch = 2 * ((size_t)((Ny + 3) & ~3) * 16 + (size_t)nrt * 16 * 4) * sizeof(double2);
-  if (nvec >= kBatchMin && !skip && nrt <= 8 && lds_batch <= 64 * 1024) {
-    int VG, nvg;
-    vector_groups(nvec, ctiles, 1024, &VG, &nvg);
-    const dim3 g(ctiles, nvg);
-#define KLST_MB(NRT_) hipLaunchKernelGGL((k_apply_mfma_batch<NRT_>), g, dim3(64 * NRT_), lds_batch, st, x, y, n, Ny, \
-                                         Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, nvec, VG)
+  Tuning tq;
+  const bool tq_ok = tune_get(Ny, Nxi, nvec, 0, &tq);
+  // the streaming kernel addresses each vector and the U table with 32-bit byte offsets
+  const bool off32 = (uint64_t)n * sizeof(double2) < ((uint64_t)1 << 32) &&
+                     (uint64_t)Ny * 2 * r * Nxi * sizeof(double) < ((uint64_t)1 << 32);
+  if (nvec >= kBatchMin && !skip && nrt <= 6 && off32 && (r == 3 || r == 4) &&
+      (!tq_ok || tq.apply_nw == 0 || tq.apply_nw == 8)) {
+    constexpr int WPG = 8;
+    // moment totals after the partials (mom holds nvec Ny r 9 entries)
+    double2* tot = mom + (size_t)nvec * Ny * r * 8;
+    const int64_t ntot = (int64_t)nvec * Ny * r;
+    hipLaunchKernelGGL(k_mom_total, dim3(nblk(ntot, 256)), dim3(256), 0, st, mom, tot, ntot, r, S);
+    const int64_t groups = (ctiles + WPG - 1) / WPG;
+    const int64_t items = groups * nvec;
+    const int64_t slots = device_cus();                  // one 8-wavefront workgroup per CU
+    const int per = (int)std::max<int64_t>(1, (items + slots - 1) / slots);
+    const int nwg = (int)((items + per - 1) / per);
+#define KLST_MS(NRT_)                                                                                        \
+  do {                                                                                                       \
+    if (r == 4)                                                                                              \
+      hipLaunchKernelGGL((k_apply_stream<NRT_, WPG, 4>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
+                         tre, tim, beta, Dx, xix, xiy, nu, U, tot, nvec, items, per);                        \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_apply_stream<NRT_, WPG, 3>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
+                         tre, tim, beta, Dx, xix, xiy, nu, U, tot, nvec, items, per);                        \
+  } while (0)
     switch (nrt) {
-      case 1: KLST_MB(1); break;
-      case 2: KLST_MB(2); break;
-      case 3: KLST_MB(3); break;
-      case 4: KLST_MB(4); break;
-      case 5: KLST_MB(5); break;
-      case 6: KLST_MB(6); break;
-      case 7: KLST_MB(7); break;
-      default: KLST_MB(8); break;
+      case 1: KLST_MS(1); break;
+      case 2: KLST_MS(2); break;
+      case 3: KLST_MS(3); break;
+      case 4: KLST_MS(4); break;
+      case 5: KLST_MS(5); break;
+      default: KLST_MS(6); break;
     }
-#undef KLST_MB
+#undef KLST_MS
     return;
   }
   int rt = 6;

@@ -30,12 +30,13 @@ void tune_clear();
 std::vector<std::pair<std::array<int, 4>, Tuning>> tune_all();
 int moment_splits(int Ny, int nvec, int Nxi, int prec);
 
-// Moment partial sums: mom must hold Ny * r * nvec * 8 entries (up to 8 column parts).
+// Moment partial sums: mom must hold Ny * r * nvec * 9 entries (up to 8 column
+// parts; the many-vector operator writes the totals over the parts after them).
 void launch_moments(hipStream_t st, const double2* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                     const double* M, double2* mom, const int* skip);
 void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const double* Dx, const double* xix,
-                  const double* xiy, const double* nu, const double* U, const double2* mom,
+                  const double* xiy, const double* nu, const double* U, double2* mom,
                   const int* skip);
 void launch_csr_build(hipStream_t st, int64_t* rowptr, int32_t* col, double2* val, int Ny, int Nxi,
                       int r, double beta, const double* Dx, const double* xix, const double* xiy,

@@ -57,6 +57,31 @@ def test_tile_choices_leave_the_operator_bit_identical(klst):
             assert torch.equal(y1, y_ref[i * wl.n:(i + 1) * wl.n])
 
 
+@pytest.mark.parametrize("tile", [None, (1, 1), (2, 4), (3, 1), (6, 4), (0, 8)])
+def test_every_operator_kernel_gives_the_same_bits(klst, tmp_path, tile):
+    """At the M = 4 shape (Ny = 96, 6 row tiles, 5 moment parts), the many-vector
+    operator under each launch choice (the streaming kernel by default or as
+    (0, 8); the tiled MFMA kernel with 1-6 row tiles and 1 or 4 wavefronts)
+    gives every vector bit for bit what a single application gives it."""
+    wl = W.config3()
+    nvec = 9
+    print(f"[case] operator kernel choice {tile} at {wl.name}", flush=True)
+    x = torch.from_numpy(np.concatenate([W.random_vector(wl.n, 90 + i) for i in range(nvec)])).to(DEV)
+    with klst.Context() as ctx:
+        ctx.assemble(wl)
+        y1 = torch.empty_like(x)
+        for i in range(nvec):
+            ctx.apply(0.3 + 0.1j, x[i * wl.n:(i + 1) * wl.n], y1[i * wl.n:(i + 1) * wl.n])
+        if tile is not None:
+            path = tmp_path / "tile.txt"
+            path.write_text(f"# one entry\n{wl.Ny} {wl.Nxi} {nvec} 0 {tile[0]} {tile[1]} 0 0\n")
+            klst.tune_load(str(path))
+        y = torch.empty_like(x)
+        ctx.apply_many(0.3 + 0.1j, nvec, x, y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1)
+
+
 def test_sweep_bit_identical_alone_and_in_mix_under_a_tuned_table(klst, tmp_path):
     wls = sorted(W.sweep(seed=4, count=64, nev=6), key=lambda w: w.n)[:6]
     opts = dict(m_max=30, pc_kernel=2, max_it=1500)

@@ -46,15 +46,15 @@ def test_noalloc_equals_apply_many_on_consecutive_calls():
 
 def test_noalloc_refuses_sizes_beyond_the_scratch():
     from paper_2607_27440_amd import klst
-    wl = W.config2()          # Ny = 64, r = 4: 2,048 scratch entries per vector, 256 vectors fit
+    wl = W.config2()          # Ny = 64, r = 4: 2,304 scratch entries per vector, 227 vectors fit
     print(f"[case] noalloc size limit {wl.name}", flush=True)
     with klst.Context() as ctx:
         ctx.assemble(wl)
-        x = torch.zeros(257 * wl.n, dtype=torch.complex128, device=DEV)
+        x = torch.zeros(228 * wl.n, dtype=torch.complex128, device=DEV)
         y = torch.empty_like(x)
         with pytest.raises(klst.KlstError) as ei:
-            ctx.apply_many_noalloc(0.0, 257, x, y)
+            ctx.apply_many_noalloc(0.0, 228, x, y)
         assert ei.value.status == klst.EINVAL
-        ctx.apply_many_noalloc(0.0, 256, x, y)
+        ctx.apply_many_noalloc(0.0, 227, x, y)
         torch.cuda.synchronize()
         assert torch.count_nonzero(y).item() == 0
