@@ -273,8 +273,9 @@ def hbm_entries(ctx, wl, torch, reps, nvec=64):
     """HBM rates on working sets above 512 MB (twice the 256 MB Infinity Cache):
     the explicit CSR product (A - tau B) x, 20 B per stored entry plus the row
     pointers and the vectors, and the matrix-free operator on nvec vectors in
-    one call (vectors in and out, 32 n B each, plus the U and M tables once).
-    Both timed with HIP events on the library's stream: average, median, min."""
+    one call (each vector read twice, by the moment sums and by the streaming
+    GEMM, and written once: 48 n B, plus the U and M tables once).  Both timed
+    with HIP events on the library's stream: average, median, min."""
     n = wl.n
     st = torch.cuda.current_stream()
     out = {}
@@ -286,7 +287,7 @@ def hbm_entries(ctx, wl, torch, reps, nvec=64):
     flops_mf = nvec * n * (4 * wl.Ny + 8 * 4 + 8)
     for name, fn, nbytes, flops in (
             ("csr_spmv", lambda: ctx.apply_csr(0.0, x, y), 20 * ctx.nnz + 8 * (n + 1) + 32 * n, 8 * ctx.nnz),
-            (f"matrix_free_x{nvec}", lambda: ctx.apply_many(0.0, nvec, xm, ym), 32 * n * nvec + tables, flops_mf),
+            (f"matrix_free_x{nvec}", lambda: ctx.apply_many(0.0, nvec, xm, ym), 48 * n * nvec + tables, flops_mf),
             ("matrix_free_x1_latency", lambda: ctx.apply(0.0, x, y), 32 * n + tables, n * (4 * wl.Ny + 40))):
         for _ in range(3):
             fn()
@@ -615,7 +616,8 @@ def run_served(a):
 
 def run_profile(a):
     """Kernel-only run for rocprofv3 (timing and HBM counters): the workload's
-    preconditioner apply and matrix-free operator apply, `kernel_reps` times each,
+    preconditioner apply, matrix-free operator apply and 64-vector operator
+    apply, `kernel_reps` times each,
     then a plain 256 MiB device copy (`kernel_reps` times) whose known traffic
     (read 256 MiB, write 256 MiB per dispatch) calibrates FETCH_SIZE / WRITE_SIZE.
     Prints one JSON line with the event-timed averages."""
@@ -654,6 +656,14 @@ def run_profile(a):
         e1.record(st)
         torch.cuda.synchronize()
         out["apply_us"] = round(e0.elapsed_time(e1) * 1e3 / a.kernel_reps, 3)
+        # the many-vector operator on 64 vectors (moments, totals, streaming kernel)
+        xm = torch.randn(64 * wl.n, dtype=torch.complex128, device="cuda")
+        ym = torch.empty_like(xm)
+        for _ in range(3):
+            ctx.apply_many(0.0, 64, xm, ym)
+        avg, med, mn = _event_times(lambda: ctx.apply_many(0.0, 64, xm, ym), a.kernel_reps, torch, st)
+        out["apply_many_64_us"] = {"avg": round(avg * 1e6, 3), "median": round(med * 1e6, 3), "min": round(mn * 1e6, 3)}
+        del xm, ym
     src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -163,6 +163,13 @@ klst_status klst_dims(const klst_ctx* ctx, int64_t* n, int64_t* nnz, int* n_bc);
  * overlap.  Uses op_mode's operator.  Errors: ESTATE (no problem), EINVAL. */
 klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* y);
 
+/* The same product in FP32, as the inner solve of a mixed-precision context
+ * computes it (Sec. 4.2's operator with every table rounded to FP32, the
+ * streaming sum on the FP32 matrix cores, FP32 accumulation): x and y are
+ * device arrays of n complex floats (interleaved re, im).  Errors: ESTATE (no
+ * problem, or the context is not mixed precision), EINVAL, EDEVICE. */
+klst_status klst_apply_f32(klst_ctx* ctx, const double tau[2], const void* x, void* y);
+
 /* Same product, batched over nvec vectors stored contiguously (vector i at
  * x + i n).  Matrix-free only. */
 klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);
@@ -272,11 +279,13 @@ klst_status klst_solve_shift_invert(klst_ctx* ctx, const double sigma[2], int ne
  * Launch autotuning.  The library keeps a process-wide table of launch choices
  * keyed by (Ny, Nxi, nvec, precision): row tiles and wavefronts of the
  * matrix-core operator (apply_tile, apply_waves; apply_waves = 8 selects the
- * streaming many-vector kernel, the default from 8 vectors on; for FP32, rows
- * per thread in apply_tile), column parts of the moment sums (moment_splits)
- * and wavefronts
- * of the block GEMVs of the preconditioners (gemv_waves); 0 = the built-in
- * heuristic.  Tile and wave choices leave results bit-identical; moment splits
+ * streaming many-vector kernel, the default from 8 vectors on at shapes with
+ * at least 4 groups of 8 column tiles; for FP32, apply_waves 1 or 4 select the
+ * FP32 matrix-core kernel and apply_waves 0 the scalar one with apply_tile =
+ * 4, 8 or 16 rows per thread), column parts of the moment sums
+ * (moment_splits) and wavefronts of the block GEMVs of the preconditioners
+ * (gemv_waves); 0 = the built-in heuristic.  FP64 tile and wave choices leave
+ * results bit-identical (FP32 ones round differently); moment splits
  * and GEMV waves change the order of summation, so the table must be fixed
  * before the solves it serves (solves that run under one table give the same
  * results alone and together).  Moment splits and GEMV waves are per shape

@@ -684,6 +684,15 @@ klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* 
   return op_apply(ctx, cd(tau[0], tau[1]), (const double2*)x, (double2*)y, 1, ctx->opt.op_mode, nullptr);
 }
 
+klst_status klst_apply_f32(klst_ctx* ctx, const double tau[2], const void* x, void* y) {
+  if (!ctx || !tau || !x || !y) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_f32 before klst_assemble");
+  if (ctx->opt.precision != 1 || !ctx->d_DxT32)
+    return fail(ctx, KLST_ESTATE, "klst_apply_f32 needs a mixed-precision context (precision = 1)");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  return op_v(ctx, cd(tau[0], tau[1]), (const float2*)x, (float2*)y, nullptr);
+}
+
 klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y) {
   if (!ctx || !tau || !x || !y || nvec < 1 || nvec > 65535) return KLST_EINVAL;
   if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many before klst_assemble");
@@ -849,8 +858,12 @@ klst_status klst_autotune(klst_ctx* ctx, int nvec, int precision, int reps, klst
   double tbest = 1e300;
   // operator tiling (result-invariant)
   std::vector<std::pair<int, int>> tiles;
-  if (precision) tiles = {{4, 0}, {8, 0}, {16, 0}};
-  else {
+  if (precision) {
+    tiles = {{4, 0}, {8, 0}, {16, 0}};                 // the scalar FP32 kernel, rows per thread
+    for (int rt : {1, 2, 3, 6})
+      if ((rt - 1) * 16 < Ny)
+        for (int nw : {1, 4}) tiles.push_back({rt, nw});   // the FP32 matrix-core kernel
+  } else {
     for (int rt : {1, 2, 3, 6})
       if ((rt - 1) * 16 < Ny)
         for (int nw : {1, 4}) tiles.push_back({rt, nw});

@@ -308,6 +308,7 @@ __global__ void __launch_bounds__(256) k_apply(const cv<R>* __restrict__ x, cv<R
 // j + 16k, D[i][j] for lane l, register q at i = l/16 + 4q, j = l%16.
 // grid (ceil(2Nxi/16), ceil(ceil(Ny/16)/RT), nvec), block 64.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 // NW wavefronts per workgroup, each a column tile of 16; with NW > 1 the D_x^T
 // row slice of the workgroup is staged once in LDS and shared.  The moments of
 // the workgroup's rows are summed from their S parts once into LDS.
@@ -468,6 +469,128 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
             const double2 ma = ms[jl * 4 + a];
             op_moment(out, ua, ma);
           }
+        }
+      }
+      yv[(int64_t)j * nc + c] = out;
+    }
+  }
+}
+
+// FP32 operator for the mixed-precision inner solve: y = (A - tau B) x with the
+// streaming GEMM on the FP32 matrix cores (v_mfma_f32_16x16x4f32).  One
+// wavefront per tile of 16 complex columns x RT 16 rows, NW wavefronts per
+// workgroup sharing an LDS copy of their D_x row slice (NW > 1); the real and
+// imaginary parts of X are two B operands sharing the D_x fragment.  Operand
+// layouts (gfx950): A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k; the
+// result D[i][j] sits in lane j + 16 (i / 4), register i % 4 (rows held four
+// to a lane, unlike the FP64 instruction).  Accumulation in FP32; the
+// epilogue's moments are the FP32 totals of the S column parts.
+// grid (ceil(ceil(2 Nxi / 16) / NW), ceil(ceil(Ny / 16) / RT), nvec), block 64 NW.
+template <int RT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_apply_mfma32(const float2* __restrict__ x, float2* __restrict__ y,
+                                                          int64_t n, int Ny, int Nxi, int r, float tau_re,
+                                                          float tau_im, float beta, const float* __restrict__ DxT,
+                                                          const float* __restrict__ xi_x,
+                                                          const float* __restrict__ xi_y,
+                                                          const float* __restrict__ nu,
+                                                          const float* __restrict__ U,
+                                                          const float2* __restrict__ mom, int S,
+                                                          const int* __restrict__ skip) {
+  extern __shared__ unsigned char lds_raw[];
+  float2* ms = reinterpret_cast<float2*>(lds_raw);                          // [RT*16][4] moments
+  float* As = reinterpret_cast<float*>(lds_raw + RT * 16 * 4 * sizeof(float2));  // [Ny4][RT*16]
+  if (skip && *skip) return;
+  const int nc = 2 * Nxi;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int v = blockIdx.z;
+  const int rt0 = blockIdx.y * RT;
+  const int W = RT * 16;
+  for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
+    const int jl = idx / r, a = idx - jl * r;
+    const int j = rt0 * 16 + jl;
+    ms[jl * 4 + a] = (j < Ny) ? mom_at<float>(mom, v, Ny, j, a, r, S) : make_float2(0.f, 0.f);
+  }
+  if (NW > 1) {
+    const int Ny4 = (Ny + 3) & ~3;
+    for (int idx = threadIdx.x; idx < Ny4 * W; idx += 64 * NW) {
+      const int m = idx / W, rl = idx - m * W;
+      const int row = rt0 * 16 + rl;
+      As[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int c0 = (blockIdx.x * NW + wv) * 16;
+  if (c0 >= nc) return;
+  const float2* xv = x + (int64_t)v * n;
+  float2* yv = y + (int64_t)v * n;
+  const int li = lane & 15, lk = lane >> 4;
+  const int cb = c0 + li;
+  flt4 are[RT], aim[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) { are[t] = flt4{0, 0, 0, 0}; aim[t] = flt4{0, 0, 0, 0}; }
+  // K loop in blocks of XB steps of 4 rows; the next block's x strip loads
+  // while the current block's MFMAs run
+  {
+    constexpr int XB = 8;
+    auto load_block = [&](int mb, float2* dst) {
+#pragma unroll
+      for (int p = 0; p < XB; ++p) {
+        const int m = mb + 4 * p + lk;
+        dst[p] = (m < Ny && cb < nc) ? xv[(int64_t)m * nc + cb] : make_float2(0.f, 0.f);
+      }
+    };
+    float2 xc[XB], xn[XB];
+    load_block(0, xc);
+    for (int mb = 0; mb < Ny; mb += 4 * XB) {
+      if (mb + 4 * XB < Ny) load_block(mb + 4 * XB, xn);
+#pragma unroll
+      for (int p = 0; p < XB; ++p) {
+        const int m = mb + 4 * p + lk;
+        if (mb + 4 * p >= Ny) break;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          float a;
+          if (NW > 1) {
+            a = As[m * W + t * 16 + li];
+          } else {
+            const int row = (rt0 + t) * 16 + li;
+            a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.f;
+          }
+          are[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xc[p].x, are[t], 0, 0, 0);
+          aim[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xc[p].y, aim[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < XB; ++p) xc[p] = xn[p];
+    }
+  }
+  // epilogue on the accumulator layout: column c, rows j = tile 16 + 4 lk + q
+  const int c = cb;
+  if (c >= nc) return;
+  const int f = c / Nxi, k = c - f * Nxi;
+  const float xik = xi_x[k], bxy = beta * xi_y[k];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jl = t * 16 + 4 * lk + q;
+      const int j = rt0 * 16 + jl;
+      if (j >= Ny) continue;
+      const float2 xjc = xv[(int64_t)j * nc + c];
+      const bool bc = (j == Ny - 1 && xik > 0.f) || (j == 0 && xik < 0.f);
+      float2 out;
+      if (bc) {
+        out = xjc;
+      } else {
+        const float dre = nu[j] - tau_re, dim = bxy - tau_im;
+        out.x = fmaf(xik, are[t][q], fmaf(dre, xjc.x, -(dim * xjc.y)));
+        out.y = fmaf(xik, aim[t][q], fmaf(dre, xjc.y, dim * xjc.x));
+        const float* Uj = U + ((int64_t)(j * 2 + f) * r) * Nxi + k;
+        for (int a = 0; a < r; ++a) {
+          const float ua = Uj[(int64_t)a * Nxi];
+          const float2 ma = ms[jl * 4 + a];
+          out.x = fmaf(-ua, ma.x, out.x);
+          out.y = fmaf(-ua, ma.y, out.y);
         }
       }
       yv[(int64_t)j * nc + c] = out;
@@ -2274,30 +2397,52 @@ void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny
   moments_t<float>(st, x, n, nvec, Ny, Nxi, r, M, mom, skip);
 }
 
-template <class R>
-static void apply_t(hipStream_t st, const cv<R>* x, cv<R>* y, int64_t n, int nvec, int Ny, int Nxi,
-                    int r, double tre, double tim, double beta, const R* DxT, const R* xix, const R* xiy,
-                    const R* nu, const R* U, const cv<R>* mom, const int* skip) {
+// FP32 operator (the mixed-precision inner solve).  Default: the FP32 matrix-
+// core kernel, row tiles per wavefront chosen for >= ~1024 wavefronts and 4
+// wavefronts per workgroup when there are enough of them.  The launch table can
+// select other tilings of it (apply_waves 1 or 4) or the scalar kernel with 4,
+// 8 or 16 rows per thread (apply_waves 0); each gives its own FP32 rounding.
+static void apply_f32(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi, int r,
+                      double tre, double tim, double beta, const float* DxT, const float* xix, const float* xiy,
+                      const float* nu, const float* U, const float2* mom, const int* skip) {
   const int nc = 2 * Nxi;
   const int cblocks = (nc + 255) / 256;
-  const int S = moment_splits(Ny, nvec, Nxi, sizeof(R) == 4 ? 1 : 0);
-  // rows per thread: as many as possible while keeping >= ~1024 wavefronts busy
-  // (or the tuned count: the rows of a thread are summed in the same order
-  // whatever their number, so the choice does not change results)
-  const int64_t waves16 = (int64_t)((nc + 63) / 64) * ((Ny + 15) / 16) * nvec;
-  const int64_t waves8 = (int64_t)((nc + 63) / 64) * ((Ny + 7) / 8) * nvec;
+  const int S = moment_splits(Ny, nvec, Nxi, 1);
   Tuning tn;
-  const int rb = tune_get(Ny, Nxi, nvec, sizeof(R) == 4 ? 1 : 0, &tn) ? tn.apply_rt : 0;
-  if (rb == 16 || (rb == 0 && waves16 >= 1024)) {
-    hipLaunchKernelGGL((k_apply<R, 16>), dim3(cblocks, (Ny + 15) / 16, nvec), dim3(256), 0, st, x, y, n, Ny,
-                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
-  } else if (rb == 8 || (rb == 0 && waves8 >= 512)) {
-    hipLaunchKernelGGL((k_apply<R, 8>), dim3(cblocks, (Ny + 7) / 8, nvec), dim3(256), 0, st, x, y, n, Ny,
-                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
-  } else {
-    hipLaunchKernelGGL((k_apply<R, 4>), dim3(cblocks, (Ny + 3) / 4, nvec), dim3(256), 0, st, x, y, n, Ny,
-                       Nxi, r, (R)tre, (R)tim, (R)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+  const bool tuned = tune_get(Ny, Nxi, nvec, 1, &tn);
+  if (tuned && tn.apply_nw == 0 && (tn.apply_rt == 4 || tn.apply_rt == 8 || tn.apply_rt == 16)) {
+    if (tn.apply_rt == 16)
+      hipLaunchKernelGGL((k_apply<float, 16>), dim3(cblocks, (Ny + 15) / 16, nvec), dim3(256), 0, st, x, y, n, Ny,
+                         Nxi, r, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+    else if (tn.apply_rt == 8)
+      hipLaunchKernelGGL((k_apply<float, 8>), dim3(cblocks, (Ny + 7) / 8, nvec), dim3(256), 0, st, x, y, n, Ny,
+                         Nxi, r, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+    else
+      hipLaunchKernelGGL((k_apply<float, 4>), dim3(cblocks, (Ny + 3) / 4, nvec), dim3(256), 0, st, x, y, n, Ny,
+                         Nxi, r, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, mom, S, skip);
+    return;
   }
+  const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
+  int rt = 6;
+  while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
+  bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
+  if (tuned && (tn.apply_nw == 1 || tn.apply_nw == 4) &&
+      (tn.apply_rt == 1 || tn.apply_rt == 2 || tn.apply_rt == 3 || tn.apply_rt == 6)) {
+    rt = tn.apply_rt;
+    wide = tn.apply_nw == 4;
+  }
+  wide = wide && (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(float) <= 96 * 1024;
+  const size_t lds = (size_t)rt * 16 * 4 * sizeof(float2) + (wide ? (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(float) : 0);
+  const dim3 g(wide ? (ctiles + 3) / 4 : ctiles, (nrt + rt - 1) / rt, nvec);
+#define KLST_M32(RT_, NW_) hipLaunchKernelGGL((k_apply_mfma32<RT_, NW_>), g, dim3(64 * NW_), lds, st, x, y, n, Ny, \
+                                              Nxi, r, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, \
+                                              mom, S, skip)
+  if (wide) {
+    if (rt == 6) KLST_M32(6, 4); else if (rt == 3) KLST_M32(3, 4); else if (rt == 2) KLST_M32(2, 4); else KLST_M32(1, 4);
+  } else {
+    if (rt == 6) KLST_M32(6, 1); else if (rt == 3) KLST_M32(3, 1); else if (rt == 2) KLST_M32(2, 1); else KLST_M32(1, 1);
+  }
+#undef KLST_M32
 }
 void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const double* Dx, const double* xix,
@@ -2315,8 +2460,12 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   // the streaming kernel addresses each vector and the U table with 32-bit byte offsets
   const bool off32 = (uint64_t)n * sizeof(double2) < ((uint64_t)1 << 32) &&
                      (uint64_t)Ny * 2 * r * Nxi * sizeof(double) < ((uint64_t)1 << 32);
+  // the streaming kernel needs enough column groups to spread items over the CUs
+  // (at 12 column tiles, 2 groups, the tiled kernel is faster at 64 vectors)
+  const int64_t sgroups = (ctiles + 7) / 8;
+  const bool stream_fits = sgroups >= 4 && sgroups * nvec >= device_cus() / 2;
   if (nvec >= kBatchMin && !skip && nrt <= 6 && off32 && (r == 3 || r == 4) &&
-      (!tq_ok || tq.apply_nw == 0 || tq.apply_nw == 8)) {
+      (tq_ok ? (tq.apply_nw == 8 || (tq.apply_nw == 0 && stream_fits)) : stream_fits)) {
     constexpr int WPG = 8;
     // moment totals after the partials (mom holds nvec Ny r 9 entries)
     double2* tot = mom + (size_t)nvec * Ny * r * 8;
@@ -2376,7 +2525,7 @@ void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nve
                   int r, double tre, double tim, double beta, const float* Dx, const float* xix,
                   const float* xiy, const float* nu, const float* U, const float2* mom,
                   const int* skip) {
-  apply_t<float>(st, x, y, n, nvec, Ny, Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, skip);
+  apply_f32(st, x, y, n, nvec, Ny, Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, skip);
 }
 
 void launch_csr_build(hipStream_t st, int64_t* rowptr, int32_t* col, double2* val, int Ny, int Nxi,

@@ -79,6 +79,7 @@ _sig = {
     "klst_assemble": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Vel), C.POINTER(Base), C.c_double]),
     "klst_dims": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
     "klst_apply": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_apply_f32": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_many": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_apply_csr": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_many_noalloc": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
@@ -313,6 +314,13 @@ class Context:
             "device complex128 contiguous tensor expected"
         return C.c_void_p(t.data_ptr())
 
+    @staticmethod
+    def _ptr32(t):
+        import torch
+        assert t.is_cuda and t.dtype == torch.complex64 and t.is_contiguous(), \
+            "device complex64 contiguous tensor expected"
+        return C.c_void_p(t.data_ptr())
+
     def _tau(self, tau):
         tau = complex(tau)
         a = np.array([tau.real, tau.imag])
@@ -321,6 +329,10 @@ class Context:
     def apply(self, tau, x, y):
         a, p = self._tau(tau)
         self._check(_lib.klst_apply(self._h, p, self._ptr(x), self._ptr(y)), "klst_apply")
+
+    def apply_f32(self, tau, x, y):
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply_f32(self._h, p, self._ptr32(x), self._ptr32(y)), "klst_apply_f32")
 
     def apply_many(self, tau, nvec, x, y):
         a, p = self._tau(tau)

@@ -23,7 +23,7 @@ def klst():
 def _declared():
     src = open(os.path.join(ROOT, "include", "klst.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(klst_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(klst_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol(klst):

@@ -125,6 +125,30 @@ def test_apply_c3_full_shape():
     assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
 
 
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c3"])
+def test_apply_f32_matches_oracle(cfg):
+    """The FP32 operator of the mixed-precision inner solve (klst_apply_f32: the
+    tables rounded to FP32, the streaming sum on the FP32 matrix cores, FP32
+    accumulation) against the oracle's FP64 product of the same FP32 input:
+    every entry within 2 gamma_L(u32) (|A - tau B| |x|)_i, the dot-product bound
+    doubled for the tables' own FP32 rounding."""
+    wl = {"c1": W.config1, "c2": W.config2, "c3": W.config3}[cfg]()
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 14).astype(np.complex64)
+    tau = 0.1 + 0.05j
+    print(f"[case] FP32 operator {wl.name}", flush=True)
+    ctx = _ctx(wl, precision=1, pc_kernel=2)
+    xd = torch.from_numpy(x).to(DEV)
+    yd = torch.empty_like(xd)
+    ctx.apply_f32(tau, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy().astype(np.complex128)
+    x64 = x.astype(np.complex128)
+    ref = P.apply_structured(x64, tau) if wl.n > 60000 else P.apply(x64, tau)
+    bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
+    assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+
+
 @pytest.mark.parametrize("cfg,nvec", [("c2", 5), ("c2", 12), ("c3", 9)])
 def test_apply_many_equals_single(cfg, nvec):
     """The batched operator (the many-vector kernels from 8 vectors on) gives every
