@@ -127,6 +127,8 @@ VARIANTS = {
         "mixed_fp32_inner": dict(precision=1),
         # one FP32 GMRES(20) cycle per correction equation, no refinement
         "mixed_fp32_inner_one_cycle": dict(precision=1, inner_max_it=20),
+        # FP64 arithmetic with the inner GMRES Krylov basis stored in FP32
+        "fp32_krylov_basis": dict(krylov32=1),
         "shift_invert_exact": dict(method=1, m_max=120, max_it=100),
     },
 }

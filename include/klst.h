@@ -89,6 +89,12 @@ typedef struct {
                            on the device)                                            */
   int method;           /* klst_solve's eigensolver: 0 = Jacobi-Davidson (default);
                            1 = shift-invert Krylov-Schur (klst_solve_shift_invert)  */
+  int krylov32;         /* FP64 solves (precision 0): 1 = store the inner GMRES
+                           Krylov basis in FP32 (arithmetic, operator,
+                           preconditioner and the outer iteration stay FP64; the
+                           Gram-Schmidt passes read half the bytes); 0 = FP64
+                           basis (default).  Ignored in mixed precision, whose
+                           basis is FP32 already.                                    */
 } klst_options;
 
 /* Spatial grid: Ny Chebyshev-Gauss-Lobatto points mapped to [-s_inf, s_inf]

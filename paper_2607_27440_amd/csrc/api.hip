@@ -490,6 +490,7 @@ void klst_default_options(klst_options* o) {
   o->inner_max_it = 0;
   o->reorth = 0;
   o->method = 0;
+  o->krylov32 = 0;
 }
 
 const char* klst_strerror(klst_status s) {
@@ -518,7 +519,7 @@ klst_status klst_create(klst_ctx** out, const klst_options* opt) {
       (o.precision != 0 && o.precision != 1) || (o.op_mode != 0 && o.op_mode != 1) || o.m_max > 248 ||
       o.pc_kernel < 0 || o.pc_kernel > 2 || (o.precision == 1 && o.pc_kernel == 0) ||
       o.inner_max_it < 0 || o.inner_max_it > 100000 || (o.reorth != 0 && o.reorth != 1) ||
-      (o.method != 0 && o.method != 1))
+      (o.method != 0 && o.method != 1) || (o.krylov32 != 0 && o.krylov32 != 1))
     return KLST_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
@@ -1157,8 +1158,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
   const int m_max = std::max(o.m_max, o.m_min + 2);
   const int m_min = o.m_min;
   const int gm = o.gmres_m;
-  // correction-equation budget: 0 selects one GMRES cycle in FP64 and three
-  // FP64-refined FP32 cycles in mixed precision
+  // correction-equation budget: inner_max_it, or for 0 one GMRES cycle in FP64
+  // and three FP64-refined FP32 cycles in mixed precision (one FP32 cycle alone
+  // can stall an ill-conditioned pair near relative residual 1e-7)
   const int imax = o.inner_max_it > 0 ? o.inner_max_it : (o.precision == 1 ? 3 * o.gmres_m : o.gmres_m);
   const cd sigma(sigma_in[0], sigma_in[1]);
   hipStream_t st = ctx->stream;
@@ -1202,6 +1204,12 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
     d32 = ws.vec32(1);
     if (!Gb32 || !Q32 || !Y32 || !a32 || !b32 || !d32 || !rho64) return KLST_ENOMEM;
   }
+  // FP64 solve with the inner GMRES Krylov basis stored in FP32: the basis and
+  // one FP64 work vector holding the current basis vector
+  const bool kb32 = !mixed && o.krylov32 == 1;
+  float2* Gk32 = kb32 ? ws.vec32(gm + 1) : nullptr;
+  double2* wk = kb32 ? ws.vec(1) : nullptr;
+  if (kb32 && (!Gk32 || !wk)) return KLST_ENOMEM;
   std::vector<cd> HQY32;   // Q32^H Y32 of the locked vectors (mixed precision)
   // Small device results gathered for one host transfer.  Every column count below
   // is at most kcap + m_max <= 250 (expansion) or kcap + 1 <= 101 (locking), so
@@ -1619,6 +1627,48 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       HIPCHK(hipGetLastError());
       return KLST_OK;
     };
+    // The same GMRES in FP64 arithmetic with the Krylov basis stored in FP32 (half
+    // the bytes of every Gram-Schmidt pass); the current basis vector is kept in
+    // FP64 in wk, and the operator and preconditioner act on it.
+    auto gmres_kb32 = [&](double2* a, double2* bw, const double2* Qt0, const double2* ut, const double2* Yt0,
+                          int kq, int budget, double2* tout, bool first) -> klst_status {
+      klst_status s2;
+      {
+        const int nch = launch_dot_partial(st, (const double2*)nullptr, 0, (const double2*)nullptr, 0, a, n,
+                                           partial, 1, nullptr);
+        launch_dot_reduce(st, partial, 0, nch, d_small, 3, nullptr, nullptr, nullptr);
+      }
+      launch_gmres_init(st, d_small, d_g, d_done, d_steps, d_beta, first ? 1 : 0);
+      launch_scale_rsqrt(st, a, wk, n, d_small, d_done, Gk32);
+      const float2* nul32 = nullptr;
+      for (int j = 0; j < budget; ++j) {
+        if ((s2 = op_v(ctx, shift, wk, bw, d_done)) != KLST_OK) return s2;
+        if ((s2 = pc_v(ctx, bw, wk, d_done)) != KLST_OK) return s2;
+        int nch = launch_dot_partial(st, Qt0, kq, ut, 1, wk, n, partial, 0, d_done);
+        launch_subm_fused(st, Yt0, kq + 1, (const double2*)nullptr, 0, partial, nch, d_Hinv, nullptr, nullptr,
+                          wk, n, nullptr, d_done);
+        double2* hcol = d_H + (size_t)j * (gm + 1);
+        nch = launch_dot_partial(st, (const float2*)Gk32, j + 1, nul32, 0, (const double2*)wk, n, partial, 1,
+                                 d_done);
+        launch_subm_fused(st, (const float2*)Gk32, j + 1, nul32, 0, partial, nch, nullptr, hcol, nullptr, wk, n,
+                          npart, d_done);
+        const int* skip2 = d_done;
+        if (o.reorth == 1) {
+          launch_reorth_test(st, partial, j + 1, nch, n, npart, 0.5, d_done, d_reorth);
+          skip2 = d_reorth;
+        }
+        nch = launch_dot_partial(st, (const float2*)Gk32, j + 1, nul32, 0, (const double2*)wk, n, partial, 0,
+                                 skip2);
+        launch_subm_fused(st, (const float2*)Gk32, j + 1, nul32, 0, partial, nch, nullptr, nullptr, hcol, wk, n,
+                          npart, skip2);
+        launch_scale_norm(st, wk, Gk32 + (size_t)(j + 1) * n, n, npart, d_small + 2, d_H, gm + 1, j, d_cs, d_sn,
+                          d_g, d_done, d_steps, d_beta, o.inner_rtol);
+      }
+      launch_gmres_solve(st, d_H, gm + 1, d_g, d_steps, d_yk);
+      launch_combine(st, (const float2*)Gk32, budget, n, d_yk, 1, 1, tout, d_steps);
+      HIPCHK(hipGetLastError());
+      return KLST_OK;
+    };
     auto set_hinv = [&](const std::vector<cd>& HQ, const double2* col, const double2* row) -> klst_status {
       const int kt = k + 1;
       std::vector<cd> Ht((size_t)kt * kt), Hi((size_t)kt * kt);
@@ -1645,8 +1695,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
       // Restarted GMRES(gm): cycles of at most gm steps until the projected
       // preconditioned residual is below inner_rtol times its initial norm or
       // inner_max_it steps are spent; each restart recomputes the residual from t.
-      if ((s = gmres(Gb, av, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
-                     std::min(gm, imax), tv, true)) != KLST_OK)
+      if ((s = kb32 ? gmres_kb32(av, bv, Qb, uv, Yb, k, std::min(gm, imax), tv, true)
+                    : gmres(Gb, av, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
+                            std::min(gm, imax), tv, true)) != KLST_OK)
         return s;
       if (imax > gm) {
         double2* resv = Tmp;                 // the rotation buffer is free here
@@ -1666,8 +1717,9 @@ extern "C" klst_status klst_solve(klst_ctx* ctx, const double sigma_in[2], int n
           sub(Yb, k + 1, nullptr, 0, d_c, resv);
           launch_axpby(st, resv, resv, n, -1.0, 0.0, 0);
           launch_axpby(st, av, resv, n, 1.0, 0.0, 1);
-          if ((s = gmres(Gb, resv, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
-                         std::min(gm, imax - used), dt, false)) != KLST_OK)
+          if ((s = kb32 ? gmres_kb32(resv, bv, Qb, uv, Yb, k, std::min(gm, imax - used), dt, false)
+                        : gmres(Gb, resv, bv, (const double2*)Qb, (const double2*)uv, (const double2*)Yb, k,
+                                std::min(gm, imax - used), dt, false)) != KLST_OK)
             return s;
           launch_axpby(st, dt, tv, n, 1.0, 0.0, 1);
         }
@@ -2196,6 +2248,7 @@ extern "C" size_t klst_footprint_bytes(int Ny, int Nxi, int nev, const klst_opti
     b += 20 * nnz + 8 * (n + 1);
   }
   b += cvec * (2ull * (m_max + 1) + 3ull * (kcap + 1) + (gm + 1) + m_max + 6 + nev);    // JD workspace
+  if (o.precision == 0 && o.krylov32 == 1) b += 8ull * n * (gm + 1) + cvec;            // FP32 Krylov basis
   const size_t ncoef = std::max({(size_t)m_max * m_max, (size_t)2 * m_max, (size_t)kcap * nev});
   b += 16ull * 512 * 256 + 16ull * (4 * 1024 + ncoef + (size_t)(kcap + 1) * (kcap + 1) +
                                     (gm + 1) * (gm + 3));                           // reductions, small

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -42,22 +43,28 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 
+// Entry of a stored vector of real type RS in arithmetic type R.
+template <class R, class RS>
+__device__ __forceinline__ cv<R> as_cv(cv<RS> v) { return mk<R>((R)v.x, (R)v.y); }
+
 // sum_{i < m} S_i[t] c[i * cstride] with the loads of eight vectors issued before
 // their products are accumulated (c indices are wave-uniform: scalar loads).
-// Vectors of real type R, coefficients in FP64 (narrowed to R), accumulation in R.
-template <class R>
-__device__ __forceinline__ cv<R> lincomb(const cv<R>* __restrict__ S, int m, int64_t n, int64_t t,
+// Vectors stored in real type RS, coefficients in FP64 (narrowed to R),
+// accumulation in R.
+template <class R, class RS = R>
+__device__ __forceinline__ cv<R> lincomb(const cv<RS>* __restrict__ S, int m, int64_t n, int64_t t,
                                          const double2* __restrict__ c, int cstride) {
   cv<R> acc = mk<R>(0, 0);
   int i = 0;
   for (; i + 8 <= m; i += 8) {
-    cv<R> sv[8];
+    cv<RS> sv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) sv[u] = S[(int64_t)(i + u) * n + t];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = cadd(acc, cmul(sv[u], narrow<R>(c[(int64_t)(i + u) * cstride])));
+    for (int u = 0; u < 8; ++u)
+      acc = cadd(acc, cmul(as_cv<R, RS>(sv[u]), narrow<R>(c[(int64_t)(i + u) * cstride])));
   }
-  for (; i < m; ++i) acc = cadd(acc, cmul(S[(int64_t)i * n + t], narrow<R>(c[(int64_t)i * cstride])));
+  for (; i < m; ++i) acc = cadd(acc, cmul(as_cv<R, RS>(S[(int64_t)i * n + t]), narrow<R>(c[(int64_t)i * cstride])));
   return acc;
 }
 
@@ -1703,9 +1710,11 @@ __global__ void __launch_bounds__(256) k_gj_unpermute(const double2* __restrict_
 
 // partial[q * nch + chunk] = sum_{t in chunk} conj(S_q[t]) x[t] for q < m; with
 // with_norm, row q = m holds sum |x[t]|^2.  grid (nch, ceil(mtot / 4)), block 256.
-template <class R>
-__global__ void __launch_bounds__(256) k_dot_partial(const cv<R>* __restrict__ s0, int m0,
-                                                     const cv<R>* __restrict__ s1, int m1,
+// The vectors S_q are stored in real type RS (the Krylov basis may be FP32
+// under FP64 arithmetic), x and the arithmetic in R.
+template <class R, class RS = R>
+__global__ void __launch_bounds__(256) k_dot_partial(const cv<RS>* __restrict__ s0, int m0,
+                                                     const cv<RS>* __restrict__ s1, int m1,
                                                      const cv<R>* __restrict__ x, int64_t n, int chunk,
                                                      double2* __restrict__ partial, int with_norm,
                                                      const int* __restrict__ skip) {
@@ -1718,23 +1727,29 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cv<R>* __restrict__ s
   const int64_t t0 = (int64_t)blockIdx.x * chunk;
   const int64_t t1 = min(n, t0 + chunk);
   R ar = 0, ai = 0;
-  const cv<R>* sv = (i < m) ? ((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n) : x;
-  int64_t t = t0 + lane;
-  for (; t + 192 < t1; t += 256) {
-    cv<R> a[4], b[4];
+  auto accumulate = [&](const auto* __restrict__ sv) {
+    using SV = std::remove_cv_t<std::remove_reference_t<decltype(sv[0])>>;
+    int64_t t = t0 + lane;
+    for (; t + 192 < t1; t += 256) {
+      SV a0[4];
+      cv<R> b[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) { a[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
+      for (int u = 0; u < 4; ++u) { a0[u] = sv[t + 64 * u]; b[u] = x[t + 64 * u]; }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      ar = fma(a[u].x, b[u].x, ar); ar = fma(a[u].y, b[u].y, ar);
-      ai = fma(a[u].x, b[u].y, ai); ai = fma(-a[u].y, b[u].x, ai);
+      for (int u = 0; u < 4; ++u) {
+        const cv<R> a = mk<R>((R)a0[u].x, (R)a0[u].y);
+        ar = fma(a.x, b[u].x, ar); ar = fma(a.y, b[u].y, ar);
+        ai = fma(a.x, b[u].y, ai); ai = fma(-a.y, b[u].x, ai);
+      }
     }
-  }
-  for (; t < t1; t += 64) {
-    const cv<R> a = sv[t], b = x[t];
-    ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
-    ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
-  }
+    for (; t < t1; t += 64) {
+      const cv<R> a = mk<R>((R)sv[t].x, (R)sv[t].y), b = x[t];
+      ar = fma(a.x, b.x, ar); ar = fma(a.y, b.y, ar);
+      ai = fma(a.x, b.y, ai); ai = fma(-a.y, b.x, ai);
+    }
+  };
+  if (i < m) accumulate((i < m0) ? s0 + (int64_t)i * n : s1 + (int64_t)(i - m0) * n);
+  else accumulate(x);
   if (i >= m) ai = 0;
   const double dr = wave_sum((double)ar);
   const double di = wave_sum((double)ai);
@@ -1798,9 +1813,9 @@ __global__ void __launch_bounds__(256) k_dot_reduce(const double2* __restrict__ 
 // (c = Hinv * sums when Hinv != nullptr).  Workgroup 0 stores c to coef_set
 // and/or adds it to coef_add.  With norm_part, each workgroup writes the partial
 // ||x_new||^2 of its slice.  grid ceil(n / 256), block 256.
-template <class R>
-__global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0, int m0,
-                                                    const cv<R>* __restrict__ s1, int m1,
+template <class R, class RS = R>
+__global__ void __launch_bounds__(256) k_subm_fused(const cv<RS>* __restrict__ s0, int m0,
+                                                    const cv<RS>* __restrict__ s1, int m1,
                                                     const double2* __restrict__ partial, int nch,
                                                     const double2* __restrict__ Hinv,
                                                     double2* __restrict__ coef_set,
@@ -1832,7 +1847,7 @@ __global__ void __launch_bounds__(256) k_subm_fused(const cv<R>* __restrict__ s0
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   R a2 = 0;
   if (t < n) {
-    const cv<R> acc = cadd(lincomb<R>(s0, m0, n, t, c, 1), lincomb<R>(s1, m1, n, t, c + m0, 1));
+    const cv<R> acc = cadd(lincomb<R, RS>(s0, m0, n, t, c, 1), lincomb<R, RS>(s1, m1, n, t, c + m0, 1));
     const cv<R> xv = csub(x[t], acc);
     x[t] = xv;
     a2 = xv.x * xv.x + xv.y * xv.y;
@@ -1872,8 +1887,8 @@ __device__ void gmres_givens_body(double2* __restrict__ H, int ldh, int j, doubl
                                   double2* __restrict__ g, int* __restrict__ done,
                                   int* __restrict__ steps, const double* __restrict__ beta,
                                   double rtol);
-template <class R>
-__global__ void __launch_bounds__(256) k_scale_norm(cv<R>* x, cv<R>* dst, int64_t n,
+template <class R, class R2 = R>
+__global__ void __launch_bounds__(256) k_scale_norm(cv<R>* x, cv<R>* dst, cv<R2>* dst2, int64_t n,
                                                     const double2* __restrict__ norm_part, int nb,
                                                     double2* __restrict__ nrm2_out,
                                                     double2* __restrict__ H, int ldh, int j,
@@ -1899,7 +1914,9 @@ __global__ void __launch_bounds__(256) k_scale_norm(cv<R>* x, cv<R>* dst, int64_
   if (t >= n) return;
   const R sc = (R)(1.0 / sqrt(tot));
   const cv<R> v = x[t];
-  (dst ? dst : x)[t] = mk<R>(v.x * sc, v.y * sc);
+  const cv<R> w = mk<R>(v.x * sc, v.y * sc);
+  (dst ? dst : x)[t] = w;
+  if (dst2) dst2[t] = mk<R2>((R2)w.x, (R2)w.y);
 }
 
 // x[t] -= sum_i S_i[t] c[i] over two segments (c on device; c[0..m0) for seg0,
@@ -1921,8 +1938,8 @@ __global__ void __launch_bounds__(256) k_subm(const cv<R>* __restrict__ s0, int 
 
 // out_j[t] = sum_i S_i[t] coef[i * ldc + j] for j < k (basis rotation V <- V U),
 // coefficients on the device.  grid.y = output vector j.
-template <class R>
-__global__ void __launch_bounds__(256) k_combine(const cv<R>* __restrict__ S, int m, int64_t n,
+template <class R, class RS = R>
+__global__ void __launch_bounds__(256) k_combine(const cv<RS>* __restrict__ S, int m, int64_t n,
                                                  const double2* __restrict__ coef, int ldc,
                                                  cv<R>* __restrict__ out,
                                                  const int* __restrict__ count) {
@@ -1930,7 +1947,7 @@ __global__ void __launch_bounds__(256) k_combine(const cv<R>* __restrict__ S, in
   const int j = blockIdx.y;
   if (t >= n) return;
   const int mm = count ? min(m, *count) : m;
-  out[(int64_t)j * n + t] = lincomb<R>(S, mm, n, t, coef + j, ldc);
+  out[(int64_t)j * n + t] = lincomb<R, RS>(S, mm, n, t, coef + j, ldc);
 }
 
 // The same rotation for CB outputs per pass: every input entry S_i[t] is read
@@ -1975,14 +1992,16 @@ __global__ void __launch_bounds__(256) k_combine_multi(const cv<R>* __restrict__
 
 // x *= 1 / sqrt(*nrm2) (nrm2 on device), optionally into dst.
 template <class R>
-__global__ void k_scale_rsqrt(cv<R>* x, cv<R>* dst, int64_t n, const double2* __restrict__ nrm2,
+__global__ void k_scale_rsqrt(cv<R>* x, cv<R>* dst, float2* dst32, int64_t n, const double2* __restrict__ nrm2,
                               const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const R sc = (R)(1.0 / sqrt(nrm2->x));
   const cv<R> v = x[t];
-  (dst ? dst : x)[t] = mk<R>(v.x * sc, v.y * sc);
+  const cv<R> w = mk<R>(v.x * sc, v.y * sc);
+  (dst ? dst : x)[t] = w;
+  if (dst32) dst32[t] = make_float2((float)w.x, (float)w.y);
 }
 
 // y = a x (+ y if accum), a host scalar.
@@ -2694,14 +2713,14 @@ int partial_chunks(int64_t n, int mtot, int* chunk) {
   return (int)((n + c - 1) / c);
 }
 
-template <class R>
-static int dot_partial_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1, const cv<R>* x,
+template <class R, class RS = R>
+static int dot_partial_t(hipStream_t st, const cv<RS>* s0, int m0, const cv<RS>* s1, int m1, const cv<R>* x,
                          int64_t n, double2* partial, int with_norm, const int* skip) {
   const int mtot = m0 + m1 + (with_norm ? 1 : 0);
   int chunk;
   const int nch = partial_chunks(n, mtot, &chunk);
   if (mtot > 0)
-    hipLaunchKernelGGL((k_dot_partial<R>), dim3(nch, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n,
+    hipLaunchKernelGGL((k_dot_partial<R, RS>), dim3(nch, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n,
                        chunk, partial, with_norm, skip);
   return nch;
 }
@@ -2712,6 +2731,10 @@ int launch_dot_partial(hipStream_t st, const double2* s0, int m0, const double2*
 int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
                        const float2* x, int64_t n, double2* partial, int with_norm, const int* skip) {
   return dot_partial_t<float>(st, s0, m0, s1, m1, x, n, partial, with_norm, skip);
+}
+int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* x, int64_t n, double2* partial, int with_norm, const int* skip) {
+  return dot_partial_t<double, float>(st, s0, m0, s1, m1, x, n, partial, with_norm, skip);
 }
 // Dynamic LDS for staging the dot partials in the consumer kernels: used when
 // they fit in 16 KB (mtot x nch <= 1024), which keeps 6 workgroups per CU for
@@ -2726,12 +2749,12 @@ void launch_dot_reduce(hipStream_t st, const double2* partial, int m, int nch, d
   hipLaunchKernelGGL(k_dot_reduce, dim3(1), dim3(256), lds, st, partial, m, nch, out, mode, Hinv, out2,
                      lds > 0 ? 1 : 0, skip);
 }
-template <class R>
-static void subm_fused_t(hipStream_t st, const cv<R>* s0, int m0, const cv<R>* s1, int m1,
+template <class R, class RS = R>
+static void subm_fused_t(hipStream_t st, const cv<RS>* s0, int m0, const cv<RS>* s1, int m1,
                          const double2* partial, int nch, const double2* Hinv, double2* coef_set,
                          double2* coef_add, cv<R>* x, int64_t n, double2* norm_part, const int* skip) {
   const size_t lds = partial_stage_bytes(m0 + m1, nch);
-  hipLaunchKernelGGL((k_subm_fused<R>), dim3(nblk(n, 256)), dim3(256), lds, st, s0, m0, s1, m1, partial, nch,
+  hipLaunchKernelGGL((k_subm_fused<R, RS>), dim3(nblk(n, 256)), dim3(256), lds, st, s0, m0, s1, m1, partial, nch,
                      Hinv, coef_set, coef_add, x, n, norm_part, lds > 0 ? 1 : 0, skip);
 }
 void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -2744,23 +2767,36 @@ void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s
                        double2* coef_add, float2* x, int64_t n, double2* norm_part, const int* skip) {
   subm_fused_t<float>(st, s0, m0, s1, m1, partial, nch, Hinv, coef_set, coef_add, x, n, norm_part, skip);
 }
+void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, double2* x, int64_t n, double2* norm_part, const int* skip) {
+  subm_fused_t<double, float>(st, s0, m0, s1, m1, partial, nch, Hinv, coef_set, coef_add, x, n, norm_part, skip);
+}
 
-template <class R>
-static void scale_norm_t(hipStream_t st, cv<R>* x, cv<R>* dst, int64_t n, const double2* norm_part,
+template <class R, class R2 = R>
+static void scale_norm_t(hipStream_t st, cv<R>* x, cv<R>* dst, cv<R2>* dst2, int64_t n, const double2* norm_part,
                          double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                          int* done, int* steps, const double* beta, double rtol) {
-  hipLaunchKernelGGL((k_scale_norm<R>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, norm_part,
+  hipLaunchKernelGGL((k_scale_norm<R, R2>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, dst2, n, norm_part,
                      (int)nblk(n, 256), nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
 }
 void launch_scale_norm(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* norm_part,
                        double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                        int* done, int* steps, const double* beta, double rtol) {
-  scale_norm_t<double>(st, x, dst, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+  scale_norm_t<double>(st, x, dst, (double2*)nullptr, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps,
+                       beta, rtol);
+}
+void launch_scale_norm(hipStream_t st, double2* x, float2* dst32, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol) {
+  scale_norm_t<double, float>(st, x, (double2*)nullptr, dst32, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done,
+                              steps, beta, rtol);
 }
 void launch_scale_norm(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* norm_part,
                        double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                        int* done, int* steps, const double* beta, double rtol) {
-  scale_norm_t<float>(st, x, dst, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps, beta, rtol);
+  scale_norm_t<float>(st, x, dst, (float2*)nullptr, n, norm_part, nrm2_out, H, ldh, j, cs, sn, g, done, steps,
+                      beta, rtol);
 }
 
 void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -2788,14 +2824,21 @@ void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const dou
   hipLaunchKernelGGL((k_combine<float>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
                      count);
 }
+void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, double2* out, const int* count) {
+  hipLaunchKernelGGL((k_combine<double, float>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
+                     count);
+}
 
 void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* nrm2,
-                        const int* skip) {
-  hipLaunchKernelGGL((k_scale_rsqrt<double>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
+                        const int* skip, float2* dst32) {
+  hipLaunchKernelGGL((k_scale_rsqrt<double>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, dst32, n, nrm2,
+                     skip);
 }
 void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* nrm2,
                         const int* skip) {
-  hipLaunchKernelGGL((k_scale_rsqrt<float>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, n, nrm2, skip);
+  hipLaunchKernelGGL((k_scale_rsqrt<float>), dim3(nblk(n, 256)), dim3(256), 0, st, x, dst, (float2*)nullptr, n,
+                     nrm2, skip);
 }
 
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,

@@ -87,8 +87,9 @@ void launch_subm(hipStream_t st, const double2* s0, int m0, const double2* s1, i
                  const double2* c, double2* x, double2* dst, int64_t n, double sign, const int* skip);
 void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, double2* out, const int* count);
+// x (or dst) = x / sqrt(nrm2); dst32, when given, also receives the result in FP32
 void launch_scale_rsqrt(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* nrm2,
-                        const int* skip);
+                        const int* skip, float2* dst32 = nullptr);
 void launch_axpby(hipStream_t st, const double2* x, double2* y, int64_t n, double are, double aim,
                   int accum);
 // *skip_out = done || ||x||^2 after a Gram-Schmidt pass (norm partials of the
@@ -136,6 +137,9 @@ void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int
                  const double2* c, float2* x, float2* dst, int64_t n, double sign, const int* skip);
 void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, float2* out, const int* count);
+// FP32-stored vectors combined into FP64 outputs
+void launch_combine(hipStream_t st, const float2* S, int m, int64_t n, const double2* coef, int ldc,
+                    int k, double2* out, const int* count);
 void launch_scale_rsqrt(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* nrm2,
                         const int* skip);
 void launch_axpby(hipStream_t st, const float2* x, float2* y, int64_t n, double are, double aim,
@@ -154,6 +158,9 @@ int launch_dot_partial(hipStream_t st, const double2* s0, int m0, const double2*
                        const double2* x, int64_t n, double2* partial, int with_norm, const int* skip);
 int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
                        const float2* x, int64_t n, double2* partial, int with_norm, const int* skip);
+// FP32-stored vectors against an FP64 x, FP64 arithmetic
+int launch_dot_partial(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* x, int64_t n, double2* partial, int with_norm, const int* skip);
 void launch_dot_reduce(hipStream_t st, const double2* partial, int m, int nch, double2* out, int mode,
                        const double2* Hinv, double2* out2, const int* skip);
 void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -162,10 +169,18 @@ void launch_subm_fused(hipStream_t st, const double2* s0, int m0, const double2*
 void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
                        const double2* partial, int nch, const double2* Hinv, double2* coef_set,
                        double2* coef_add, float2* x, int64_t n, double2* norm_part, const int* skip);
+// FP32-stored vectors subtracted from an FP64 x, FP64 arithmetic
+void launch_subm_fused(hipStream_t st, const float2* s0, int m0, const float2* s1, int m1,
+                       const double2* partial, int nch, const double2* Hinv, double2* coef_set,
+                       double2* coef_add, double2* x, int64_t n, double2* norm_part, const int* skip);
 void launch_scale_norm(hipStream_t st, double2* x, double2* dst, int64_t n, const double2* norm_part,
                        double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                        int* done, int* steps, const double* beta, double rtol);
 void launch_scale_norm(hipStream_t st, float2* x, float2* dst, int64_t n, const double2* norm_part,
+                       double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
+                       int* done, int* steps, const double* beta, double rtol);
+// FP64 x normalised in place, its FP32 copy written to dst32
+void launch_scale_norm(hipStream_t st, double2* x, float2* dst32, int64_t n, const double2* norm_part,
                        double2* nrm2_out, double2* H, int ldh, int j, double* cs, double2* sn, double2* g,
                        int* done, int* steps, const double* beta, double rtol);
 

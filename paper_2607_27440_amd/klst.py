@@ -31,7 +31,7 @@ class Options(C.Structure):
                 ("m_min", C.c_int), ("gmres_m", C.c_int), ("max_it", C.c_int), ("tol", C.c_double),
                 ("inner_rtol", C.c_double), ("fix", C.c_double), ("seed", C.c_uint64),
                 ("pc_kernel", C.c_int), ("inner_max_it", C.c_int),
-                ("reorth", C.c_int), ("method", C.c_int)]
+                ("reorth", C.c_int), ("method", C.c_int), ("krylov32", C.c_int)]
 
 
 class Grid(C.Structure):

@@ -92,7 +92,7 @@ def test_create_without_device_fails_cleanly(klst):
 @pytest.mark.parametrize("kw", [dict(m_max=249), dict(m_min=0), dict(m_min=10, m_max=11), dict(gmres_m=0),
                                 dict(gmres_m=257), dict(tol=0.0), dict(inner_rtol=-1.0), dict(precision=2),
                                 dict(op_mode=2), dict(pc_kernel=3), dict(precision=1, pc_kernel=0),
-                                dict(inner_max_it=-1), dict(reorth=2), dict(method=2), dict(lines_per_block=0),
+                                dict(inner_max_it=-1), dict(reorth=2), dict(method=2), dict(krylov32=2), dict(lines_per_block=0),
                                 dict(lines_per_block=17), dict(max_it=0)])
 def test_invalid_options_are_rejected_before_any_device_use(klst, kw):
     """Option validation precedes device selection: every out-of-range option

@@ -469,10 +469,13 @@ def test_solve_c3_mixed_precision_matches_oracle_reference():
 
 
 @pytest.mark.parametrize("workload", ["c2", "c3", "m4_gh48", "pb_q20", "pb_q24", "pb_q32"])
-def test_bench_configurations_match_oracle(workload, c2_reference):
+@pytest.mark.parametrize("krylov32", [0, 1])
+def test_bench_configurations_match_oracle(workload, c2_reference, krylov32):
     """The solve exactly as bench.py times it (its workload options) against the
     oracle: config 2 against shift-invert Arnoldi, the other shapes against their
-    stored references; the nearest set complete, residuals gated in FP64."""
+    stored references; the nearest set complete, residuals gated in FP64.  Also
+    with the inner GMRES Krylov basis stored in FP32 (krylov32 = 1), which must
+    meet the same FP64 bar."""
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
@@ -488,7 +491,7 @@ def test_bench_configurations_match_oracle(workload, c2_reference):
         ref, kap = (_c3_reference() if workload == "c3" else _golden(workload))
         normA = _norm1_bound(P)
         tie = 1e-5 if workload == "c3" else 1e-8
-    ctx = _ctx(wl, **opts)
+    ctx = _ctx(wl, **opts, krylov32=krylov32)
     out = ctx.solve(wl.sigma, wl.nev)
     print(out["stats"], flush=True)
     assert out["nconv"] == wl.nev and np.all(out["resid"] <= 1e-10), out["stats"]
