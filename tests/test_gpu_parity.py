@@ -628,3 +628,82 @@ def test_solve_paper_shape_matches_oracle_reference(case, method):
     assert not skipped, skipped
     d = np.abs(out["lam"] - wl.sigma)
     assert np.all(np.diff(d) >= -1e-12 * d[1:])
+
+
+def _ragged(Dv):
+    """N_y = 40 (three row tiles, the last 8 rows long) at a velocity count whose
+    2 N_xi is not a multiple of 16: D_v = 1 (N_xi = 7, rank 3, one partial
+    column tile) or D_v = 2 (N_xi = 35, rank 4, five column tiles, the last 6
+    columns wide, one partly filled column group)."""
+    return W.make_workload(f"ragged_dv{Dv}_ny40", mach=2.0, Ny=40, Qx=7, Qy=5, beta=0.5,
+                           sigma=0.0, nev=4, base="bimodal", delta=2.5, Dv=Dv)
+
+
+@pytest.mark.parametrize("tile", [None, (1, 1), (2, 4), (3, 1), (0, 8)])
+@pytest.mark.parametrize("Dv", [1, 2])
+def test_apply_many_ragged_tiles(Dv, tile, tmp_path):
+    """Ragged row and column tiles under every FP64 operator kernel (the tiled
+    MFMA kernel at 1-3 row tiles and 1 or 4 wavefronts, the streaming kernel
+    as (0, 8)): each vector of a 9-vector batch equals its single application
+    bit for bit, and that is within the dot-product bound of the oracle."""
+    klst = _klst()
+    wl = _ragged(Dv)
+    P = O.Pencil(wl)
+    nvec, tau = 9, 0.2 - 0.4j
+    x = np.stack([W.random_vector(wl.n, 200 + i) for i in range(nvec)])
+    klst.tune_clear()
+    try:
+        ctx = _ctx(wl)
+        xd = _dev(x.ravel())
+        y1 = torch.empty_like(xd)
+        for i in range(nvec):
+            ctx.apply(tau, xd[i * wl.n:(i + 1) * wl.n], y1[i * wl.n:(i + 1) * wl.n])
+        if tile is not None:
+            path = tmp_path / "tile.txt"
+            path.write_text(f"{wl.Ny} {wl.Nxi} {nvec} 0 {tile[0]} {tile[1]} 0 0\n")
+            klst.tune_load(str(path))
+        print(f"[case] ragged D_v={Dv} tiles {tile}", flush=True)
+        y = torch.empty_like(xd)
+        ctx.apply_many(tau, nvec, xd, y)
+        torch.cuda.synchronize()
+        assert torch.equal(y, y1)
+        yh = y.cpu().numpy().reshape(nvec, wl.n)
+        for i in range(nvec):
+            ref = P.apply(x[i], tau)
+            bound = _gamma(P) * _abs_bound(P, x[i], tau) + 1e-300
+            assert np.all(np.abs(yh[i] - ref) <= bound), np.max(np.abs(yh[i] - ref) / bound)
+    finally:
+        klst.tune_clear()
+
+
+@pytest.mark.parametrize("tile", [None, (1, 1), (3, 4), (2, 1), (0, 4), (0, 8), (0, 16)])
+@pytest.mark.parametrize("Dv", [1, 2])
+def test_apply_f32_ragged_tiles(Dv, tile, tmp_path):
+    """The FP32 operator at ragged row and column tiles under each of its
+    kernels (matrix-core tilings; the scalar kernel at 4, 8 or 16 rows per
+    thread) against the oracle's FP64 product of the same FP32 input, within
+    the FP32 dot-product bound doubled for the tables' rounding."""
+    klst = _klst()
+    wl = _ragged(Dv)
+    P = O.Pencil(wl)
+    x = W.random_vector(wl.n, 31).astype(np.complex64)
+    tau = 0.1 + 0.05j
+    klst.tune_clear()
+    try:
+        ctx = _ctx(wl, precision=1, pc_kernel=2)
+        if tile is not None:
+            path = tmp_path / "tile.txt"
+            path.write_text(f"{wl.Ny} {wl.Nxi} 1 1 {tile[0]} {tile[1]} 0 0\n")
+            klst.tune_load(str(path))
+        print(f"[case] FP32 ragged D_v={Dv} tiles {tile}", flush=True)
+        xd = torch.from_numpy(x).to(DEV)
+        yd = torch.empty_like(xd)
+        ctx.apply_f32(tau, xd, yd)
+        torch.cuda.synchronize()
+        y = yd.cpu().numpy().astype(np.complex128)
+        x64 = x.astype(np.complex128)
+        ref = P.apply(x64, tau)
+        bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
+        assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
+    finally:
+        klst.tune_clear()
