@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
                                                  cv<R>* __restrict__ mom, int S,
                                                  const int* __restrict__ skip, int vmaj) {
   __shared__ double2 sh[4][4];
-  if (skip && *skip) return;
+  const int sk = skip ? *skip : 0;
   // vmaj > 0: a 1-D grid of Ny S vmaj workgroups ordered node-part major, vector
   // minor, spread over the XCDs by xcd_item (a node's M rows are read from one
   // L2 for all vectors); else grid (Ny S, nvec)
@@ -178,15 +178,40 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
   const int cbeg = part * per, cend = min(nc, cbeg + per);
   const cv<R>* xj = x + (int64_t)v * n + (int64_t)j * nc;
   R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-  for (int c = cbeg + threadIdx.x; c < cend; c += 256) {
-    const cv<R> xv = xj[c];
-    for (int a = 0; a < 4; ++a) {
-      if (a < r) {
-        const R mw = M[((int64_t)j * r + a) * nc + c];
-        ar[a] += mw * xv.x;
-        ai[a] += mw * xv.y;
+  // columns c, c + 256, ... in order; four of them (x and the r M rows) loaded
+  // together, the first four before the skip flag is tested
+  const R* Mj = M + (int64_t)j * r * nc;
+  cv<R> xv[4];
+  R mw[4][4];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = c0 + 256 * u;
+      const bool ok = c < cend;
+      xv[u] = ok ? xj[c] : mk<R>(0, 0);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) mw[u][a] = (ok && a < r) ? Mj[(int64_t)a * nc + c] : (R)0;
+    }
+  };
+  int c0 = cbeg + threadIdx.x;
+  load(c0);
+  if (sk) return;
+  for (;;) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (c0 + 256 * u < cend) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a < r) {
+            ar[a] += mw[u][a] * xv[u].x;
+            ai[a] += mw[u][a] * xv[u].y;
+          }
+        }
       }
     }
+    c0 += 1024;
+    if (c0 >= cend) break;
+    load(c0);
   }
   // all r sums of the four wavefronts in one exchange: wave sums, one barrier,
   // then thread a adds the four waves' values in wave order
@@ -313,7 +338,8 @@ __global__ void __launch_bounds__(256) k_apply(const cv<R>* __restrict__ x, cv<R
 // rows; the real and imaginary parts of X are two B operands sharing the D_x
 // fragment.  Operand layouts (gfx950): A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, D[i][j] for lane l, register q at i = l/16 + 4q, j = l%16.
-// grid (ceil(2Nxi/16), ceil(ceil(Ny/16)/RT), nvec), block 64.
+// 1-D grid of gx gy nvec workgroups, gx = ceil(ceil(2 Nxi / 16) / NW), gy =
+// ceil(ceil(Ny / 16) / RT), block 64 NW.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 // NW wavefronts per workgroup, each a column tile of 16; with NW > 1 the D_x^T
@@ -334,51 +360,38 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
   extern __shared__ unsigned char lds_raw[];
   double2* ms = reinterpret_cast<double2*>(lds_raw);                 // [RT*16][4] moments
   double* As = reinterpret_cast<double*>(lds_raw + RT * 16 * 4 * sizeof(double2));  // [Ny4][RT*16]
-  if (skip && *skip) return;
+  const int sk = skip ? *skip : 0;
   const int nc = 2 * Nxi;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nrt = (Ny + 15) / 16;
-  // vmaj > 0: a 1-D grid of gx gy vmaj workgroups ordered tile major, vector
-  // minor, spread over the XCDs by xcd_item (a column tile's U entries and D_x
-  // rows are read from one L2 for all vectors); else grid (gx, gy, nvec)
+  // A 1-D grid spread over the XCDs by xcd_item.  vmaj > 0: gx gy vmaj
+  // workgroups ordered tile major, vector minor (a column tile's U entries and
+  // D_x rows are read from one L2 for all vectors).  vmaj == 0 (one vector):
+  // gx gy workgroups ordered column tile major, row group minor (the row groups
+  // of a column tile read its x strip from one L2).
   int bx, by, v;
+  const int64_t item = xcd_item(blockIdx.x, gridDim.x);
   if (vmaj > 0) {
-    const int64_t item = xcd_item(blockIdx.x, gridDim.x);
     v = (int)(item % vmaj);
     const int q = (int)(item / vmaj);
     bx = q % gx;
     by = q / gx;
   } else {
-    bx = blockIdx.x;
-    by = blockIdx.y;
-    v = blockIdx.z;
+    v = 0;
+    by = (int)(item % gy);
+    bx = (int)(item / gy);
   }
-  (void)gy;
   const int rt0 = by * RT;
   const int W = RT * 16;
-  for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
-    const int jl = idx / r, a = idx - jl * r;
-    const int j = rt0 * 16 + jl;
-    ms[jl * 4 + a] = (j < Ny) ? mom_at<double>(mom, v, Ny, j, a, r, S) : make_double2(0.0, 0.0);
-  }
-  if (NW > 1) {
-    const int Ny4 = (Ny + 3) & ~3;
-    for (int idx = threadIdx.x; idx < Ny4 * W; idx += 64 * NW) {
-      const int m = idx / W, rl = idx - m * W;
-      const int row = rt0 * 16 + rl;
-      As[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
-    }
-  }
-  __syncthreads();
   const int c0 = (bx * NW + wv) * 16;
-  if (c0 >= nc) return;
   const double2* xv = x + (int64_t)v * n;
   double2* yv = y + (int64_t)v * n;
   const int li = lane & 15, lk = lane >> 4;
   const int cb = c0 + li;
-  // With one row tile (the single-vector launches) the epilogue's operands (x
-  // at the tile's rows, nu, the U columns) are loaded before the K loop, so they
-  // arrive while the MFMAs run.
+  // Loads that need neither the moments nor the D_x slice are issued first, so
+  // they are in flight while those are staged: with one row tile (the
+  // single-vector launches) the epilogue's operands (x at the tile's rows, nu,
+  // the U columns), and in every tiling the first block of the x strip.
   constexpr bool kPre = (RT == 1);
   double2 pre_x[4];
   double pre_nu[4], pre_u[4][4];
@@ -396,48 +409,62 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
         pre_u[q][a] = (ok && a < r) ? U[((int64_t)(j * 2 + fp) * r + a) * Nxi + kp] : 0.0;
     }
   }
-  dbl4 are[RT], aim[RT];
-#pragma unroll
-  for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
   // The K loop runs in blocks of XB steps of 4 rows, the next block's x strip
   // loading while the current block's MFMAs run (XB loads in flight per lane).
   // One-wavefront workgroups (small launches) take 8 steps per block; the wide
   // path, already at 2 waves per SIMD from its LDS slice and accumulators,
   // takes 4 (measured at the M = 4 shape, 64 vectors: 374 us per launch against
   // 446 us with one step of prefetch and 581 us with 8).
-  {
-    constexpr int XB = (NW == 1) ? 8 : 4;
-    auto load_block = [&](int mb, double2* dst) {
+  constexpr int XB = (NW == 1) ? 8 : 4;
+  auto load_block = [&](int mb, double2* dst) {
 #pragma unroll
-      for (int p = 0; p < XB; ++p) {
-        const int m = mb + 4 * p + lk;
-        dst[p] = (m < Ny && cb < nc) ? xv[(int64_t)m * nc + cb] : make_double2(0.0, 0.0);
-      }
-    };
-    double2 xc[XB], xn[XB];
-    load_block(0, xc);
-    for (int mb = 0; mb < Ny; mb += 4 * XB) {
-      if (mb + 4 * XB < Ny) load_block(mb + 4 * XB, xn);
-#pragma unroll
-      for (int p = 0; p < XB; ++p) {
-        const int m = mb + 4 * p + lk;
-        if (mb + 4 * p >= Ny) break;
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          double a;
-          if (NW > 1) {
-            a = As[m * W + t * 16 + li];
-          } else {
-            const int row = (rt0 + t) * 16 + li;
-            a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
-          }
-          are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].x, are[t], 0, 0, 0);
-          aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].y, aim[t], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int p = 0; p < XB; ++p) xc[p] = xn[p];
+    for (int p = 0; p < XB; ++p) {
+      const int m = mb + 4 * p + lk;
+      dst[p] = (m < Ny && cb < nc) ? xv[(int64_t)m * nc + cb] : make_double2(0.0, 0.0);
     }
+  };
+  double2 xc[XB], xn[XB];
+  load_block(0, xc);
+  if (sk) return;
+  for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
+    const int jl = idx / r, a = idx - jl * r;
+    const int j = rt0 * 16 + jl;
+    ms[jl * 4 + a] = (j < Ny) ? mom_at<double>(mom, v, Ny, j, a, r, S) : make_double2(0.0, 0.0);
+  }
+  if (NW > 1) {
+    const int Ny4 = (Ny + 3) & ~3;
+    for (int idx = threadIdx.x; idx < Ny4 * W; idx += 64 * NW) {
+      const int m = idx / W, rl = idx - m * W;
+      const int row = rt0 * 16 + rl;
+      As[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (c0 >= nc) return;
+  dbl4 are[RT], aim[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
+  for (int mb = 0; mb < Ny; mb += 4 * XB) {
+    if (mb + 4 * XB < Ny) load_block(mb + 4 * XB, xn);
+#pragma unroll
+    for (int p = 0; p < XB; ++p) {
+      const int m = mb + 4 * p + lk;
+      if (mb + 4 * p >= Ny) break;
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        double a;
+        if (NW > 1) {
+          a = As[m * W + t * 16 + li];
+        } else {
+          const int row = (rt0 + t) * 16 + li;
+          a = (row < Ny && m < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+        }
+        are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].x, are[t], 0, 0, 0);
+        aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xc[p].y, aim[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < XB; ++p) xc[p] = xn[p];
   }
   // epilogue on the accumulator layout: column c, rows j = tile*16 + lk + 4q
   const int c = c0 + li;
@@ -492,7 +519,8 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma(const double2* __restric
 // result D[i][j] sits in lane j + 16 (i / 4), register i % 4 (rows held four
 // to a lane, unlike the FP64 instruction).  Accumulation in FP32; the
 // epilogue's moments are the FP32 totals of the S column parts.
-// grid (ceil(ceil(2 Nxi / 16) / NW), ceil(ceil(Ny / 16) / RT), nvec), block 64 NW.
+// 1-D grid of gx gy nvec workgroups, gx = ceil(ceil(2 Nxi / 16) / NW), gy =
+// ceil(ceil(Ny / 16) / RT), block 64 NW.
 template <int RT, int NW>
 __global__ void __launch_bounds__(64 * NW) k_apply_mfma32(const float2* __restrict__ x, float2* __restrict__ y,
                                                           int64_t n, int Ny, int Nxi, int r, float tau_re,
@@ -502,15 +530,21 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma32(const float2* __restri
                                                           const float* __restrict__ nu,
                                                           const float* __restrict__ U,
                                                           const float2* __restrict__ mom, int S,
-                                                          const int* __restrict__ skip) {
+                                                          const int* __restrict__ skip, int gx, int gy) {
   extern __shared__ unsigned char lds_raw[];
   float2* ms = reinterpret_cast<float2*>(lds_raw);                          // [RT*16][4] moments
   float* As = reinterpret_cast<float*>(lds_raw + RT * 16 * 4 * sizeof(float2));  // [Ny4][RT*16]
   if (skip && *skip) return;
   const int nc = 2 * Nxi;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int v = blockIdx.z;
-  const int rt0 = blockIdx.y * RT;
+  // 1-D grid over the XCDs, ordered vector, column tile, row group (fastest):
+  // the row groups of a column tile read its x strip from one L2
+  const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+  const int by = (int)(item % gy);
+  const int64_t rest = item / gy;
+  const int bx = (int)(rest % gx);
+  const int v = (int)(rest / gx);
+  const int rt0 = by * RT;
   const int W = RT * 16;
   for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
     const int jl = idx / r, a = idx - jl * r;
@@ -526,7 +560,7 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma32(const float2* __restri
     }
   }
   __syncthreads();
-  const int c0 = (blockIdx.x * NW + wv) * 16;
+  const int c0 = (bx * NW + wv) * 16;
   if (c0 >= nc) return;
   const float2* xv = x + (int64_t)v * n;
   float2* yv = y + (int64_t)v * n;
@@ -2452,10 +2486,11 @@ static void apply_f32(hipStream_t st, const float2* x, float2* y, int64_t n, int
   }
   wide = wide && (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(float) <= 96 * 1024;
   const size_t lds = (size_t)rt * 16 * 4 * sizeof(float2) + (wide ? (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(float) : 0);
-  const dim3 g(wide ? (ctiles + 3) / 4 : ctiles, (nrt + rt - 1) / rt, nvec);
+  const int gx = wide ? (ctiles + 3) / 4 : ctiles, gy = (nrt + rt - 1) / rt;
+  const dim3 g((unsigned)((int64_t)gx * gy * nvec));
 #define KLST_M32(RT_, NW_) hipLaunchKernelGGL((k_apply_mfma32<RT_, NW_>), g, dim3(64 * NW_), lds, st, x, y, n, Ny, \
                                               Nxi, r, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, \
-                                              mom, S, skip)
+                                              mom, S, skip, gx, gy)
   if (wide) {
     if (rt == 6) KLST_M32(6, 4); else if (rt == 3) KLST_M32(3, 4); else if (rt == 2) KLST_M32(2, 4); else KLST_M32(1, 4);
   } else {
@@ -2517,7 +2552,10 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   }
   int rt = 6;
   while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
-  bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
+  // a single vector takes 4 wavefronts per workgroup sharing the D_x slice from
+  // LDS once it has 4 column tiles (M = 4 shape: 22.4 against 23.7 us per
+  // moments + operator; the tuned launch tables of the sweep shapes pick it too)
+  bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512 || (nvec == 1 && ctiles >= 4);
   // tuned row tiles and waves per workgroup (every output entry is accumulated
   // in the same order whatever the tiling, so the choice does not change results)
   Tuning tn;
@@ -2529,7 +2567,7 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
   const size_t lds_m = (size_t)rt * 16 * 4 * sizeof(double2);
   const size_t lds = lds_m + (wide ? (size_t)((Ny + 3) & ~3) * rt * 16 * sizeof(double) : 0);
   const int gx = wide ? (ctiles + 3) / 4 : ctiles, gy = (nrt + rt - 1) / rt;
-  const dim3 g = nvec > 1 ? dim3(gx * gy * nvec) : dim3(gx, gy, nvec);
+  const dim3 g(gx * gy * nvec);
   const int vmaj = nvec > 1 ? nvec : 0;
 #define KLST_MF(RT_, NW_) hipLaunchKernelGGL((k_apply_mfma<RT_, NW_>), g, dim3(64 * NW_), lds, st, x, y, n, Ny, \
                                              Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, S, skip, gx, gy, vmaj)
