@@ -1743,7 +1743,9 @@ __global__ void __launch_bounds__(256) k_gj_unpermute(const double2* __restrict_
 // order, so all workgroups obtain bit-identical coefficients.
 
 // partial[q * nch + chunk] = sum_{t in chunk} conj(S_q[t]) x[t] for q < m; with
-// with_norm, row q = m holds sum |x[t]|^2.  grid (nch, ceil(mtot / 4)), block 256.
+// with_norm, row q = m holds sum |x[t]|^2.  1-D grid of nch ceil(mtot / 4)
+// workgroups, block 256: item (chunk, row group) in chunk-major XCD order, so
+// the row groups that read one chunk of x do so from one L2.
 // The vectors S_q are stored in real type RS (the Krylov basis may be FP32
 // under FP64 arithmetic), x and the arithmetic in R.
 template <class R, class RS = R>
@@ -1756,9 +1758,13 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cv<RS>* __restrict__ 
   const int m = m0 + m1;
   const int mtot = m + (with_norm ? 1 : 0);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.y * 4 + wv;
+  const int gy = (mtot + 3) / 4;
+  const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+  const int bx = (int)(item / gy), by = (int)(item - (int64_t)bx * gy);
+  const int nch = gridDim.x / gy;
+  const int i = by * 4 + wv;
   if (i >= mtot) return;
-  const int64_t t0 = (int64_t)blockIdx.x * chunk;
+  const int64_t t0 = (int64_t)bx * chunk;
   const int64_t t1 = min(n, t0 + chunk);
   R ar = 0, ai = 0;
   auto accumulate = [&](const auto* __restrict__ sv) {
@@ -1787,7 +1793,7 @@ __global__ void __launch_bounds__(256) k_dot_partial(const cv<RS>* __restrict__ 
   if (i >= m) ai = 0;
   const double dr = wave_sum((double)ar);
   const double di = wave_sum((double)ai);
-  if (lane == 0) partial[(int64_t)i * gridDim.x + blockIdx.x] = make_double2(dr, di);
+  if (lane == 0) partial[(int64_t)i * nch + bx] = make_double2(dr, di);
 }
 
 // c[q] = sum over chunks of partial[q * nch + chunk], q < mtot, into LDS; one
@@ -1987,13 +1993,18 @@ __global__ void __launch_bounds__(256) k_combine(const cv<RS>* __restrict__ S, i
 // The same rotation for CB outputs per pass: every input entry S_i[t] is read
 // once per group of CB outputs instead of once per output; each output is
 // accumulated in the order of k_combine (i = 0, 1, ...), so the results are
-// bit-identical to it.  grid (ceil(n / 256), ceil(k / CB)).
+// bit-identical to it.  1-D grid of ceil(n / 256) ceil(k / CB) workgroups.
 template <class R, int CB>
 __global__ void __launch_bounds__(256) k_combine_multi(const cv<R>* __restrict__ S, int m, int64_t n,
                                                        const double2* __restrict__ coef, int ldc, int k,
                                                        cv<R>* __restrict__ out, const int* __restrict__ count) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int j0 = blockIdx.y * CB;
+  // 1-D grid, item (entry block, output group) in entry-block-major XCD order:
+  // the groups that read the same entries of S do so from one L2
+  const int ng = (k + CB - 1) / CB;
+  const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+  const int64_t tb = item / ng;
+  const int64_t t = tb * blockDim.x + threadIdx.x;
+  const int j0 = (int)(item - tb * ng) * CB;
   if (t >= n) return;
   const int mm = count ? min(m, *count) : m;
   cv<R> acc[CB];
@@ -2758,8 +2769,8 @@ static int dot_partial_t(hipStream_t st, const cv<RS>* s0, int m0, const cv<RS>*
   int chunk;
   const int nch = partial_chunks(n, mtot, &chunk);
   if (mtot > 0)
-    hipLaunchKernelGGL((k_dot_partial<R, RS>), dim3(nch, (mtot + 3) / 4), dim3(256), 0, st, s0, m0, s1, m1, x, n,
-                       chunk, partial, with_norm, skip);
+    hipLaunchKernelGGL((k_dot_partial<R, RS>), dim3(nch * ((mtot + 3) / 4)), dim3(256), 0, st, s0, m0, s1, m1, x,
+                       n, chunk, partial, with_norm, skip);
   return nch;
 }
 int launch_dot_partial(hipStream_t st, const double2* s0, int m0, const double2* s1, int m1,
@@ -2851,7 +2862,7 @@ void launch_subm(hipStream_t st, const float2* s0, int m0, const float2* s1, int
 void launch_combine(hipStream_t st, const double2* S, int m, int64_t n, const double2* coef, int ldc,
                     int k, double2* out, const int* count) {
   if (k >= 2)
-    hipLaunchKernelGGL((k_combine_multi<double, 8>), dim3(nblk(n, 256), (k + 7) / 8), dim3(256), 0, st, S, m, n,
+    hipLaunchKernelGGL((k_combine_multi<double, 8>), dim3(nblk(n, 256) * ((k + 7) / 8)), dim3(256), 0, st, S, m, n,
                        coef, ldc, k, out, count);
   else
     hipLaunchKernelGGL((k_combine<double>), dim3(nblk(n, 256), k), dim3(256), 0, st, S, m, n, coef, ldc, out,
