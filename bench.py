@@ -129,6 +129,9 @@ VARIANTS = {
         "mixed_fp32_inner_one_cycle": dict(precision=1, inner_max_it=20),
         # FP64 arithmetic with the inner GMRES Krylov basis stored in FP32
         "fp32_krylov_basis": dict(krylov32=1),
+        # classical Gram-Schmidt with the second pass only where the first kept
+        # less than 1/sqrt(2) of the norm (DGKS test on the device)
+        "dgks_second_pass": dict(reorth=1),
         "shift_invert_exact": dict(method=1, m_max=120, max_it=100),
     },
 }

@@ -630,10 +630,18 @@ bool sorted_schur(int m, const cd* G, cd* Uo, cd* To, int nsort) {
 }
 
 bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
-  std::vector<cd> H(G, G + (size_t)m * m);
-  auto h = [&](int i, int j) -> cd& { return H[(size_t)i * m + j]; };
+  // Real and imaginary parts in separate row-major arrays, so that the row
+  // sweeps of every step run over contiguous doubles; each complex product is
+  // written out as (a c - b d, a d + b c), the formula of the complex type.
+  const size_t mm = (size_t)m * m;
+  std::vector<double> Hr(mm), Hi(mm);
+  for (size_t q = 0; q < mm; ++q) { Hr[q] = G[q].real(); Hi[q] = G[q].imag(); }
+  auto hr = [&](int i) { return &Hr[(size_t)i * m]; };
+  auto hi_ = [&](int i) { return &Hi[(size_t)i * m]; };
+  auto h = [&](int i, int j) { return cd(Hr[(size_t)i * m + j], Hi[(size_t)i * m + j]); };
+  auto set = [&](int i, int j, cd z) { Hr[(size_t)i * m + j] = z.real(); Hi[(size_t)i * m + j] = z.imag(); };
   // Hessenberg reduction (similarity only: no transformation is kept)
-  std::vector<cd> v(m), t(m);
+  std::vector<double> vr(m), vi(m), tr(m), ti(m);
   for (int k = 0; k < m - 2; ++k) {
     double nrm = 0;
     for (int i = k + 1; i < m; ++i) nrm += std::norm(h(i, k));
@@ -641,31 +649,54 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
     if (nrm == 0.0) continue;
     const cd x0 = h(k + 1, k);
     const cd ph = (std::abs(x0) > 0) ? x0 / std::abs(x0) : cd(1.0);
-    for (int i = k + 1; i < m; ++i) v[i] = h(i, k);
-    v[k + 1] += ph * nrm;
+    for (int i = k + 1; i < m; ++i) { vr[i] = Hr[(size_t)i * m + k]; vi[i] = Hi[(size_t)i * m + k]; }
+    {
+      const cd v1 = cd(vr[k + 1], vi[k + 1]) + ph * nrm;
+      vr[k + 1] = v1.real();
+      vi[k + 1] = v1.imag();
+    }
     double vn = 0;
-    for (int i = k + 1; i < m; ++i) vn += std::norm(v[i]);
+    for (int i = k + 1; i < m; ++i) vn += std::norm(cd(vr[i], vi[i]));
     if (vn == 0.0) continue;
     const double f = 2.0 / vn;
-    std::fill(t.begin() + k, t.end(), cd(0.0));
+    // H <- P H: t = v^H H over columns k.., H -= v t
+    for (int jc = k; jc < m; ++jc) { tr[jc] = 0.0; ti[jc] = 0.0; }
     for (int i = k + 1; i < m; ++i) {
-      const cd vc = std::conj(v[i]);
-      const cd* hi = &h(i, 0);
-      for (int jc = k; jc < m; ++jc) t[jc] += vc * hi[jc];
+      const double a = vr[i], b = -vi[i];
+      const double* r = hr(i);
+      const double* s = hi_(i);
+      for (int jc = k; jc < m; ++jc) {
+        tr[jc] += a * r[jc] - b * s[jc];
+        ti[jc] += a * s[jc] + b * r[jc];
+      }
     }
     for (int i = k + 1; i < m; ++i) {
-      const cd vi = v[i] * f;
-      cd* hi = &h(i, 0);
-      for (int jc = k; jc < m; ++jc) hi[jc] -= vi * t[jc];
+      const double a = vr[i] * f, b = vi[i] * f;
+      double* r = hr(i);
+      double* s = hi_(i);
+      for (int jc = k; jc < m; ++jc) {
+        r[jc] -= a * tr[jc] - b * ti[jc];
+        s[jc] -= a * ti[jc] + b * tr[jc];
+      }
     }
+    // H <- H P (rows)
     for (int ir = 0; ir < m; ++ir) {
-      cd sum = 0;
-      cd* hr = &h(ir, 0);
-      for (int i = k + 1; i < m; ++i) sum += hr[i] * v[i];
-      sum *= f;
-      for (int i = k + 1; i < m; ++i) hr[i] -= sum * std::conj(v[i]);
+      double* r = hr(ir);
+      double* s = hi_(ir);
+      double sr = 0.0, si = 0.0;
+      for (int i = k + 1; i < m; ++i) {
+        sr += r[i] * vr[i] - s[i] * vi[i];
+        si += r[i] * vi[i] + s[i] * vr[i];
+      }
+      sr *= f;
+      si *= f;
+      for (int i = k + 1; i < m; ++i) {
+        // sum conj(v_i) = (sr vr + si vi, si vr - sr vi)
+        r[i] -= sr * vr[i] - si * (-vi[i]);
+        s[i] -= sr * (-vi[i]) + si * vr[i];
+      }
     }
-    for (int i = k + 2; i < m; ++i) h(i, k) = 0.0;
+    for (int i = k + 2; i < m; ++i) { Hr[(size_t)i * m + k] = 0.0; Hi[(size_t)i * m + k] = 0.0; }
   }
   // eigenvalues only: single-shift QR restricted to the active window
   const double eps = 2.220446049250313e-16;
@@ -678,7 +709,7 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
       const double sub = cabs1(h(lo, lo - 1));
       double scale = cabs1(h(lo, lo)) + cabs1(h(lo - 1, lo - 1));
       if (scale == 0.0) scale = 1.0;
-      if (sub <= eps * scale) { h(lo, lo - 1) = 0.0; break; }
+      if (sub <= eps * scale) { set(lo, lo - 1, 0.0); break; }
       --lo;
     }
     if (lo == hi) { --hi; since = 0; continue; }
@@ -688,10 +719,10 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
     if (since % 11 == 10) {
       sh = d + cd(0.75 * std::abs(c), 0.0);
     } else {
-      const cd tr = 0.5 * (a - d);
-      const cd disc = std::sqrt(tr * tr + bb * c);
-      const cd e1 = d - (bb * c) / (tr + disc), e2 = d - (bb * c) / (tr - disc);
-      const bool ok1 = std::abs(tr + disc) > 0, ok2 = std::abs(tr - disc) > 0;
+      const cd tr2 = 0.5 * (a - d);
+      const cd disc = std::sqrt(tr2 * tr2 + bb * c);
+      const cd e1 = d - (bb * c) / (tr2 + disc), e2 = d - (bb * c) / (tr2 - disc);
+      const bool ok1 = std::abs(tr2 + disc) > 0, ok2 = std::abs(tr2 - disc) > 0;
       if (ok1 && ok2) sh = (std::abs(e1 - d) < std::abs(e2 - d)) ? e1 : e2;
       else if (ok1) sh = e1;
       else if (ok2) sh = e2;
@@ -703,20 +734,30 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
       else { f0 = h(k, k - 1); g0 = h(k + 1, k - 1); }
       double cs; cd sn;
       givens(f0, g0, cs, sn);
-      const cd snc = std::conj(sn);
-      cd* rk = &h(k, 0);
-      cd* rk1 = &h(k + 1, 0);
+      const double snr = sn.real(), sni = sn.imag();
+      // rows k, k+1: (cs x + sn y, -conj(sn) x + cs y)
+      double* rk = hr(k);
+      double* ik = hi_(k);
+      double* rk1 = hr(k + 1);
+      double* ik1 = hi_(k + 1);
       for (int jc = (k == lo ? lo : k - 1); jc <= hi; ++jc) {
-        const cd xx = rk[jc], yy = rk1[jc];
-        rk[jc] = cs * xx + sn * yy;
-        rk1[jc] = -snc * xx + cs * yy;
+        const double xr = rk[jc], xi = ik[jc], yr = rk1[jc], yi = ik1[jc];
+        rk[jc] = cs * xr + (snr * yr - sni * yi);
+        ik[jc] = cs * xi + (snr * yi + sni * yr);
+        rk1[jc] = (-snr * xr - sni * xi) + cs * yr;
+        ik1[jc] = (-snr * xi + sni * xr) + cs * yi;
       }
-      if (k > lo) h(k + 1, k - 1) = 0.0;
+      if (k > lo) set(k + 1, k - 1, 0.0);
+      // columns k, k+1: (cs x + conj(sn) y, -sn x + cs y)
       const int rmax = std::min(k + 2, hi);
       for (int ir = lo; ir <= rmax; ++ir) {
-        const cd xx = h(ir, k), yy = h(ir, k + 1);
-        h(ir, k) = cs * xx + snc * yy;
-        h(ir, k + 1) = -sn * xx + cs * yy;
+        double* r = hr(ir);
+        double* s = hi_(ir);
+        const double xr = r[k], xi = s[k], yr = r[k + 1], yi = s[k + 1];
+        r[k] = cs * xr + (snr * yr - (-sni) * yi);
+        s[k] = cs * xi + (snr * yi + (-sni) * yr);
+        r[k + 1] = (-snr * xr - (-sni) * xi) + cs * yr;
+        s[k + 1] = (-snr * xi + (-sni) * xr) + cs * yi;
       }
     }
   }
@@ -727,34 +768,56 @@ bool dominant_eig(int m, const cd* G, cd& mu, cd* x) {
   // eigenvector by inverse iteration with G - mu I (LU, partial pivoting; an
   // exactly zero pivot is replaced by eps ||G||)
   double gn = 0;
-  for (size_t q = 0; q < (size_t)m * m; ++q) gn = std::max(gn, std::abs(G[q]));
-  std::vector<cd> Lu(G, G + (size_t)m * m);
-  for (int i = 0; i < m; ++i) Lu[(size_t)i * m + i] -= mu;
+  for (size_t q = 0; q < mm; ++q) gn = std::max(gn, std::abs(G[q]));
+  std::vector<double> Lr(mm), Li(mm);
+  for (size_t q = 0; q < mm; ++q) { Lr[q] = G[q].real(); Li[q] = G[q].imag(); }
+  for (int i = 0; i < m; ++i) {
+    const cd dd = cd(Lr[(size_t)i * m + i], Li[(size_t)i * m + i]) - mu;
+    Lr[(size_t)i * m + i] = dd.real();
+    Li[(size_t)i * m + i] = dd.imag();
+  }
+  auto L = [&](int i, int j) { return cd(Lr[(size_t)i * m + j], Li[(size_t)i * m + j]); };
   std::vector<int> piv(m);
   for (int k = 0; k < m; ++k) {
     int p = k;
     for (int i = k + 1; i < m; ++i)
-      if (std::abs(Lu[(size_t)i * m + k]) > std::abs(Lu[(size_t)p * m + k])) p = i;
+      if (std::abs(L(i, k)) > std::abs(L(p, k))) p = i;
     piv[k] = p;
     if (p != k)
-      for (int j = 0; j < m; ++j) std::swap(Lu[(size_t)p * m + j], Lu[(size_t)k * m + j]);
-    cd& pk = Lu[(size_t)k * m + k];
-    if (std::abs(pk) == 0.0) pk = eps * std::max(gn, 1e-300);
+      for (int j = 0; j < m; ++j) {
+        std::swap(Lr[(size_t)p * m + j], Lr[(size_t)k * m + j]);
+        std::swap(Li[(size_t)p * m + j], Li[(size_t)k * m + j]);
+      }
+    cd pk = L(k, k);
+    if (std::abs(pk) == 0.0) {
+      pk = eps * std::max(gn, 1e-300);
+      Lr[(size_t)k * m + k] = pk.real();
+      Li[(size_t)k * m + k] = pk.imag();
+    }
+    const double* ur = &Lr[(size_t)k * m];
+    const double* ui = &Li[(size_t)k * m];
     for (int i = k + 1; i < m; ++i) {
-      const cd l = Lu[(size_t)i * m + k] / pk;
-      Lu[(size_t)i * m + k] = l;
+      const cd l = L(i, k) / pk;
+      Lr[(size_t)i * m + k] = l.real();
+      Li[(size_t)i * m + k] = l.imag();
       if (l == 0.0) continue;
-      for (int j = k + 1; j < m; ++j) Lu[(size_t)i * m + j] -= l * Lu[(size_t)k * m + j];
+      const double a = l.real(), b = l.imag();
+      double* r = &Lr[(size_t)i * m];
+      double* s = &Li[(size_t)i * m];
+      for (int j = k + 1; j < m; ++j) {
+        r[j] -= a * ur[j] - b * ui[j];
+        s[j] -= a * ui[j] + b * ur[j];
+      }
     }
   }
   std::vector<cd> y(m, cd(1.0));
   for (int it = 0; it < 2; ++it) {
     for (int k = 0; k < m; ++k) std::swap(y[k], y[piv[k]]);
     for (int i = 0; i < m; ++i)
-      for (int j = 0; j < i; ++j) y[i] -= Lu[(size_t)i * m + j] * y[j];
+      for (int j = 0; j < i; ++j) y[i] -= L(i, j) * y[j];
     for (int i = m - 1; i >= 0; --i) {
-      for (int j = i + 1; j < m; ++j) y[i] -= Lu[(size_t)i * m + j] * y[j];
-      y[i] /= Lu[(size_t)i * m + i];
+      for (int j = i + 1; j < m; ++j) y[i] -= L(i, j) * y[j];
+      y[i] /= L(i, i);
     }
     double nn = 0;
     for (int i = 0; i < m; ++i) nn += std::norm(y[i]);
