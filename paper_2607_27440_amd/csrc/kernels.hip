@@ -1811,10 +1811,19 @@ __device__ __forceinline__ void reduce_partials(const double2* __restrict__ part
     __syncthreads();
     src = stage;
   }
+  // each lane adds its chunks in order lane, lane + 64, ...; four of them are
+  // loaded together (a chunk count that is not a multiple of 64 is predicated)
   for (int q = wv; q < mtot; q += nw) {
     const double2* pq = src + (int64_t)q * nch;
     double sr = 0.0, si = 0.0;
-    for (int cc = lane; cc < nch; cc += 64) { const double2 pv = pq[cc]; sr += pv.x; si += pv.y; }
+    for (int c0 = lane; c0 < nch; c0 += 256) {
+      double2 pv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) pv[i] = (c0 + 64 * i < nch) ? pq[c0 + 64 * i] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (c0 + 64 * i < nch) { sr += pv[i].x; si += pv[i].y; }
+    }
     sr = wave_sum(sr);
     si = wave_sum(si);
     if (lane == 0) c[q] = make_double2(sr, si);
@@ -1939,8 +1948,16 @@ __global__ void __launch_bounds__(256) k_scale_norm(cv<R>* x, cv<R>* dst, cv<R2>
   __shared__ double2 sh[4];
   __shared__ double tot;
   if (done && *done) return;
+  // each thread adds its partials b = tid, tid + 256, ... in order, four loaded together
   double ps = 0.0;
-  for (int b = threadIdx.x; b < nb; b += 256) ps += norm_part[b].x;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 1024) {
+    double pv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pv[i] = (b0 + 256 * i < nb) ? norm_part[b0 + 256 * i].x : 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (b0 + 256 * i < nb) ps += pv[i];
+  }
   const double2 s2 = block_sum256(make_double2(ps, 0.0), sh);
   if (threadIdx.x == 0) {
     tot = s2.x;
