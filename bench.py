@@ -382,7 +382,21 @@ def cpu_baseline(wl, seconds, opts, gpu_outer=None, repeats=3):
     return line
 
 
+# JD options of the sweep draws (batched and served modes).  FP64: GMRES(20),
+# restarts keeping 6 of 30 vectors.  Mixed precision: GMRES(15) keeping 12, with
+# the library's three FP64-refined FP32 cycles per correction equation (306-315
+# against 282 eigenpairs/s on the batched and served sets).  A sweep of the
+# batched mode over GMRES(10-20), 6-15 vectors kept, theta switches at 1e-2-1e-4
+# and one to three FP32 cycles found faster settings (two cycles: 340; FP64 with
+# GMRES(15) keeping 12: 463 against 417), but each left two draws of the served
+# request mix unconverged after 2,000 outer iterations.
 SWEEP_OPTS = dict(pc_kernel=2, m_max=30, m_min=6, gmres_m=20)
+SWEEP_MIXED = dict(m_min=12, gmres_m=15)
+
+
+def sweep_opts(prec):
+    """JD options of a sweep draw in FP64 (prec = 0) or mixed precision (prec = 1)."""
+    return dict(SWEEP_OPTS, **(SWEEP_MIXED if prec else {}))
 
 
 def _common(metric, unit, value, a, el, nsteps, dtype, config, extra):
@@ -493,7 +507,7 @@ def run_batched(a):
     wls = workloads.sweep(seed=4, count=a.count, nev=8)
 
     def run(slots, prec, method=0):
-        with klst.Server(slots=slots, precision=prec, max_it=a.max_it, method=method, **SWEEP_OPTS) as sv:
+        with klst.Server(slots=slots, precision=prec, max_it=a.max_it, method=method, **sweep_opts(prec)) as sv:
             if a.warmup:
                 sv.solve_all(wls[:2])
             t = time.perf_counter()
@@ -505,7 +519,7 @@ def run_batched(a):
     prec = 0 if a.precision == "fp64" else 1
     tune = None
     if not a.no_tune:
-        tune = tune_shapes(wls, SWEEP_OPTS, prec, a.tune_cache)
+        tune = tune_shapes(wls, sweep_opts(prec), prec, a.tune_cache)
         log(f"[bench] launch table: {tune}")
     log(f"[bench] batched: {len(wls)} solves, serial plain FP64 baseline")
     g0, e0, _, _ = run(1, 0)
@@ -515,7 +529,7 @@ def run_batched(a):
     g3, e3, res3, _ = run(a.slots, prec, method=1)
     lat = [r["service_s"] for r in res]
     cfg = {"workload": f"sweep_seed4_{len(wls)}_solves_nev8", "slots": a.slots, "precision": a.precision,
-           "max_it": a.max_it, **SWEEP_OPTS}
+           "max_it": a.max_it, **sweep_opts(prec)}
     other = "mixed" if prec == 0 else "fp64"
     return _common("eigenpairs/s at rel. residual <= 1e-10 (batched sweep)", "eigenpairs/s", g1 / e1, a, e1,
                    len(wls), "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
@@ -553,10 +567,10 @@ def run_served(a):
     prec = 0 if a.precision == "fp64" else 1
     tune = None
     if not a.no_tune:
-        tune = tune_shapes(reqs, SWEEP_OPTS, prec, a.tune_cache)
+        tune = tune_shapes(reqs, sweep_opts(prec), prec, a.tune_cache)
     fracs = [float(v) for v in a.rates.split(",")]
     per_rate = {}
-    with klst.Server(slots=a.slots, precision=prec, max_it=a.max_it, **SWEEP_OPTS) as sv:
+    with klst.Server(slots=a.slots, precision=prec, max_it=a.max_it, **sweep_opts(prec)) as sv:
         cal = reqs[: min(48, len(reqs))]
         sv.solve_all(cal[:4])
         t = time.perf_counter()
@@ -592,7 +606,7 @@ def run_served(a):
                 f"{ {k: v for k, v in per_rate[frac].items() if k != 'arrive'} }")
         st = sv.stats()
     # baseline: plain FP64, one request at a time in arrival order
-    with klst.Server(slots=1, precision=0, max_it=a.max_it, **SWEEP_OPTS) as sb:
+    with klst.Server(slots=1, precision=0, max_it=a.max_it, **sweep_opts(0)) as sb:
         serv, goodb = [], []
         for wl in reqs:
             r = sb.solve_all([wl])[0]
@@ -614,7 +628,7 @@ def run_served(a):
     main = per_rate.get(0.7, per_rate[fracs[0]])
     cfg = {"workload": f"served_poisson_seed5_{a.requests}req_after_{a.warm_requests}_95pct_sweep_5pct_ny64_nxi96_nev8",
            "slots": a.slots, "rate_fraction": 0.7 if 0.7 in per_rate else fracs[0],
-           "saturated_requests_per_s": round(sat, 3), "precision": a.precision, "max_it": a.max_it, **SWEEP_OPTS}
+           "saturated_requests_per_s": round(sat, 3), "precision": a.precision, "max_it": a.max_it, **sweep_opts(prec)}
     return _common("eigenpairs/s at rel. residual <= 1e-10 (served sweep)", "eigenpairs/s",
                    main["eigenpairs_per_s"], a, 0.0, a.requests, "c128" if prec == 0 else "c64-inner/c128-outer", cfg,
                    {"p50_latency_s": main["p50_latency_s"], "p99_latency_s": main["p99_latency_s"],
