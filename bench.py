@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix cores)
+FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (vector and matrix cores)
 # HBM bytes per launch of the roofline kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE,
 # each scaled by the same counter's reading for a 256 MiB copy; keyed by workload,
 # valid for the kernel as counted (the profile named beside each figure)
@@ -298,7 +299,7 @@ def blockjacobi_roofline(ctx, wl, torch, reps):
             "bytes_per_launch": nbytes}
 
 
-def hbm_entries(ctx, wl, torch, reps, nvec=64):
+def hbm_entries(ctx, wl, torch, reps, nvec=64, ctx32=None, nvec32=128):
     """HBM rates on working sets above 512 MB (twice the 256 MB Infinity Cache):
     the explicit CSR product (A - tau B) x, 20 B per stored entry plus the row
     pointers and the vectors, and the matrix-free operator on nvec vectors in
@@ -326,6 +327,25 @@ def hbm_entries(ctx, wl, torch, reps, nvec=64):
                      "frac_hbm": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4),
                      "TFLOP/s": round(flops / avg / 1e12, 3),
                      "frac_fp64": round(flops / avg / 1e12 / FP64_PEAK_TFLOPS, 4)}
+    if ctx32 is not None:
+        # the FP32 operator of the mixed-precision inner solve on nvec32 vectors
+        # (x read by the moment sums and by the streaming GEMM, y written: 24 n B
+        # per vector, plus the FP32 U and M tables once)
+        xf = torch.randn(nvec32 * n, dtype=torch.complex64, device="cuda")
+        yf = torch.empty_like(xf)
+        fn = lambda: ctx32.apply_many_f32(0.0, nvec32, xf, yf)
+        nbytes = 24 * n * nvec32 + tables // 2
+        flops = nvec32 * n * (4 * wl.Ny + 8 * 4 + 8)
+        for _ in range(3):
+            fn()
+        avg, med, mn = _event_times(fn, reps, torch, st)
+        out[f"matrix_free_fp32_x{nvec32}"] = {
+            "avg_us": round(avg * 1e6, 3), "median_us": round(med * 1e6, 3), "min_us": round(mn * 1e6, 3),
+            "bytes": nbytes, "GB/s": round(nbytes / avg / 1e9, 2),
+            "frac_hbm": round(nbytes / avg / 1e9 / HBM_PEAK_GBS, 4),
+            "TFLOP/s": round(flops / avg / 1e12, 3),
+            "frac_fp32": round(flops / avg / 1e12 / FP32_PEAK_TFLOPS, 4)}
+        del xf, yf
     return out
 
 
@@ -808,7 +828,9 @@ def main():
     else:
         roof = blockjacobi_roofline(ctx, wl, torch, a.kernel_reps)
     log(f"[bench] roofline {roof}")
-    hbm = hbm_entries(ctx, wl, torch, max(10, a.kernel_reps // 10))
+    with klst.Context(stream=st.cuda_stream, precision=1, **opts) as ctx32:
+        ctx32.assemble(wl)
+        hbm = hbm_entries(ctx, wl, torch, max(10, a.kernel_reps // 10), ctx32=ctx32)
     log(f"[bench] hbm {hbm}")
     line = {
         "metric": "eigenpairs/s at rel. residual <= 1e-10",

@@ -176,6 +176,17 @@ klst_status klst_apply(klst_ctx* ctx, const double tau[2], const void* x, void* 
  * problem, or the context is not mixed precision), EINVAL, EDEVICE. */
 klst_status klst_apply_f32(klst_ctx* ctx, const double tau[2], const void* x, void* y);
 
+/* The FP32 product batched over nvec vectors of n complex floats stored
+ * contiguously (vector i at x + i n, device memory; x and y must not
+ * overlap): the FP32 moment sums of every vector, then the FP32 matrix-core
+ * operator over all of them in one launch.  Each vector's result is the FP32
+ * product above up to the rounding of its tiling (the launch shape depends on
+ * nvec).  The FP32 moment partials grow to nvec vectors on first use (context
+ * memory, freed with the problem).  Errors: ESTATE (no problem, or the context
+ * is not mixed precision), EINVAL (null pointer, nvec outside 1..65535),
+ * ENOMEM, EDEVICE. */
+klst_status klst_apply_many_f32(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);
+
 /* Same product, batched over nvec vectors stored contiguously (vector i at
  * x + i n).  Matrix-free only. */
 klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y);

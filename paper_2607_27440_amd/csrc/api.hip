@@ -42,6 +42,7 @@ struct klst_ctx {
          *d_U = nullptr, *d_M = nullptr;
   double2* d_mom = nullptr;
   int mom_cap = 0;   // vectors
+  int mom32_cap = 0; // vectors the FP32 moment partials hold
   // post-processing: weights, base macros [Ny][rho, u, E, T], NONEQ base g
   double *d_w = nullptr, *d_base = nullptr, *d_gc = nullptr;
   // explicit CSR
@@ -157,6 +158,7 @@ void free_problem(klst_ctx* ctx) {
   dfree(ctx, ctx->d_Pinv32); dfree(ctx, ctx->d_Sinv32); dfree(ctx, ctx->d_capd32);
   dfree(ctx, ctx->d_w); dfree(ctx, ctx->d_base); dfree(ctx, ctx->d_gc);
   ctx->mom_cap = 0;
+  ctx->mom32_cap = 0;
   ctx->pc_ready = false;
   ctx->assembled = false;
 }
@@ -166,6 +168,16 @@ klst_status ensure_mom(klst_ctx* ctx, int nvec) {
   dfree(ctx, ctx->d_mom);
   ALLOC(ctx->d_mom, sizeof(double2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 9);
   ctx->mom_cap = nvec;
+  return KLST_OK;
+}
+
+// FP32 moment partials for nvec vectors (up to 8 column parts each).
+klst_status ensure_mom32(klst_ctx* ctx, int nvec) {
+  if (ctx->mom32_cap >= nvec) return KLST_OK;
+  dfree(ctx, ctx->d_mom32);
+  ctx->mom32_cap = 0;
+  ALLOC(ctx->d_mom32, sizeof(float2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 8);
+  ctx->mom32_cap = nvec;
   return KLST_OK;
 }
 
@@ -438,6 +450,7 @@ klst_status upload_fp32_tables(klst_ctx* ctx) {
   if ((s = up(ctx->d_U32, q.U)) != KLST_OK) return s;
   if ((s = up(ctx->d_M32, q.M)) != KLST_OK) return s;
   ALLOC(ctx->d_mom32, sizeof(float2) * (size_t)q.Ny * q.r * 8);
+  ctx->mom32_cap = 1;
   return KLST_OK;
 }
 
@@ -692,6 +705,25 @@ klst_status klst_apply_f32(klst_ctx* ctx, const double tau[2], const void* x, vo
     return fail(ctx, KLST_ESTATE, "klst_apply_f32 needs a mixed-precision context (precision = 1)");
   HIPCHK(hipSetDevice(ctx->opt.device));
   return op_v(ctx, cd(tau[0], tau[1]), (const float2*)x, (float2*)y, nullptr);
+}
+
+klst_status klst_apply_many_f32(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y) {
+  if (!ctx || !tau || !x || !y || nvec < 1 || nvec > 65535) return KLST_EINVAL;
+  if (!ctx->assembled) return fail(ctx, KLST_ESTATE, "klst_apply_many_f32 before klst_assemble");
+  if (ctx->opt.precision != 1 || !ctx->d_DxT32)
+    return fail(ctx, KLST_ESTATE, "klst_apply_many_f32 needs a mixed-precision context (precision = 1)");
+  HIPCHK(hipSetDevice(ctx->opt.device));
+  klst_status s = ensure_mom32(ctx, nvec);
+  if (s != KLST_OK) return s;
+  const klst::Problem& p = ctx->prob;
+  klst::dev::launch_moments(ctx->stream, (const float2*)x, p.n(), nvec, p.Ny, p.Nxi, p.r, ctx->d_M32, ctx->d_mom32,
+                            nullptr);
+  klst::dev::launch_apply(ctx->stream, (const float2*)x, (float2*)y, p.n(), nvec, p.Ny, p.Nxi, p.r, tau[0], tau[1],
+                          p.beta, ctx->d_DxT32, ctx->d_xix32, ctx->d_xiy32, ctx->d_nu32, ctx->d_U32, ctx->d_mom32,
+                          nullptr);
+  HIPCHK(hipGetLastError());
+  ctx->stats.op_applies += nvec;
+  return KLST_OK;
 }
 
 klst_status klst_apply_many(klst_ctx* ctx, const double tau[2], int nvec, const void* x, void* y) {

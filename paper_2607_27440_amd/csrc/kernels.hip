@@ -842,38 +842,38 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
 // wavefront sums is double buffered with one LDS-only barrier, so those loads
 // stay in flight across it.  grid (Ny S, vector groups), block 256; CPT =
 // columns per thread (the part has <= 256 CPT).
-template <int CPT>
-__global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict__ x, int64_t n, int Ny, int Nxi,
-                                                       int r, const double* __restrict__ M,
-                                                       double2* __restrict__ mom, int S, int nvec, int VG) {
+template <class R, int CPT>
+__global__ void __launch_bounds__(256) k_moments_batch(const cv<R>* __restrict__ x, int64_t n, int Ny, int Nxi,
+                                                       int r, const R* __restrict__ M,
+                                                       cv<R>* __restrict__ mom, int S, int nvec, int VG) {
   __shared__ double2 sh[2][4][4];
   const int j = blockIdx.x / S, part = blockIdx.x - j * S;
   const int v0 = blockIdx.y * VG, v1 = min(nvec, v0 + VG);
   const int nc = 2 * Nxi;
   const int per = (nc + S - 1) / S;
   const int cbeg = part * per, cend = min(nc, cbeg + per);
-  double mw[CPT][4];
+  R mw[CPT][4];
 #pragma unroll
   for (int i = 0; i < CPT; ++i) {
     const int cc = cbeg + threadIdx.x + 256 * i;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) mw[i][a] = (cc < cend && a < r) ? M[((int64_t)j * r + a) * nc + cc] : 0.0;
+    for (int a = 0; a < 4; ++a) mw[i][a] = (cc < cend && a < r) ? M[((int64_t)j * r + a) * nc + cc] : (R)0;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  auto load = [&](int v, double2* xr) {
-    const double2* xj = x + (int64_t)v * n + (int64_t)j * nc;
+  auto load = [&](int v, cv<R>* xr) {
+    const cv<R>* xj = x + (int64_t)v * n + (int64_t)j * nc;
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int cc = cbeg + threadIdx.x + 256 * i;
-      xr[i] = (cc < cend) ? xj[cc] : make_double2(0.0, 0.0);
+      xr[i] = (cc < cend) ? xj[cc] : mk<R>(0, 0);
     }
   };
-  double2 xc[CPT], xn[CPT];
+  cv<R> xc[CPT], xn[CPT];
   if (v0 < v1) load(v0, xc);
   for (int v = v0; v < v1; ++v) {
     const int buf = (v - v0) & 1;
     if (v + 1 < v1) load(v + 1, xn);
-    double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+    R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int cc = cbeg + threadIdx.x + 256 * i;
@@ -890,7 +890,7 @@ __global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if (a < r) {
-        const double sr = wave_sum(ar[a]), si = wave_sum(ai[a]);
+        const double sr = wave_sum((double)ar[a]), si = wave_sum((double)ai[a]);
         if (lane == 0) sh[buf][wv][a] = make_double2(sr, si);
       }
     }
@@ -900,7 +900,7 @@ __global__ void __launch_bounds__(256) k_moments_batch(const double2* __restrict
     if (threadIdx.x < r) {
       double2 sres = make_double2(0.0, 0.0);
       for (int w = 0; w < 4; ++w) sres = cadd(sres, sh[buf][w][threadIdx.x]);
-      mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = sres;
+      mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = mk<R>((R)sres.x, (R)sres.y);
     }
 #pragma unroll
     for (int i = 0; i < CPT; ++i) xc[i] = xn[i];
@@ -2448,18 +2448,18 @@ template <class R>
 static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int Ny, int Nxi, int r,
                       const R* M, cv<R>* mom, const int* skip) {
   const int S = moment_splits(Ny, nvec, Nxi, sizeof(R) == 4 ? 1 : 0);
-  if constexpr (sizeof(R) == 8) {
+  {
     const int per = (2 * Nxi + S - 1) / S;
     if (nvec >= kBatchMin && !skip && per <= 3 * 256) {
       int VG, nvg;
       vector_groups(nvec, (int64_t)Ny * S, 2048, &VG, &nvg);
       const dim3 g(Ny * S, nvg);
       if (per <= 256)
-        hipLaunchKernelGGL((k_moments_batch<1>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+        hipLaunchKernelGGL((k_moments_batch<R, 1>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
       else if (per <= 512)
-        hipLaunchKernelGGL((k_moments_batch<2>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+        hipLaunchKernelGGL((k_moments_batch<R, 2>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
       else
-        hipLaunchKernelGGL((k_moments_batch<3>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
+        hipLaunchKernelGGL((k_moments_batch<R, 3>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
       return;
     }
   }
@@ -2506,6 +2506,9 @@ static void apply_f32(hipStream_t st, const float2* x, float2* y, int64_t n, int
   const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
   int rt = 6;
   while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
+  // many vectors: at most two row tiles per wavefront (M = 4 shape, 128 vectors:
+  // 345 us against 405 us with six)
+  if (nvec >= kBatchMin) rt = std::min(rt, 2);
   bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
   if (tuned && (tn.apply_nw == 1 || tn.apply_nw == 4) &&
       (tn.apply_rt == 1 || tn.apply_rt == 2 || tn.apply_rt == 3 || tn.apply_rt == 6)) {

@@ -80,6 +80,7 @@ _sig = {
     "klst_dims": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
     "klst_apply": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_f32": (C.c_int, [_P, _D2, _P, _P]),
+    "klst_apply_many_f32": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_apply_many": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
     "klst_apply_csr": (C.c_int, [_P, _D2, _P, _P]),
     "klst_apply_many_noalloc": (C.c_int, [_P, _D2, C.c_int, _P, _P]),
@@ -334,12 +335,25 @@ class Context:
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_f32(self._h, p, self._ptr32(x), self._ptr32(y)), "klst_apply_f32")
 
+    def _check_many(self, nvec, x, y):
+        need = int(nvec) * self.n
+        if x.numel() < need or y.numel() < need:
+            raise ValueError(f"{nvec} vectors of {self.n} entries need {need} elements in x and y")
+
+    def apply_many_f32(self, tau, nvec, x, y):
+        self._check_many(nvec, x, y)
+        a, p = self._tau(tau)
+        self._check(_lib.klst_apply_many_f32(self._h, p, int(nvec), self._ptr32(x), self._ptr32(y)),
+                    "klst_apply_many_f32")
+
     def apply_many(self, tau, nvec, x, y):
+        self._check_many(nvec, x, y)
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_many(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
                     "klst_apply_many")
 
     def apply_many_noalloc(self, tau, nvec, x, y):
+        self._check_many(nvec, x, y)
         a, p = self._tau(tau)
         self._check(_lib.klst_apply_many_noalloc(self._h, p, int(nvec), self._ptr(x), self._ptr(y)),
                     "klst_apply_many_noalloc")

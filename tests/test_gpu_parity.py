@@ -707,3 +707,27 @@ def test_apply_f32_ragged_tiles(Dv, tile, tmp_path):
         assert np.all(np.abs(y - ref) <= bound), np.max(np.abs(y - ref) / bound)
     finally:
         klst.tune_clear()
+
+
+@pytest.mark.parametrize("cfg,nvec", [("c2", 5), ("c3", 3), ("ragged2", 9)])
+def test_apply_many_f32_matches_oracle(cfg, nvec):
+    """The batched FP32 operator (klst_apply_many_f32: FP32 moments of every
+    vector, then the FP32 matrix-core operator over all of them in one launch)
+    against the oracle's FP64 product of each FP32 input vector, within the FP32
+    dot-product bound doubled for the tables' own rounding."""
+    wl = {"c2": W.config2, "c3": W.config3, "ragged2": lambda: _ragged(2)}[cfg]()
+    P = O.Pencil(wl)
+    x = np.stack([W.random_vector(wl.n, 60 + i) for i in range(nvec)]).astype(np.complex64)
+    tau = -0.2 + 0.3j
+    print(f"[case] batched FP32 operator {wl.name} x {nvec}", flush=True)
+    ctx = _ctx(wl, precision=1, pc_kernel=2)
+    xd = torch.from_numpy(x.ravel()).to(DEV)
+    yd = torch.empty_like(xd)
+    ctx.apply_many_f32(tau, nvec, xd, yd)
+    torch.cuda.synchronize()
+    y = yd.cpu().numpy().astype(np.complex128).reshape(nvec, wl.n)
+    for i in range(nvec):
+        x64 = x[i].astype(np.complex128)
+        ref = P.apply_structured(x64, tau) if wl.n > 60000 else P.apply(x64, tau)
+        bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
+        assert np.all(np.abs(y[i] - ref) <= bound), (i, np.max(np.abs(y[i] - ref) / bound))
