@@ -679,8 +679,8 @@ def run_served(a):
 
 def run_profile(a):
     """Kernel-only run for rocprofv3 (timing and HBM counters): the workload's
-    preconditioner apply, matrix-free operator apply and 64-vector operator
-    apply, `kernel_reps` times each,
+    preconditioner apply, matrix-free operator apply, 64-vector operator apply
+    and 128-vector FP32 operator apply, `kernel_reps` times each,
     then a plain 256 MiB device copy (`kernel_reps` times) whose known traffic
     (read 256 MiB, write 256 MiB per dispatch) calibrates FETCH_SIZE / WRITE_SIZE.
     Prints one JSON line with the event-timed averages."""
@@ -727,6 +727,17 @@ def run_profile(a):
         avg, med, mn = _event_times(lambda: ctx.apply_many(0.0, 64, xm, ym), a.kernel_reps, torch, st)
         out["apply_many_64_us"] = {"avg": round(avg * 1e6, 3), "median": round(med * 1e6, 3), "min": round(mn * 1e6, 3)}
         del xm, ym
+    # the FP32 operator of the mixed-precision inner solve on 128 vectors
+    with klst.Context(stream=st.cuda_stream, precision=1, **opts) as ctx32:
+        ctx32.assemble(wl)
+        xf = torch.randn(128 * wl.n, dtype=torch.complex64, device="cuda")
+        yf = torch.empty_like(xf)
+        for _ in range(3):
+            ctx32.apply_many_f32(0.0, 128, xf, yf)
+        avg, med, mn = _event_times(lambda: ctx32.apply_many_f32(0.0, 128, xf, yf), a.kernel_reps, torch, st)
+        out["apply_many_f32_128_us"] = {"avg": round(avg * 1e6, 3), "median": round(med * 1e6, 3),
+                                        "min": round(mn * 1e6, 3)}
+        del xf, yf
     src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -537,13 +537,15 @@ __global__ void __launch_bounds__(64 * NW) k_apply_mfma32(const float2* __restri
   if (skip && *skip) return;
   const int nc = 2 * Nxi;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // 1-D grid over the XCDs, ordered vector, column tile, row group (fastest):
-  // the row groups of a column tile read its x strip from one L2
+  // 1-D grid over the XCDs, ordered column tile, vector, row group (fastest):
+  // the row groups of a column tile read its x strip from one L2, and the
+  // vectors of a column tile its U columns
   const int64_t item = xcd_item(blockIdx.x, gridDim.x);
+  const int nv = (int)(gridDim.x / ((int64_t)gx * gy));
   const int by = (int)(item % gy);
   const int64_t rest = item / gy;
-  const int bx = (int)(rest % gx);
-  const int v = (int)(rest / gx);
+  const int v = (int)(rest % nv);
+  const int bx = (int)(rest / nv);
   const int rt0 = by * RT;
   const int W = RT * 16;
   for (int idx = threadIdx.x; idx < W * r; idx += 64 * NW) {
