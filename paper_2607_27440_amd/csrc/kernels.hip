@@ -843,7 +843,9 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
 // entries load while the current one is reduced; the per-vector exchange of
 // wavefront sums is double buffered with one LDS-only barrier, so those loads
 // stay in flight across it.  grid (Ny S, vector groups), block 256; CPT =
-// columns per thread (the part has <= 256 CPT).
+// columns per thread (the part has <= 256 CPT).  R: FP64, or FP32 for the
+// mixed solve's tables (sums in R per thread, wavefront sums in FP64, as in
+// k_moments).
 template <class R, int CPT>
 __global__ void __launch_bounds__(256) k_moments_batch(const cv<R>* __restrict__ x, int64_t n, int Ny, int Nxi,
                                                        int r, const R* __restrict__ M,
