@@ -171,12 +171,13 @@ klst_status ensure_mom(klst_ctx* ctx, int nvec) {
   return KLST_OK;
 }
 
-// FP32 moment partials for nvec vectors (up to 8 column parts each).
+// FP32 moment partials for nvec vectors (up to 8 column parts each) and their
+// totals (the streaming kernel's input).
 klst_status ensure_mom32(klst_ctx* ctx, int nvec) {
   if (ctx->mom32_cap >= nvec) return KLST_OK;
   dfree(ctx, ctx->d_mom32);
   ctx->mom32_cap = 0;
-  ALLOC(ctx->d_mom32, sizeof(float2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 8);
+  ALLOC(ctx->d_mom32, sizeof(float2) * (size_t)ctx->prob.Ny * ctx->prob.r * nvec * 9);
   ctx->mom32_cap = nvec;
   return KLST_OK;
 }

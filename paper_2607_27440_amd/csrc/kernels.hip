@@ -146,6 +146,17 @@ __device__ __forceinline__ void op_moment(double2& o, double ua, double2 ma) {
   o.x = fma(-ua, ma.x, o.x);
   o.y = fma(-ua, ma.y, o.y);
 }
+// The same entry in FP32 (the mixed solve's operator), as k_apply_mfma32 forms it.
+__device__ __forceinline__ float2 op_out(float xik, float sr, float si, float dre, float dim, float2 xjc) {
+  float2 o;
+  o.x = fmaf(xik, sr, fmaf(dre, xjc.x, -(dim * xjc.y)));
+  o.y = fmaf(xik, si, fmaf(dre, xjc.y, dim * xjc.x));
+  return o;
+}
+__device__ __forceinline__ void op_moment(float2& o, float ua, float2 ma) {
+  o.x = fmaf(-ua, ma.x, o.x);
+  o.y = fmaf(-ua, ma.y, o.y);
+}
 
 // Perturbation moments m_a(j) = sum_{f,p} M[j][a][f][p] x[j][f][p] (rank r <= 4)
 // for each node j and vector v, split over S column parts: workgroup
@@ -342,6 +353,21 @@ __global__ void __launch_bounds__(256) k_apply(const cv<R>* __restrict__ x, cv<R
 // ceil(ceil(Ny / 16) / RT), block 64 NW.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+// One matrix-core step acc += A B of a 16 x 16 x 4 tile in precision R, and the
+// tile row that register q of lane group lk (lane / 16) holds: rows lk + 4 q for
+// v_mfma_f64_16x16x4f64, rows 4 lk + q for v_mfma_f32_16x16x4f32.
+template <class R> struct mfma_acc { typedef dbl4 type; };
+template <> struct mfma_acc<float> { typedef flt4 type; };
+__device__ __forceinline__ dbl4 mfma4(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ flt4 mfma4(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+template <class R>
+__device__ __forceinline__ int acc_row(int lk, int q) {
+  return sizeof(R) == 8 ? lk + 4 * q : 4 * lk + q;
+}
 // NW wavefronts per workgroup, each a column tile of 16; with NW > 1 the D_x^T
 // row slice of the workgroup is staged once in LDS and shared.  The moments of
 // the workgroup's rows are summed from their S parts once into LDS.
@@ -654,16 +680,17 @@ __device__ __forceinline__ void st_off(T* base, uint32_t byte_off, T v) {
 
 // Totals of the S moment parts of nvec vectors, in the order of mom_at:
 // tot[(v Ny + j) r + a].  One thread per entry.
-__global__ void __launch_bounds__(256) k_mom_total(const double2* __restrict__ mom, double2* __restrict__ tot,
+template <class R>
+__global__ void __launch_bounds__(256) k_mom_total(const cv<R>* __restrict__ mom, cv<R>* __restrict__ tot,
                                                    int64_t count, int r, int S) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= count) return;
   const int64_t vj = e / r, a = e - vj * r;
-  const double2* p = mom + vj * S * r + a;
-  double2 part[8];
+  const cv<R>* p = mom + vj * S * r + a;
+  cv<R> part[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) part[q] = (q < S) ? p[(int64_t)q * r] : make_double2(0.0, 0.0);
-  double2 s = part[0];
+  for (int q = 0; q < 8; ++q) part[q] = (q < S) ? p[(int64_t)q * r] : mk<R>(0, 0);
+  cv<R> s = part[0];
 #pragma unroll
   for (int q = 1; q < 8; ++q)
     if (q < S) s = cadd(s, part[q]);
@@ -693,22 +720,24 @@ __global__ void __launch_bounds__(256) k_mom_total(const double2* __restrict__ m
 // column group are reused from one L2.  A wavefront whose tile lies past the
 // last column (in the last group) only relays the next item's first chunk.
 // grid ceil(items / per), block 64 WPG; items = ceil(ceil(2 Nxi / 16) / WPG) nvec.
-template <int NRT, int WPG, int RR>
-__global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __restrict__ x,
-                                                          double2* __restrict__ y, int64_t n, int Ny,
-                                                          int Nxi, double tau_re, double tau_im,
-                                                          double beta, const double* __restrict__ DxT,
-                                                          const double* __restrict__ xi_x,
-                                                          const double* __restrict__ xi_y,
-                                                          const double* __restrict__ nu,
-                                                          const double* __restrict__ U,
-                                                          const double2* __restrict__ mtot, int nvec,
+template <class R, int NRT, int WPG, int RR>
+__global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restrict__ x,
+                                                          cv<R>* __restrict__ y, int64_t n, int Ny,
+                                                          int Nxi, R tau_re, R tau_im,
+                                                          R beta, const R* __restrict__ DxT,
+                                                          const R* __restrict__ xi_x,
+                                                          const R* __restrict__ xi_y,
+                                                          const R* __restrict__ nu,
+                                                          const R* __restrict__ U,
+                                                          const cv<R>* __restrict__ mtot, int nvec,
                                                           int64_t nitems, int per) {
+  typedef typename mfma_acc<R>::type acc4;
+  constexpr uint32_t XS = sizeof(cv<R>), RS = sizeof(R);   // bytes per entry
   constexpr int K4 = 4 * NRT;             // K steps of 4 rows, N_y <= 16 NRT
   constexpr int XB = 4;                   // K steps per chunk
   constexpr int NMOM = NRT * 16 * 4;      // moments of one vector: rows x 4
-  __shared__ double afs[K4 * NRT * 64];   // [step][row tile][lane]
-  __shared__ double2 ms[2][NMOM];         // [buffer][row * 4 + a]
+  __shared__ R afs[K4 * NRT * 64];        // [step][row tile][lane]
+  __shared__ cv<R> ms[2][NMOM];          // [buffer][row * 4 + a]
   const int nc = 2 * Nxi;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -720,7 +749,7 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
     const int l = idx & 63, st = idx >> 6;
     const int t = st % NRT, s = st / NRT;
     const int m = 4 * s + (l >> 4), row = t * 16 + (l & 15);
-    afs[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : 0.0;
+    afs[idx] = (m < Ny && row < Ny) ? DxT[(int64_t)m * Ny + row] : (R)0;
   }
   const int nsteps = (Ny + 3) >> 2;
   const int nch = (nsteps + XB - 1) / XB;
@@ -728,19 +757,19 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
   const int mj = threadIdx.x >> 2, ma = threadIdx.x & 3;
   // moment entry (mj, ma) of vector v
   auto mom_load = [&](int v) {
-    return (mthr && mj < Ny && ma < RR) ? mtot[((int64_t)v * Ny + mj) * RR + ma] : make_double2(0.0, 0.0);
+    return (mthr && mj < Ny && ma < RR) ? mtot[((int64_t)v * Ny + mj) * RR + ma] : mk<R>(0, 0);
   };
-  auto load_chunk = [&](int v, int c, int ch, double2* dst) {
-    const double2* xv = x + (int64_t)v * n;
+  auto load_chunk = [&](int v, int c, int ch, cv<R>* dst) {
+    const cv<R>* xv = x + (int64_t)v * n;
 #pragma unroll
     for (int p = 0; p < XB; ++p) {
       const int m = 4 * (ch * XB + p) + lk;
-      dst[p] = (m < Ny && c < nc) ? ld_off(xv, (uint32_t)(m * nc + c) * 16u) : make_double2(0.0, 0.0);
+      dst[p] = (m < Ny && c < nc) ? ld_off(xv, (uint32_t)(m * nc + c) * XS) : mk<R>(0, 0);
     }
   };
   int v = (int)(i0 % nvec), g = (int)(i0 / nvec);
   if (mthr) ms[0][threadIdx.x] = mom_load(v);
-  double2 xa[XB], xb[XB];
+  cv<R> xa[XB], xb[XB];
   load_chunk(v, (g * WPG + w) * 16 + li, 0, xa);
   __syncthreads();
   int buf = 0;
@@ -749,9 +778,9 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
     const bool more = it + 1 < i1;
     const int vn = (v + 1 == nvec) ? 0 : v + 1, gn = (v + 1 == nvec) ? g + 1 : g;
     const int cn = (gn * WPG + w) * 16 + li;
-    dbl4 are[NRT], aim[NRT];
+    acc4 are[NRT], aim[NRT];
 #pragma unroll
-    for (int t = 0; t < NRT; ++t) { are[t] = dbl4{0, 0, 0, 0}; aim[t] = dbl4{0, 0, 0, 0}; }
+    for (int t = 0; t < NRT; ++t) { are[t] = acc4{0, 0, 0, 0}; aim[t] = acc4{0, 0, 0, 0}; }
     if ((g * WPG + w) * 16 < nc) {
       for (int ch = 0; ch < nch; ++ch) {
         if (ch + 1 < nch) load_chunk(v, c, ch + 1, xb);
@@ -762,9 +791,9 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
           if (s < nsteps) {
 #pragma unroll
             for (int t = 0; t < NRT; ++t) {
-              const double a = afs[(s * NRT + t) * 64 + lane];
-              are[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xa[p].x, are[t], 0, 0, 0);
-              aim[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xa[p].y, aim[t], 0, 0, 0);
+              const R a = afs[(s * NRT + t) * 64 + lane];
+              are[t] = mfma4(a, xa[p].x, are[t]);
+              aim[t] = mfma4(a, xa[p].y, aim[t]);
             }
           }
         }
@@ -775,7 +804,7 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
       load_chunk(vn, cn, 0, xa);
     }
     // the next item's moments load during the epilogue
-    const double2 mnext = more ? mom_load(vn) : make_double2(0.0, 0.0);
+    const cv<R> mnext = more ? mom_load(vn) : mk<R>(0, 0);
     // epilogue on the accumulator layout: column c, rows j = t 16 + lk + 4 q.
     // The row index is made opaque per item so the compiler keeps no
     // per-row masks or offsets live across items; loads take clamped rows and
@@ -784,40 +813,40 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const double2* __rest
     asm volatile("" : "+v"(lko));
     if (c < nc) {
       const int f = c / Nxi, k = c - f * Nxi;
-      const double xik = xi_x[k], bxy = beta * xi_y[k];
-      const double2* xv = x + (int64_t)v * n;
-      double2* yv = y + (int64_t)v * n;
-      const double2* mb = ms[buf];
+      const R xik = xi_x[k], bxy = beta * xi_y[k];
+      const cv<R>* xv = x + (int64_t)v * n;
+      cv<R>* yv = y + (int64_t)v * n;
+      const cv<R>* mb = ms[buf];
 #pragma unroll
       for (int t = 0; t < NRT; ++t) {
         if (t * 16 < Ny) {
-          double2 xq[4];
-          double nq[4], uq[4][RR];
+          cv<R> xq[4];
+          R nq[4], uq[4][RR];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int jc = min(t * 16 + lko + 4 * q, Ny - 1);
-            xq[q] = ld_off(xv, (uint32_t)(jc * nc + c) * 16u);
+            const int jc = min(t * 16 + acc_row<R>(lko, q), Ny - 1);
+            xq[q] = ld_off(xv, (uint32_t)(jc * nc + c) * XS);
             nq[q] = nu[jc];
 #pragma unroll
             for (int a = 0; a < RR; ++a)
-              uq[q][a] = ld_off(U + (int64_t)a * Nxi, (uint32_t)((jc * 2 + f) * RR * Nxi + k) * 8u);
+              uq[q][a] = ld_off(U + (int64_t)a * Nxi, (uint32_t)((jc * 2 + f) * RR * Nxi + k) * RS);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int j = t * 16 + lko + 4 * q;
+            const int j = t * 16 + acc_row<R>(lko, q);
             if (j < Ny) {
-              const double2 xjc = xq[q];
-              const bool bc = (j == Ny - 1 && xik > 0.0) || (j == 0 && xik < 0.0);
-              double2 out;
+              const cv<R> xjc = xq[q];
+              const bool bc = (j == Ny - 1 && xik > (R)0) || (j == 0 && xik < (R)0);
+              cv<R> out;
               if (bc) {
                 out = xjc;
               } else {
-                const double dre = nq[q] - tau_re, dim = bxy - tau_im;
+                const R dre = nq[q] - tau_re, dim = bxy - tau_im;
                 out = op_out(xik, are[t][q], aim[t][q], dre, dim, xjc);
 #pragma unroll
                 for (int a = 0; a < RR; ++a) op_moment(out, uq[q][a], mb[j * 4 + a]);
               }
-              st_off(yv, (uint32_t)(j * nc + c) * 16u, out);
+              st_off(yv, (uint32_t)(j * nc + c) * XS, out);
             }
           }
         }
@@ -2489,7 +2518,7 @@ void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny
 // 8 or 16 rows per thread (apply_waves 0); each gives its own FP32 rounding.
 static void apply_f32(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi, int r,
                       double tre, double tim, double beta, const float* DxT, const float* xix, const float* xiy,
-                      const float* nu, const float* U, const float2* mom, const int* skip) {
+                      const float* nu, const float* U, float2* mom, const int* skip) {
   const int nc = 2 * Nxi;
   const int cblocks = (nc + 255) / 256;
   const int S = moment_splits(Ny, nvec, Nxi, 1);
@@ -2508,10 +2537,46 @@ static void apply_f32(hipStream_t st, const float2* x, float2* y, int64_t n, int
     return;
   }
   const int ctiles = (nc + 15) / 16, nrt = (Ny + 15) / 16;
+  // many vectors: the streaming kernel, as for FP64 (the moment totals after the
+  // partials: mom holds nvec Ny r 9 entries)
+  const bool off32 = (uint64_t)n * sizeof(float2) < ((uint64_t)1 << 32) &&
+                     (uint64_t)Ny * 2 * r * Nxi * sizeof(float) < ((uint64_t)1 << 32);
+  const int64_t sgroups = (ctiles + 7) / 8;
+  const bool stream_fits = sgroups >= 4 && sgroups * nvec >= device_cus() / 2;
+  if (nvec >= kBatchMin && !skip && nrt <= 6 && off32 && (r == 3 || r == 4) &&
+      (tuned ? (tn.apply_nw == 8 || (tn.apply_nw == 0 && stream_fits)) : stream_fits)) {
+    constexpr int WPG = 8;
+    float2* tot = mom + (size_t)nvec * Ny * r * 8;
+    const int64_t ntot = (int64_t)nvec * Ny * r;
+    hipLaunchKernelGGL(k_mom_total<float>, dim3(nblk(ntot, 256)), dim3(256), 0, st, mom, tot, ntot, r, S);
+    const int64_t items = sgroups * nvec;
+    const int64_t slots = device_cus();
+    const int per = (int)std::max<int64_t>(1, (items + slots - 1) / slots);
+    const int nwg = (int)((items + per - 1) / per);
+#define KLST_MS32(NRT_)                                                                                      \
+  do {                                                                                                       \
+    if (r == 4)                                                                                              \
+      hipLaunchKernelGGL((k_apply_stream<float, NRT_, WPG, 4>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, \
+                         Nxi, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, tot, nvec, items, per); \
+    else                                                                                                     \
+      hipLaunchKernelGGL((k_apply_stream<float, NRT_, WPG, 3>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, \
+                         Nxi, (float)tre, (float)tim, (float)beta, DxT, xix, xiy, nu, U, tot, nvec, items, per); \
+  } while (0)
+    switch (nrt) {
+      case 1: KLST_MS32(1); break;
+      case 2: KLST_MS32(2); break;
+      case 3: KLST_MS32(3); break;
+      case 4: KLST_MS32(4); break;
+      case 5: KLST_MS32(5); break;
+      default: KLST_MS32(6); break;
+    }
+#undef KLST_MS32
+    return;
+  }
   int rt = 6;
   while (rt > 1 && (int64_t)ctiles * ((nrt + rt - 1) / rt) * nvec < 1024) rt = (rt == 6) ? 3 : (rt == 3 ? 2 : 1);
-  // many vectors: at most two row tiles per wavefront (M = 4 shape, 128 vectors:
-  // 345 us against 405 us with six)
+  // many vectors on the tiled kernel: at most two row tiles per wavefront (M = 4
+  // shape, 128 vectors: 345 us against 405 us with six)
   if (nvec >= kBatchMin) rt = std::min(rt, 2);
   bool wide = (int64_t)((ctiles + 3) / 4) * ((nrt + rt - 1) / rt) * nvec >= 512;
   if (tuned && (tn.apply_nw == 1 || tn.apply_nw == 4) &&
@@ -2559,7 +2624,7 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
     // moment totals after the partials (mom holds nvec Ny r 9 entries)
     double2* tot = mom + (size_t)nvec * Ny * r * 8;
     const int64_t ntot = (int64_t)nvec * Ny * r;
-    hipLaunchKernelGGL(k_mom_total, dim3(nblk(ntot, 256)), dim3(256), 0, st, mom, tot, ntot, r, S);
+    hipLaunchKernelGGL(k_mom_total<double>, dim3(nblk(ntot, 256)), dim3(256), 0, st, mom, tot, ntot, r, S);
     const int64_t groups = (ctiles + WPG - 1) / WPG;
     const int64_t items = groups * nvec;
     const int64_t slots = device_cus();                  // one 8-wavefront workgroup per CU
@@ -2568,10 +2633,10 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
 #define KLST_MS(NRT_)                                                                                        \
   do {                                                                                                       \
     if (r == 4)                                                                                              \
-      hipLaunchKernelGGL((k_apply_stream<NRT_, WPG, 4>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
+      hipLaunchKernelGGL((k_apply_stream<double, NRT_, WPG, 4>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
                          tre, tim, beta, Dx, xix, xiy, nu, U, tot, nvec, items, per);                        \
     else                                                                                                     \
-      hipLaunchKernelGGL((k_apply_stream<NRT_, WPG, 3>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
+      hipLaunchKernelGGL((k_apply_stream<double, NRT_, WPG, 3>), dim3(nwg), dim3(64 * WPG), 0, st, x, y, n, Ny, Nxi, \
                          tre, tim, beta, Dx, xix, xiy, nu, U, tot, nvec, items, per);                        \
   } while (0)
     switch (nrt) {
@@ -2615,7 +2680,7 @@ void launch_apply(hipStream_t st, const double2* x, double2* y, int64_t n, int n
 }
 void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const float* Dx, const float* xix,
-                  const float* xiy, const float* nu, const float* U, const float2* mom,
+                  const float* xiy, const float* nu, const float* U, float2* mom,
                   const int* skip) {
   apply_f32(st, x, y, n, nvec, Ny, Nxi, r, tre, tim, beta, Dx, xix, xiy, nu, U, mom, skip);
 }

@@ -129,7 +129,7 @@ void launch_moments(hipStream_t st, const float2* x, int64_t n, int nvec, int Ny
                     const float* M, float2* mom, const int* skip);
 void launch_apply(hipStream_t st, const float2* x, float2* y, int64_t n, int nvec, int Ny, int Nxi,
                   int r, double tre, double tim, double beta, const float* Dx, const float* xix,
-                  const float* xiy, const float* nu, const float* U, const float2* mom,
+                  const float* xiy, const float* nu, const float* U, float2* mom,
                   const int* skip);
 void launch_blockinv_apply(hipStream_t st, const float2* x, float2* y, int Ny, int Nxi, int nl,
                            int nblocks, const float2* Kinv, const int64_t* koff, const int* skip);

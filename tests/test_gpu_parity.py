@@ -731,3 +731,42 @@ def test_apply_many_f32_matches_oracle(cfg, nvec):
         ref = P.apply_structured(x64, tau) if wl.n > 60000 else P.apply(x64, tau)
         bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
         assert np.all(np.abs(y[i] - ref) <= bound), (i, np.max(np.abs(y[i] - ref) / bound))
+
+
+@pytest.mark.parametrize("cfg", ["c3", "ragged1", "ragged2"])
+def test_apply_many_f32_streaming_kernel(cfg, tmp_path):
+    """The FP32 streaming many-vector kernel (chosen through the launch table
+    as (0, 8)) against the tiled FP32 kernel at two row tiles and four
+    wavefronts: both accumulate every entry's streaming sum over K in the same
+    order on the FP32 matrix cores and form the epilogue with the same fused
+    multiply-adds, so they agree bit for bit; and each vector is within the
+    FP32 bound of the oracle's product."""
+    klst = _klst()
+    wl = {"c3": W.config3, "ragged1": lambda: _ragged(1), "ragged2": lambda: _ragged(2)}[cfg]()
+    P = O.Pencil(wl)
+    nvec, tau = 9, 0.15 - 0.25j
+    x = np.stack([W.random_vector(wl.n, 300 + i) for i in range(nvec)]).astype(np.complex64)
+    xd = torch.from_numpy(x.ravel()).to(DEV)
+    out = {}
+    klst.tune_clear()
+    try:
+        ctx = _ctx(wl, precision=1, pc_kernel=2)
+        for name, tile in (("tiled", (2, 4)), ("stream", (0, 8))):
+            path = tmp_path / f"{name}.txt"
+            path.write_text(f"{wl.Ny} {wl.Nxi} {nvec} 1 {tile[0]} {tile[1]} 0 0\n")
+            klst.tune_clear()
+            klst.tune_load(str(path))
+            print(f"[case] FP32 batched {name} {wl.name}", flush=True)
+            yd = torch.empty_like(xd)
+            ctx.apply_many_f32(tau, nvec, xd, yd)
+            torch.cuda.synchronize()
+            out[name] = yd
+    finally:
+        klst.tune_clear()
+    assert torch.equal(out["stream"], out["tiled"])
+    y = out["stream"].cpu().numpy().astype(np.complex128).reshape(nvec, wl.n)
+    for i in range(nvec):
+        x64 = x[i].astype(np.complex128)
+        ref = P.apply_structured(x64, tau) if wl.n > 60000 else P.apply(x64, tau)
+        bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
+        assert np.all(np.abs(y[i] - ref) <= bound), (i, np.max(np.abs(y[i] - ref) / bound))
