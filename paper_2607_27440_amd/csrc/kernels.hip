@@ -701,8 +701,9 @@ __global__ void __launch_bounds__(256) k_mom_total(const cv<R>* __restrict__ mom
 // item is (group of WPG 16-column tiles, vector v); wavefront w computes the
 // whole output strip (all N_y rows) of column tile WPG g + w for vector v.
 // * The D_x fragments of every row tile (the A operands of
-//   v_mfma_f64_16x16x4f64) sit in LDS in lane order, so each K step reads them
-//   conflict-free with one 8-byte load per lane and row tile.
+//   v_mfma_f64_16x16x4f64, or of v_mfma_f32_16x16x4f32 for R = float, the
+//   mixed solve's operator) sit in LDS in lane order, so each K step reads them
+//   conflict-free with one load per lane and row tile.
 // * The x strip streams from memory into registers in chunks of XB K steps;
 //   the next chunk, of this item or of the next, loads while the current
 //   chunk's MFMAs run.  The one barrier per item orders only LDS (an LDS-only
@@ -714,7 +715,8 @@ __global__ void __launch_bounds__(256) k_mom_total(const cv<R>* __restrict__ mom
 //   plus a 32-bit byte offset (each vector and table is under 4 GiB, checked by
 //   the launcher), which keeps the address arithmetic in few registers.
 // Every output entry is accumulated as in k_apply_mfma (K in steps of 4 from 0,
-// then op_out and op_moment), so the results are bit-identical to it.
+// then op_out and op_moment), so the results are bit-identical to it (to
+// k_apply_mfma32 for R = float).
 // Workgroup b takes a contiguous range of items, ordered column group major and
 // vector minor, at its XCD-ordered index, so the U entries and tables of a
 // column group are reused from one L2.  A wavefront whose tile lies past the
