@@ -2486,8 +2486,10 @@ static void moments_t(hipStream_t st, const cv<R>* x, int64_t n, int nvec, int N
   {
     const int per = (2 * Nxi + S - 1) / S;
     if (nvec >= kBatchMin && !skip && per <= 3 * 256) {
+      // about 4,096 workgroups (M = 4 shape, 128 FP32 vectors: 370 against
+      // 388 us for the whole operator with 2,048; no change beyond)
       int VG, nvg;
-      vector_groups(nvec, (int64_t)Ny * S, 2048, &VG, &nvg);
+      vector_groups(nvec, (int64_t)Ny * S, 4096, &VG, &nvg);
       const dim3 g(Ny * S, nvg);
       if (per <= 256)
         hipLaunchKernelGGL((k_moments_batch<R, 1>), g, dim3(256), 0, st, x, n, Ny, Nxi, r, M, mom, S, nvec, VG);
