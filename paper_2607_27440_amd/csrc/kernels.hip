@@ -736,10 +736,19 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restri
   typedef typename mfma_acc<R>::type acc4;
   constexpr uint32_t XS = sizeof(cv<R>), RS = sizeof(R);   // bytes per entry
   constexpr int K4 = 4 * NRT;             // K steps of 4 rows, N_y <= 16 NRT
-  constexpr int XB = 4;                   // K steps per chunk
+  constexpr int XB = 4;                   // K steps per chunk: one row tile of x
+  static_assert(XB * 4 == 16, "a chunk of x rows is one row tile");
   constexpr int NMOM = NRT * 16 * 4;      // moments of one vector: rows x 4
   __shared__ R afs[K4 * NRT * 64];        // [step][row tile][lane]
   __shared__ cv<R> ms[2][NMOM];          // [buffer][row * 4 + a]
+  // The x entries of the first KEEP row tiles, as the chunk loop loads them
+  // (chunk t is row tile t), kept per wavefront for the epilogue in the LDS that
+  // the one workgroup per CU leaves free: [tile][wavefront][K step][lane]
+  constexpr int LDS_WG = 160 * 1024;
+  constexpr int USED = K4 * NRT * 64 * (int)sizeof(R) + 2 * NMOM * (int)sizeof(cv<R>);
+  constexpr int PER_TILE = WPG * XB * 64 * (int)sizeof(cv<R>);
+  constexpr int KEEP = ((LDS_WG - USED) / PER_TILE < NRT) ? (LDS_WG - USED) / PER_TILE : NRT;
+  __shared__ cv<R> xk[(KEEP > 0 ? KEEP : 1) * WPG * XB * 64];
   const int nc = 2 * Nxi;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
@@ -787,6 +796,10 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restri
       for (int ch = 0; ch < nch; ++ch) {
         if (ch + 1 < nch) load_chunk(v, c, ch + 1, xb);
         else if (more) load_chunk(vn, cn, 0, xb);
+        if (ch < KEEP) {
+#pragma unroll
+          for (int p = 0; p < XB; ++p) xk[((ch * WPG + w) * XB + p) * 64 + lane] = xa[p];
+        }
 #pragma unroll
         for (int p = 0; p < XB; ++p) {
           const int s = ch * XB + p;
@@ -813,6 +826,10 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restri
     // only the stores are guarded.
     int lko = lk;
     asm volatile("" : "+v"(lko));
+    // the kept entries were written by other lanes of this wavefront (FP32 layout)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
     if (c < nc) {
       const int f = c / Nxi, k = c - f * Nxi;
       const R xik = xi_x[k], bxy = beta * xi_y[k];
@@ -826,8 +843,13 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restri
           R nq[4], uq[4][RR];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int jc = min(t * 16 + acc_row<R>(lko, q), Ny - 1);
-            xq[q] = ld_off(xv, (uint32_t)(jc * nc + c) * XS);
+            const int rho = acc_row<R>(lko, q), jc = min(t * 16 + rho, Ny - 1);
+            // row 16 t + rho was the B operand of K step 4 t + rho / 4 in lane
+            // li + 16 (rho % 4)
+            if (t < KEEP)
+              xq[q] = xk[((t * WPG + w) * XB + (rho >> 2)) * 64 + li + 16 * (rho & 3)];
+            else
+              xq[q] = ld_off(xv, (uint32_t)(jc * nc + c) * XS);
             nq[q] = nu[jc];
 #pragma unroll
             for (int a = 0; a < RR; ++a)
