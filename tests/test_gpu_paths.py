@@ -9,9 +9,9 @@ the oracle:
     entry by entry against the oracle's structured product, and the exported
     CSR matrix at config 2 against the oracle's assembled A;
   * Jacobi-Davidson with the explicit CSR operator (op_mode 1) at config 2;
-  * eigenvectors against the oracle's (SURVEY rule c4): at config 1 within a
-    bound derived from the residuals and the second-smallest singular value of
-    A - lambda B, at config 2 within 10 e_i kappa_i.
+  * eigenvectors against the oracle's, not only the eigenvalues: at config 1
+    within a bound derived from the residuals and the second-smallest singular
+    value of A - lambda B, at config 2 within 10 e_i kappa_i.
 """
 import numpy as np
 import pytest
