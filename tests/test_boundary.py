@@ -36,7 +36,11 @@ def test_library_exports_every_declared_symbol(klst):
 
 @pytest.mark.parametrize("mk", [W.config1, W.config2,
                                 lambda: W.make_workload("dv1", mach=2.2, Ny=9, Qx=12, Qy=1, beta=0.4,
-                                                        sigma=0, nev=2, base="bimodal", delta=2.0, Dv=1)])
+                                                        sigma=0, nev=2, base="bimodal", delta=2.0, Dv=1),
+                                lambda: W.make_workload("ny56", mach=2.0, Ny=56, Qx=7, Qy=5, beta=0.5,
+                                                        sigma=0, nev=4, base="bimodal", delta=2.5, Dv=2),
+                                lambda: W.make_workload("ny72", mach=2.0, Ny=72, Qx=7, Qy=5, beta=0.5,
+                                                        sigma=0, nev=4, base="bimodal", delta=2.5, Dv=2)])
 def test_host_tables_match_oracle(klst, mk):
     wl = mk()
     P = O.Pencil(wl)
@@ -46,6 +50,10 @@ def test_host_tables_match_oracle(klst, mk):
     assert rel(t["nu"], P.state["nu"]) <= 1e-14
     assert rel(t["U"], P.U) <= 1e-13
     assert rel(t["M"], P.M) <= 1e-13
+    # node by node, relative to the node's largest entry
+    for j in range(P.Ny):
+        assert rel(t["U"][j], P.U[j]) <= 1e-13, j
+        assert rel(t["M"][j], P.M[j]) <= 1e-13, j
     assert (t["bc"] == P.bc).all()
 
 

@@ -48,6 +48,28 @@ def _abs_bound(P, x, tau):
     return y.ravel()
 
 
+def _table_bound(P, x, eps_dx=1e-14, eps_nu=1e-14, eps_u=1e-13, eps_m=1e-13):
+    """Entrywise bound of |(A_lib - A) x| when the library's own assembly lies
+    within eps of the oracle's tables (the agreement the host-table test
+    asserts: D_x and nu relative to their largest entry, U and M node by node
+    relative to the node's largest entry); first order in the differences,
+    zero on the boundary rows (y = x there)."""
+    wl = P.wl
+    ax = np.abs(x).reshape(P.Ny, 2, P.Nxi)
+    aU, aM = np.abs(P.U), np.abs(P.M)
+    dD = eps_dx * np.abs(P.Dx).max()
+    dn = eps_nu * np.abs(P.state["nu"]).max()
+    dU = eps_u * aU.max(axis=(1, 2, 3))                             # per node
+    dM = eps_m * aM.max(axis=(1, 2, 3))
+    y = np.broadcast_to(dD * ax.sum(axis=0)[None] * np.abs(wl.xi_x)[None, None, :], ax.shape).copy()
+    y += dn * ax
+    m = np.einsum("jafk,jfk->ja", aM, ax)                           # |M| |x| per node and moment
+    y += (dU * m.sum(axis=1))[:, None, None]                        # |dU| |M| |x|
+    y += (dM * ax.sum(axis=(1, 2)))[:, None, None] * aU.sum(axis=2)  # |U| |dM| |x|
+    y[P.bc] = 0.0
+    return y.ravel()
+
+
 def _norm1_bound(P):
     """Upper bound of ||A||_1 (largest column sum of |A|) from the structured pieces,
     by the triangle inequality on every entry; needs no assembled matrix."""
@@ -770,3 +792,61 @@ def test_apply_many_f32_streaming_kernel(cfg, tmp_path):
         ref = P.apply_structured(x64, tau) if wl.n > 60000 else P.apply(x64, tau)
         bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
         assert np.all(np.abs(y[i] - ref) <= bound), (i, np.max(np.abs(y[i] - ref) / bound))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("Ny", [56, 72])
+def test_apply_many_streaming_kernel_row_tiles(Ny, prec, tmp_path):
+    """The streaming many-vector kernel at 4 and 5 row tiles, the last one 8
+    rows long, where its LDS holds the x entries of only some row tiles for the
+    epilogue in FP64 (three of four, three of five) and of all of them in FP32:
+    bit for bit what the single-vector application (FP64) or the tiled FP32
+    kernel gives, and within the oracle's product by the dot-product bound
+    plus, in FP64, the bound of the two assemblies' table differences (at these
+    shapes some small U entries differ by far more than the rounding of a dot
+    product relative to themselves, though by under 1e-14 of the table)."""
+    klst = _klst()
+    wl = W.make_workload(f"stream_ny{Ny}", mach=2.0, Ny=Ny, Qx=7, Qy=5, beta=0.5,
+                         sigma=0.0, nev=4, base="bimodal", delta=2.5, Dv=2)
+    P = O.Pencil(wl)
+    nvec, tau = 9, 0.3 - 0.1j
+    x = np.stack([W.random_vector(wl.n, 500 + i) for i in range(nvec)])
+    if prec:
+        x = x.astype(np.complex64)
+    xd = torch.from_numpy(x.ravel()).to(DEV)
+    klst.tune_clear()
+    try:
+        ctx = _ctx(wl, precision=prec, pc_kernel=2)
+        if prec:
+            path = tmp_path / "tiled.txt"
+            path.write_text(f"{wl.Ny} {wl.Nxi} {nvec} 1 2 4 0 0\n")
+            klst.tune_load(str(path))
+            y1 = torch.empty_like(xd)
+            ctx.apply_many_f32(tau, nvec, xd, y1)
+            klst.tune_clear()
+        else:
+            y1 = torch.empty_like(xd)
+            for i in range(nvec):
+                ctx.apply(tau, xd[i * wl.n:(i + 1) * wl.n], y1[i * wl.n:(i + 1) * wl.n])
+        path = tmp_path / "stream.txt"
+        path.write_text(f"{wl.Ny} {wl.Nxi} {nvec} {prec} 0 8 0 0\n")
+        klst.tune_load(str(path))
+        print(f"[case] streaming kernel N_y={Ny} precision {prec}", flush=True)
+        y = torch.empty_like(xd)
+        if prec:
+            ctx.apply_many_f32(tau, nvec, xd, y)
+        else:
+            ctx.apply_many(tau, nvec, xd, y)
+        torch.cuda.synchronize()
+    finally:
+        klst.tune_clear()
+    assert torch.equal(y, y1)
+    yh = y.cpu().numpy().astype(np.complex128).reshape(nvec, wl.n)
+    for i in range(nvec):
+        x64 = x[i].astype(np.complex128)
+        ref = P.apply(x64, tau)
+        if prec:
+            bound = 2 * (P.Ny + 2 * P.Nxi + P.r + 8) * 2.0 ** -24 * _abs_bound(P, x64, tau) + 1e-30
+        else:
+            bound = _gamma(P) * _abs_bound(P, x64, tau) + _table_bound(P, x64) + 1e-300
+        assert np.all(np.abs(yh[i] - ref) <= bound), (i, np.max(np.abs(yh[i] - ref) / bound))
