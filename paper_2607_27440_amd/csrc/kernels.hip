@@ -102,6 +102,57 @@ __device__ __forceinline__ double wave_sum(double v) {
   return h0 + h1;
 }
 
+// lane ^ 4 within each row of 16: lanes 0-3 and 8-11 read lane + 4 (row_shl:4),
+// lanes 4-7 and 12-15 read lane - 4 (row_shr:4)
+__device__ __forceinline__ double dpp_xor4_f64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  int rlo = __builtin_amdgcn_update_dpp(0, lo, 0x104, 0xF, 0x5, false);
+  int rhi = __builtin_amdgcn_update_dpp(0, hi, 0x104, 0xF, 0x5, false);
+  rlo = __builtin_amdgcn_update_dpp(rlo, lo, 0x114, 0xF, 0xA, false);
+  rhi = __builtin_amdgcn_update_dpp(rhi, hi, 0x114, 0xF, 0xA, false);
+  return __hiloint2double(rhi, rlo);
+}
+
+// Eight wavefront sums at once, each bit for bit the one wave_sum gives: the
+// same pairs at every level (lanes l ^ 1, l ^ 2, l ^ 4, l ^ 8, l ^ 16, then the
+// two 32-lane halves), but at each of the first three levels a lane keeps half
+// of its values and adds its partner's copies of just those, so the later
+// levels move one value instead of eight.  Lane l returns the sum of
+// p[4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1)].  All lanes active.
+__device__ __forceinline__ double wave_sum8(const double (&p)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b0 = (lane & 1) != 0, b1 = (lane & 2) != 0, b2 = (lane & 4) != 0;
+  double q[4], t[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double keep = b0 ? p[4 + i] : p[i], send = b0 ? p[i] : p[4 + i];
+    q[i] = keep + dpp_f64<0xB1>(send);         // quad_perm [1, 0, 3, 2]
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double keep = b1 ? q[2 + i] : q[i], send = b1 ? q[i] : q[2 + i];
+    t[i] = keep + dpp_f64<0x4E>(send);         // quad_perm [2, 3, 0, 1]
+  }
+  double v;
+  {
+    const double keep = b2 ? t[1] : t[0], send = b2 ? t[0] : t[1];
+    v = keep + dpp_xor4_f64(send);
+  }
+  v += dpp_f64<0x128>(v);                      // row_ror:8 = lane ^ 8 within 16
+  {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);   // lane ^ 16 within 32
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    v += __hiloint2double(hi, lo);
+  }
+  {
+    const int addr = (lane ^ 32) << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    v += __hiloint2double(hi, lo);
+  }
+  return v;
+}
+
 // Sum of a double2 over a 256-thread block, result valid in thread 0.
 __device__ __forceinline__ double2 block_sum256(double2 v, double2* sh /*[4]*/) {
   v.x = wave_sum(v.x);
@@ -224,15 +275,21 @@ __global__ void __launch_bounds__(256) k_moments(const cv<R>* __restrict__ x, in
     if (c0 >= cend) break;
     load(c0);
   }
-  // all r sums of the four wavefronts in one exchange: wave sums, one barrier,
-  // then thread a adds the four waves' values in wave order
+  // all r sums of the four wavefronts in one exchange: the eight wave sums
+  // together (wave_sum8, lane l < 8 holding entry q(l) of sh[wv] read as 8
+  // doubles), one barrier, then thread a adds the four waves' values in wave
+  // order
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double pv[8];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    if (a < r) {
-      const double sr = wave_sum((double)ar[a]), si = wave_sum((double)ai[a]);
-      if (lane == 0) sh[wv][a] = make_double2(sr, si);
-    }
+    pv[2 * a] = (a < r) ? (double)ar[a] : 0.0;
+    pv[2 * a + 1] = (a < r) ? (double)ai[a] : 0.0;
+  }
+  const double ws = wave_sum8(pv);
+  if (lane < 8) {
+    const int q = 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1);
+    if ((q >> 1) < r) reinterpret_cast<double*>(&sh[wv][0])[q] = ws;
   }
   __syncthreads();
   if (threadIdx.x < r) {
@@ -892,10 +949,11 @@ __global__ void __launch_bounds__(64 * WPG) k_apply_stream(const cv<R>* __restri
 // Moment partials of a group of vectors per workgroup (node j, column part):
 // each thread holds the M entries of its columns (the columns k_moments gives
 // it) in registers and sums every vector of the group in the order of
-// k_moments, so the partials are bit-identical to it.  The next vector's x
-// entries load while the current one is reduced; the per-vector exchange of
-// wavefront sums is double buffered with one LDS-only barrier, so those loads
-// stay in flight across it.  grid (Ny S, vector groups), block 256; CPT =
+// k_moments, so the partials are bit-identical to it (the eight wavefront sums
+// of a vector together, by wave_sum8).  The next two vectors' x entries load
+// while the current one is reduced; the per-vector exchange of wavefront sums
+// is double buffered with one LDS-only barrier, so those loads stay in flight
+// across it.  grid (Ny S, vector groups), block 256; CPT =
 // columns per thread (the part has <= 256 CPT).  R: FP64, or FP32 for the
 // mixed solve's tables (sums in R per thread, wavefront sums in FP64, as in
 // k_moments).
@@ -925,11 +983,12 @@ __global__ void __launch_bounds__(256) k_moments_batch(const cv<R>* __restrict__
       xr[i] = (cc < cend) ? xj[cc] : mk<R>(0, 0);
     }
   };
-  cv<R> xc[CPT], xn[CPT];
+  cv<R> xc[CPT], xn[CPT], xn2[CPT];
   if (v0 < v1) load(v0, xc);
+  if (v0 + 1 < v1) load(v0 + 1, xn);
   for (int v = v0; v < v1; ++v) {
     const int buf = (v - v0) & 1;
-    if (v + 1 < v1) load(v + 1, xn);
+    if (v + 2 < v1) load(v + 2, xn2);
     R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -944,12 +1003,18 @@ __global__ void __launch_bounds__(256) k_moments_batch(const cv<R>* __restrict__
         }
       }
     }
+    // the wavefront sums of (re, im) of every moment at once; lane l < 8 holds
+    // entry q(l) of sh[buf][wv] read as 8 doubles
+    double pv[8];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-      if (a < r) {
-        const double sr = wave_sum((double)ar[a]), si = wave_sum((double)ai[a]);
-        if (lane == 0) sh[buf][wv][a] = make_double2(sr, si);
-      }
+      pv[2 * a] = (a < r) ? (double)ar[a] : 0.0;
+      pv[2 * a + 1] = (a < r) ? (double)ai[a] : 0.0;
+    }
+    const double ws = wave_sum8(pv);
+    if (lane < 8) {
+      const int q = 4 * (lane & 1) + 2 * ((lane >> 1) & 1) + ((lane >> 2) & 1);
+      if ((q >> 1) < r) reinterpret_cast<double*>(&sh[buf][wv][0])[q] = ws;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -960,7 +1025,10 @@ __global__ void __launch_bounds__(256) k_moments_batch(const cv<R>* __restrict__
       mom[(((int64_t)v * Ny + j) * S + part) * r + threadIdx.x] = mk<R>((R)sres.x, (R)sres.y);
     }
 #pragma unroll
-    for (int i = 0; i < CPT; ++i) xc[i] = xn[i];
+    for (int i = 0; i < CPT; ++i) {
+      xc[i] = xn[i];
+      xn[i] = xn2[i];
+    }
   }
 }
 
